@@ -1,0 +1,150 @@
+/*
+ * hines.h -- C-ABI of the MI355X batched Hines solver (libhines.so).
+ *
+ * The library solves, for every cell (neuron) of a forest, the linear system
+ * A x = b of one implicit-Euler step of the discretised cable equation
+ * (F. Huber, "Efficient Tree Solver for Hines Matrices on the GPU", §1, the
+ * discrete system following the cable equation).  A is symmetric and strictly
+ * diagonally dominant, so elimination needs no pivoting.  The solve is the
+ * Hines algorithm (§2, Listing 2): backward elimination from the leaves to the
+ * root through the parent array, a root solve, forward substitution from the
+ * root to the leaves, carried out level-synchronously with one lane per branch
+ * (§3) on a branch-to-lane assignment computed once at setup (§4-§6).
+ *
+ * Numbering (the "user numbering"), matching §2:
+ *   - cell c owns compartments [cell_offsets[c], cell_offsets[c+1]);
+ *   - the first compartment of a cell is its root and has parent -1;
+ *   - every other compartment i has cell_offsets[c] <= parent[i] < i.
+ * Matrix values:
+ *   - diag[i]  = A[i][i];
+ *   - upper[i] = A[i][parent[i]] = A[parent[i]][i], the signed entry (the
+ *     negative edge conductance for the cable matrix); upper[root] is ignored.
+ *
+ * Conventions of every call:
+ *   - Errors are return codes; nothing is thrown across the ABI.  A message for
+ *     the last error of the calling thread is available from hines_last_error.
+ *   - Device pointers are owned by the caller and are never retained or freed.
+ *   - Device work is asynchronous on the given stream (a hipStream_t; NULL is
+ *     the default stream).  Launch failures are reported as HINES_ERR_HIP; a
+ *     fault inside a kernel surfaces at the caller's next synchronisation.
+ *   - A plan may be used by one stream at a time.
+ */
+#ifndef HINES_H
+#define HINES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hines_plan hines_plan; /* opaque, owned by the library */
+
+typedef enum hines_status {
+  HINES_OK = 0,
+  HINES_ERR_NULL = 1,          /* a required pointer is NULL */
+  HINES_ERR_BAD_OFFSETS = 2,   /* cell_offsets not 0 < ... < n, or sizes out of range */
+  HINES_ERR_BAD_PARENT = 3,    /* a root's parent is not -1, or parent[i] outside [cell start, i) */
+  HINES_ERR_BAD_BRANCHES = 4,  /* branch layout invalid (see hines_setup) */
+  HINES_ERR_TOO_WIDE = 5,      /* reserved */
+  HINES_ERR_NCELLS = 6,        /* ncells differs from the plan's */
+  HINES_ERR_OPTION = 7,        /* an option value is out of range */
+  HINES_ERR_OOM = 8,           /* host or device allocation failed */
+  HINES_ERR_HIP = 9,           /* a HIP runtime call or kernel launch failed */
+  HINES_ERR_TOO_BIG = 10,      /* a group does not fit the device's LDS */
+  HINES_ERR_NOT_SDD = 11,      /* reserved for matrix checks */
+  HINES_ERR_STATE = 12         /* the plan was built host_only, or similar misuse */
+} hines_status;
+
+/* Setup options (paper §4-§6).  Obtain defaults from hines_default_options. */
+typedef struct hines_options {
+  int32_t rebalance_root;     /* §6: re-root each cell at its tree centre (0/1)            */
+  int32_t split_branches;     /* §6: split branches longer than their level's average (0/1) */
+  int32_t group_width;        /* §3-§4: lanes per group; multiple of 64 in [64, 1024]      */
+  int32_t cell_order;         /* §4 greedy packing order: 0 input order, 1 size descending  */
+  int32_t max_group_unknowns; /* cap on compartments packed into one group; 0 = automatic   */
+  int32_t host_only;          /* 1: build the tables only (no device upload, no solve)      */
+  int32_t keep_tables;        /* 1: keep the exported tables for hines_get_table            */
+  int32_t bitwise;            /* 1: IEEE divisions and unfused updates, so the solution equals
+                                 the plain algorithm (§2 Listing 2) on the plan numbering bit
+                                 for bit; 0 (default): reciprocal + fused multiply-add form   */
+  int32_t reserved[8];        /* must be 0 */
+} hines_options;
+
+/* Plan summary. */
+typedef struct hines_plan_info {
+  int64_t n, ncells, nbranches, ngroups, nsegments;
+  int32_t max_level;          /* deepest branch level (root branch = 0) */
+  int32_t nclasses;           /* LDS size classes (kernel launches per solve) */
+  int64_t device_table_bytes; /* device memory held by the plan */
+  int64_t max_group_lds_bytes;
+} hines_plan_info;
+
+/* Table ids for hines_get_table (all exported as int64). */
+enum {
+  HINES_TABLE_NODE_PLAN = 0,         /* [n]  plan index of each user compartment              */
+  HINES_TABLE_BRANCHES = 1,          /* [nb*8] per plan branch: cell, level, first user index,
+                                        direction (+1/-1), length, parent branch (-1), group,
+                                        breadth-first rank in its cell                         */
+  HINES_TABLE_U_SRC = 2,             /* [n] per plan index: the user index whose upper[] holds
+                                        its coupling to the plan parent (-1 for roots)         */
+  HINES_TABLE_GROUP_OFFSETS = 3,     /* [ngroups+1]                                            */
+  HINES_TABLE_GROUP_CELLS = 4,       /* [ncells] cells of the groups, packing order            */
+  HINES_TABLE_GROUP_SEG_OFFSETS = 5, /* [ngroups+1] first (group, level) segment of each group */
+  HINES_TABLE_SEG_OFFSETS = 6,       /* [nseg+1] first lane of each segment                    */
+  HINES_TABLE_LANES = 7              /* [nb] plan branch ids in (group, level, lane) order     */
+};
+
+/* Fill *opt with the defaults: no re-rooting, no splitting, group_width 64,
+ * input cell order, automatic cap, device upload, keep tables. */
+void hines_default_options(hines_options* opt);
+
+/* Build a plan (paper §4: "computed once during the setup phase"; §6: the
+ * optional balancing and splitting passes run before the packing).
+ *   parent[n], cell_offsets[ncells+1]: host arrays in the user numbering.
+ *   branch_offsets[nbranches+1]: optional host array (NULL: branches are the
+ *     maximal runs of consecutive compartments, §2).  If given it must run from
+ *     0 to n, increase strictly, start a branch at every cell start, and have
+ *     parent[i] == i-1 inside each branch.  Branches are further cut after any
+ *     compartment that has a child outside its branch.  Ignored when
+ *     rebalance_root is set.
+ *   opt: NULL for defaults.
+ * Host arrays are only read during the call.  The plan's device tables are
+ * allocated on the current device.  On error *out is set to NULL. */
+hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch_offsets,
+                         int64_t nbranches, const int64_t* cell_offsets, int32_t ncells,
+                         const hines_options* opt, hines_plan** out);
+
+/* Solve A x = rhs for all cells in FP64 (paper §2 Listing 2, §3 level-
+ * synchronous sweeps, §5 one read of each matrix entry per sweep).
+ *   diag, upper, rhs, x: device arrays of n doubles in the user numbering.
+ *   x may alias rhs; it must not alias diag or upper.
+ *   ncells must equal the plan's cell count.
+ * Inputs are not modified.  Asynchronous on stream. */
+hines_status hines_solve(const hines_plan* plan, const double* diag, const double* upper,
+                         const double* rhs, double* x, int32_t ncells, void* stream);
+
+/* Summary counts of a plan. */
+hines_status hines_plan_info_get(const hines_plan* plan, hines_plan_info* info);
+
+/* Copy table `which` (HINES_TABLE_*) to host memory as int64.  With
+ * host_out == NULL only *count is set.  capacity is in elements;
+ * HINES_ERR_OPTION if too small, unknown id, or tables were not kept. */
+hines_status hines_get_table(const hines_plan* plan, int32_t which, int64_t* host_out,
+                             int64_t capacity, int64_t* count);
+
+/* Free the plan and its device tables (synchronises the device first).
+ * NULL is accepted. */
+hines_status hines_destroy(hines_plan* plan);
+
+/* Static description of a status code. */
+const char* hines_status_str(hines_status s);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* hines_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HINES_H */

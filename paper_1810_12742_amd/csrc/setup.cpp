@@ -1,0 +1,612 @@
+// Host-side setup of the fine-grained Hines solver (paper §4-§6).  O(N) in the
+// number of compartments except for the per-(group, level) lane sorts.
+//
+// Rules (the paper leaves tie-breaks open; these are the ones this library
+// fixes):
+//  * branches: a compartment continues the branch of its parent q iff q has
+//    exactly one child, the two are consecutive user indices, the step keeps
+//    the branch's direction, and no user branch starts there (§2, §5);
+//  * re-rooting: the tree centre, smaller user index on a tie (§6);
+//  * numbering: branches breadth first, children by ascending user index of
+//    their first compartment; compartments by distance to the root (§6);
+//  * splitting: per level over all cells, cut at floor(level average) (§6);
+//  * packing: greedy, every level's count <= group width (§4);
+//  * lanes: per (group, level) by descending length, ties (cell, rank) (§4).
+#include "setup.hpp"
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <new>
+#include <numeric>
+
+namespace hines {
+namespace {
+
+struct Builder {
+  const int32_t* parent;
+  int64_t n;
+  const int64_t* boff;
+  int64_t nb_user;
+  const int64_t* coff;
+  int64_t ncells;
+  Options opt;
+  HostPlan& P;
+  std::string& err;
+
+  // branch records (creation order; tails of splits are appended)
+  std::vector<int32_t> bfirst, bdir, blen, bparent, bcell, btail, bcl_lo, bcl_hi;
+  std::vector<int32_t> clist;      // children lists (ascending first compartment)
+  std::vector<int32_t> root_br;    // root branch of each cell
+  std::vector<int32_t> npar;       // parent in the (re-rooted) orientation
+
+  Builder(const int32_t* p, int64_t n_, const int64_t* bo, int64_t nb, const int64_t* co, int64_t nc,
+          const Options& o, HostPlan& out, std::string& e)
+      : parent(p), n(n_), boff(bo), nb_user(nb), coff(co), ncells(nc), opt(o), P(out), err(e) {}
+
+  Status fail(Status s, const std::string& m) {
+    err = m;
+    return s;
+  }
+
+  Status validate() {
+    if (n < 0 || ncells < 0) return fail(ERR_BAD_OFFSETS, "negative size");
+    if (n > INT32_MAX) return fail(ERR_BAD_OFFSETS, "more than 2^31-1 compartments");
+    if (ncells > INT32_MAX) return fail(ERR_BAD_OFFSETS, "too many cells");
+    if (n > 0 && !parent) return fail(ERR_NULL, "parent is NULL");
+    if (!coff) return fail(ERR_NULL, "cell_offsets is NULL");
+    if (opt.group_width < 64 || opt.group_width > 1024 || opt.group_width % 64)
+      return fail(ERR_OPTION, "group_width must be a multiple of 64 in [64, 1024]");
+    if (opt.cell_order != 0 && opt.cell_order != 1) return fail(ERR_OPTION, "cell_order must be 0 or 1");
+    if (opt.max_group_unknowns < 0) return fail(ERR_OPTION, "max_group_unknowns < 0");
+    if (coff[0] != 0 || coff[ncells] != n) return fail(ERR_BAD_OFFSETS, "cell_offsets must run from 0 to n");
+    for (int64_t c = 0; c < ncells; ++c)
+      if (coff[c + 1] <= coff[c]) return fail(ERR_BAD_OFFSETS, "cells must be non-empty and increasing");
+    for (int64_t c = 0; c < ncells; ++c) {
+      int64_t lo = coff[c], hi = coff[c + 1];
+      if (parent[lo] != -1) return fail(ERR_BAD_PARENT, "root " + std::to_string(lo) + " must have parent -1");
+      for (int64_t i = lo + 1; i < hi; ++i)
+        if (!(parent[i] >= lo && parent[i] < i))
+          return fail(ERR_BAD_PARENT, "parent[" + std::to_string(i) + "] out of [cell start, i)");
+    }
+    if (boff) {
+      if (nb_user < (n > 0 ? 1 : 0)) return fail(ERR_BAD_BRANCHES, "empty branch layout");
+      if (boff[0] != 0 || boff[nb_user] != n) return fail(ERR_BAD_BRANCHES, "branch_offsets must run from 0 to n");
+      for (int64_t k = 0; k < nb_user; ++k) {
+        if (boff[k + 1] <= boff[k]) return fail(ERR_BAD_BRANCHES, "branches must be non-empty and increasing");
+        for (int64_t i = boff[k] + 1; i < boff[k + 1]; ++i)
+          if (parent[i] != i - 1) return fail(ERR_BAD_BRANCHES, "parent[i] != i-1 inside a branch");
+      }
+      // every cell start must be a branch start (both arrays ascending)
+      int64_t k = 0;
+      for (int64_t c = 0; c < ncells; ++c) {
+        while (k < nb_user && boff[k] < coff[c]) ++k;
+        if (k >= nb_user || boff[k] != coff[c]) return fail(ERR_BAD_BRANCHES, "a branch crosses a cell start");
+      }
+    }
+    return OK;
+  }
+
+  // Re-root every cell at its centre; fills npar and a parent-first order.
+  void reroot(std::vector<int32_t>& order) {
+    order.resize(n);
+    int64_t maxm = 0;
+    for (int64_t c = 0; c < ncells; ++c) maxm = std::max(maxm, coff[c + 1] - coff[c]);
+    std::vector<int32_t> deg(maxm + 1), adj(2 * std::max<int64_t>(maxm - 1, 0)), dist(maxm), prev(maxm),
+        q(maxm);
+    for (int64_t c = 0; c < ncells; ++c) {
+      const int32_t lo = (int32_t)coff[c];
+      const int32_t m = (int32_t)(coff[c + 1] - coff[c]);
+      std::fill(deg.begin(), deg.begin() + m + 1, 0);
+      for (int32_t i = 1; i < m; ++i) {
+        ++deg[i + 1];
+        ++deg[parent[lo + i] - lo + 1];
+      }
+      for (int32_t i = 0; i < m; ++i) deg[i + 1] += deg[i];
+      std::vector<int32_t> fillpos(deg.begin(), deg.begin() + m);
+      for (int32_t i = 1; i < m; ++i) {
+        int32_t p = parent[lo + i] - lo;
+        adj[fillpos[i]++] = p;
+        adj[fillpos[p]++] = i;
+      }
+      auto bfs = [&](int32_t s) -> int32_t {  // returns farthest node (smallest index on ties)
+        std::fill(dist.begin(), dist.begin() + m, -1);
+        int32_t head = 0, tail = 0;
+        q[tail++] = s;
+        dist[s] = 0;
+        prev[s] = -1;
+        while (head < tail) {
+          int32_t v = q[head++];
+          for (int32_t e = deg[v]; e < deg[v + 1]; ++e) {
+            int32_t w = adj[e];
+            if (dist[w] < 0) {
+              dist[w] = dist[v] + 1;
+              prev[w] = v;
+              q[tail++] = w;
+            }
+          }
+        }
+        int32_t far = 0, best = s;
+        for (int32_t v = 0; v < m; ++v)
+          if (dist[v] > far || (dist[v] == far && v < best)) {
+            far = dist[v];
+            best = v;
+          }
+        return best;
+      };
+      int32_t a = bfs(0);
+      int32_t b = bfs(a);
+      int32_t D = dist[b];
+      // path b -> a through prev; position k from a is node at distance k
+      std::vector<int32_t> path;
+      path.reserve(D + 1);
+      for (int32_t v = b; v != -1; v = prev[v]) path.push_back(v);
+      std::reverse(path.begin(), path.end());
+      int32_t centre = std::min(path[D / 2], path[(D + 1) / 2]);
+      // orientation away from the centre, breadth first
+      std::fill(dist.begin(), dist.begin() + m, -1);
+      int32_t head = 0, tail = 0;
+      q[tail++] = centre;
+      dist[centre] = 0;
+      npar[lo + centre] = -1;
+      while (head < tail) {
+        int32_t v = q[head++];
+        order[lo + head - 1] = lo + v;
+        for (int32_t e = deg[v]; e < deg[v + 1]; ++e) {
+          int32_t w = adj[e];
+          if (dist[w] < 0) {
+            dist[w] = 0;
+            npar[lo + w] = lo + v;
+            q[tail++] = w;
+          }
+        }
+      }
+    }
+  }
+
+  int32_t new_branch(int32_t first, int32_t par, int32_t cell) {
+    int32_t id = (int32_t)bfirst.size();
+    bfirst.push_back(first);
+    bdir.push_back(1);
+    blen.push_back(1);
+    bparent.push_back(par);
+    bcell.push_back(cell);
+    return id;
+  }
+
+  Status run() {
+    Status s = validate();
+    if (s != OK) return s;
+    P.n = n;
+    P.ncells = ncells;
+    P.opt = opt;
+
+    // ---- orientation ----
+    npar.assign(parent, parent + n);
+    std::vector<int32_t> order;
+    if (opt.rebalance_root) reroot(order);
+    std::vector<uint8_t> nch(n, 0);
+    for (int64_t i = 0; i < n; ++i)
+      if (npar[i] >= 0 && nch[npar[i]] < 2) ++nch[npar[i]];
+    std::vector<uint8_t> ustart;
+    if (boff && !opt.rebalance_root) {
+      ustart.assign(n, 0);
+      for (int64_t k = 0; k < nb_user; ++k) ustart[boff[k]] = 1;
+    }
+
+    // ---- branches ----
+    std::vector<int32_t> br(n);
+    root_br.assign(ncells, -1);
+    for (int64_t c = 0; c < ncells; ++c) {
+      for (int64_t k = coff[c]; k < coff[c + 1]; ++k) {
+        int32_t i = opt.rebalance_root ? order[k] : (int32_t)k;
+        int32_t qn = npar[i];
+        if (qn < 0) {
+          br[i] = new_branch(i, -1, (int32_t)c);
+          root_br[c] = br[i];
+          continue;
+        }
+        int32_t bq = br[qn];
+        bool qfirst = bfirst[bq] == qn;
+        int32_t step = i - qn;
+        bool cont = nch[qn] == 1 && (step == 1 || step == -1) && (qfirst || step == bdir[bq]) &&
+                    !(!ustart.empty() && ustart[i]);
+        if (cont) {
+          if (qfirst) bdir[bq] = step;
+          ++blen[bq];
+          br[i] = bq;
+        } else {
+          br[i] = new_branch(i, bq, (int32_t)c);
+        }
+      }
+    }
+    std::vector<uint8_t>().swap(nch);
+    std::vector<uint8_t>().swap(ustart);
+    std::vector<int32_t>().swap(order);
+    const int64_t nb0 = (int64_t)bfirst.size();
+    // children lists, ascending first compartment
+    bcl_lo.assign(nb0, 0);
+    bcl_hi.assign(nb0, 0);
+    btail.assign(nb0, -1);
+    {
+      std::vector<int32_t> cnt(nb0 + 1, 0);
+      for (int64_t b = 0; b < nb0; ++b)
+        if (bparent[b] >= 0) ++cnt[bparent[b] + 1];
+      for (int64_t b = 0; b < nb0; ++b) cnt[b + 1] += cnt[b];
+      for (int64_t b = 0; b < nb0; ++b) {
+        bcl_lo[b] = cnt[b];
+        bcl_hi[b] = cnt[b];
+      }
+      clist.assign(cnt[nb0], 0);
+      for (int64_t i = 0; i < n; ++i) {
+        int32_t b = br[i];
+        if (bfirst[b] == i && bparent[b] >= 0) clist[bcl_hi[bparent[b]]++] = b;
+      }
+    }
+    std::vector<int32_t>().swap(br);
+
+    // ---- split (level by level over all cells) ----
+    if (opt.split_branches) {
+      std::vector<int32_t> cur(root_br.begin(), root_br.end()), nxt;
+      while (!cur.empty()) {
+        int64_t S = 0;
+        for (int32_t b : cur) S += blen[b];
+        const int64_t m = (int64_t)cur.size();
+        nxt.clear();
+        for (int32_t b : cur) {
+          if ((int64_t)blen[b] * m > S) {
+            int32_t k = (int32_t)(S / m);
+            int32_t t = (int32_t)bfirst.size();
+            bfirst.push_back(bfirst[b] + bdir[b] * k);
+            bdir.push_back(bdir[b]);
+            blen.push_back(blen[b] - k);
+            bparent.push_back(b);
+            bcell.push_back(bcell[b]);
+            btail.push_back(-1);
+            bcl_lo.push_back(bcl_lo[b]);
+            bcl_hi.push_back(bcl_hi[b]);
+            for (int32_t e = bcl_lo[b]; e < bcl_hi[b]; ++e) bparent[clist[e]] = t;
+            bcl_lo[b] = bcl_hi[b] = 0;
+            btail[b] = t;
+            blen[b] = k;
+          }
+          if (btail[b] >= 0)
+            nxt.push_back(btail[b]);
+          else
+            for (int32_t e = bcl_lo[b]; e < bcl_hi[b]; ++e) nxt.push_back(clist[e]);
+        }
+        cur.swap(nxt);
+      }
+    }
+    const int64_t nb = (int64_t)bfirst.size();
+    P.nbranches = nb;
+
+    // ---- breadth-first numbering, levels ----
+    std::vector<int32_t> gorder;  // gid -> creation id
+    gorder.reserve(nb);
+    std::vector<int32_t> glevel(nb), grank(nb), gfchild(nb, -1), gnchild(nb, 0), gid_of(nb);
+    std::vector<int64_t> cell_br_lo(ncells + 1, 0);
+    for (int64_t c = 0; c < ncells; ++c) {
+      int64_t head = (int64_t)gorder.size();
+      cell_br_lo[c] = head;
+      gorder.push_back(root_br[c]);
+      glevel[head] = 0;
+      for (int64_t k = head; k < (int64_t)gorder.size(); ++k) {
+        int32_t b = gorder[k];
+        grank[k] = (int32_t)(k - head);
+        int32_t first = (int32_t)gorder.size();
+        int32_t cntc = 0;
+        if (btail[b] >= 0) {
+          glevel[gorder.size()] = glevel[k] + 1;
+          gorder.push_back(btail[b]);
+          cntc = 1;
+        } else {
+          for (int32_t e = bcl_lo[b]; e < bcl_hi[b]; ++e) {
+            glevel[gorder.size()] = glevel[k] + 1;
+            gorder.push_back(clist[e]);
+            ++cntc;
+          }
+        }
+        if (cntc) {
+          gfchild[k] = first;
+          gnchild[k] = cntc;
+        }
+      }
+    }
+    cell_br_lo[ncells] = (int64_t)gorder.size();
+    for (int64_t k = 0; k < nb; ++k) gid_of[gorder[k]] = (int32_t)k;
+    std::vector<int32_t>().swap(clist);
+    std::vector<int32_t>().swap(bcl_lo);
+    std::vector<int32_t>().swap(bcl_hi);
+    std::vector<int32_t>().swap(btail);
+
+    // per gid branch fields
+    std::vector<int32_t> gfirst(nb), gdir(nb), glen(nb), gparent(nb), gcell(nb);
+    for (int64_t k = 0; k < nb; ++k) {
+      int32_t b = gorder[k];
+      gfirst[k] = bfirst[b];
+      gdir[k] = bdir[b];
+      glen[k] = blen[b];
+      gparent[k] = bparent[b] >= 0 ? gid_of[bparent[b]] : -1;
+      gcell[k] = bcell[b];
+    }
+    for (auto* v : {&bfirst, &bdir, &blen, &bparent, &bcell, &gorder, &gid_of, &root_br})
+      std::vector<int32_t>().swap(*v);
+    int32_t maxlev = -1;
+    for (int64_t k = 0; k < nb; ++k) maxlev = std::max(maxlev, glevel[k]);
+    P.max_level = maxlev;
+
+    // ---- node numbering and coupling sources ----
+    std::vector<int32_t> node_plan(n), u_src(n);
+    {
+      int64_t off = 0;
+      int32_t curcell = -1;
+      for (int64_t k = 0; k < nb; ++k) {
+        if (gcell[k] != curcell) {
+          curcell = gcell[k];
+          off = coff[curcell];
+        }
+        for (int32_t j = 0; j < glen[k]; ++j) node_plan[gfirst[k] + gdir[k] * j] = (int32_t)(off + j);
+        for (int32_t j = 0; j < glen[k]; ++j) {
+          int32_t i = gfirst[k] + gdir[k] * j;
+          int32_t qn;
+          if (j > 0)
+            qn = i - gdir[k];
+          else if (gparent[k] >= 0) {
+            int32_t pb = gparent[k];
+            qn = gfirst[pb] + gdir[pb] * (glen[pb] - 1);
+          } else {
+            u_src[off + j] = -1;
+            continue;
+          }
+          u_src[off + j] = (parent[i] == qn) ? i : qn;  // flipped edge: stored at the old child
+        }
+        off += glen[k];
+      }
+    }
+
+    // ---- packing (§4) ----
+    std::vector<int64_t> cnt_off(ncells + 1, 0);
+    for (int64_t c = 0; c < ncells; ++c) {
+      int64_t hi = cell_br_lo[c + 1];
+      int32_t nl = glevel[hi - 1] + 1;  // breadth first: last branch is deepest
+      cnt_off[c + 1] = cnt_off[c] + nl;
+    }
+    std::vector<int32_t> lvl_lo(cnt_off[ncells] + ncells, 0);  // per cell: nl+1 prefix
+    // lvl_lo[cnt_off[c] + c + l] = first gid of level l in cell c
+    for (int64_t c = 0; c < ncells; ++c) {
+      int64_t base = cnt_off[c] + c;
+      int32_t nl = (int32_t)(cnt_off[c + 1] - cnt_off[c]);
+      int64_t k = cell_br_lo[c];
+      for (int32_t l = 0; l <= nl; ++l) {
+        while (k < cell_br_lo[c + 1] && glevel[k] < l) ++k;
+        lvl_lo[base + l] = (int32_t)(k - cell_br_lo[c]);
+      }
+    }
+    auto cell_level_count = [&](int64_t c, int32_t l) -> int32_t {
+      int64_t base = cnt_off[c] + c;
+      int32_t nl = (int32_t)(cnt_off[c + 1] - cnt_off[c]);
+      if (l >= nl) return 0;
+      return lvl_lo[base + l + 1] - lvl_lo[base + l];
+    };
+    std::vector<int64_t> cells(ncells);
+    std::iota(cells.begin(), cells.end(), 0);
+    if (opt.cell_order == 1)
+      std::stable_sort(cells.begin(), cells.end(),
+                       [&](int64_t a, int64_t b) { return coff[a + 1] - coff[a] > coff[b + 1] - coff[b]; });
+    const int32_t T = opt.group_width;
+    const int64_t cap = opt.max_group_unknowns;
+    std::vector<int32_t> gcnt(maxlev + 2, 0);
+    P.group_offsets.assign(1, 0);
+    P.group_cells.clear();
+    P.group_cells.reserve(ncells);
+    {
+      int32_t gnl = 0;
+      int64_t gU = 0;
+      for (int64_t c : cells) {
+        int32_t nl = (int32_t)(cnt_off[c + 1] - cnt_off[c]);
+        int64_t sz = coff[c + 1] - coff[c];
+        bool open = (int64_t)P.group_cells.size() > P.group_offsets.back();
+        bool fits = true;
+        if (open) {
+          for (int32_t l = 0; l < nl && fits; ++l)
+            if (gcnt[l] + cell_level_count(c, l) > T) fits = false;
+          if (cap && gU + sz > cap) fits = false;
+        }
+        if (open && !fits) {
+          P.group_offsets.push_back((int64_t)P.group_cells.size());
+          std::fill(gcnt.begin(), gcnt.begin() + gnl, 0);
+          gnl = 0;
+          gU = 0;
+        }
+        P.group_cells.push_back(c);
+        for (int32_t l = 0; l < nl; ++l) gcnt[l] += cell_level_count(c, l);
+        gnl = std::max(gnl, nl);
+        gU += sz;
+      }
+      if ((int64_t)P.group_cells.size() > P.group_offsets.back())
+        P.group_offsets.push_back((int64_t)P.group_cells.size());
+    }
+    const int64_t ng = (int64_t)P.group_offsets.size() - 1;
+    P.ngroups = ng;
+    std::vector<int32_t> group_of_cell(ncells, 0);
+    for (int64_t g = 0; g < ng; ++g)
+      for (int64_t e = P.group_offsets[g]; e < P.group_offsets[g + 1]; ++e) group_of_cell[P.group_cells[e]] = (int32_t)g;
+
+    // ---- lanes (§4, Fig 4.1) and kernel tables ----
+    P.kgroup.assign(ng, KGroup{});
+    P.kcell.assign(ncells, KCell{});
+    P.kbranch.assign(nb, KBranch{});
+    P.lanes.assign(nb, 0);
+    P.kseg.clear();
+    P.group_seg_offsets.assign(ng + 1, 0);
+    std::vector<int32_t> cell_lds(ncells, 0), cell_gbr(ncells, 0);  // per cell: LDS offset, first group-local id
+    int64_t lane = 0;
+    std::vector<int32_t> seg;
+    for (int64_t g = 0; g < ng; ++g) {
+      KGroup& G = P.kgroup[g];
+      G.seg_begin = (int32_t)P.kseg.size();
+      G.cell_begin = (int32_t)P.group_offsets[g];
+      G.ncell = (int32_t)(P.group_offsets[g + 1] - P.group_offsets[g]);
+      int64_t U = 0, nbr = 0;
+      int32_t gnl = 0;
+      // Contiguous groups (consecutive cells) keep the user layout in LDS:
+      // slot k holds user index user_base + k with user_base even, so one
+      // aligned range copy stages the whole group.  Others: each cell starts
+      // at an even slot.
+      bool contig = true;
+      for (int64_t e = P.group_offsets[g] + 1; e < P.group_offsets[g + 1]; ++e)
+        if (P.group_cells[e] != P.group_cells[e - 1] + 1) contig = false;
+      const int64_t c_first = P.group_cells[P.group_offsets[g]];
+      const int64_t ubase = coff[c_first] & ~(int64_t)1;
+      G.contig = contig ? 1 : 0;
+      G.user_base = contig ? ubase : 0;
+      G.user_lo = contig ? (int32_t)(coff[c_first] - ubase) : 0;
+      G.user_n = 0;
+      G.pad = 0;
+      if (contig) U = coff[c_first] - ubase;
+      for (int64_t e = P.group_offsets[g]; e < P.group_offsets[g + 1]; ++e) {
+        int64_t c = P.group_cells[e];
+        if (!contig) U = (U + 1) & ~(int64_t)1;  // each cell starts 16-byte aligned in the LDS image
+        G.user_n += (int32_t)(coff[c + 1] - coff[c]);
+        cell_lds[c] = (int32_t)U;
+        cell_gbr[c] = (int32_t)nbr;
+        P.kcell[e] = KCell{coff[c], (int32_t)(coff[c + 1] - coff[c]), (int32_t)U};
+        U += coff[c + 1] - coff[c];
+        nbr += cell_br_lo[c + 1] - cell_br_lo[c];
+        gnl = std::max(gnl, (int32_t)(cnt_off[c + 1] - cnt_off[c]));
+      }
+      U = (U + 1) & ~(int64_t)1;
+      G.nunk = (int32_t)std::min<int64_t>(U, INT32_MAX);
+      G.nbr = (int32_t)nbr;
+      G.nlev = gnl;
+      G.br_begin = (int32_t)lane;
+      int64_t cost = 0;
+      for (int32_t l = 0; l < gnl; ++l) {
+        seg.clear();
+        for (int64_t e = P.group_offsets[g]; e < P.group_offsets[g + 1]; ++e) {
+          int64_t c = P.group_cells[e];
+          int32_t nl = (int32_t)(cnt_off[c + 1] - cnt_off[c]);
+          if (l >= nl) continue;
+          int64_t base = cnt_off[c] + c;
+          for (int32_t r = lvl_lo[base + l]; r < lvl_lo[base + l + 1]; ++r) seg.push_back((int32_t)(cell_br_lo[c] + r));
+        }
+        std::sort(seg.begin(), seg.end(), [&](int32_t a, int32_t b) {
+          if (glen[a] != glen[b]) return glen[a] > glen[b];
+          if (gcell[a] != gcell[b]) return gcell[a] < gcell[b];
+          return grank[a] < grank[b];
+        });
+        P.kseg.push_back((int32_t)lane);
+        for (size_t t = 0; t < seg.size(); t += (size_t)T) cost += glen[seg[t]];
+        for (int32_t k : seg) {
+          P.lanes[lane] = k;
+          const int32_t c = gcell[k];
+          auto local = [&](int32_t user) { return cell_lds[c] + (int32_t)(user - coff[c]); };
+          int32_t f_start = local(gfirst[k]);
+          int32_t f_lendir = gdir[k] > 0 ? glen[k] : -glen[k];
+          int32_t f_u0 = -1, f_pslot = -1;
+          if (gparent[k] >= 0) {
+            int32_t pb = gparent[k];
+            int32_t plast = gfirst[pb] + gdir[pb] * (glen[pb] - 1);
+            f_pslot = local(plast);
+            f_u0 = local(u_src[node_plan[gfirst[k]]]);
+          }
+          int32_t f_self = cell_gbr[c] + grank[k];
+          int32_t f_child0 = gnchild[k] ? cell_gbr[c] + grank[gfchild[k]] : 0;
+          KBranch& B = P.kbranch[lane];
+          if (U > kMaxGroupSlots || nbr > kMaxGroupSlots) {
+            P.kernel_tables_fit = false;
+            B = KBranch{};
+          } else {
+            B.start = (int16_t)f_start;
+            B.lendir = (int16_t)f_lendir;
+            B.u0 = (int16_t)f_u0;
+            B.pslot = (int16_t)f_pslot;
+            B.self = (int16_t)f_self;
+            B.child0 = (int16_t)f_child0;
+            B.nchild = (int16_t)gnchild[k];
+            B.pad = 0;
+          }
+          ++lane;
+        }
+      }
+      G.cost = (int32_t)std::min<int64_t>(cost, INT32_MAX);
+      P.group_seg_offsets[g + 1] = (int64_t)P.kseg.size();
+    }
+    P.kseg.push_back((int32_t)lane);
+    P.nseg = (int64_t)P.kseg.size() - 1;
+    P.seg_offsets.assign(P.kseg.begin(), P.kseg.end());
+
+    // ---- exported tables ----
+    if (opt.keep_tables) {
+      P.node_plan.swap(node_plan);
+      P.u_src.swap(u_src);
+      P.br_cell.swap(gcell);
+      P.br_level.swap(glevel);
+      P.br_first.swap(gfirst);
+      P.br_dir.swap(gdir);
+      P.br_len.swap(glen);
+      P.br_parent.swap(gparent);
+      P.br_rank.swap(grank);
+      P.br_group.resize(nb);
+      for (int64_t k = 0; k < nb; ++k) P.br_group[k] = group_of_cell[P.br_cell[k]];
+    }
+    return OK;
+  }
+};
+
+}  // namespace
+
+Status build_plan(const int32_t* parent, int64_t n, const int64_t* branch_offsets, int64_t nbranches,
+                  const int64_t* cell_offsets, int64_t ncells, const Options& opt, HostPlan& out,
+                  std::string& err) {
+  try {
+    Builder b(parent, n, branch_offsets, nbranches, cell_offsets, ncells, opt, out, err);
+    return b.run();
+  } catch (const std::bad_alloc&) {
+    err = "host allocation failed during setup";
+    return ERR_OOM;
+  }
+}
+
+int64_t export_table(const HostPlan& p, int32_t id, int64_t* out, int64_t capacity) {
+  auto put = [&](const auto& v) -> int64_t {
+    int64_t cnt = (int64_t)v.size();
+    if (out) {
+      if (capacity < cnt) return -1;
+      for (int64_t k = 0; k < cnt; ++k) out[k] = (int64_t)v[k];
+    }
+    return cnt;
+  };
+  if (!p.opt.keep_tables && (id == T_NODE_PLAN || id == T_BRANCHES || id == T_U_SRC)) return -1;
+  switch (id) {
+    case T_NODE_PLAN: return put(p.node_plan);
+    case T_U_SRC: return put(p.u_src);
+    case T_BRANCHES: {
+      int64_t nb = p.nbranches, cnt = nb * 8;
+      if (out) {
+        if (capacity < cnt) return -1;
+        for (int64_t k = 0; k < nb; ++k) {
+          int64_t* r = out + 8 * k;
+          r[0] = p.br_cell[k];
+          r[1] = p.br_level[k];
+          r[2] = p.br_first[k];
+          r[3] = p.br_dir[k];
+          r[4] = p.br_len[k];
+          r[5] = p.br_parent[k];
+          r[6] = p.br_group[k];
+          r[7] = p.br_rank[k];
+        }
+      }
+      return cnt;
+    }
+    case T_GROUP_OFFSETS: return put(p.group_offsets);
+    case T_GROUP_CELLS: return put(p.group_cells);
+    case T_GROUP_SEG_OFFSETS: return put(p.group_seg_offsets);
+    case T_SEG_OFFSETS: return put(p.seg_offsets);
+    case T_LANES: return put(p.lanes);
+    default: return -1;
+  }
+}
+
+}  // namespace hines

@@ -1,0 +1,122 @@
+// Host-side setup of the fine-grained Hines solver: compartment numbering,
+// level schedule, branch-to-lane assignment and the device tables of the
+// solve kernels (paper §4 "distribution ... computed once during the setup
+// phase", §5 memory layout, §6 work balancing).  Pure C++17; no HIP.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace hines {
+
+enum Status : int32_t {
+  OK = 0,
+  ERR_NULL = 1,
+  ERR_BAD_OFFSETS = 2,
+  ERR_BAD_PARENT = 3,
+  ERR_BAD_BRANCHES = 4,
+  ERR_TOO_WIDE = 5,
+  ERR_NCELLS = 6,
+  ERR_OPTION = 7,
+  ERR_OOM = 8,
+  ERR_HIP = 9,
+  ERR_TOO_BIG = 10,
+  ERR_NOT_SDD = 11,
+  ERR_STATE = 12,
+};
+
+struct Options {
+  int32_t rebalance_root = 0;      // §6: re-root each cell at its tree centre
+  int32_t split_branches = 0;      // §6: per-level split of longer-than-average branches
+  int32_t group_width = 64;        // §4: lanes per group (multiple of 64, <= 1024)
+  int32_t cell_order = 0;          // §4 packing order: 0 input, 1 size descending
+  int32_t max_group_unknowns = 0;  // packing cap on compartments per group (0: none)
+  int32_t host_only = 0;           // build tables only, no device upload
+  int32_t keep_tables = 1;         // keep the exported tables after setup
+  int32_t bitwise = 0;             // IEEE divisions, unfused updates: equal to the plain algorithm bit for bit
+};
+
+// Table ids for export (shared with the C-ABI).
+enum TableId : int32_t {
+  T_NODE_PLAN = 0,        // int64[n]
+  T_BRANCHES = 1,         // int64[nb*8]: cell, level, first, dir, len, parent, group, rank
+  T_U_SRC = 2,            // int64[n] in plan order
+  T_GROUP_OFFSETS = 3,    // int64[ngroups+1]
+  T_GROUP_CELLS = 4,      // int64[ncells]
+  T_GROUP_SEG_OFFSETS = 5,  // int64[ngroups+1]
+  T_SEG_OFFSETS = 6,      // int64[nseg+1]
+  T_LANES = 7,            // int64[nb]
+  T_NUM = 8,
+};
+
+// Per-branch record of the LDS-staged solve kernel, in (group, level, lane)
+// order; 16 bytes so that one DMA lane moves one record.  All indices are
+// group-local: positions in the group's LDS image (its cells concatenated in
+// packing order) or group-local breadth-first branch ids.  A group's LDS image
+// holds at most a few thousand compartments, far inside int16.
+struct KBranch {
+  int16_t start;   // LDS index of the branch's root-side compartment
+  int16_t lendir;  // len, negated when the branch runs toward lower user indices
+  int16_t u0;      // LDS index of the coupling of position 0 to its parent (-1: root)
+  int16_t pslot;   // LDS index of the parent compartment (-1: root)
+  int16_t self;    // group-local breadth-first id (slot of its elimination contribution)
+  int16_t child0;  // group-local id of the first child branch
+  int16_t nchild;  // number of child branches (ids child0 .. child0+nchild-1)
+  int16_t pad;
+};
+static_assert(sizeof(KBranch) == 16, "one DMA lane per record");
+
+constexpr int32_t kMaxGroupSlots = 32766;  // largest LDS image the int16 records address
+
+struct KGroup {
+  int64_t user_base;   // contiguous groups: user index of LDS slot 0 (even)
+  int32_t seg_begin;   // first entry of this group in the segment table
+  int32_t nlev;        // levels (segments)
+  int32_t cell_begin;  // first entry in the group-cell table
+  int32_t ncell;
+  int32_t nunk;        // LDS slots per array: compartments + alignment padding (even)
+  int32_t nbr;         // branches in the group
+  int32_t cost;        // sum over levels of the longest branch (critical path)
+  int32_t br_begin;    // first record of the group in the branch table
+  int32_t contig;      // 1: cells are one user range [user_lo, user_hi); LDS slot k <-> user_base + k
+  int32_t user_lo;     // contiguous groups: first user index relative to user_base (0 or 1)
+  int32_t user_n;      // contiguous groups: compartments in the range
+  int32_t pad;
+};
+static_assert(sizeof(KGroup) == 56, "layout");
+
+struct KCell {
+  int64_t user_lo;  // first user index of the cell
+  int32_t n;        // compartments
+  int32_t lds;      // offset of the cell in the group's LDS image
+};
+
+struct HostPlan {
+  int64_t n = 0, ncells = 0, nbranches = 0, ngroups = 0, nseg = 0;
+  int32_t max_level = -1;
+  Options opt;
+
+  // exported tables (compact)
+  std::vector<int32_t> node_plan;                       // [n]
+  std::vector<int32_t> br_cell, br_level, br_first, br_dir, br_len, br_parent, br_group, br_rank;
+  std::vector<int32_t> u_src;                           // [n], plan order
+  std::vector<int64_t> group_offsets, group_cells, group_seg_offsets, seg_offsets;
+  std::vector<int32_t> lanes;                           // [nb]
+
+  // kernel tables
+  std::vector<KBranch> kbranch;   // [nb] lane order
+  std::vector<KGroup> kgroup;     // [ngroups]
+  std::vector<int32_t> kseg;      // [nseg+1] begin of each segment in kbranch
+  std::vector<KCell> kcell;       // [ncells] group order
+  bool kernel_tables_fit = true;  // every group addressable by the int16 records
+};
+
+Status build_plan(const int32_t* parent, int64_t n, const int64_t* branch_offsets, int64_t nbranches,
+                  const int64_t* cell_offsets, int64_t ncells, const Options& opt, HostPlan& out,
+                  std::string& err);
+
+// Copy table `id` into out (int64), returns the element count (or -1).
+int64_t export_table(const HostPlan& p, int32_t id, int64_t* out, int64_t capacity);
+
+}  // namespace hines

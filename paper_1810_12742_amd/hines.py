@@ -1,0 +1,170 @@
+"""ctypes binding of libhines.so (include/hines.h): argument marshalling only.
+
+Device arrays are torch tensors (float64, contiguous, on the plan's device);
+torch provides the memory and the current stream, the library does the work.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "libhines.so")
+_lib = None
+
+TABLES = {
+    "node_plan": 0, "branches": 1, "u_src": 2, "group_offsets": 3, "group_cells": 4,
+    "group_seg_offsets": 5, "seg_offsets": 6, "lanes": 7,
+}
+STATUS = {0: "OK", 1: "NULL", 2: "BAD_OFFSETS", 3: "BAD_PARENT", 4: "BAD_BRANCHES", 5: "TOO_WIDE",
+          6: "NCELLS", 7: "OPTION", 8: "OOM", 9: "HIP", 10: "TOO_BIG", 11: "NOT_SDD", 12: "STATE"}
+
+
+class HinesError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.code = STATUS.get(status, str(status))
+        super().__init__(f"hines error {self.code} ({status}): {message}")
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("rebalance_root", ctypes.c_int32), ("split_branches", ctypes.c_int32),
+                ("group_width", ctypes.c_int32), ("cell_order", ctypes.c_int32),
+                ("max_group_unknowns", ctypes.c_int32), ("host_only", ctypes.c_int32),
+                ("keep_tables", ctypes.c_int32), ("bitwise", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("ncells", ctypes.c_int64), ("nbranches", ctypes.c_int64),
+                ("ngroups", ctypes.c_int64), ("nsegments", ctypes.c_int64), ("max_level", ctypes.c_int32),
+                ("nclasses", ctypes.c_int32), ("device_table_bytes", ctypes.c_int64),
+                ("max_group_lds_bytes", ctypes.c_int64)]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load libhines.so (after torch, so that it binds to torch's HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is not built; run `python -m paper_1810_12742_amd.build`")
+    import torch  # noqa: F401  (HIP runtime of the process)
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.hines_default_options.argtypes = [ctypes.POINTER(_Options)]
+    lib.hines_default_options.restype = None
+    lib.hines_setup.argtypes = [P, I64, P, I64, P, I32, ctypes.POINTER(_Options), ctypes.POINTER(P)]
+    lib.hines_solve.argtypes = [P, P, P, P, P, I32, P]
+    lib.hines_plan_info_get.argtypes = [P, ctypes.POINTER(_Info)]
+    lib.hines_get_table.argtypes = [P, I32, P, I64, ctypes.POINTER(I64)]
+    lib.hines_destroy.argtypes = [P]
+    lib.hines_status_str.argtypes = [I32]
+    lib.hines_status_str.restype = ctypes.c_char_p
+    lib.hines_last_error.argtypes = []
+    lib.hines_last_error.restype = ctypes.c_char_p
+    for name in ("hines_setup", "hines_solve", "hines_plan_info_get", "hines_get_table", "hines_destroy"):
+        getattr(lib, name).restype = I32
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise HinesError(status, load().hines_last_error().decode())
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(np.asarray(a), dtype=dtype)
+
+
+def _dev(t, n, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name}: need contiguous {dtype} with {n} elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A setup plan (``hines_setup``) and the solves that use it."""
+
+    def __init__(self, parent, cell_offsets, branch_offsets=None, *, rebalance_root=False,
+                 split_branches=False, group_width=64, cell_order=0, max_group_unknowns=None,
+                 host_only=False, keep_tables=True, bitwise=False):
+        lib = load()
+        opt = _Options()
+        lib.hines_default_options(ctypes.byref(opt))
+        opt.rebalance_root = int(bool(rebalance_root))
+        opt.split_branches = int(bool(split_branches))
+        opt.group_width = int(group_width)
+        opt.cell_order = int(cell_order)
+        if max_group_unknowns is not None:
+            opt.max_group_unknowns = int(max_group_unknowns)
+        opt.host_only = int(bool(host_only))
+        opt.keep_tables = int(bool(keep_tables))
+        opt.bitwise = int(bool(bitwise))
+        self._par = _host(parent, np.int32)
+        self._coff = _host(cell_offsets, np.int64)
+        bo = None if branch_offsets is None else _host(branch_offsets, np.int64)
+        self.n = int(self._par.shape[0])
+        self.ncells = int(self._coff.shape[0] - 1)
+        handle = ctypes.c_void_p()
+        st = lib.hines_setup(
+            ctypes.c_void_p(self._par.ctypes.data), self.n,
+            None if bo is None else ctypes.c_void_p(bo.ctypes.data), 0 if bo is None else bo.shape[0] - 1,
+            ctypes.c_void_p(self._coff.ctypes.data), self.ncells, ctypes.byref(opt), ctypes.byref(handle))
+        _check(st)
+        self._h = handle
+        self.options = {f: getattr(opt, f) for f, _ in _Options._fields_ if f != "reserved"}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _check(load().hines_destroy(h))
+        self._h = None
+
+    @property
+    def info(self) -> dict:
+        inf = _Info()
+        _check(load().hines_plan_info_get(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in _Info._fields_}
+
+    def table(self, name: str) -> np.ndarray:
+        lib = load()
+        which = TABLES[name]
+        cnt = ctypes.c_int64()
+        _check(lib.hines_get_table(self._h, which, None, 0, ctypes.byref(cnt)))
+        out = np.empty(cnt.value, dtype=np.int64)
+        _check(lib.hines_get_table(self._h, which, ctypes.c_void_p(out.ctypes.data), out.shape[0],
+                                   ctypes.byref(cnt)))
+        return out.reshape(-1, 8) if name == "branches" else out
+
+    def tables(self) -> dict:
+        return {k: self.table(k) for k in TABLES}
+
+    def solve(self, diag, upper, rhs, out=None, stream=None):
+        """x = A^-1 rhs on the device (``hines_solve``); returns ``out``."""
+        import torch
+        if out is None:
+            out = torch.empty_like(rhs)
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(load().hines_solve(self._h, _dev(diag, self.n, torch.float64, "diag"),
+                                  _dev(upper, self.n, torch.float64, "upper"),
+                                  _dev(rhs, self.n, torch.float64, "rhs"),
+                                  _dev(out, self.n, torch.float64, "out"), self.ncells,
+                                  ctypes.c_void_p(st.cuda_stream)))
+        return out
