@@ -29,7 +29,7 @@ METRIC = "Hines unknowns solved/s and % HBM roofline, plain FP64 vs batched/FP32
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UNKNOWN = 32  # read diag, upper, rhs; write x (FP64)
 # Launch configuration of the timed solve (setup options of the plan).
-C2_OPTIONS = dict(max_group_unknowns=2048, split_branches=1, cell_order=0, group_width=64)
+C2_OPTIONS = dict(max_group_unknowns=1536, split_branches=0, cell_order=0, group_width=64)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hines_solve_c2.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1810_12742_amd", "csrc", "hines.hip")
 
@@ -154,7 +154,7 @@ def main(argv=None):
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "k_solve_lds_f64<64,false>",
+            "kernel": "k_solve_sched_f64" if info["kernel"] == 1 else "k_solve_lds_f64",
             "bytes_per_launch": bytes_per_solve / launches,
             "avg_launch_us": ms * 1e3 / launches,
         },

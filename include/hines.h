@@ -68,7 +68,11 @@ typedef struct hines_options {
   int32_t bitwise;            /* 1: IEEE divisions and unfused updates, so the solution equals
                                  the plain algorithm (§2 Listing 2) on the plan numbering bit
                                  for bit; 0 (default): reciprocal + fused multiply-add form   */
-  int32_t reserved[8];        /* must be 0 */
+  int32_t level_sync;         /* 1: level-synchronous sweeps with a barrier per level (§3);
+                                 0 (default): when every branch runs toward higher user indices
+                                 and bitwise is 0, a static per-lane schedule computed at setup
+                                 (each branch starts once its children are done; no barriers) */
+  int32_t reserved[7];        /* must be 0 */
 } hines_options;
 
 /* Plan summary. */
@@ -78,6 +82,8 @@ typedef struct hines_plan_info {
   int32_t nclasses;           /* LDS size classes (kernel launches per solve) */
   int64_t device_table_bytes; /* device memory held by the plan */
   int64_t max_group_lds_bytes;
+  int32_t kernel;             /* 0 level-synchronous, 1 scheduled, 2 level-synchronous bitwise */
+  int32_t max_makespan;       /* scheduled plans: longest schedule, in iterations */
 } hines_plan_info;
 
 /* Table ids for hines_get_table (all exported as int64). */

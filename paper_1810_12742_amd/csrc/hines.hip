@@ -66,7 +66,8 @@ struct LdsLayout {
   __host__ __device__ int64_t br_off_bytes() const { return 8 * (3 * (int64_t)nunk + 2 * (int64_t)nbr_pad); }
   __host__ __device__ int64_t seg_off_bytes() const { return br_off_bytes() + 16 * (int64_t)nbr_pad; }
   __host__ __device__ int64_t bytes() const {
-    return (seg_off_bytes() + 4 * ((int64_t)nlev + 1) + 15) & ~(int64_t)15;
+    const int64_t ints = (int64_t)nlev + 1 > hines::kSchedLanes + 1 ? (int64_t)nlev + 1 : hines::kSchedLanes + 1;
+    return (seg_off_bytes() + 4 * ints + 15) & ~(int64_t)15;
   }
 };
 __host__ __device__ inline LdsLayout lds_layout(const KGroup& g) { return LdsLayout{g.nunk, (g.nbr + 1) & ~1, g.nlev}; }
@@ -82,6 +83,7 @@ struct DevTables {
   const int32_t* seg;   // first lane of each (group, level) segment; nseg+1 entries
   const KCell* cell;    // group order
   const int32_t* glist; // group ids of one launch
+  const int32_t* lanes; // scheduled plans: per group kSchedLanes + 1 record offsets
 };
 
 }  // namespace
@@ -148,16 +150,19 @@ __device__ __forceinline__ void stage_range(const double* d, const double* u, co
 template <int T>
 __device__ __forceinline__ void stage_group(const DevTables& tb, const KGroup& G, const LdsLayout& L,
                                             const double* d, const double* u, const double* rhs, char* lds,
-                                            int tid) {
+                                            int tid, const int32_t* lane_table = nullptr) {
   double* D = (double*)lds;
   double* U = D + L.u_off();
   double* B = D + L.b_off();
   dma16<T>(tb.br + G.br_begin, lds + L.br_off_bytes(), G.nbr, tid);
-  dma4<T>(tb.seg + G.seg_begin, lds + L.seg_off_bytes(), G.nlev + 1, tid);
+  if (lane_table)
+    dma4<T>(lane_table, lds + L.seg_off_bytes(), hines::kSchedLanes + 1, tid);
+  else
+    dma4<T>(tb.seg + G.seg_begin, lds + L.seg_off_bytes(), G.nlev + 1, tid);
   if (G.contig) {
-    // slots [0, user_lo + user_n) <-> user [user_base, ...); slot 0 is even-aligned
+    // slots kLdsPad + [0, user_lo + user_n) <-> user [user_base, ...); both ends 16-byte aligned
     const int span = G.user_lo + G.user_n;
-    stage_range<T>(d, u, rhs, G.user_base, span & ~1, 0, D, U, B, tid);
+    stage_range<T>(d, u, rhs, G.user_base, span & ~1, hines::kLdsPad, D, U, B, tid);
     double t0 = 0.0, t1 = 0.0, t2 = 0.0;
     const bool tail = (span & 1) && tid == 0;
     if (tail) {
@@ -168,9 +173,9 @@ __device__ __forceinline__ void stage_group(const DevTables& tb, const KGroup& G
     }
     __builtin_amdgcn_s_waitcnt(0);
     if (tail) {
-      D[span - 1] = t0;
-      U[span - 1] = t1;
-      B[span - 1] = t2;
+      D[hines::kLdsPad + span - 1] = t0;
+      U[hines::kLdsPad + span - 1] = t1;
+      B[hines::kLdsPad + span - 1] = t2;
     }
   } else {
     for (int c = 0; c < G.ncell; ++c) {
@@ -207,12 +212,13 @@ template <int T>
 __device__ __forceinline__ void store_group(const DevTables& tb, const KGroup& G, const double* B, double* x,
                                             int tid) {
   if (G.contig) {
-    // the user range starts at slot user_lo (0 or 1); store slot-aligned pairs
-    // from the first even slot, then the edges
+    // the user range starts at slot kLdsPad + user_lo (user_lo 0 or 1); store
+    // slot-aligned pairs from the first even slot, then the edges
     const int lo = G.user_lo, hi = G.user_lo + G.user_n;
-    const int a = (lo + 1) & ~1;  // first even slot at or after lo
-    if (lo < a && tid == 0) x[G.user_base + lo] = B[lo];
-    if (hi > a) store_range<T>(B, a, x, G.user_base + a, hi - a, tid);
+    const int a = (lo + 1) & ~1;  // first even offset at or after lo
+    const double* Bp = B + hines::kLdsPad;
+    if (lo < a && tid == 0) x[G.user_base + lo] = Bp[lo];
+    if (hi > a) store_range<T>(Bp, a, x, G.user_base + a, hi - a, tid);
   } else {
     for (int c = 0; c < G.ncell; ++c) {
       const KCell C = tb.cell[G.cell_begin + c];
@@ -340,6 +346,104 @@ __device__ __forceinline__ void forward_fast(const KBranch br, const double* D, 
   }
 }
 
+// Ascending branches (no re-rooting): compartment j of a branch sits at LDS
+// slot start + j, so a chunk of 8 positions is a fixed window addressed from
+// one base with immediate offsets.  The window may reach 8 slots beyond the
+// branch (into the padding or other branches); those values are never used
+// and nothing outside the branch is written.
+__device__ __forceinline__ void backward_asc(const KBranch br, double* D, const double* U, double* B, double* CD,
+                                             double* CB) {
+  const int len = br.lendir;
+  int i = br.start + len - 1;
+  double dl = D[i], bl = B[i];
+  for (int k = br.nchild - 1; k >= 0; --k) {
+    dl = dl - CD[br.child0 + k];
+    bl = bl - CB[br.child0 + k];
+  }
+  int rem = len - 1;
+  while (rem > 0) {
+    const int n = rem < kChunk ? rem : kChunk;
+    const double* pd = D + (i - kChunk);  // pd[8-k] = D[i-k], pd[7-k] = D[i-k-1]
+    const double* pu = U + (i - kChunk);
+    const double* pb = B + (i - kChunk);
+    double uu[kChunk], dm[kChunk], bm[kChunk], ff[kChunk], yy[kChunk];
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      uu[k] = pu[kChunk - k];
+      dm[k] = pd[kChunk - 1 - k];
+      bm[k] = pb[kChunk - 1 - k];
+    }
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      if (k < n) {
+        const double r = rcp_nr(dl);
+        ff[k] = uu[k] * r;
+        yy[k] = bl * r;
+        dl = __builtin_fma(-ff[k], uu[k], dm[k]);
+        bl = __builtin_fma(-ff[k], bl, bm[k]);
+      }
+    }
+    double* qd = D + (i - kChunk);
+    double* qb = B + (i - kChunk);
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      if (k < n) {
+        qd[kChunk - k] = ff[k];
+        qb[kChunk - k] = yy[k];
+      }
+    }
+    i -= n;
+    rem -= n;
+  }
+  const double r = rcp_nr(dl);
+  if (br.u0 >= 0) {
+    const double uu = U[br.u0];
+    const double f = uu * r;
+    D[i] = f;
+    B[i] = bl * r;
+    CD[br.self] = f * uu;
+    CB[br.self] = f * bl;
+  } else {
+    B[i] = bl * r;
+  }
+}
+
+__device__ __forceinline__ void forward_asc(const KBranch br, const double* D, double* B) {
+  const int len = br.lendir;
+  int i = br.start;
+  double xp;
+  if (br.u0 >= 0) {
+    xp = __builtin_fma(-D[i], B[br.pslot], B[i]);
+    B[i] = xp;
+  } else {
+    xp = B[i];
+  }
+  int rem = len - 1;
+  while (rem > 0) {
+    const int n = rem < kChunk ? rem : kChunk;
+    const double* pd = D + (i + 1);
+    double* pb = B + (i + 1);
+    double ff[kChunk], yy[kChunk], xs[kChunk];
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      ff[k] = pd[k];
+      yy[k] = pb[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      if (k < n) {
+        xp = __builtin_fma(-ff[k], xp, yy[k]);
+        xs[k] = xp;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k)
+      if (k < n) pb[k] = xs[k];
+    i += n;
+    rem -= n;
+  }
+}
+
 __device__ __forceinline__ void backward_bitwise(const KBranch br, double* D, const double* U, double* B, double* CD,
                                                  double* CB) {
 #pragma clang fp contract(off)
@@ -396,7 +500,30 @@ __device__ __forceinline__ void forward_bitwise(const KBranch br, const double* 
   }
 }
 
-template <int T, bool BITWISE>
+enum { kModeFast = 0, kModeBitwise = 1, kModeAscending = 2 };
+
+template <int MODE>
+__device__ __forceinline__ void backward_branch(const KBranch br, double* D, const double* U, double* B, double* CD,
+                                                double* CB) {
+  if constexpr (MODE == kModeBitwise)
+    backward_bitwise(br, D, U, B, CD, CB);
+  else if constexpr (MODE == kModeAscending)
+    backward_asc(br, D, U, B, CD, CB);
+  else
+    backward_fast(br, D, U, B, CD, CB);
+}
+
+template <int MODE>
+__device__ __forceinline__ void forward_branch(const KBranch br, const double* D, const double* U, double* B) {
+  if constexpr (MODE == kModeBitwise)
+    forward_bitwise(br, D, U, B);
+  else if constexpr (MODE == kModeAscending)
+    forward_asc(br, D, B);
+  else
+    forward_fast(br, D, B);
+}
+
+template <int T, int MODE>
 __global__ __launch_bounds__(T) void k_solve_lds_f64(DevTables tb, const double* __restrict__ d,
                                                      const double* __restrict__ u, const double* rhs,
                                                      double* x) {
@@ -429,18 +556,8 @@ __global__ __launch_bounds__(T) void k_solve_lds_f64(DevTables tb, const double*
       p0 = seg[l - 1] - brb;
       if (p0 + tid < s0) nxt = BR[p0 + tid];
     }
-    if (s0 + tid < s1) {
-      if constexpr (BITWISE)
-        backward_bitwise(cur, D, U, B, CD, CB);
-      else
-        backward_fast(cur, D, U, B, CD, CB);
-    }
-    for (int e = s0 + tid + T; e < s1; e += T) {
-      if constexpr (BITWISE)
-        backward_bitwise(BR[e], D, U, B, CD, CB);
-      else
-        backward_fast(BR[e], D, U, B, CD, CB);
-    }
+    if (s0 + tid < s1) backward_branch<MODE>(cur, D, U, B, CD, CB);
+    for (int e = s0 + tid + T; e < s1; e += T) backward_branch<MODE>(BR[e], D, U, B, CD, CB);
     __syncthreads();
     s1 = s0;
     s0 = p0;
@@ -458,18 +575,8 @@ __global__ __launch_bounds__(T) void k_solve_lds_f64(DevTables tb, const double*
       p1 = seg[l + 2] - brb;
       if (s1 + tid < p1) nxt = BR[s1 + tid];
     }
-    if (s0 + tid < s1) {
-      if constexpr (BITWISE)
-        forward_bitwise(cur, D, U, B);
-      else
-        forward_fast(cur, D, B);
-    }
-    for (int e = s0 + tid + T; e < s1; e += T) {
-      if constexpr (BITWISE)
-        forward_bitwise(BR[e], D, U, B);
-      else
-        forward_fast(BR[e], D, B);
-    }
+    if (s0 + tid < s1) forward_branch<MODE>(cur, D, U, B);
+    for (int e = s0 + tid + T; e < s1; e += T) forward_branch<MODE>(BR[e], D, U, B);
     __syncthreads();
     s0 = s1;
     s1 = p1;
@@ -479,16 +586,200 @@ __global__ __launch_bounds__(T) void k_solve_lds_f64(DevTables tb, const double*
   store_group<T>(tb, G, B, x, tid);
 }
 
+// ---------------------------------------------------------------------------
+// Scheduled FP64 solve (ascending branches, fast form).  One wave per group;
+// lane t runs the branches the setup assigned to it, each starting at its
+// scheduled iteration.  In one iteration a lane eliminates up to kSchedChunk
+// compartments of its current branch; a branch starts only after every child
+// branch finished in an earlier iteration, so its children's contributions
+// are in LDS.  The forward sweep replays the schedule backwards in time: a
+// branch's parent compartment is solved in a later backward iteration, hence
+// in an earlier forward one.  No barrier is needed between iterations: the
+// group is one wave and the LDS executes a wave's operations in order; the
+// signal fence only keeps the compiler from moving LDS accesses across
+// iterations.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int sched_itlen(int len) {
+  const int k = (len - 1 + hines::kSchedChunk - 1) / hines::kSchedChunk;
+  return k > 1 ? k : 1;
+}
+
+__global__ __launch_bounds__(64) void k_solve_sched_f64(DevTables tb, const double* __restrict__ d,
+                                                        const double* __restrict__ u, const double* rhs,
+                                                        double* x) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  const int g = tb.glist[blockIdx.x];
+  const KGroup G = tb.grp[g];
+  const LdsLayout L = lds_layout(G);
+  double* D = (double*)lds_raw;
+  double* U = D + L.u_off();
+  double* B = D + L.b_off();
+  double* CD = D + L.cd_off();
+  double* CB = D + L.cb_off();
+  const KBranch* BR = (const KBranch*)(lds_raw + L.br_off_bytes());
+  const int* LO = (const int*)(lds_raw + L.seg_off_bytes());
+  const int lane = threadIdx.x;
+
+  stage_group<64>(tb, G, L, d, u, rhs, lds_raw, lane, tb.lanes + (int64_t)g * (hines::kSchedLanes + 1));
+
+  const int q0 = LO[lane], q1 = LO[lane + 1];
+  const int F = G.makespan;
+
+  // ---- backward ----
+  {
+    int q = q0;
+    KBranch rec{};
+    int js = 0x7fffffff;
+    if (q < q1) {
+      rec = BR[q];
+      js = rec.pad;
+    }
+    int i = 0, rem = -1;
+    double dl = 0.0, bl = 0.0;
+    for (int it = 0; it < F; ++it) {
+      if (q < q1 && it >= js) {
+        if (it == js) {
+          i = rec.start + rec.lendir - 1;
+          dl = D[i];
+          bl = B[i];
+          for (int k = rec.nchild - 1; k >= 0; --k) {
+            dl = dl - CD[rec.child0 + k];
+            bl = bl - CB[rec.child0 + k];
+          }
+          rem = rec.lendir - 1;
+        }
+        if (rem > 0) {
+          const int n = rem < kChunk ? rem : kChunk;
+          const double* pd = D + (i - kChunk);
+          const double* pu = U + (i - kChunk);
+          const double* pb = B + (i - kChunk);
+          double uu[kChunk], dm[kChunk], bm[kChunk], ff[kChunk], yy[kChunk];
+#pragma unroll
+          for (int k = 0; k < kChunk; ++k) {
+            uu[k] = pu[kChunk - k];
+            dm[k] = pd[kChunk - 1 - k];
+            bm[k] = pb[kChunk - 1 - k];
+          }
+#pragma unroll
+          for (int k = 0; k < kChunk; ++k) {
+            if (k < n) {
+              const double r = rcp_nr(dl);
+              ff[k] = uu[k] * r;
+              yy[k] = bl * r;
+              dl = __builtin_fma(-ff[k], uu[k], dm[k]);
+              bl = __builtin_fma(-ff[k], bl, bm[k]);
+            }
+          }
+          double* qd = D + (i - kChunk);
+          double* qb = B + (i - kChunk);
+#pragma unroll
+          for (int k = 0; k < kChunk; ++k) {
+            if (k < n) {
+              qd[kChunk - k] = ff[k];
+              qb[kChunk - k] = yy[k];
+            }
+          }
+          i -= n;
+          rem -= n;
+        }
+        if (rem == 0) {
+          const double r = rcp_nr(dl);
+          if (rec.u0 >= 0) {
+            const double uu = U[rec.u0];
+            const double f = uu * r;
+            D[i] = f;
+            B[i] = bl * r;
+            CD[rec.self] = f * uu;
+            CB[rec.self] = f * bl;
+          } else {
+            B[i] = bl * r;
+          }
+          ++q;
+          rem = -1;
+          if (q < q1) {
+            rec = BR[q];
+            js = rec.pad;
+          }
+        }
+      }
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    }
+  }
+  __syncthreads();
+
+  // ---- forward: the same schedule, backwards in time ----
+  {
+    int q = q1 - 1;
+    KBranch rec{};
+    int je = -1;
+    if (q >= q0) {
+      rec = BR[q];
+      je = rec.pad + sched_itlen(rec.lendir) - 1;
+    }
+    int i = 0, rem = -1;
+    double xp = 0.0;
+    for (int it = F - 1; it >= 0; --it) {
+      if (q >= q0 && it <= je) {
+        if (it == je) {
+          i = rec.start;
+          if (rec.u0 >= 0) {
+            xp = __builtin_fma(-D[i], B[rec.pslot], B[i]);
+            B[i] = xp;
+          } else {
+            xp = B[i];
+          }
+          rem = rec.lendir - 1;
+        }
+        if (rem > 0) {
+          const int n = rem < kChunk ? rem : kChunk;
+          const double* pd = D + (i + 1);
+          double* pb = B + (i + 1);
+          double ff[kChunk], yy[kChunk], xs[kChunk];
+#pragma unroll
+          for (int k = 0; k < kChunk; ++k) {
+            ff[k] = pd[k];
+            yy[k] = pb[k];
+          }
+#pragma unroll
+          for (int k = 0; k < kChunk; ++k) {
+            if (k < n) {
+              xp = __builtin_fma(-ff[k], xp, yy[k]);
+              xs[k] = xp;
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < kChunk; ++k)
+            if (k < n) pb[k] = xs[k];
+          i += n;
+          rem -= n;
+        }
+        if (rem == 0) {
+          --q;
+          rem = -1;
+          if (q >= q0) {
+            rec = BR[q];
+            je = rec.pad + sched_itlen(rec.lendir) - 1;
+          }
+        }
+      }
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    }
+  }
+  __syncthreads();
+
+  store_group<64>(tb, G, B, x, lane);
+}
+
 namespace {
 
-template <int T, bool BW>
+template <int T, int MODE>
 hipError_t launch_solve_f64(const hines_plan* p, const double* d, const double* u, const double* b, double* x,
                             hipStream_t s) {
   for (const auto& bk : p->buckets) {
     if (bk.count == 0) continue;
     DevTables t = p->t;
     t.glist = p->t.glist + bk.first;
-    hipLaunchKernelGGL((k_solve_lds_f64<T, BW>), dim3(bk.count), dim3(T), bk.lds_bytes, s, t, d, u, b, x);
+    hipLaunchKernelGGL((k_solve_lds_f64<T, MODE>), dim3(bk.count), dim3(T), bk.lds_bytes, s, t, d, u, b, x);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -497,14 +788,19 @@ hipError_t launch_solve_f64(const hines_plan* p, const double* d, const double* 
 
 template <int T>
 hipError_t allow_lds_f64() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_solve_lds_f64<T, false>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_solve_lds_f64<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             kMaxLdsBytes);
+  const void* fns[] = {(const void*)k_solve_lds_f64<T, kModeFast>, (const void*)k_solve_lds_f64<T, kModeBitwise>,
+                       (const void*)k_solve_lds_f64<T, kModeAscending>};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t allow_lds(int T) {
+  hipError_t e0 = hipFuncSetAttribute((const void*)k_solve_sched_f64, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      kMaxLdsBytes);
+  if (e0 != hipSuccess) return e0;
   switch (T) {
     case 64: return allow_lds_f64<64>();
     case 128: return allow_lds_f64<128>();
@@ -515,11 +811,26 @@ hipError_t allow_lds(int T) {
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_sched_f64(const hines_plan* p, const double* d, const double* u, const double* b, double* x,
+                            hipStream_t s) {
+  for (const auto& bk : p->buckets) {
+    if (bk.count == 0) continue;
+    DevTables t = p->t;
+    t.glist = p->t.glist + bk.first;
+    hipLaunchKernelGGL(k_solve_sched_f64, dim3(bk.count), dim3(64), bk.lds_bytes, s, t, d, u, b, x);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 template <int T>
 hipError_t launch_f64(const hines_plan* p, const double* d, const double* u, const double* b, double* x,
                       hipStream_t s) {
-  return p->host.opt.bitwise ? launch_solve_f64<T, true>(p, d, u, b, x, s)
-                             : launch_solve_f64<T, false>(p, d, u, b, x, s);
+  if (p->host.scheduled) return launch_sched_f64(p, d, u, b, x, s);
+  if (p->host.opt.bitwise) return launch_solve_f64<T, kModeBitwise>(p, d, u, b, x, s);
+  if (p->host.all_ascending) return launch_solve_f64<T, kModeAscending>(p, d, u, b, x, s);
+  return launch_solve_f64<T, kModeFast>(p, d, u, b, x, s);
 }
 
 // Every index a kernel derives from the tables must stay inside the group's
@@ -536,20 +847,21 @@ bool check_kernel_tables(const hines::HostPlan& P, std::string& why) {
       why = "segment range";
       return false;
     }
-    int64_t U = 0;
+    const int64_t pad = hines::kLdsPad;
+    int64_t U = pad;
     if (G.contig) {
       if ((G.user_base & 1) || G.user_base < 0 || G.user_lo < 0 || G.user_lo > 1 ||
           G.user_base + G.user_lo + G.user_n > P.n) {
         why = "contiguous group range";
         return false;
       }
-      U = G.user_lo;
+      U = pad + G.user_lo;
     }
     for (int c = 0; c < G.ncell; ++c) {
       const KCell& C = P.kcell[G.cell_begin + c];
       bool good = C.n > 0 && C.user_lo >= 0 && C.user_lo + C.n <= P.n;
       if (G.contig)
-        good = good && C.lds == U && C.user_lo == G.user_base + C.lds;
+        good = good && C.lds == U && C.user_lo == G.user_base + C.lds - pad;
       else
         good = good && C.lds >= U && C.lds <= U + 1 && !(C.lds & 1);
       if (!good) {
@@ -558,11 +870,11 @@ bool check_kernel_tables(const hines::HostPlan& P, std::string& why) {
       }
       U = C.lds + C.n;
     }
-    if (G.contig && U != G.user_lo + G.user_n) {
+    if (G.contig && U != pad + G.user_lo + G.user_n) {
       why = "contiguous group size";
       return false;
     }
-    if (G.nunk < U || G.nunk > U + 1 || (G.nunk & 1)) {
+    if (G.nunk < U + pad || G.nunk > U + pad + 1 || (G.nunk & 1)) {
       why = "group size";
       return false;
     }
@@ -572,14 +884,62 @@ bool check_kernel_tables(const hines::HostPlan& P, std::string& why) {
         int len = B.lendir > 0 ? B.lendir : -B.lendir;
         int dir = B.lendir > 0 ? 1 : -1;
         int last = B.start + dir * (len - 1);
-        bool good = len >= 1 && B.start >= 0 && B.start < U && last >= 0 && last < U && B.self >= 0 &&
+        bool good = len >= 1 && B.start >= pad && B.start < U && last >= pad && last < U && B.self >= 0 &&
                     B.self < G.nbr && B.nchild >= 0 && (B.nchild == 0 || (B.child0 >= 0 && B.child0 + B.nchild <= G.nbr));
-        if (B.u0 >= 0 || B.pslot >= 0) good = good && B.u0 >= 0 && B.u0 < U && B.pslot >= 0 && B.pslot < U;
+        if (B.u0 >= 0 || B.pslot >= 0) good = good && B.u0 >= pad && B.u0 < U && B.pslot >= pad && B.pslot < U;
+        if (P.all_ascending && dir < 0) good = false;
         if (!good) {
           why = "branch table";
           return false;
         }
       }
+  }
+  if (P.scheduled) {
+    // lanes' branches must not overlap in time and every branch must start
+    // after its children finished; everything inside the makespan
+    const int W = hines::kSchedLanes;
+    if ((int64_t)P.klane.size() != P.ngroups * (W + 1)) {
+      why = "lane table size";
+      return false;
+    }
+    std::vector<int32_t> st, fin;
+    for (int64_t g = 0; g < P.ngroups; ++g) {
+      const KGroup& G = P.kgroup[g];
+      const int32_t* lo = &P.klane[g * (W + 1)];
+      if (lo[0] != 0 || lo[W] != G.nbr || G.makespan <= 0 || G.makespan > 30000) {
+        why = "lane offsets";
+        return false;
+      }
+      st.assign(G.nbr, -1);
+      fin.assign(G.nbr, -1);
+      for (int ln = 0; ln < W; ++ln) {
+        if (lo[ln + 1] < lo[ln]) {
+          why = "lane offsets order";
+          return false;
+        }
+        int32_t t = 0;
+        for (int32_t r = lo[ln]; r < lo[ln + 1]; ++r) {
+          const KBranch& B = P.kbranch[G.br_begin + r];
+          const int len = B.lendir;
+          const int itl = std::max(1, (len - 1 + hines::kSchedChunk - 1) / hines::kSchedChunk);
+          if (B.pad < t || B.pad + itl > G.makespan || B.self < 0 || B.self >= G.nbr || st[B.self] >= 0) {
+            why = "lane timeline";
+            return false;
+          }
+          st[B.self] = B.pad;
+          fin[B.self] = B.pad + itl;
+          t = B.pad + itl;
+        }
+      }
+      for (int32_t r = 0; r < G.nbr; ++r) {
+        const KBranch& B = P.kbranch[G.br_begin + r];
+        for (int c = B.child0; c < B.child0 + B.nchild; ++c)
+          if (st[c] < 0 || fin[c] > st[B.self]) {
+            why = "schedule order";
+            return false;
+          }
+      }
+    }
   }
   return true;
 }
@@ -609,7 +969,7 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
     opt = *opt_in;
   else
     hines_default_options(&opt);
-  for (int k = 0; k < 8; ++k)
+  for (int k = 0; k < 7; ++k)
     if (opt.reserved[k] != 0) return set_err(HINES_ERR_OPTION, "reserved option fields must be 0");
   hines::Options o;
   o.rebalance_root = opt.rebalance_root != 0;
@@ -620,6 +980,7 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   o.host_only = opt.host_only != 0;
   o.keep_tables = opt.keep_tables != 0;
   o.bitwise = opt.bitwise != 0;
+  o.scheduler = opt.level_sync ? 0 : 1;
   hines_plan* p = new (std::nothrow) hines_plan();
   if (!p) return set_err(HINES_ERR_OOM, "host allocation failed");
   std::string why;
@@ -673,7 +1034,8 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   const int64_t sz_seg = al((int64_t)P.kseg.size() * sizeof(int32_t));
   const int64_t sz_cell = al((int64_t)P.kcell.size() * sizeof(KCell));
   const int64_t sz_gl = al((int64_t)glist.size() * sizeof(int32_t));
-  const int64_t total = sz_br + sz_grp + sz_seg + sz_cell + sz_gl + 256;
+  const int64_t sz_ln = al((int64_t)P.klane.size() * sizeof(int32_t));
+  const int64_t total = sz_br + sz_grp + sz_seg + sz_cell + sz_gl + sz_ln + 256;
   hipError_t e = hipGetDevice(&p->device);
   if (e == hipSuccess) e = allow_lds(o.group_width);
   if (e != hipSuccess) {
@@ -707,6 +1069,9 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   off += sz_cell;
   p->t.glist = (const int32_t*)(base + off);
   if (e == hipSuccess) e = up(glist.data(), (int64_t)glist.size() * sizeof(int32_t), off);
+  off += sz_gl;
+  p->t.lanes = P.scheduled ? (const int32_t*)(base + off) : nullptr;
+  if (e == hipSuccess && P.scheduled) e = up(P.klane.data(), (int64_t)P.klane.size() * sizeof(int32_t), off);
   if (e != hipSuccess) {
     hipFree(p->dev_mem);
     delete p;
@@ -757,6 +1122,11 @@ hines_status hines_plan_info_get(const hines_plan* p, hines_plan_info* info) {
   info->nclasses = nb;
   info->device_table_bytes = p->dev_bytes;
   info->max_group_lds_bytes = p->max_lds;
+  info->kernel = p->host.scheduled ? 1 : (p->host.opt.bitwise ? 2 : 0);
+  int32_t mk = 0;
+  if (p->host.scheduled)
+    for (const auto& G : p->host.kgroup) mk = std::max(mk, G.makespan);
+  info->max_makespan = mk;
   return ok();
 }
 

@@ -23,6 +23,102 @@
 namespace hines {
 namespace {
 
+// Heavy-path lane schedule of one group.  Input: the group's branches in
+// group-local breadth-first order (children after parents), with length,
+// parent and children ranges.  Output: start iteration and lane per branch,
+// and the makespan.  Returns false if no schedule was found.
+struct SchedIn {
+  int32_t len, parent, child0, nchild;
+};
+
+static bool schedule_group(const std::vector<SchedIn>& br, std::vector<int32_t>& start, std::vector<int32_t>& lane_of,
+                           int32_t& makespan) {
+  const int32_t nb = (int32_t)br.size();
+  std::vector<int32_t> itl(nb), fin(nb), heavy(nb, -1), plen(nb, 0);
+  int64_t total = 0;
+  for (int32_t b = 0; b < nb; ++b) {
+    itl[b] = std::max<int32_t>(1, (br[b].len - 1 + kSchedChunk - 1) / kSchedChunk);
+    total += itl[b];
+  }
+  // as soon as possible: a branch starts when its last child finishes
+  for (int32_t b = nb - 1; b >= 0; --b) {
+    int32_t hf = 0, h = -1;
+    for (int32_t c = br[b].child0; c < br[b].child0 + br[b].nchild; ++c)
+      if (h < 0 || fin[c] > hf) {  // the child finishing last; the smallest id on ties
+        hf = fin[c];
+        h = c;
+      }
+    heavy[b] = h;
+    fin[b] = hf + itl[b];
+  }
+  // path length from each branch down its heavy chain
+  for (int32_t b = nb - 1; b >= 0; --b) plen[b] = itl[b] + (heavy[b] >= 0 ? plen[heavy[b]] : 0);
+  int32_t F = 0;
+  for (int32_t b = 0; b < nb; ++b)
+    if (br[b].parent < 0) F = std::max(F, fin[b]);
+  start.assign(nb, 0);
+  lane_of.assign(nb, 0);
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> busy(kSchedLanes);
+  struct Item {
+    int32_t deadline, top;
+  };
+  for (int64_t tries = 0; F <= total + 1 && F < 32000; ++tries, ++F) {
+    for (auto& v : busy) v.clear();
+    std::vector<Item> work;
+    for (int32_t b = nb - 1; b >= 0; --b)
+      if (br[b].parent < 0) work.push_back({F, b});
+    bool ok = true;
+    while (!work.empty()) {
+      // latest deadline first; longer path first on ties
+      size_t pick = 0;
+      for (size_t k = 1; k < work.size(); ++k) {
+        const Item &a = work[k], &bb = work[pick];
+        if (a.deadline > bb.deadline || (a.deadline == bb.deadline && plen[a.top] > plen[bb.top]) ||
+            (a.deadline == bb.deadline && plen[a.top] == plen[bb.top] && a.top < bb.top))
+          pick = k;
+      }
+      const Item it = work[pick];
+      work.erase(work.begin() + (std::ptrdiff_t)pick);
+      const int32_t L = plen[it.top];
+      int32_t best_end = -1, best_lane = -1;
+      for (int32_t ln = 0; ln < kSchedLanes; ++ln) {
+        int32_t end = it.deadline;
+        const auto& iv = busy[ln];  // sorted by start
+        for (int64_t k = (int64_t)iv.size() - 1; k >= 0; --k) {
+          if (iv[k].first >= end) continue;           // entirely after the window end
+          if (iv[k].second <= end - L) break;         // gap [iv.second, end) fits
+          end = iv[k].first;                          // move the window before this interval
+        }
+        if (end - L >= 0 && end > best_end) {
+          best_end = end;
+          best_lane = ln;
+        }
+      }
+      if (best_lane < 0) {
+        ok = false;
+        break;
+      }
+      auto& iv = busy[best_lane];
+      iv.push_back({best_end - L, best_end});
+      std::sort(iv.begin(), iv.end());
+      // branches of the path from the top down
+      int32_t t = best_end;
+      for (int32_t b = it.top; b >= 0; b = heavy[b]) {
+        t -= itl[b];
+        start[b] = t;
+        lane_of[b] = best_lane;
+        for (int32_t c = br[b].child0; c < br[b].child0 + br[b].nchild; ++c)
+          if (c != heavy[b]) work.push_back({t, c});
+      }
+    }
+    if (ok) {
+      makespan = F;
+      return true;
+    }
+  }
+  return false;
+}
+
 struct Builder {
   const int32_t* parent;
   int64_t n;
@@ -463,8 +559,8 @@ struct Builder {
       G.user_base = contig ? ubase : 0;
       G.user_lo = contig ? (int32_t)(coff[c_first] - ubase) : 0;
       G.user_n = 0;
-      G.pad = 0;
-      if (contig) U = coff[c_first] - ubase;
+      G.makespan = 0;
+      U = kLdsPad + (contig ? coff[c_first] - ubase : 0);
       for (int64_t e = P.group_offsets[g]; e < P.group_offsets[g + 1]; ++e) {
         int64_t c = P.group_cells[e];
         if (!contig) U = (U + 1) & ~(int64_t)1;  // each cell starts 16-byte aligned in the LDS image
@@ -476,7 +572,7 @@ struct Builder {
         nbr += cell_br_lo[c + 1] - cell_br_lo[c];
         gnl = std::max(gnl, (int32_t)(cnt_off[c + 1] - cnt_off[c]));
       }
-      U = (U + 1) & ~(int64_t)1;
+      U = (U + kLdsPad + 1) & ~(int64_t)1;  // back padding, even size
       G.nunk = (int32_t)std::min<int64_t>(U, INT32_MAX);
       G.nbr = (int32_t)nbr;
       G.nlev = gnl;
@@ -504,6 +600,7 @@ struct Builder {
           auto local = [&](int32_t user) { return cell_lds[c] + (int32_t)(user - coff[c]); };
           int32_t f_start = local(gfirst[k]);
           int32_t f_lendir = gdir[k] > 0 ? glen[k] : -glen[k];
+          if (gdir[k] < 0) P.all_ascending = false;
           int32_t f_u0 = -1, f_pslot = -1;
           if (gparent[k] >= 0) {
             int32_t pb = gparent[k];
@@ -535,6 +632,60 @@ struct Builder {
     }
     P.kseg.push_back((int32_t)lane);
     P.nseg = (int64_t)P.kseg.size() - 1;
+
+    // ---- static lane schedule (ascending fast path) ----
+    if (opt.scheduler && !opt.bitwise && P.all_ascending && P.kernel_tables_fit && !opt.host_only) {
+      P.klane.assign((size_t)ng * (kSchedLanes + 1), 0);
+      std::vector<SchedIn> sin;
+      std::vector<int32_t> st, ln, order;
+      std::vector<KBranch> tmp;
+      std::vector<KBranch> sched(P.kbranch);  // committed only if every group is scheduled
+      bool all_ok = true;
+      for (int64_t g = 0; g < ng && all_ok; ++g) {
+        KGroup& G = P.kgroup[g];
+        const int32_t nbg = G.nbr;
+        sin.assign(nbg, SchedIn{0, -1, 0, 0});
+        std::vector<int32_t> rec_of(nbg, -1);  // group-local BFS id -> record index in the group
+        for (int32_t r = 0; r < nbg; ++r) {
+          const KBranch& B = P.kbranch[G.br_begin + r];
+          rec_of[B.self] = r;
+          sin[B.self] = SchedIn{B.lendir, -1, B.child0, B.nchild};
+        }
+        for (int32_t b = 0; b < nbg; ++b)
+          for (int32_t c = sin[b].child0; c < sin[b].child0 + sin[b].nchild; ++c) sin[c].parent = b;
+        int32_t F = 0;
+        if (!schedule_group(sin, st, ln, F)) {
+          all_ok = false;
+          break;
+        }
+        G.makespan = F;
+        order.resize(nbg);
+        std::iota(order.begin(), order.end(), 0);
+        std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+          if (ln[a] != ln[b]) return ln[a] < ln[b];
+          return st[a] < st[b];
+        });
+        tmp.resize(nbg);
+        int32_t* lo = &P.klane[(size_t)g * (kSchedLanes + 1)];
+        int32_t cur = 0;
+        for (int32_t lane_id = 0; lane_id <= kSchedLanes; ++lane_id) {
+          while (cur < nbg && ln[order[cur]] < lane_id) ++cur;
+          lo[lane_id] = cur;
+        }
+        for (int32_t k = 0; k < nbg; ++k) {
+          const int32_t b = order[k];
+          tmp[k] = P.kbranch[G.br_begin + rec_of[b]];
+          tmp[k].pad = (int16_t)st[b];
+        }
+        std::copy(tmp.begin(), tmp.end(), sched.begin() + G.br_begin);
+      }
+      if (all_ok) {
+        P.kbranch.swap(sched);
+        P.scheduled = true;
+      } else {
+        std::vector<int32_t>().swap(P.klane);  // level-synchronous kernel instead
+      }
+    }
     P.seg_offsets.assign(P.kseg.begin(), P.kseg.end());
 
     // ---- exported tables ----

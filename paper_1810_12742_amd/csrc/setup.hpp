@@ -35,7 +35,20 @@ struct Options {
   int32_t host_only = 0;           // build tables only, no device upload
   int32_t keep_tables = 1;         // keep the exported tables after setup
   int32_t bitwise = 0;             // IEEE divisions, unfused updates: equal to the plain algorithm bit for bit
+  int32_t scheduler = 1;           // 1: static heavy-path lane schedule when every branch ascends;
+                                   // 0: level-synchronous sweeps (paper §3)
 };
+
+// Static lane schedule of one group (used by the scheduled solve kernel).
+// Time is counted in iterations; in one iteration a lane eliminates up to
+// kSchedChunk compartments of one branch.  A branch b occupies
+// it_len(b) = max(1, ceil((len_b - 1) / kSchedChunk)) consecutive iterations on
+// one lane and may start only after all its child branches have finished.  A
+// lane continues from a branch into its parent when that child finishes last
+// (the heavy path); the other children are placed as late as their deadline
+// allows on any free lane.
+constexpr int32_t kSchedChunk = 8;
+constexpr int32_t kSchedLanes = 64;
 
 // Table ids for export (shared with the C-ABI).
 enum TableId : int32_t {
@@ -63,11 +76,15 @@ struct KBranch {
   int16_t self;    // group-local breadth-first id (slot of its elimination contribution)
   int16_t child0;  // group-local id of the first child branch
   int16_t nchild;  // number of child branches (ids child0 .. child0+nchild-1)
-  int16_t pad;
+  int16_t pad;     // scheduled kernel: first iteration of the branch
 };
 static_assert(sizeof(KBranch) == 16, "one DMA lane per record");
 
 constexpr int32_t kMaxGroupSlots = 32766;  // largest LDS image the int16 records address
+// Unused slots in front of and behind a group's compartments in its LDS image,
+// so that the solve kernels may read a fixed window of 8 compartments around
+// any position without bounds checks.
+constexpr int32_t kLdsPad = 8;
 
 struct KGroup {
   int64_t user_base;   // contiguous groups: user index of LDS slot 0 (even)
@@ -79,10 +96,10 @@ struct KGroup {
   int32_t nbr;         // branches in the group
   int32_t cost;        // sum over levels of the longest branch (critical path)
   int32_t br_begin;    // first record of the group in the branch table
-  int32_t contig;      // 1: cells are one user range [user_lo, user_hi); LDS slot k <-> user_base + k
+  int32_t contig;      // 1: cells are one user range; LDS slot kLdsPad + k <-> user index user_base + k
   int32_t user_lo;     // contiguous groups: first user index relative to user_base (0 or 1)
   int32_t user_n;      // contiguous groups: compartments in the range
-  int32_t pad;
+  int32_t makespan;    // scheduled kernel: iterations of each sweep
 };
 static_assert(sizeof(KGroup) == 56, "layout");
 
@@ -110,6 +127,9 @@ struct HostPlan {
   std::vector<int32_t> kseg;      // [nseg+1] begin of each segment in kbranch
   std::vector<KCell> kcell;       // [ncells] group order
   bool kernel_tables_fit = true;  // every group addressable by the int16 records
+  bool all_ascending = true;      // every branch runs toward higher user indices
+  bool scheduled = false;         // kbranch is in (group, lane, start) order with start in KBranch::pad
+  std::vector<int32_t> klane;     // scheduled: per group kSchedLanes + 1 record offsets (group-relative)
 };
 
 Status build_plan(const int32_t* parent, int64_t n, const int64_t* branch_offsets, int64_t nbranches,

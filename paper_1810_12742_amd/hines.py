@@ -34,14 +34,15 @@ class _Options(ctypes.Structure):
                 ("group_width", ctypes.c_int32), ("cell_order", ctypes.c_int32),
                 ("max_group_unknowns", ctypes.c_int32), ("host_only", ctypes.c_int32),
                 ("keep_tables", ctypes.c_int32), ("bitwise", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("level_sync", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("ncells", ctypes.c_int64), ("nbranches", ctypes.c_int64),
                 ("ngroups", ctypes.c_int64), ("nsegments", ctypes.c_int64), ("max_level", ctypes.c_int32),
                 ("nclasses", ctypes.c_int32), ("device_table_bytes", ctypes.c_int64),
-                ("max_group_lds_bytes", ctypes.c_int64)]
+                ("max_group_lds_bytes", ctypes.c_int64), ("kernel", ctypes.c_int32),
+                ("max_makespan", ctypes.c_int32)]
 
 
 def library_path() -> str:
@@ -98,7 +99,7 @@ class Plan:
 
     def __init__(self, parent, cell_offsets, branch_offsets=None, *, rebalance_root=False,
                  split_branches=False, group_width=64, cell_order=0, max_group_unknowns=None,
-                 host_only=False, keep_tables=True, bitwise=False):
+                 host_only=False, keep_tables=True, bitwise=False, level_sync=False):
         lib = load()
         opt = _Options()
         lib.hines_default_options(ctypes.byref(opt))
@@ -111,6 +112,7 @@ class Plan:
         opt.host_only = int(bool(host_only))
         opt.keep_tables = int(bool(keep_tables))
         opt.bitwise = int(bool(bitwise))
+        opt.level_sync = int(bool(level_sync))
         self._par = _host(parent, np.int32)
         self._coff = _host(cell_offsets, np.int64)
         bo = None if branch_offsets is None else _host(branch_offsets, np.int64)

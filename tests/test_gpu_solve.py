@@ -60,12 +60,19 @@ OPTS = [
     dict(split_branches=1, max_group_unknowns=512),
     dict(group_width=128, max_group_unknowns=4096),
     dict(group_width=256, max_group_unknowns=5000, split_branches=1),
+    dict(level_sync=1),
+    dict(level_sync=1, split_branches=1, max_group_unknowns=3000),
 ]
 
 
 @pytest.mark.parametrize("opts", OPTS, ids=lambda o: ",".join(f"{k}={v}" for k, v in o.items()) or "default")
 def test_c2_slice_all_options(torch_dev, opts):
+    from paper_1810_12742_amd import Plan
     s = configs.c2(1536)
+    f0 = s.forest
+    info = Plan(f0.parent, f0.cell_offsets, f0.branch_offsets, **opts).info
+    want = 0 if (opts.get("level_sync") or opts.get("rebalance_root")) else 1
+    assert info["kernel"] == want
     f = s.forest
     xo = oracle.solve(f, s.diag, s.upper, s.rhs)
     x = gpu_solve(torch_dev, s, **opts)
