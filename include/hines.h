@@ -84,7 +84,10 @@ typedef struct hines_plan_info {
   int64_t max_group_lds_bytes;
   int32_t kernel;             /* 0 level-synchronous, 1 scheduled, 2 level-synchronous bitwise */
   int32_t max_makespan;       /* scheduled plans: longest schedule, in iterations */
+  int64_t workspace_groups;   /* groups too large for LDS, solved from a global workspace */
 } hines_plan_info;
+
+typedef struct hines_timeloop hines_timeloop; /* opaque: a captured multi-step graph */
 
 /* Table ids for hines_get_table (all exported as int64). */
 enum {
@@ -129,6 +132,52 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
  * Inputs are not modified.  Asynchronous on stream. */
 hines_status hines_solve(const hines_plan* plan, const double* diag, const double* upper,
                          const double* rhs, double* x, int32_t ncells, void* stream);
+
+/* One implicit-Euler step of the discrete cable system (paper §1: the
+ * current is evaluated at the old step):
+ *     A v_out = c * v_in + I,   A given by (diag, upper),
+ * with I = i_inj (device array, per compartment, constant) when i_inj is
+ * non-NULL, else I_i = noise_sigma * Z_i where Z_i is a standard normal drawn
+ * from Philox4x32-10 (Salmon et al., SC'11) keyed by (noise_seed, 0) with
+ * counter (i mod 2^32, i div 2^32, step, 0) for user index i, and turned into a
+ * normal by Box-Muller on two 52-bit uniforms; noise_sigma == 0 and i_inj ==
+ * NULL give I = 0.  The right-hand side is formed inside the solve kernels.
+ * v_out may alias v_in (in-place update); no other aliasing.  Async on stream. */
+hines_status hines_timestep(const hines_plan* plan, const double* diag, const double* upper, const double* c,
+                            const double* v_in, double* v_out, const double* i_inj, double noise_sigma,
+                            uint32_t noise_seed, uint32_t step, int32_t ncells, void* stream);
+
+/* Capture nsteps consecutive hines_timestep calls, updating v in place with
+ * steps first_step .. first_step + nsteps - 1, into a HIP graph (captured on
+ * a private stream; nothing runs during creation).  Each
+ * hines_timeloop_launch replays the same steps on `stream`; the arrays are
+ * bound at creation and must stay valid.  The plan must outlive the loop. */
+hines_status hines_timeloop_create(const hines_plan* plan, const double* diag, const double* upper,
+                                   const double* c, double* v, const double* i_inj, double noise_sigma,
+                                   uint32_t noise_seed, uint32_t first_step, int32_t nsteps, int32_t ncells,
+                                   hines_timeloop** out);
+hines_status hines_timeloop_launch(hines_timeloop* loop, void* stream);
+hines_status hines_timeloop_destroy(hines_timeloop* loop);
+
+/* Element-wise kernels of the adjoint of the time loop (paper §1: A is
+ * symmetric, A = diag(c) + L(a) with L the weighted graph Laplacian of the
+ * tree).  All arrays are device arrays in the user numbering; a[i] is the
+ * conductance of the edge (i, parent[i]) (a[root] is ignored).  The first call
+ * uploads the parent array and child lists of the plan.
+ *   hines_assemble:   diag_i = c_i + a_i + sum_{k: parent[k]=i} a_k (children in
+ *                     ascending order), upper_i = -a_i (0 at roots).
+ *   hines_gather_roots: out[cell] = v[first compartment of cell].
+ *   hines_adjoint_rhs:  mu = c * lam_next (lam_next may be NULL: 0), plus
+ *                     g_roots[cell] at each cell's root.
+ *   hines_adjoint_accumulate: grad_i += lam; grad_c += lam * (v_prev - v);
+ *                     grad_a[i] += -(lam_i - lam_p)(v_i - v_p), p = parent[i]. */
+hines_status hines_assemble(hines_plan* plan, const double* a, const double* c, double* diag, double* upper,
+                            void* stream);
+hines_status hines_gather_roots(hines_plan* plan, const double* v, double* out, void* stream);
+hines_status hines_adjoint_rhs(hines_plan* plan, const double* c, const double* lam_next, const double* g_roots,
+                               double* mu, void* stream);
+hines_status hines_adjoint_accumulate(hines_plan* plan, const double* lam, const double* v, const double* v_prev,
+                                      double* grad_a, double* grad_c, double* grad_i, void* stream);
 
 /* Summary counts of a plan. */
 hines_status hines_plan_info_get(const hines_plan* plan, hines_plan_info* info);

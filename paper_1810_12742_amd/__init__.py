@@ -6,6 +6,6 @@ built in-tree by ``paper_1810_12742_amd.build``); :mod:`.hines` is a thin
 ctypes binding that only marshals arguments.  Nothing here computes on the
 CPU: if the library is missing, every call raises.
 """
-from .hines import HinesError, Plan, TABLES, library_path, load
+from .hines import HinesError, Plan, TABLES, TimeLoop, library_path, load
 
-__all__ = ["HinesError", "Plan", "TABLES", "library_path", "load"]
+__all__ = ["HinesError", "Plan", "TABLES", "TimeLoop", "library_path", "load"]

@@ -555,6 +555,7 @@ struct Builder {
         if (P.group_cells[e] != P.group_cells[e - 1] + 1) contig = false;
       const int64_t c_first = P.group_cells[P.group_offsets[g]];
       const int64_t ubase = coff[c_first] & ~(int64_t)1;
+      G.ws_off = -1;
       G.contig = contig ? 1 : 0;
       G.user_base = contig ? ubase : 0;
       G.user_lo = contig ? (int32_t)(coff[c_first] - ubase) : 0;
@@ -633,7 +634,18 @@ struct Builder {
     P.kseg.push_back((int32_t)lane);
     P.nseg = (int64_t)P.kseg.size() - 1;
 
-    // ---- static lane schedule (ascending fast path) ----
+    // ---- groups whose image exceeds LDS run from a global workspace ----
+    P.ws_doubles = 0;
+    for (int64_t g = 0; g < ng; ++g) {
+      KGroup& G = P.kgroup[g];
+      const LdsLayout lds{G.nunk, (G.nbr + 1) & ~1, G.nlev};
+      if (lds.bytes() > kLdsLimitBytes) {
+        G.ws_off = P.ws_doubles;
+        P.ws_doubles += 3 * (int64_t)G.nunk;
+      }
+    }
+
+    // ---- static lane schedule (ascending fast path, groups staged in LDS) ----
     if (opt.scheduler && !opt.bitwise && P.all_ascending && P.kernel_tables_fit && !opt.host_only) {
       P.klane.assign((size_t)ng * (kSchedLanes + 1), 0);
       std::vector<SchedIn> sin;
@@ -643,6 +655,7 @@ struct Builder {
       bool all_ok = true;
       for (int64_t g = 0; g < ng && all_ok; ++g) {
         KGroup& G = P.kgroup[g];
+        if (G.ws_off >= 0) continue;  // level-synchronous from the workspace
         const int32_t nbg = G.nbr;
         sin.assign(nbg, SchedIn{0, -1, 0, 0});
         std::vector<int32_t> rec_of(nbg, -1);  // group-local BFS id -> record index in the group

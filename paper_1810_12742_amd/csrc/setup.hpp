@@ -50,6 +50,25 @@ struct Options {
 constexpr int32_t kSchedChunk = 8;
 constexpr int32_t kSchedLanes = 64;
 
+// LDS image of a group: d, u, b per slot (nimg slots; 0 when the compartment
+// arrays live in the global workspace), two elimination contributions per
+// branch, the branch records and a table of level or lane offsets.  Every
+// region starts 16-byte aligned.
+struct LdsLayout {
+  int32_t nimg, nbr_pad, nlev;
+  constexpr int64_t u_off() const { return nimg; }  // doubles
+  constexpr int64_t b_off() const { return 2 * (int64_t)nimg; }
+  constexpr int64_t cd_off() const { return 3 * (int64_t)nimg; }
+  constexpr int64_t cb_off() const { return 3 * (int64_t)nimg + nbr_pad; }
+  constexpr int64_t br_off_bytes() const { return 8 * (3 * (int64_t)nimg + 2 * (int64_t)nbr_pad); }
+  constexpr int64_t tab_off_bytes() const { return br_off_bytes() + 16 * (int64_t)nbr_pad; }
+  constexpr int64_t bytes() const {
+    const int64_t ints = (int64_t)nlev + 1 > kSchedLanes + 1 ? (int64_t)nlev + 1 : kSchedLanes + 1;
+    return (tab_off_bytes() + 4 * ints + 15) & ~(int64_t)15;
+  }
+};
+constexpr int64_t kLdsLimitBytes = 160 * 1024;  // gfx950 LDS per workgroup
+
 // Table ids for export (shared with the C-ABI).
 enum TableId : int32_t {
   T_NODE_PLAN = 0,        // int64[n]
@@ -87,7 +106,9 @@ constexpr int32_t kMaxGroupSlots = 32766;  // largest LDS image the int16 record
 constexpr int32_t kLdsPad = 8;
 
 struct KGroup {
-  int64_t user_base;   // contiguous groups: user index of LDS slot 0 (even)
+  int64_t user_base;   // contiguous groups: user index of LDS slot kLdsPad (even)
+  int64_t ws_off;      // groups whose image exceeds LDS: offset (doubles) of the image in the
+                       // global workspace; -1 for groups staged in LDS
   int32_t seg_begin;   // first entry of this group in the segment table
   int32_t nlev;        // levels (segments)
   int32_t cell_begin;  // first entry in the group-cell table
@@ -101,7 +122,7 @@ struct KGroup {
   int32_t user_n;      // contiguous groups: compartments in the range
   int32_t makespan;    // scheduled kernel: iterations of each sweep
 };
-static_assert(sizeof(KGroup) == 56, "layout");
+static_assert(sizeof(KGroup) == 64, "layout");
 
 struct KCell {
   int64_t user_lo;  // first user index of the cell
@@ -130,6 +151,7 @@ struct HostPlan {
   bool all_ascending = true;      // every branch runs toward higher user indices
   bool scheduled = false;         // kbranch is in (group, lane, start) order with start in KBranch::pad
   std::vector<int32_t> klane;     // scheduled: per group kSchedLanes + 1 record offsets (group-relative)
+  int64_t ws_doubles = 0;         // global workspace for groups that exceed LDS
 };
 
 Status build_plan(const int32_t* parent, int64_t n, const int64_t* branch_offsets, int64_t nbranches,

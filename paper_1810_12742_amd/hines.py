@@ -42,7 +42,7 @@ class _Info(ctypes.Structure):
                 ("ngroups", ctypes.c_int64), ("nsegments", ctypes.c_int64), ("max_level", ctypes.c_int32),
                 ("nclasses", ctypes.c_int32), ("device_table_bytes", ctypes.c_int64),
                 ("max_group_lds_bytes", ctypes.c_int64), ("kernel", ctypes.c_int32),
-                ("max_makespan", ctypes.c_int32)]
+                ("max_makespan", ctypes.c_int32), ("workspace_groups", ctypes.c_int64)]
 
 
 def library_path() -> str:
@@ -70,7 +70,18 @@ def load():
     lib.hines_status_str.restype = ctypes.c_char_p
     lib.hines_last_error.argtypes = []
     lib.hines_last_error.restype = ctypes.c_char_p
-    for name in ("hines_setup", "hines_solve", "hines_plan_info_get", "hines_get_table", "hines_destroy"):
+    U32, D = ctypes.c_uint32, ctypes.c_double
+    lib.hines_timestep.argtypes = [P, P, P, P, P, P, P, D, U32, U32, I32, P]
+    lib.hines_timeloop_create.argtypes = [P, P, P, P, P, P, D, U32, U32, I32, I32, ctypes.POINTER(P)]
+    lib.hines_timeloop_launch.argtypes = [P, P]
+    lib.hines_timeloop_destroy.argtypes = [P]
+    lib.hines_assemble.argtypes = [P, P, P, P, P, P]
+    lib.hines_gather_roots.argtypes = [P, P, P, P]
+    lib.hines_adjoint_rhs.argtypes = [P, P, P, P, P, P]
+    lib.hines_adjoint_accumulate.argtypes = [P, P, P, P, P, P, P, P]
+    for name in ("hines_setup", "hines_solve", "hines_plan_info_get", "hines_get_table", "hines_destroy",
+                 "hines_timestep", "hines_timeloop_create", "hines_timeloop_launch", "hines_timeloop_destroy",
+                 "hines_assemble", "hines_gather_roots", "hines_adjoint_rhs", "hines_adjoint_accumulate"):
         getattr(lib, name).restype = I32
     _lib = lib
     return lib
@@ -170,3 +181,97 @@ class Plan:
                                   _dev(out, self.n, torch.float64, "out"), self.ncells,
                                   ctypes.c_void_p(st.cuda_stream)))
         return out
+
+    # ---- time loop (paper §1: one implicit-Euler system per step) ----------
+    def timestep(self, diag, upper, c, v_in, v_out=None, i_inj=None, noise_sigma=0.0, noise_seed=0, step=0,
+                 stream=None):
+        """v_out = A^-1 (c v_in + I) (``hines_timestep``); v_out may be v_in."""
+        import torch
+        if v_out is None:
+            v_out = torch.empty_like(v_in)
+        st = stream if stream is not None else torch.cuda.current_stream()
+        f64 = torch.float64
+        _check(load().hines_timestep(
+            self._h, _dev(diag, self.n, f64, "diag"), _dev(upper, self.n, f64, "upper"), _dev(c, self.n, f64, "c"),
+            _dev(v_in, self.n, f64, "v_in"), _dev(v_out, self.n, f64, "v_out"),
+            None if i_inj is None else _dev(i_inj, self.n, f64, "i_inj"), float(noise_sigma),
+            int(noise_seed) & 0xFFFFFFFF, int(step) & 0xFFFFFFFF, self.ncells, ctypes.c_void_p(st.cuda_stream)))
+        return v_out
+
+    def timeloop(self, diag, upper, c, v, nsteps, first_step=0, i_inj=None, noise_sigma=0.0, noise_seed=0):
+        """A captured graph of ``nsteps`` in-place steps of ``v`` (``hines_timeloop_create``)."""
+        import torch
+        f64 = torch.float64
+        h = ctypes.c_void_p()
+        keep = (diag, upper, c, v, i_inj)
+        _check(load().hines_timeloop_create(
+            self._h, _dev(diag, self.n, f64, "diag"), _dev(upper, self.n, f64, "upper"), _dev(c, self.n, f64, "c"),
+            _dev(v, self.n, f64, "v"), None if i_inj is None else _dev(i_inj, self.n, f64, "i_inj"),
+            float(noise_sigma), int(noise_seed) & 0xFFFFFFFF, int(first_step) & 0xFFFFFFFF, int(nsteps),
+            self.ncells, ctypes.byref(h)))
+        return TimeLoop(h, self, keep)
+
+    # ---- element-wise kernels of the adjoint ----------------------------------
+    def assemble(self, a, c, diag=None, upper=None, stream=None):
+        import torch
+        diag = torch.empty_like(c) if diag is None else diag
+        upper = torch.empty_like(c) if upper is None else upper
+        st = stream if stream is not None else torch.cuda.current_stream()
+        f64 = torch.float64
+        _check(load().hines_assemble(self._h, _dev(a, self.n, f64, "a"), _dev(c, self.n, f64, "c"),
+                                     _dev(diag, self.n, f64, "diag"), _dev(upper, self.n, f64, "upper"),
+                                     ctypes.c_void_p(st.cuda_stream)))
+        return diag, upper
+
+    def gather_roots(self, v, out=None, stream=None):
+        import torch
+        out = torch.empty(self.ncells, dtype=torch.float64, device=v.device) if out is None else out
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(load().hines_gather_roots(self._h, _dev(v, self.n, torch.float64, "v"),
+                                         _dev(out, self.ncells, torch.float64, "out"), ctypes.c_void_p(st.cuda_stream)))
+        return out
+
+    def adjoint_rhs(self, c, lam_next, g_roots, mu=None, stream=None):
+        import torch
+        mu = torch.empty_like(c) if mu is None else mu
+        st = stream if stream is not None else torch.cuda.current_stream()
+        f64 = torch.float64
+        _check(load().hines_adjoint_rhs(self._h, _dev(c, self.n, f64, "c"),
+                                        None if lam_next is None else _dev(lam_next, self.n, f64, "lam_next"),
+                                        _dev(g_roots, self.ncells, f64, "g_roots"), _dev(mu, self.n, f64, "mu"),
+                                        ctypes.c_void_p(st.cuda_stream)))
+        return mu
+
+    def adjoint_accumulate(self, lam, v, v_prev, grad_a, grad_c, grad_i, stream=None):
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        f64 = torch.float64
+        _check(load().hines_adjoint_accumulate(
+            self._h, _dev(lam, self.n, f64, "lam"), _dev(v, self.n, f64, "v"), _dev(v_prev, self.n, f64, "v_prev"),
+            _dev(grad_a, self.n, f64, "grad_a"), _dev(grad_c, self.n, f64, "grad_c"),
+            _dev(grad_i, self.n, f64, "grad_i"), ctypes.c_void_p(st.cuda_stream)))
+
+
+class TimeLoop:
+    """A captured multi-step graph (``hines_timeloop_*``)."""
+
+    def __init__(self, handle, plan, keep):
+        self._h = handle
+        self._plan = plan   # the plan must outlive the loop
+        self._keep = keep   # and so must the bound arrays
+
+    def launch(self, stream=None):
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(load().hines_timeloop_launch(self._h, ctypes.c_void_p(st.cuda_stream)))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _check(load().hines_timeloop_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

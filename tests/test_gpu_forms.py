@@ -1,0 +1,204 @@
+"""GPU parity of the time loop (in-kernel right-hand side, hipGraph capture,
+workspace path for cells too large for LDS) and of the adjoint, against the
+FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import configs, grow_random_forest, cable_values
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    return torch, torch.device("cuda")
+
+
+def cell_rel_err(f, x, xo):
+    err = np.maximum.reduceat(np.abs(x - xo), f.cell_offsets[:-1])
+    scale = np.maximum.reduceat(np.abs(xo), f.cell_offsets[:-1])
+    return float(np.max(err / np.maximum(scale, 1e-300)))
+
+
+def mixed_system():
+    """Cells of 50, 500, 5000 and 8000 compartments (the last exceed LDS)."""
+    rng = np.random.default_rng(12)
+    sizes = np.array([50, 500, 5000, 8000, 50, 500, 50, 8000, 5000, 50] * 3)
+    f = grow_random_forest(rng, len(sizes), target_size=sizes)
+    return cable_values(f, np.random.default_rng(13), a_kind="cable", dt=0.025, rhs=False)
+
+
+def test_plain_solve_with_workspace_groups(torch_dev):
+    torch, dev = torch_dev
+    from paper_1810_12742_amd import Plan
+    s = mixed_system()
+    f = s.forest
+    b = np.random.default_rng(1).standard_normal(f.n)
+    xo = oracle.solve(f, s.diag, s.upper, b)
+    for opts in (dict(), dict(level_sync=1), dict(bitwise=1), dict(rebalance_root=1, split_branches=1)):
+        p = Plan(f.parent, f.cell_offsets, f.branch_offsets, **opts)
+        assert p.info["workspace_groups"] >= 6
+        d = torch.from_numpy(s.diag).to(dev)
+        u = torch.from_numpy(s.upper).to(dev)
+        x = p.solve(d, u, torch.from_numpy(b).to(dev))
+        xg = x.cpu().numpy()
+        assert cell_rel_err(f, xg, xo) <= TOL, opts
+        if opts.get("bitwise"):
+            assert np.array_equal(xg, xo)
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(level_sync=1), dict(split_branches=1)])
+def test_timestep_noise_vs_oracle(torch_dev, opts):
+    torch, dev = torch_dev
+    from paper_1810_12742_amd import Plan
+    s = mixed_system()
+    f = s.forest
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets, **opts)
+    d = torch.from_numpy(s.diag).to(dev)
+    u = torch.from_numpy(s.upper).to(dev)
+    c = torch.from_numpy(s.c).to(dev)
+    V = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    steps = 4
+    for k in range(steps):
+        p.timestep(d, u, c, V, V, noise_sigma=0.1, noise_seed=3, step=k)
+    Vo = oracle.timeloop(f, s.diag, s.upper, s.c, steps, noise_seed=3, noise_sigma=0.1)
+    assert cell_rel_err(f, V.cpu().numpy(), Vo) <= TOL
+
+
+def test_timestep_constant_current_and_graph(torch_dev):
+    torch, dev = torch_dev
+    from paper_1810_12742_amd import Plan
+    s = mixed_system()
+    f = s.forest
+    I = 0.1 * np.random.default_rng(4).standard_normal(f.n)
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets)
+    d = torch.from_numpy(s.diag).to(dev)
+    u = torch.from_numpy(s.upper).to(dev)
+    c = torch.from_numpy(s.c).to(dev)
+    It = torch.from_numpy(I).to(dev)
+    steps = 6
+    # eager, out of place
+    Va = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    for k in range(steps):
+        Va = p.timestep(d, u, c, Va, i_inj=It, step=k)
+    Vo = oracle.timeloop(f, s.diag, s.upper, s.c, steps, I_const=I)
+    assert cell_rel_err(f, Va.cpu().numpy(), Vo) <= TOL
+    # captured graph, in place; replayed twice with eager work in between
+    Vg = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    loop = p.timeloop(d, u, c, Vg, steps, i_inj=It)
+    loop.launch()
+    torch.cuda.synchronize()
+    first = Vg.cpu().numpy().copy()
+    assert np.array_equal(first, Va.cpu().numpy())
+    _ = (d * 2).sum().item()
+    loop.launch()
+    torch.cuda.synchronize()
+    Vo2 = oracle.timeloop(f, s.diag, s.upper, s.c, steps, V0=Vo, I_const=I)
+    assert cell_rel_err(f, Vg.cpu().numpy(), Vo2) <= TOL
+    loop.close()
+
+
+def test_noise_graph_and_charge_conservation(torch_dev):
+    """Column sums of A equal c, so per cell sum c V^{k+1} = sum c V^k + sum I^k."""
+    torch, dev = torch_dev
+    from paper_1810_12742_amd import Plan
+    s = configs.c3(600)
+    f = s.forest
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets)
+    d = torch.from_numpy(s.diag).to(dev)
+    u = torch.from_numpy(s.upper).to(dev)
+    c = torch.from_numpy(s.c).to(dev)
+    V = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    steps = 5
+    loop = p.timeloop(d, u, c, V, steps, noise_sigma=0.1, noise_seed=3, first_step=0)
+    loop.launch()
+    torch.cuda.synchronize()
+    Vg = V.cpu().numpy()
+    cid = np.repeat(np.arange(f.ncells), np.diff(f.cell_offsets))
+    total_I = np.zeros(f.ncells)
+    idx = np.arange(f.n, dtype=np.int64)
+    for k in range(steps):
+        total_I += np.bincount(cid, weights=oracle.noise(3, k, idx, 0.1), minlength=f.ncells)
+    lhs = np.bincount(cid, weights=s.c * Vg, minlength=f.ncells)
+    scale = np.bincount(cid, weights=np.abs(s.c * Vg), minlength=f.ncells) + 1.0
+    assert np.max(np.abs(lhs - total_I) / scale) < 1e-11
+    # and a sample of cells against the oracle
+    sample = np.arange(0, f.ncells, 37)
+    sub = f.subset(sample)
+    lo = f.cell_offsets[sample]
+    hi = f.cell_offsets[sample + 1]
+    gidx = np.concatenate([np.arange(a, b) for a, b in zip(lo, hi)])
+    Vs = np.zeros(sub.n)
+    for k in range(steps):
+        Is = oracle.noise(3, k, gidx, 0.1)
+        Vs = oracle.solve(sub, s.diag[gidx], s.upper[gidx], s.c[gidx] * Vs + Is)
+    assert cell_rel_err(sub, Vg[gidx], Vs) <= TOL
+    loop.close()
+
+
+def test_adjoint_vs_oracle(torch_dev):
+    torch, dev = torch_dev
+    from paper_1810_12742_amd import Plan
+    from paper_1810_12742_amd.adjoint import soma_traces
+    s = configs.c5(48, size=300)
+    f = s.forest
+    steps, every = 23, 5
+    target = s.meta["target"]
+    I = s.meta["I"]
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets)
+    a_t = torch.from_numpy(s.a).to(dev).requires_grad_(True)
+    c_t = torch.from_numpy(s.c).to(dev).requires_grad_(True)
+    I_t = torch.from_numpy(I).to(dev).requires_grad_(True)
+    tr = soma_traces(p, a_t, c_t, I_t, steps, every)
+    loss = ((tr - torch.from_numpy(target).to(dev)) ** 2).sum()
+    loss.backward()
+    lo, ga, gc, gI, _ = oracle.adjoint(f, s.a, s.c, I, target, steps)
+    assert abs(loss.item() - lo) <= 1e-12 * abs(lo)
+    nr = f.parent >= 0
+
+    def rel(x, y):
+        return np.max(np.abs(x - y)) / np.max(np.abs(y))
+    assert rel(a_t.grad.cpu().numpy()[nr], ga[nr]) <= 1e-10
+    assert rel(c_t.grad.cpu().numpy(), gc) <= 1e-10
+    assert rel(I_t.grad.cpu().numpy(), gI) <= 1e-10
+    assert np.all(a_t.grad.cpu().numpy()[~nr] == 0)
+
+
+def test_adjoint_central_differences_on_device(torch_dev):
+    """Central differences (h = 1e-6) of one cell's loss term against the
+    adjoint gradient, for a few parameters."""
+    torch, dev = torch_dev
+    from paper_1810_12742_amd import Plan
+    from paper_1810_12742_amd.adjoint import soma_traces
+    s = configs.c5(6, size=120)
+    f = s.forest
+    steps = 12
+    target = torch.from_numpy(s.meta["target"]).to(dev)
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets)
+    base = {k: torch.from_numpy(v).to(dev) for k, v in (("a", s.a), ("c", s.c), ("I", s.meta["I"]))}
+
+    def loss(params):
+        tr = soma_traces(p, params["a"], params["c"], params["I"], steps, 4)
+        return ((tr - target) ** 2).sum()
+
+    params = {k: v.clone().requires_grad_(True) for k, v in base.items()}
+    loss(params).backward()
+    rng = np.random.default_rng(9)
+    h = 1e-6
+    for kind in ("a", "c", "I"):
+        for _ in range(3):
+            i = int(rng.integers(1, f.n))
+            if kind == "a" and f.parent[i] < 0:
+                continue
+            vals = []
+            for sgn in (1, -1):
+                pp = {k: v.clone() for k, v in base.items()}
+                pp[kind][i] += sgn * h
+                vals.append(loss(pp).item())
+            fd = (vals[0] - vals[1]) / (2 * h)
+            g = params[kind].grad[i].item()
+            assert abs(fd - g) <= 2e-5 * max(abs(g), 1e-2), (kind, i, fd, g)

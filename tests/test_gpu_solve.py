@@ -199,11 +199,22 @@ def test_error_paths(torch_dev):
     assert st == 12  # x aliases diag
     st = lib.hines_solve(p._h, None, P(u.data_ptr()), P(b.data_ptr()), P(b.data_ptr()), 2, None)
     assert st == 1
-    # a cell too large for one workgroup's LDS
+    # a cell whose compartments exceed LDS runs from the global workspace
     n = 8000
     par = np.arange(-1, n - 1, dtype=np.int32)
+    big = Plan(par, np.array([0, n]), None)
+    assert big.info["workspace_groups"] == 1
+    rng = np.random.default_rng(8)
+    dd = 2.0 + rng.random(n)
+    uu = -rng.random(n) * 0.9
+    bb = rng.standard_normal(n)
+    f1 = Forest(par, np.array([0, n]), np.array([0, n]))
+    xg = big.solve(torch.from_numpy(dd).to(dev), torch.from_numpy(uu).to(dev), torch.from_numpy(bb).to(dev))
+    assert cell_rel_err(f1, xg.cpu().numpy(), oracle.solve(f1, dd, uu, bb)) <= TOL
+    # a group whose branch tables alone exceed LDS is refused: a star of 6000 branches
+    par = np.concatenate([[-1], np.zeros(6000, dtype=np.int32)]).astype(np.int32)
     with pytest.raises(HinesError) as ei:
-        Plan(par, np.array([0, n]), None)
+        Plan(par, np.array([0, 6001]), None)
     assert ei.value.code == "TOO_BIG"
     # empty forest: nothing to do
     pe = Plan(np.zeros(0, dtype=np.int32), np.zeros(1, dtype=np.int64), None)
