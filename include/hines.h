@@ -133,6 +133,18 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
 hines_status hines_solve(const hines_plan* plan, const double* diag, const double* upper,
                          const double* rhs, double* x, int32_t ncells, void* stream);
 
+/* FP32 storage and elimination with FP64 refinement.  The matrix is the FP32
+ * one (diag32, upper32: device float arrays, user numbering), widened exactly
+ * where FP64 arithmetic is used; rhs and x are FP64.  Sweep 0 solves
+ * A x = fl32(rhs) in FP32; each further sweep (up to `sweeps`, at most 8)
+ * forms r = rhs - A x in FP64, solves A d = fl32(r) in FP32 and adds d to x
+ * in FP64.  The group's matrix, rhs and solution stay in LDS across sweeps,
+ * so HBM sees 24 bytes per compartment whatever the number of sweeps.
+ * HINES_ERR_TOO_BIG if a group does not fit this kernel's LDS image.
+ * x may alias rhs.  Async on stream. */
+hines_status hines_solve_mixed(const hines_plan* plan, const float* diag32, const float* upper32,
+                               const double* rhs, double* x, int32_t sweeps, int32_t ncells, void* stream);
+
 /* One implicit-Euler step of the discrete cable system (paper §1: the
  * current is evaluated at the old step):
  *     A v_out = c * v_in + I,   A given by (diag, upper),

@@ -79,6 +79,8 @@ struct hines_plan {
     int32_t lds_bytes, first, count, global;
   };
   std::vector<Bucket> buckets;
+  std::vector<Bucket> mixed_buckets;  // FP32+refinement kernel (its own LDS layout)
+  bool mixed_ok = false;              // every group fits the mixed layout in LDS
   int64_t max_lds = 0;
   // user-numbering tables of the element-wise kernels, uploaded on first use
   std::vector<int32_t> parent_host;
@@ -142,11 +144,31 @@ hipError_t launch_solve(const hines_plan* p, const RhsSpec& rs, const double* d,
   return hipSuccess;
 }
 
+hipError_t launch_mixed(const hines_plan* p, const float* d32, const float* u32, const double* b, double* x,
+                        int sweeps, hipStream_t s) {
+  for (const auto& bk : p->mixed_buckets) {
+    if (bk.count == 0) continue;
+    DevTables t = p->t;
+    t.glist = p->t.glist + bk.first;
+    switch (p->host.opt.group_width) {
+      case 64: hipLaunchKernelGGL(hdev::k_solve_mixed<64>, dim3(bk.count), dim3(64), bk.lds_bytes, s, t, d32, u32, b, x, sweeps); break;
+      case 128: hipLaunchKernelGGL(hdev::k_solve_mixed<128>, dim3(bk.count), dim3(128), bk.lds_bytes, s, t, d32, u32, b, x, sweeps); break;
+      case 256: hipLaunchKernelGGL(hdev::k_solve_mixed<256>, dim3(bk.count), dim3(256), bk.lds_bytes, s, t, d32, u32, b, x, sweeps); break;
+      case 512: hipLaunchKernelGGL(hdev::k_solve_mixed<512>, dim3(bk.count), dim3(512), bk.lds_bytes, s, t, d32, u32, b, x, sweeps); break;
+      default: hipLaunchKernelGGL(hdev::k_solve_mixed<1024>, dim3(bk.count), dim3(1024), bk.lds_bytes, s, t, d32, u32, b, x, sweeps); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 template <int T>
 hipError_t allow_lds_t() {
   const void* fns[] = {(const void*)hdev::k_solve_level<T, hdev::kModeFast, false>,
                        (const void*)hdev::k_solve_level<T, hdev::kModeBitwise, false>,
-                       (const void*)hdev::k_solve_level<T, hdev::kModeAscending, false>};
+                       (const void*)hdev::k_solve_level<T, hdev::kModeAscending, false>,
+                       (const void*)hdev::k_solve_mixed<T>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)hines::kLdsLimitBytes);
     if (e != hipSuccess) return e;
@@ -437,6 +459,25 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
     p->buckets.push_back({lds, (int32_t)glist.size(), (int32_t)m.size(), k == nbk ? 1 : 0});
     glist.insert(glist.end(), m.begin(), m.end());
   }
+  // buckets of the FP32+refinement kernel (its LDS image holds 32 bytes per slot)
+  {
+    std::vector<std::vector<int32_t>> mm(nbk);
+    p->mixed_ok = true;
+    for (int64_t g = 0; g < P.ngroups && p->mixed_ok; ++g) {
+      const int64_t bytes = hdev::mixed_layout(P.kgroup[g]).bytes();
+      int k = 0;
+      while (k < nbk && kBuckets[k] < bytes) ++k;
+      if (k == nbk) p->mixed_ok = false;
+      else mm[k].push_back((int32_t)g);
+    }
+    if (p->mixed_ok)
+      for (int k = 0; k < nbk; ++k) {
+        auto& m = mm[k];
+        std::stable_sort(m.begin(), m.end(), [&](int32_t a, int32_t b) { return P.kgroup[a].cost > P.kgroup[b].cost; });
+        p->mixed_buckets.push_back({kBuckets[k], (int32_t)glist.size(), (int32_t)m.size(), 0});
+        glist.insert(glist.end(), m.begin(), m.end());
+      }
+  }
   if (o.host_only) {
     *out = p;
     return ok();
@@ -452,7 +493,8 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   const int64_t sz_gl = al((int64_t)glist.size() * sizeof(int32_t));
   const int64_t sz_ln = al((int64_t)P.klane.size() * sizeof(int32_t));
   const int64_t sz_ws = al(P.ws_doubles * (int64_t)sizeof(double));
-  const int64_t total = sz_br + sz_grp + sz_seg + sz_cell + sz_gl + sz_ln + sz_ws + 256;
+  const int64_t sz_bl = al((int64_t)P.kbranch_level.size() * sizeof(KBranch));
+  const int64_t total = sz_br + sz_grp + sz_seg + sz_cell + sz_gl + sz_ln + sz_ws + sz_bl + 256;
   hipError_t e = hipGetDevice(&p->device);
   if (e == hipSuccess) e = allow_lds(o.group_width);
   if (e != hipSuccess) {
@@ -491,6 +533,12 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   if (e == hipSuccess && P.scheduled) e = up(P.klane.data(), (int64_t)P.klane.size() * sizeof(int32_t), off);
   off += sz_ln;
   p->t.ws = P.ws_doubles > 0 ? (double*)(base + off) : nullptr;
+  off += sz_ws;
+  p->t.br_level = p->t.br;
+  if (P.scheduled) {
+    p->t.br_level = (const KBranch*)(base + off);
+    if (e == hipSuccess) e = up(P.kbranch_level.data(), (int64_t)P.kbranch_level.size() * sizeof(KBranch), off);
+  }
   if (e != hipSuccess) {
     hipFree(p->dev_mem);
     delete p;
@@ -498,6 +546,7 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   }
   // the kernel tables now live on the device
   std::vector<KBranch>().swap(p->host.kbranch);
+  std::vector<KBranch>().swap(p->host.kbranch_level);
   *out = p;
   return ok();
 }
@@ -514,6 +563,21 @@ hines_status hines_solve(const hines_plan* p, const double* diag, const double* 
   rs.rhs = rhs;
   rs.mode = hdev::kRhsGiven;
   return run_solve(p, rs, diag, upper, x, stream);
+}
+
+hines_status hines_solve_mixed(const hines_plan* p, const float* diag32, const float* upper32, const double* rhs,
+                               double* x, int32_t sweeps, int32_t ncells, void* stream) {
+  hines_status st = check_call(p, ncells);
+  if (st != HINES_OK) return st;
+  if (sweeps < 0 || sweeps > 8) return set_err(HINES_ERR_OPTION, "sweeps must be in [0, 8]");
+  if (p->host.n == 0) return ok();
+  if (!diag32 || !upper32 || !rhs || !x) return set_err(HINES_ERR_NULL, "a device array is NULL");
+  if (!p->mixed_ok) return set_err(HINES_ERR_TOO_BIG, "a group does not fit the FP32+refinement LDS image");
+  if ((const void*)x == (const void*)diag32 || (const void*)x == (const void*)upper32)
+    return set_err(HINES_ERR_STATE, "x must not alias diag or upper");
+  hipError_t e = launch_mixed(p, diag32, upper32, rhs, x, sweeps, (hipStream_t)stream);
+  if (e != hipSuccess) return set_err(HINES_ERR_HIP, "launch: %s", hipGetErrorString(e));
+  return ok();
 }
 
 hines_status hines_timestep(const hines_plan* p, const double* diag, const double* upper, const double* c,

@@ -29,6 +29,7 @@ struct DevTables {
   const int32_t* glist;  // group ids of one launch
   const int32_t* lanes;  // scheduled plans: per group kSchedLanes + 1 record offsets
   double* ws;            // global images of groups that exceed LDS
+  const KBranch* br_level;  // records in level order (same as br unless scheduled)
 };
 
 // Right-hand side of a solve: given (kRhsGiven), c v + i (kRhsCV; i may be
@@ -670,6 +671,182 @@ __global__ __launch_bounds__(64) void k_solve_sched(DevTables tb, RhsSpec rs, co
   }
   __syncthreads();
   store_group<64>(tb, G, B, x, lane);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 storage with FP64 refinement.  The matrix is the FP32 one (diag32,
+// upper32), widened exactly where FP64 is used.  In LDS: d32, u32, f32 and a
+// FP32 work vector w (4 bytes each), the FP64 rhs b and solution x.
+//   sweep 0:  w = fl32(b); solve32(w); x = w
+//   sweep s:  r = b - A x (FP64); w = fl32(r); solve32(w); x += w
+// solve32 is the fast form of the sweeps in FP32 (level-synchronous).  The
+// residual pulls each branch's children's couplings u_c x_c through the
+// contribution slots, so every row is summed in a fixed order.
+// ---------------------------------------------------------------------------
+struct MixedLayout {
+  int32_t nimg, nbr_pad, nlev;
+  // floats d32, u32, f32, w at 0, nimg, 2 nimg, 3 nimg; doubles b, x after
+  constexpr int64_t b_off_bytes() const { return 16 * (int64_t)nimg; }
+  constexpr int64_t x_off_bytes() const { return 24 * (int64_t)nimg; }
+  constexpr int64_t c_off_bytes() const { return 32 * (int64_t)nimg; }  // 2 nbr_pad doubles
+  constexpr int64_t br_off_bytes() const { return c_off_bytes() + 16 * (int64_t)nbr_pad; }
+  constexpr int64_t tab_off_bytes() const { return br_off_bytes() + 16 * (int64_t)nbr_pad; }
+  constexpr int64_t bytes() const {
+    const int64_t ints = (int64_t)nlev + 1;
+    return (tab_off_bytes() + 4 * ints + 15) & ~(int64_t)15;
+  }
+};
+__host__ __device__ constexpr MixedLayout mixed_layout(const KGroup& g) {
+  return MixedLayout{g.nunk, (g.nbr + 1) & ~1, g.nlev};
+}
+
+template <int T>
+__device__ __forceinline__ void stage_mixed_range(const float* d32, const float* u32, const double* b, int64_t lo,
+                                                  int n, int slot, float* D, float* U, double* B, int tid) {
+  dma4<T>(d32 + lo, D + slot, n, tid);
+  dma4<T>(u32 + lo, U + slot, n, tid);
+  dma16<T>(b + lo, B + slot, n >> 1, tid);
+  if ((n & 1) && tid == 0) B[slot + n - 1] = b[lo + n - 1];
+}
+
+// One FP32 solve of A32 w' = w in place (generic branch direction).
+template <int T>
+__device__ __forceinline__ void solve32_level(const KBranch* BR, const int* seg, int brb, int nlev, const float* D,
+                                              const float* U, float* F, float* W, float* CD, float* CB, int tid) {
+  for (int l = nlev - 1; l >= 0; --l) {
+    for (int e = seg[l] - brb + tid; e < seg[l + 1] - brb; e += T) {
+      const KBranch br = BR[e];
+      const int dir = br.lendir > 0 ? 1 : -1;
+      const int len = br.lendir > 0 ? br.lendir : -br.lendir;
+      const int uoff = dir > 0 ? 0 : 1;
+      int i = br.start + dir * (len - 1);
+      float dl = D[i], bl = W[i];
+      for (int k = br.nchild - 1; k >= 0; --k) {
+        dl = dl - CD[br.child0 + k];
+        bl = bl - CB[br.child0 + k];
+      }
+      for (int j = len - 1; j >= 1; --j) {
+        const float uu = U[i + uoff];
+        const float r = __builtin_amdgcn_rcpf(dl);
+        const float f = uu * r;
+        F[i] = f;
+        W[i] = bl * r;
+        dl = __builtin_fmaf(-f, uu, D[i - dir]);
+        bl = __builtin_fmaf(-f, bl, W[i - dir]);
+        i -= dir;
+      }
+      const float r = __builtin_amdgcn_rcpf(dl);
+      if (br.u0 >= 0) {
+        const float uu = U[br.u0];
+        const float f = uu * r;
+        F[i] = f;
+        W[i] = bl * r;
+        CD[br.self] = f * uu;
+        CB[br.self] = f * bl;
+      } else {
+        W[i] = bl * r;
+      }
+    }
+    __syncthreads();
+  }
+  for (int l = 0; l < nlev; ++l) {
+    for (int e = seg[l] - brb + tid; e < seg[l + 1] - brb; e += T) {
+      const KBranch br = BR[e];
+      const int dir = br.lendir > 0 ? 1 : -1;
+      const int len = br.lendir > 0 ? br.lendir : -br.lendir;
+      int i = br.start;
+      float xp;
+      if (br.u0 >= 0) {
+        xp = __builtin_fmaf(-F[i], W[br.pslot], W[i]);
+        W[i] = xp;
+      } else {
+        xp = W[i];
+      }
+      for (int j = 1; j < len; ++j) {
+        i += dir;
+        xp = __builtin_fmaf(-F[i], xp, W[i]);
+        W[i] = xp;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// w = fl32(b - A x) over every compartment of the group.
+template <int T>
+__device__ __forceinline__ void residual_mixed(const KBranch* BR, int nbr, const float* D, const float* U,
+                                               const double* B, const double* X, float* W, double* C, int tid) {
+  for (int e = tid; e < nbr; e += T) {
+    const KBranch br = BR[e];
+    if (br.u0 >= 0) C[br.self] = (double)U[br.u0] * X[br.start];
+  }
+  __syncthreads();
+  for (int e = tid; e < nbr; e += T) {
+    const KBranch br = BR[e];
+    const int dir = br.lendir > 0 ? 1 : -1;
+    const int len = br.lendir > 0 ? br.lendir : -br.lendir;
+    const int uoff = dir > 0 ? 0 : 1;
+    int i = br.start;
+    for (int j = 0; j < len; ++j, i += dir) {
+      double r = B[i] - (double)D[i] * X[i];
+      if (j > 0)
+        r = r - (double)U[i + uoff] * X[i - dir];
+      else if (br.u0 >= 0)
+        r = r - (double)U[br.u0] * X[br.pslot];
+      if (j < len - 1) {
+        r = r - (double)U[i + dir + uoff] * X[i + dir];
+      } else {
+        for (int k = br.nchild - 1; k >= 0; --k) r = r - C[br.child0 + k];
+      }
+      W[i] = (float)r;
+    }
+  }
+  __syncthreads();
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_solve_mixed(DevTables tb, const float* __restrict__ d32,
+                                                   const float* __restrict__ u32, const double* b, double* x,
+                                                   int sweeps) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  const int g = tb.glist[blockIdx.x];
+  const KGroup G = tb.grp[g];
+  const MixedLayout L = mixed_layout(G);
+  float* D = (float*)lds_raw;
+  float* U = D + L.nimg;
+  float* F = D + 2 * (int64_t)L.nimg;
+  float* W = D + 3 * (int64_t)L.nimg;
+  double* B = (double*)(lds_raw + L.b_off_bytes());
+  double* X = (double*)(lds_raw + L.x_off_bytes());
+  double* C = (double*)(lds_raw + L.c_off_bytes());
+  float* CD = (float*)C;
+  float* CB = CD + L.nbr_pad;
+  const KBranch* BR = (const KBranch*)(lds_raw + L.br_off_bytes());
+  int* seg = (int*)(lds_raw + L.tab_off_bytes());
+  const int tid = threadIdx.x;
+
+  dma16<T>(tb.br_level + G.br_begin, lds_raw + L.br_off_bytes(), G.nbr, tid);
+  dma4<T>(tb.seg + G.seg_begin, seg, G.nlev + 1, tid);
+  if (G.contig) {
+    stage_mixed_range<T>(d32, u32, b, G.user_base, G.user_lo + G.user_n, kLdsPad, D, U, B, tid);
+  } else {
+    for (int c = 0; c < G.ncell; ++c) {
+      const KCell Cc = tb.cell[G.cell_begin + c];
+      stage_mixed_range<T>(d32, u32, b, Cc.user_lo, Cc.n, Cc.lds, D, U, B, tid);
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int k = tid; k < L.nimg; k += T) W[k] = (float)B[k];
+  __syncthreads();
+  const int brb = G.br_begin;
+  for (int s = 0; s <= sweeps; ++s) {
+    solve32_level<T>(BR, seg, brb, G.nlev, D, U, F, W, CD, CB, tid);
+    for (int k = tid; k < L.nimg; k += T) X[k] = (s == 0 ? 0.0 : X[k]) + (double)W[k];
+    __syncthreads();
+    if (s < sweeps) residual_mixed<T>(BR, G.nbr, D, U, B, X, W, C, tid);
+  }
+  store_group<T>(tb, G, X, x, tid);
 }
 
 // ---------------------------------------------------------------------------

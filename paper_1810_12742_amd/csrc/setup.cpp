@@ -693,6 +693,7 @@ struct Builder {
         std::copy(tmp.begin(), tmp.end(), sched.begin() + G.br_begin);
       }
       if (all_ok) {
+        P.kbranch_level.swap(P.kbranch);
         P.kbranch.swap(sched);
         P.scheduled = true;
       } else {

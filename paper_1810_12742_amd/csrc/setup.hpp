@@ -151,6 +151,7 @@ struct HostPlan {
   bool all_ascending = true;      // every branch runs toward higher user indices
   bool scheduled = false;         // kbranch is in (group, lane, start) order with start in KBranch::pad
   std::vector<int32_t> klane;     // scheduled: per group kSchedLanes + 1 record offsets (group-relative)
+  std::vector<KBranch> kbranch_level;  // scheduled: the records in level order (kbranch holds lane order)
   int64_t ws_doubles = 0;         // global workspace for groups that exceed LDS
 };
 

@@ -202,3 +202,37 @@ def test_adjoint_central_differences_on_device(torch_dev):
             fd = (vals[0] - vals[1]) / (2 * h)
             g = params[kind].grad[i].item()
             assert abs(fd - g) <= 2e-5 * max(abs(g), 1e-2), (kind, i, fd, g)
+
+
+@pytest.mark.parametrize("dt", [0.001, 0.025, 1.0])
+def test_mixed_precision_refinement(torch_dev, dt):
+    """FP32 storage + FP64 refinement converges to the FP64 solution of the
+    FP32-rounded matrix (the matrix the refinement can reach)."""
+    torch, dev = torch_dev
+    from paper_1810_12742_amd import Plan
+    s = configs.c4(dts=(dt,), ncells=768)[dt]
+    f = s.forest
+    d32 = s.diag.astype(np.float32)
+    u32 = s.upper.astype(np.float32)
+    xs = oracle.solve(f, d32.astype(np.float64), u32.astype(np.float64), s.rhs)
+    oracle_its = oracle.refine(f, d32, u32, s.rhs, sweeps=3)
+    errs = []
+    for opts in (dict(), dict(level_sync=1), dict(split_branches=1, max_group_unknowns=1024)):
+        p = Plan(f.parent, f.cell_offsets, f.branch_offsets, **opts)
+        D = torch.from_numpy(d32).to(dev)
+        U = torch.from_numpy(u32).to(dev)
+        B = torch.from_numpy(s.rhs).to(dev)
+        errs = []
+        for sweeps in range(4):
+            x = p.solve_mixed(D, U, B, sweeps=sweeps).cpu().numpy()
+            errs.append(cell_rel_err(f, x, xs))
+        assert errs[0] > 1e-10  # FP32 alone is far from FP64
+        assert errs[-1] <= 1e-11, (opts, errs)
+        assert errs[1] < errs[0]
+        # the oracle's own refinement converges the same way
+        oerr = [cell_rel_err(f, xi, xs) for xi in oracle_its]
+        assert oerr[-1] <= 1e-11
+        # in-place form (x aliases rhs)
+        B2 = B.clone()
+        p.solve_mixed(D, U, B2, out=B2, sweeps=3)
+        assert cell_rel_err(f, B2.cpu().numpy(), xs) <= 1e-11
