@@ -30,13 +30,21 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_UNKNOWN = 32  # read diag, upper, rhs; write x (FP64)
 # Launch configuration of the timed solve (setup options of the plan).
 C2_OPTIONS = dict(max_group_unknowns=1536, split_branches=0, cell_order=0, group_width=64)
+CALIB_BYTES = 512 << 20  # bytes read (and written) by one calibration copy
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hines_solve_c2.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1810_12742_amd", "csrc", "hines.hip")
+KERNEL_SRC_DIR = os.path.join(ROOT, "paper_1810_12742_amd", "csrc")
 
 
 def _kernel_sha() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()
+    """SHA-256 over the kernel and plan-builder sources (both decide the bytes
+    a launch moves)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(KERNEL_SRC_DIR)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(KERNEL_SRC_DIR, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
 
 
 def _traffic(n_launches_per_solve: int):
@@ -78,6 +86,9 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed region, run a plain device copy of 512 MiB (read and write) three "
+                         "times, the reference kernel for scaling HBM byte counters")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the per-cell solve has no cross-GPU step and the path is "
@@ -113,6 +124,15 @@ def main(argv=None):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
+
+    if args.copy_calibration:
+        src = torch.empty(CALIB_BYTES // 8, dtype=torch.float64, device=dev).uniform_()
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     err = None
     if not args.no_check:

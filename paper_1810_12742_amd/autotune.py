@@ -1,0 +1,103 @@
+"""Autotuner of the setup options (branch grouping) for one workload on one
+device.
+
+For each candidate option set it builds a plan (hines_setup), times the
+solve on the caller's data with HIP events, and keeps the fastest.  Results
+are cached in a JSON file keyed by a hash of the morphology (parent array,
+branch layout, cell offsets), the device name and the candidate list, so a
+simulation that sets up the same cells again reuses the choice.
+
+The candidates cover the knobs of paper §4-§6 that change the kernel tables:
+the cap on compartments per group (LDS image size, hence occupancy), branch
+splitting, cell order for packing, and the kernel (static lane schedule or
+level-synchronous sweeps).
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import numpy as np
+
+DEFAULT_CANDIDATES = [
+    dict(max_group_unknowns=mg, split_branches=sp, cell_order=co, level_sync=ls)
+    for mg in (1024, 1536, 2048, 3072)
+    for sp in (0, 1)
+    for co in (0, 1)
+    for ls in (0, 1)
+]
+
+CACHE = os.path.join(os.path.expanduser("~"), ".cache", "hines_mi355x_autotune.json")
+
+
+def _key(parent, cell_offsets, branch_offsets, device_name, candidates) -> str:
+    h = hashlib.sha256()
+    for a in (parent, cell_offsets, branch_offsets):
+        if a is not None:
+            h.update(np.ascontiguousarray(a).tobytes())
+    h.update(device_name.encode())
+    h.update(json.dumps(candidates, sort_keys=True).encode())
+    return h.hexdigest()
+
+
+def _time(plan, run, reps, torch):
+    for _ in range(2):
+        run(plan)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        run(plan)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def autotune(parent, cell_offsets, branch_offsets, run, *, candidates=None, reps=5, cache_path=CACHE,
+             use_cache=True, verbose=False):
+    """Pick the fastest option set.
+
+    ``run(plan)`` performs one timed unit of work with a plan (for example one
+    ``plan.solve`` on device arrays).  Returns ``(best_options, results)`` with
+    ``results`` a list of ``(options, ms)``; failing candidates (for example
+    groups that do not fit) are skipped."""
+    import torch
+    from .hines import HinesError, Plan
+
+    cands = candidates or DEFAULT_CANDIDATES
+    dev_name = torch.cuda.get_device_name(torch.cuda.current_device())
+    key = _key(parent, cell_offsets, branch_offsets, dev_name, cands)
+    store = {}
+    if use_cache and cache_path and os.path.exists(cache_path):
+        try:
+            with open(cache_path) as fh:
+                store = json.load(fh)
+        except (OSError, ValueError):
+            store = {}
+        if key in store:
+            hit = store[key]
+            return hit["best"], [(r[0], r[1]) for r in hit["results"]]
+    results = []
+    for opts in cands:
+        try:
+            plan = Plan(parent, cell_offsets, branch_offsets, **opts)
+        except HinesError:
+            continue
+        ms = _time(plan, run, reps, torch)
+        plan.close()
+        results.append((opts, ms))
+        if verbose:
+            print(f"autotune {opts}: {ms:.4f} ms", flush=True)
+    if not results:
+        raise RuntimeError("no candidate option set could be built")
+    best = min(results, key=lambda r: r[1])[0]
+    if cache_path:
+        store[key] = {"best": best, "results": [[o, ms] for o, ms in results], "device": dev_name}
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(store, fh)
+        os.replace(tmp, cache_path)
+    return best, results

@@ -236,3 +236,24 @@ def test_mixed_precision_refinement(torch_dev, dt):
         B2 = B.clone()
         p.solve_mixed(D, U, B2, out=B2, sweeps=3)
         assert cell_rel_err(f, B2.cpu().numpy(), xs) <= 1e-11
+
+
+def test_autotune_picks_a_measured_candidate(torch_dev, tmp_path):
+    torch, dev = torch_dev
+    from paper_1810_12742_amd.autotune import autotune
+    s = configs.c3(400)
+    f = s.forest
+    d = torch.from_numpy(s.diag).to(dev)
+    u = torch.from_numpy(s.upper).to(dev)
+    b = torch.from_numpy(np.random.default_rng(2).standard_normal(f.n)).to(dev)
+    x = torch.empty_like(b)
+    cands = [dict(max_group_unknowns=1024), dict(max_group_unknowns=2048, level_sync=1),
+             dict(split_branches=1, cell_order=1)]
+    cache = str(tmp_path / "tune.json")
+    best, res = autotune(f.parent, f.cell_offsets, f.branch_offsets, lambda p: p.solve(d, u, b, out=x),
+                         candidates=cands, reps=2, cache_path=cache)
+    assert len(res) == 3 and best in cands
+    assert min(res, key=lambda r: r[1])[0] == best
+    best2, _ = autotune(f.parent, f.cell_offsets, f.branch_offsets, lambda p: 1 / 0, candidates=cands,
+                        cache_path=cache)
+    assert best2 == best  # served from the cache, nothing re-timed
