@@ -1,11 +1,18 @@
-"""Benchmark of the batched FP64 Hines solve on one MI355X.
+"""Benchmark of the batched Hines solve on one MI355X.
 
-Workload: 65,536 synthetic neuron-shaped cells (random binary dendritic
-trees, 16-256 branches, geometric branch lengths of mean 12 capped at 64,
-about 1.06e8 compartments), cable-equation coefficients at dt = 0.025, one
-right-hand side; seed 1.  Inputs are resident in HBM before the timed region.
-A step is one hines_solve over all cells: every matrix entry is read from HBM
-once and the solution written once (32 algorithmic bytes per compartment).
+Default workload (the headline): 65,536 synthetic neuron-shaped cells (random
+binary dendritic trees, 16-256 branches, geometric branch lengths of mean 12
+capped at 64, about 1.06e8 compartments), cable-equation coefficients at
+dt = 0.025, one right-hand side; seed 1.  Inputs are resident in HBM before
+the timed region.  A step is one hines_solve over all cells: every matrix
+entry is read from HBM once and the solution written once (32 algorithmic
+bytes per compartment).  The same line carries the FP32-storage + FP64
+refinement form on the same cells at dt in {0.001, 0.025, 1.0}.
+
+Other workloads (``--workload``): ``c3`` the batched implicit-Euler time loop
+(200,000 cells of 50/500/5,000/20,000 compartments, noise current, K steps per
+captured graph), ``c5`` the adjoint (16,384 cells x 1,000 compartments, 100
+steps, checkpoints every 10).
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: the solve is per cell
 and needs no communication; this build measures one GPU.
@@ -33,6 +40,7 @@ C2_OPTIONS = dict(max_group_unknowns=1536, split_branches=0, cell_order=0, group
 CALIB_BYTES = 512 << 20  # bytes read (and written) by one calibration copy
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hines_solve_c2.json")
 KERNEL_SRC_DIR = os.path.join(ROOT, "paper_1810_12742_amd", "csrc")
+C4_DTS = (0.001, 0.025, 1.0)
 
 
 def _kernel_sha() -> str:
@@ -60,6 +68,29 @@ def _traffic(n_launches_per_solve: int):
     return t.get("bytes_per_launch")
 
 
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _time(torch, fn, steps, warmup, stream):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def cell_rel_err(f, x, xo):
+    e = np.maximum.reduceat(np.abs(x - xo), f.cell_offsets[:-1])
+    s = np.maximum.reduceat(np.abs(xo), f.cell_offsets[:-1])
+    return float(np.max(e / np.maximum(s, 1e-300)))
+
+
 def cpu_baseline(system, budget_s: float = 12.0):
     """The FP64 oracle on the host cores: repeated full solves of the same
     workload until about ``budget_s`` seconds of wall time have passed."""
@@ -79,28 +110,46 @@ def cpu_baseline(system, budget_s: float = 12.0):
             "sample": f"full workload ({f.n} unknowns), {reps} solves, {el:.1f} s, OpenMP over cells"}
 
 
-def main(argv=None):
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="after the timed region, run a plain device copy of 512 MiB (read and write) three "
-                         "times, the reference kernel for scaling HBM byte counters")
-    args = ap.parse_args(argv)
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU: the per-cell solve has no cross-GPU step and the path is "
-              f"built for a single MI355X (asked for --gpus {args.gpus})", file=sys.stderr)
-        return 2
+def fp32_refine(torch, dev, plan, s, fp64_ms, reps, check):
+    """FP32 storage + FP64 refinement on the same cells at each dt: errors
+    after 0..3 sweeps against the FP64 solution of the FP32-rounded matrix, and
+    throughput with 3 sweeps against the FP64 solve."""
+    import oracle
+    f = s.forest
+    out = {}
+    b = torch.from_numpy(s.rhs).to(dev)
+    x = torch.empty_like(b)
+    stream = torch.cuda.current_stream()
+    nonroot = f.parent >= 0
+    child_a = np.bincount(f.parent[nonroot], weights=s.a[nonroot], minlength=f.n)
+    for dt in C4_DTS:
+        c = s.meta["sigma_cm"] / dt
+        diag = c + np.where(nonroot, s.a, 0.0) + child_a
+        d32 = diag.astype(np.float32)
+        u32 = s.upper.astype(np.float32)
+        D = torch.from_numpy(d32).to(dev)
+        U = torch.from_numpy(u32).to(dev)
+        rec = {"dominance_ratio_median": float(np.median(diag / np.maximum(diag - c, 1e-300)))}
+        if check:
+            xs = oracle.solve(f, d32.astype(np.float64), u32.astype(np.float64), s.rhs)
+            errs = []
+            for sw in range(4):
+                plan.solve_mixed(D, U, b, out=x, sweeps=sw)
+                errs.append(cell_rel_err(f, x.cpu().numpy(), xs))
+            rec["err_after_sweeps"] = errs
+        ms = _time(torch, lambda: plan.solve_mixed(D, U, b, out=x, sweeps=3), reps, 2, stream)
+        rec["ms_3_sweeps"] = ms
+        rec["unknowns_per_s"] = f.n / (ms * 1e-3)
+        rec["speed_vs_fp64"] = fp64_ms / ms
+        out[str(dt)] = rec
+        del D, U
+    return out
 
-    import torch
+
+def run_c2(args, torch, dev):
     from workloads import configs
     from paper_1810_12742_amd import Plan
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     s = configs.c2()
     f = s.forest
     t0 = time.perf_counter()
@@ -112,18 +161,7 @@ def main(argv=None):
     b = torch.from_numpy(s.rhs).to(dev)
     x = torch.empty_like(b)
     stream = torch.cuda.current_stream()
-
-    for _ in range(args.warmup):
-        plan.solve(d, u, b, out=x, stream=stream)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.steps):
-        plan.solve(d, u, b, out=x, stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
+    ms = _time(torch, lambda: plan.solve(d, u, b, out=x, stream=stream), args.steps, args.warmup, stream)
 
     if args.copy_calibration:
         src = torch.empty(CALIB_BYTES // 8, dtype=torch.float64, device=dev).uniform_()
@@ -137,17 +175,12 @@ def main(argv=None):
     err = None
     if not args.no_check:
         import oracle
-        xo = oracle.solve(f, s.diag, s.upper, s.rhs)
-        xg = x.cpu().numpy()
-        e = np.maximum.reduceat(np.abs(xg - xo), f.cell_offsets[:-1])
-        sc = np.maximum.reduceat(np.abs(xo), f.cell_offsets[:-1])
-        err = float(np.max(e / sc))
+        err = cell_rel_err(f, x.cpu().numpy(), oracle.solve(f, s.diag, s.upper, s.rhs))
 
     n = f.n
     launches = max(1, int(info["nclasses"]))
     bytes_per_solve = BYTES_PER_UNKNOWN * n
     achieved = bytes_per_solve / (ms * 1e-3) / 1e9
-    traffic = _traffic(launches)
     out = {
         "metric": METRIC,
         "value": n / (ms * 1e-3),
@@ -173,17 +206,172 @@ def main(argv=None):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "kernel": "k_solve_sched_f64" if info["kernel"] == 1 else "k_solve_lds_f64",
+            "traffic": _traffic(launches),
+            "kernel": "k_solve_flow" if info["kernel"] == 1 else "k_solve_level",
             "bytes_per_launch": bytes_per_solve / launches,
             "avg_launch_us": ms * 1e3 / launches,
         },
         "max_rel_err_vs_oracle": err,
     }
+    if not args.no_forms:
+        del d, u
+        out["fp32_refine"] = fp32_refine(torch, dev, plan, s, ms, max(3, args.steps // 2), not args.no_check)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s)
-    print(json.dumps(out), flush=True)
     plan.close()
+    return out
+
+
+def run_c3(args, torch, dev):
+    """Batched time loop: V^{k+1} = A^-1 (c V^k + 0.1 Z_k), V^0 = 0, K steps in
+    one captured graph, grouping options picked by the autotuner on a sample
+    of the cells."""
+    from workloads import configs
+    from paper_1810_12742_amd import Plan
+    from paper_1810_12742_amd.autotune import autotune
+
+    ncells = args.cells or configs.C3_CELLS
+    # autotune on a 4,000-cell draw of the same recipe (same size mix)
+    smp = configs.c3(min(4000, ncells), seed=7)
+    fs = smp.forest
+    ds, us, cs = (torch.from_numpy(a).to(dev) for a in (smp.diag, smp.upper, smp.c))
+    vs = torch.zeros(fs.n, dtype=torch.float64, device=dev)
+    cands = [dict(max_group_unknowns=m, level_sync=l) for m in (1536, 3000) for l in (0, 1)]
+    best, tried = autotune(fs.parent, fs.cell_offsets, fs.branch_offsets,
+                           lambda p: p.timestep(ds, us, cs, vs, vs, noise_sigma=0.1, noise_seed=3),
+                           candidates=cands, reps=3, cache_path=None)
+    del ds, us, cs, vs
+
+    s = configs.c3(ncells)
+    f = s.forest
+    t0 = time.perf_counter()
+    plan = Plan(f.parent, f.cell_offsets, f.branch_offsets, **best)
+    setup_s = time.perf_counter() - t0
+    d, u, c = (torch.from_numpy(a).to(dev) for a in (s.diag, s.upper, s.c))
+    V = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    K = args.graph_steps
+    # step 0 alone: charge conservation over every cell (column sums of A are c)
+    plan.timestep(d, u, c, V, V, noise_sigma=0.1, noise_seed=3, step=0)
+    torch.cuda.synchronize()
+    check = None
+    if not args.no_check:
+        import oracle
+        cid = np.repeat(np.arange(f.ncells), np.diff(f.cell_offsets))
+        Vh = V.cpu().numpy()
+        inj = np.bincount(cid, weights=oracle.noise(3, 0, np.arange(f.n, dtype=np.int64), 0.1), minlength=f.ncells)
+        q = np.bincount(cid, weights=s.c * Vh, minlength=f.ncells)
+        scale = np.bincount(cid, weights=np.abs(s.c * Vh), minlength=f.ncells) + 1.0
+        check = float(np.max(np.abs(q - inj) / scale))
+    loop = plan.timeloop(d, u, c, V, K, first_step=1, noise_sigma=0.1, noise_seed=3)
+    stream = torch.cuda.current_stream()
+    ms = _time(torch, loop.launch, args.steps, args.warmup, stream)
+    n = f.n
+    bytes_per_step = 40 * n  # read d, u, c, V; write V
+    achieved = bytes_per_step * K / (ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": n * K / (ms * 1e-3), "unit": "unknown-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"c3: {f.ncells} cells of 50/500/5000/20000 compartments, implicit Euler with "
+                               f"noise current, {K} steps per captured graph (one graph launch per step here)",
+                   "ncells": f.ncells, "unknowns": n, "graph_steps": K, "options": best,
+                   "autotune_ms": [[o, round(t, 4)] for o, t in tried], "setup_s": round(setup_s, 2),
+                   "groups": plan.info["ngroups"], "workspace_groups": plan.info["workspace_groups"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "time step (flow/level)",
+                     "bytes_per_step": bytes_per_step},
+        "charge_conservation_max_rel_err_step0": check,
+    }
+    loop.close()
+    plan.close()
+    return out
+
+
+def run_c5(args, torch, dev):
+    """Adjoint of the soma-trace loss through 100 implicit-Euler steps."""
+    from workloads import configs
+    from paper_1810_12742_amd import Plan
+    from paper_1810_12742_amd.adjoint import soma_traces
+
+    s = configs.c5(args.cells or configs.C5_CELLS)
+    f = s.forest
+    steps = s.meta["steps"]
+    every = s.meta["checkpoint_every"]
+    plan = Plan(f.parent, f.cell_offsets, f.branch_offsets)
+    a = torch.from_numpy(s.a).to(dev).requires_grad_(True)
+    c = torch.from_numpy(s.c).to(dev).requires_grad_(True)
+    I = torch.from_numpy(s.meta["I"]).to(dev).requires_grad_(True)
+    target = torch.from_numpy(s.meta["target"]).to(dev)
+
+    def fwd():
+        return ((soma_traces(plan, a, c, I, steps, every) - target) ** 2).sum()
+
+    for _ in range(args.warmup):
+        fwd().backward()
+    torch.cuda.synchronize()
+    tf = tb = 0.0
+    for _ in range(args.steps):
+        a.grad = c.grad = I.grad = None
+        e0, e1 = _events(torch)
+        e2 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        loss = fwd()
+        e1.record()
+        loss.backward()
+        e2.record()
+        torch.cuda.synchronize()
+        tf += e0.elapsed_time(e1)
+        tb += e1.elapsed_time(e2)
+    tf /= args.steps
+    tb /= args.steps
+    err = None
+    if not args.no_check:
+        import oracle
+        lo, ga, gc, gI, _ = oracle.adjoint(f, s.a, s.c, s.meta["I"], s.meta["target"], steps)
+        nr = f.parent >= 0
+
+        def rel(x, y):
+            return float(np.max(np.abs(x - y)) / np.max(np.abs(y)))
+        err = {"loss": abs(loss.item() - lo) / abs(lo), "d_a": rel(a.grad.cpu().numpy()[nr], ga[nr]),
+               "d_c": rel(c.grad.cpu().numpy(), gc), "d_I": rel(I.grad.cpu().numpy(), gI)}
+    n = f.n
+    ms = tf + tb
+    return {
+        "metric": METRIC, "value": n * steps / (ms * 1e-3), "unit": "unknown-steps/s (forward + adjoint)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"c5: {f.ncells} cells x ~1000 compartments, {steps} implicit-Euler steps, "
+                               f"loss sum (V_soma - target)^2, checkpoints every {every}",
+                   "ncells": f.ncells, "unknowns": n, "forward_ms": tf, "backward_ms": tb},
+        "max_rel_err_vs_oracle_adjoint": err,
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=("c2", "c3", "c5"), default="c2")
+    ap.add_argument("--cells", type=int, default=0, help="c3/c5: number of cells (default: the full workload)")
+    ap.add_argument("--graph-steps", type=int, default=100, help="c3: time steps per captured graph")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="c2: skip the FP32+refinement measurement")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed region, run a plain device copy of 512 MiB (read and write) three "
+                         "times, the reference kernel for scaling HBM byte counters")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: the per-cell solve has no cross-GPU step and the path is "
+              f"built for a single MI355X (asked for --gpus {args.gpus})", file=sys.stderr)
+        return 2
+
+    import torch
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    run = {"c2": run_c2, "c3": run_c3, "c5": run_c5}[args.workload]
+    print(json.dumps(run(args, torch, dev)), flush=True)
     return 0
 
 

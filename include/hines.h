@@ -82,7 +82,7 @@ typedef struct hines_plan_info {
   int32_t nclasses;           /* LDS size classes (kernel launches per solve) */
   int64_t device_table_bytes; /* device memory held by the plan */
   int64_t max_group_lds_bytes;
-  int32_t kernel;             /* 0 level-synchronous, 1 scheduled, 2 level-synchronous bitwise */
+  int32_t kernel;             /* 0 level-synchronous, 1 flow (static step schedule), 2 bitwise */
   int32_t max_makespan;       /* scheduled plans: longest schedule, in iterations */
   int64_t workspace_groups;   /* groups too large for LDS, solved from a global workspace */
 } hines_plan_info;
@@ -101,7 +101,15 @@ enum {
   HINES_TABLE_GROUP_CELLS = 4,       /* [ncells] cells of the groups, packing order            */
   HINES_TABLE_GROUP_SEG_OFFSETS = 5, /* [ngroups+1] first (group, level) segment of each group */
   HINES_TABLE_SEG_OFFSETS = 6,       /* [nseg+1] first lane of each segment                    */
-  HINES_TABLE_LANES = 7              /* [nb] plan branch ids in (group, level, lane) order     */
+  HINES_TABLE_LANES = 7,             /* [nb] plan branch ids in (group, level, lane) order     */
+  /* Step schedule of the flow kernel (plans with flow, see hines_plan_info.kernel == 1): */
+  HINES_TABLE_FLOW_GROUPS = 8,       /* [ngroups*6] step_off, pos_off, aux_off, nsteps, nelem,
+                                        npush per group (nsteps 0: group solved elsewhere)  */
+  HINES_TABLE_FLOW_MASKS = 9,        /* [2*steps] per step: active-lane and push-lane masks
+                                        (64-bit patterns stored in int64)                    */
+  HINES_TABLE_FLOW_POS = 10,         /* [elements] LDS position of each element of a group's
+                                        staging order; 0x8000 marks a cell root              */
+  HINES_TABLE_FLOW_AUX = 11          /* [pushes] position receiving each push, step order     */
 };
 
 /* Fill *opt with the defaults: no re-rooting, no splitting, group_width 64,

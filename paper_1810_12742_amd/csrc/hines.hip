@@ -4,17 +4,21 @@
 // Design (paper §3-§5 re-thought for CDNA4):
 //  * one workgroup solves one packed group of cells (§3: all work of a matrix
 //    stays inside one block, so only block-level synchronisation is needed);
-//  * a group's compartments are contiguous user ranges: they are streamed
-//    from HBM into LDS by global->LDS DMA, eliminated there and the solution
-//    is streamed back, so every matrix entry crosses HBM once (the role of
-//    the paper's interleaved layout, §5, is played by LDS); groups too large
-//    for LDS run the same sweeps on a global workspace image;
-//  * one lane per branch (§3); the level-synchronous kernel sorts lanes by
-//    branch length inside a level (§4, Fig 4.1); plans whose branches all run
-//    toward higher user indices use a static per-lane schedule instead;
-//  * sibling branches never write the same parent compartment: each branch
-//    stores its elimination contribution in its own slot and the parent's
-//    lane pulls its children's slots in a fixed order (no atomics);
+//  * every matrix entry crosses HBM once: a group is staged into LDS,
+//    eliminated there and its solution written back (the role of the paper's
+//    interleaved layout, §5, is played by the LDS image); groups too large
+//    for LDS run the level-synchronous sweeps on a global workspace image;
+//  * fast path (flow kernel): one wave per group runs a static step schedule
+//    built by the setup: in each step every busy lane eliminates one
+//    compartment, heavy children hand their contribution to the parent in
+//    registers, light children add theirs into the parent's LDS entry, and
+//    the compartments of a step sit in consecutive LDS entries, so a step's
+//    LDS traffic is conflict-free and needs no per-lane bookkeeping;
+//  * level-synchronous path (§3, §4 Fig 4.1): one lane per branch, lanes of
+//    a level sorted by branch length, a barrier between levels; children
+//    store their contribution in their own slot and the parent pulls them in
+//    a fixed order (used for re-rooted plans, bitwise mode and workspace
+//    groups);
 //  * groups are bucketed by LDS footprint, one launch per bucket, so the
 //    occupancy follows the footprint; inside a launch the groups with the
 //    longest critical path come first.
@@ -77,6 +81,7 @@ struct hines_plan {
   DevTables t{};
   struct Bucket {
     int32_t lds_bytes, first, count, global;
+    int32_t level;  // 1: level-synchronous kernel for an LDS group of a flow plan
   };
   std::vector<Bucket> buckets;
   std::vector<Bucket> mixed_buckets;  // FP32+refinement kernel (its own LDS layout)
@@ -116,8 +121,15 @@ void launch_bucket(const hines_plan* p, const hines_plan::Bucket& bk, const RhsS
                    const double* u, double* x, hipStream_t s) {
   DevTables t = p->t;
   t.glist = p->t.glist + bk.first;
-  if (p->host.scheduled && !bk.global) {
-    hipLaunchKernelGGL(hdev::k_solve_sched, dim3(bk.count), dim3(64), bk.lds_bytes, s, t, rs, d, u, x);
+  if (p->host.flow && !bk.global && !bk.level) {
+    if (rs.mode == hdev::kRhsGiven)
+      hipLaunchKernelGGL(hdev::k_solve_flow<hdev::kFlowGiven>, dim3(bk.count), dim3(64), bk.lds_bytes, s, t, rs, d, u, x);
+    else if (rs.mode == hdev::kRhsNoise)
+      hipLaunchKernelGGL(hdev::k_solve_flow<hdev::kFlowNoise>, dim3(bk.count), dim3(64), bk.lds_bytes, s, t, rs, d, u, x);
+    else if (rs.icur)
+      hipLaunchKernelGGL(hdev::k_solve_flow<hdev::kFlowCVI>, dim3(bk.count), dim3(64), bk.lds_bytes, s, t, rs, d, u, x);
+    else
+      hipLaunchKernelGGL(hdev::k_solve_flow<hdev::kFlowCV>, dim3(bk.count), dim3(64), bk.lds_bytes, s, t, rs, d, u, x);
   } else if (p->host.opt.bitwise) {
     launch_level<T, hdev::kModeBitwise>(t, bk, rs, d, u, x, s);
   } else if (p->host.all_ascending) {
@@ -177,7 +189,10 @@ hipError_t allow_lds_t() {
 }
 
 hipError_t allow_lds(int T) {
-  const void* fns[] = {(const void*)hdev::k_solve_sched,
+  const void* fns[] = {(const void*)hdev::k_solve_flow<hdev::kFlowGiven>,
+                       (const void*)hdev::k_solve_flow<hdev::kFlowCV>,
+                       (const void*)hdev::k_solve_flow<hdev::kFlowCVI>,
+                       (const void*)hdev::k_solve_flow<hdev::kFlowNoise>,
                        (const void*)hdev::k_solve_level<kGlobalT, hdev::kModeFast, true>,
                        (const void*)hdev::k_solve_level<kGlobalT, hdev::kModeBitwise, true>,
                        (const void*)hdev::k_solve_level<kGlobalT, hdev::kModeAscending, true>};
@@ -267,52 +282,56 @@ bool check_kernel_tables(const hines::HostPlan& P, std::string& why, bool& capac
       }
     }
   }
-  if (P.scheduled) {
-    const int W = hines::kSchedLanes;
-    if ((int64_t)P.klane.size() != P.ngroups * (W + 1)) {
-      why = "lane table size";
+  if (P.flow) {
+    // every LDS index the flow kernel forms: positions R + rank < nelem,
+    // push ranks < naux, stored positions and push targets < nelem
+    if ((int64_t)P.kflow.size() != P.ngroups) {
+      why = "flow table size";
       return false;
     }
-    std::vector<int32_t> st, fin;
+    std::vector<uint8_t> seen;
     for (int64_t g = 0; g < P.ngroups; ++g) {
       const KGroup& G = P.kgroup[g];
+      const hines::KFlow& W = P.kflow[g];
       if (G.ws_off >= 0) continue;
-      const int32_t* lo = &P.klane[g * (W + 1)];
-      if (lo[0] != 0 || lo[W] != G.nbr || G.makespan <= 0 || G.makespan > 30000) {
-        why = "lane offsets";
+      if (W.nstep == 0 && W.nelem == 0 && W.naux == 0) continue;  // level kernel in LDS
+      if (W.nstep < 0 || (W.nstep & 3) || W.nstep > hines::kMaxSteps + 3 || W.nelem != G.user_n || W.naux < 0 ||
+          W.step_off < 0 || 2 * (W.step_off + W.nstep) > (int64_t)P.fmask.size() || W.pos_off < 0 ||
+          W.pos_off + W.nelem > (int64_t)P.fpos.size() || W.aux_off < 0 ||
+          W.aux_off + W.naux > (int64_t)P.faux.size() || hines::flow_lds_bytes(W) > hines::kLdsLimitBytes) {
+        why = "flow group record";
+        capacity = hines::flow_lds_bytes(W) > hines::kLdsLimitBytes;
         return false;
       }
-      st.assign(G.nbr, -1);
-      fin.assign(G.nbr, -1);
-      for (int ln = 0; ln < W; ++ln) {
-        if (lo[ln + 1] < lo[ln]) {
-          why = "lane offsets order";
+      int64_t act = 0, push = 0;
+      for (int32_t t = 0; t < W.nstep; ++t) {
+        const uint64_t M = P.fmask[2 * (W.step_off + t)], E = P.fmask[2 * (W.step_off + t) + 1];
+        if (E & ~M) {
+          why = "flow push outside the active lanes";
           return false;
         }
-        int32_t t = 0;
-        for (int32_t r = lo[ln]; r < lo[ln + 1]; ++r) {
-          const KBranch& B = P.kbranch[G.br_begin + r];
-          const int itl = std::max(1, (B.lendir - 1 + hines::kSchedChunk - 1) / hines::kSchedChunk);
-          if (B.pad < t || B.pad + itl > G.makespan || st[B.self] >= 0) {
-            why = "lane timeline";
-            return false;
-          }
-          st[B.self] = B.pad;
-          fin[B.self] = B.pad + itl;
-          t = B.pad + itl;
-        }
+        act += __builtin_popcountll(M);
+        push += __builtin_popcountll(E);
       }
-      for (int32_t r = 0; r < G.nbr; ++r) {
-        const KBranch& B = P.kbranch[G.br_begin + r];
-        if (st[B.self] < 0) {
-          why = "unscheduled branch";
+      if (act != W.nelem || push != W.naux) {
+        why = "flow mask counts";
+        return false;
+      }
+      seen.assign(W.nelem, 0);
+      for (int32_t e = 0; e < W.nelem; ++e) {
+        const int32_t q = P.fpos[W.pos_off + e] & 0x7fff;
+        if (q >= W.nelem || seen[q]) {
+          why = "flow positions";
           return false;
         }
-        for (int c = B.child0; c < B.child0 + B.nchild; ++c)
-          if (fin[c] > st[B.self]) {
-            why = "schedule order";
-            return false;
-          }
+        seen[q] = 1;
+      }
+      for (int32_t k = 0; k < W.naux; ++k) {
+        const int32_t q = P.faux[W.aux_off + k];
+        if (q < 0 || q >= W.nelem) {
+          why = "flow push target";
+          return false;
+        }
       }
     }
   }
@@ -433,30 +452,37 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
     return set_err(capacity ? HINES_ERR_TOO_BIG : HINES_ERR_STATE, "kernel tables: %s", why.c_str());
   }
   const hines::HostPlan& P = p->host;
-  // buckets by LDS footprint; groups whose image lives in the workspace form their own bucket
+  // buckets by LDS footprint and kernel: flow groups, level-synchronous LDS
+  // groups (plans without a flow schedule, or groups whose schedule does not
+  // fit LDS), and groups whose image lives in the workspace
   const int nbk = (int)(sizeof kBuckets / sizeof kBuckets[0]);
-  std::vector<std::vector<int32_t>> members(nbk + 1);
+  std::vector<std::vector<int32_t>> members(2 * nbk + 1);
   int64_t global_lds = 0;
   for (int64_t g = 0; g < P.ngroups; ++g) {
     const KGroup& G = P.kgroup[g];
-    const int64_t bytes = layout_of(G).bytes();
-    p->max_lds = std::max(p->max_lds, bytes);
     if (G.ws_off >= 0) {
-      members[nbk].push_back((int32_t)g);
+      const int64_t bytes = layout_of(G).bytes();
+      p->max_lds = std::max(p->max_lds, bytes);
+      members[2 * nbk].push_back((int32_t)g);
       global_lds = std::max(global_lds, bytes);
       continue;
     }
+    const bool fl = P.flow && P.kflow[g].nstep > 0;
+    const int64_t bytes = fl ? hines::flow_lds_bytes(P.kflow[g]) : layout_of(G).bytes();
+    p->max_lds = std::max(p->max_lds, bytes);
     int k = 0;
     while (k < nbk && kBuckets[k] < bytes) ++k;
     if (k == nbk) k = nbk - 1;  // host_only plans only; checked above otherwise
-    members[k].push_back((int32_t)g);
+    members[(fl ? 0 : nbk) + k].push_back((int32_t)g);
   }
   std::vector<int32_t> glist;
-  for (int k = 0; k <= nbk; ++k) {
+  for (int k = 0; k <= 2 * nbk; ++k) {
     auto& m = members[k];
+    if (m.empty()) continue;
     std::stable_sort(m.begin(), m.end(), [&](int32_t a, int32_t b) { return P.kgroup[a].cost > P.kgroup[b].cost; });
-    const int32_t lds = k < nbk ? kBuckets[k] : (int32_t)((global_lds + 255) & ~(int64_t)255);
-    p->buckets.push_back({lds, (int32_t)glist.size(), (int32_t)m.size(), k == nbk ? 1 : 0});
+    const bool glob = k == 2 * nbk;
+    const int32_t lds = glob ? (int32_t)((global_lds + 255) & ~(int64_t)255) : kBuckets[k % nbk];
+    p->buckets.push_back({lds, (int32_t)glist.size(), (int32_t)m.size(), glob ? 1 : 0, (!glob && k >= nbk) ? 1 : 0});
     glist.insert(glist.end(), m.begin(), m.end());
   }
   // buckets of the FP32+refinement kernel (its LDS image holds 32 bytes per slot)
@@ -474,7 +500,7 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
       for (int k = 0; k < nbk; ++k) {
         auto& m = mm[k];
         std::stable_sort(m.begin(), m.end(), [&](int32_t a, int32_t b) { return P.kgroup[a].cost > P.kgroup[b].cost; });
-        p->mixed_buckets.push_back({kBuckets[k], (int32_t)glist.size(), (int32_t)m.size(), 0});
+        p->mixed_buckets.push_back({kBuckets[k], (int32_t)glist.size(), (int32_t)m.size(), 0, 0});
         glist.insert(glist.end(), m.begin(), m.end());
       }
   }
@@ -491,10 +517,12 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   const int64_t sz_seg = al((int64_t)P.kseg.size() * sizeof(int32_t));
   const int64_t sz_cell = al((int64_t)P.kcell.size() * sizeof(KCell));
   const int64_t sz_gl = al((int64_t)glist.size() * sizeof(int32_t));
-  const int64_t sz_ln = al((int64_t)P.klane.size() * sizeof(int32_t));
   const int64_t sz_ws = al(P.ws_doubles * (int64_t)sizeof(double));
-  const int64_t sz_bl = al((int64_t)P.kbranch_level.size() * sizeof(KBranch));
-  const int64_t total = sz_br + sz_grp + sz_seg + sz_cell + sz_gl + sz_ln + sz_ws + sz_bl + 256;
+  const int64_t sz_fl = al((int64_t)P.kflow.size() * sizeof(hines::KFlow));
+  const int64_t sz_fm = al((int64_t)P.fmask.size() * sizeof(uint64_t));
+  const int64_t sz_fp = al((int64_t)P.fpos.size() * sizeof(uint16_t));
+  const int64_t sz_fa = al((int64_t)P.faux.size() * sizeof(int16_t));
+  const int64_t total = sz_br + sz_grp + sz_seg + sz_cell + sz_gl + sz_ws + sz_fl + sz_fm + sz_fp + sz_fa + 256;
   hipError_t e = hipGetDevice(&p->device);
   if (e == hipSuccess) e = allow_lds(o.group_width);
   if (e != hipSuccess) {
@@ -529,16 +557,20 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   p->t.glist = (const int32_t*)(base + off);
   if (e == hipSuccess) e = up(glist.data(), (int64_t)glist.size() * sizeof(int32_t), off);
   off += sz_gl;
-  p->t.lanes = P.scheduled ? (const int32_t*)(base + off) : nullptr;
-  if (e == hipSuccess && P.scheduled) e = up(P.klane.data(), (int64_t)P.klane.size() * sizeof(int32_t), off);
-  off += sz_ln;
   p->t.ws = P.ws_doubles > 0 ? (double*)(base + off) : nullptr;
   off += sz_ws;
-  p->t.br_level = p->t.br;
-  if (P.scheduled) {
-    p->t.br_level = (const KBranch*)(base + off);
-    if (e == hipSuccess) e = up(P.kbranch_level.data(), (int64_t)P.kbranch_level.size() * sizeof(KBranch), off);
-  }
+  p->t.flow = (const hines::KFlow*)(base + off);
+  if (e == hipSuccess) e = up(P.kflow.data(), (int64_t)P.kflow.size() * sizeof(hines::KFlow), off);
+  off += sz_fl;
+  p->t.fmask = (const uint64_t*)(base + off);
+  if (e == hipSuccess) e = up(P.fmask.data(), (int64_t)P.fmask.size() * sizeof(uint64_t), off);
+  off += sz_fm;
+  p->t.fpos = (const uint16_t*)(base + off);
+  if (e == hipSuccess) e = up(P.fpos.data(), (int64_t)P.fpos.size() * sizeof(uint16_t), off);
+  off += sz_fp;
+  p->t.faux = (const int16_t*)(base + off);
+  if (e == hipSuccess) e = up(P.faux.data(), (int64_t)P.faux.size() * sizeof(int16_t), off);
+  off += sz_fa;
   if (e != hipSuccess) {
     hipFree(p->dev_mem);
     delete p;
@@ -546,7 +578,11 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   }
   // the kernel tables now live on the device
   std::vector<KBranch>().swap(p->host.kbranch);
-  std::vector<KBranch>().swap(p->host.kbranch_level);
+  if (!o.keep_tables) {
+    std::vector<uint64_t>().swap(p->host.fmask);
+    std::vector<uint16_t>().swap(p->host.fpos);
+    std::vector<int16_t>().swap(p->host.faux);
+  }
   *out = p;
   return ok();
 }
@@ -737,11 +773,11 @@ hines_status hines_plan_info_get(const hines_plan* p, hines_plan_info* info) {
   info->nclasses = nb;
   info->device_table_bytes = p->dev_bytes;
   info->max_group_lds_bytes = p->max_lds;
-  info->kernel = p->host.scheduled ? 1 : (p->host.opt.bitwise ? 2 : 0);
+  info->kernel = p->host.flow ? 1 : (p->host.opt.bitwise ? 2 : 0);
   int32_t mk = 0;
   int64_t ng_ws = 0;
   for (const auto& G : p->host.kgroup) {
-    if (p->host.scheduled && G.ws_off < 0) mk = std::max(mk, G.makespan);
+    if (p->host.flow && G.ws_off < 0) mk = std::max(mk, G.makespan);
     ng_ws += G.ws_off >= 0;
   }
   info->max_makespan = mk;

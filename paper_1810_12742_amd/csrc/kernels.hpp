@@ -22,14 +22,16 @@ using hines::kLdsPad;
 using hines::LdsLayout;
 
 struct DevTables {
-  const KBranch* br;     // per group: level order, or (lane, start) order when scheduled
+  const KBranch* br;     // per group, level order
   const KGroup* grp;
   const int32_t* seg;    // first record of each (group, level) segment
   const KCell* cell;     // group order
   const int32_t* glist;  // group ids of one launch
-  const int32_t* lanes;  // scheduled plans: per group kSchedLanes + 1 record offsets
   double* ws;            // global images of groups that exceed LDS
-  const KBranch* br_level;  // records in level order (same as br unless scheduled)
+  const hines::KFlow* flow;  // flow kernel: per group
+  const uint64_t* fmask;     // flow kernel: active and push masks per step
+  const uint16_t* fpos;      // flow kernel: position of every element
+  const int16_t* faux;       // flow kernel: parent position of every push
 };
 
 // Right-hand side of a solve: given (kRhsGiven), c v + i (kRhsCV; i may be
@@ -143,13 +145,9 @@ __device__ __forceinline__ void stage_range(const RhsSpec& rs, const double* d, 
 template <int T, bool GLOBAL>
 __device__ __forceinline__ void stage_group(const DevTables& tb, const KGroup& G, const LdsLayout& L,
                                             const RhsSpec& rs, const double* d, const double* u, double* D,
-                                            double* U, double* B, char* lds, int tid,
-                                            const int32_t* lane_table) {
+                                            double* U, double* B, char* lds, int tid) {
   dma16<T>(tb.br + G.br_begin, lds + L.br_off_bytes(), G.nbr, tid);
-  if (lane_table)
-    dma4<T>(lane_table, lds + L.tab_off_bytes(), hines::kSchedLanes + 1, tid);
-  else
-    dma4<T>(tb.seg + G.seg_begin, lds + L.tab_off_bytes(), G.nlev + 1, tid);
+  dma4<T>(tb.seg + G.seg_begin, lds + L.tab_off_bytes(), G.nlev + 1, tid);
   if (G.contig) {
     // slots kLdsPad + [0, user_lo + user_n) <-> user [user_base, ...)
     stage_range<T, GLOBAL>(rs, d, u, G.user_base, G.user_lo + G.user_n, kLdsPad, D, U, B, tid);
@@ -202,7 +200,7 @@ __device__ __forceinline__ double rcp_nr(double d) {
   return __builtin_fma(r, t, r);
 }
 
-constexpr int kChunk = hines::kSchedChunk;  // compartments held in registers per LDS round trip
+constexpr int kChunk = 8;  // compartments held in registers per LDS round trip
 
 // ---------------------------------------------------------------------------
 // Sweeps of one branch (paper §2 Listing 2, §3).  Branch compartments p_0 (root
@@ -514,7 +512,7 @@ __global__ __launch_bounds__(T) void k_solve_level(DevTables tb, RhsSpec rs, con
   const int tid = threadIdx.x;
   const int brb = G.br_begin;
 
-  stage_group<T, GLOBAL>(tb, G, L, rs, d, u, D, U, B, lds_raw, tid, nullptr);
+  stage_group<T, GLOBAL>(tb, G, L, rs, d, u, D, U, B, lds_raw, tid);
 
   int s1 = seg[G.nlev] - brb;
   int s0 = seg[G.nlev - 1] - brb;
@@ -557,120 +555,251 @@ __global__ __launch_bounds__(T) void k_solve_level(DevTables tb, RhsSpec rs, con
 }
 
 // ---------------------------------------------------------------------------
-// Scheduled solve (ascending branches, fast form, image in LDS).  One wave
-// per group; lane t runs the branches the setup assigned to it, each from its
-// scheduled iteration on; in one iteration a lane eliminates up to kChunk
-// compartments of its current branch.  A branch starts only after every child
-// branch finished in an earlier iteration, so the children's contributions
-// are in LDS.  The forward sweep replays the schedule backwards in time: a
-// branch's parent compartment is solved in a later backward iteration, hence
-// in an earlier forward one.  The group is one wave and the LDS executes a
-// wave's operations in order, so no barrier is needed between iterations; the
-// signal fence keeps the compiler from moving LDS accesses across iterations.
+// Flow solve (ascending branches whose children hang off their far end, fast
+// form, image in LDS).  One wave per group runs the group's static step
+// schedule: at step t, lane l eliminates one compartment, stored at position
+// R[t] + (active lanes below l), so the lanes of a step touch consecutive
+// LDS entries.  Per position the image holds d, u, b (24 bytes); the
+// backward sweep overwrites d with f = u / d' and b with y = b' / d', the
+// forward sweep overwrites y with x.
+//
+// Contributions to a parent (paper §2: d_p -= u_i^2 / d'_i, b_p -= u_i b'_i / d'_i)
+// travel in two ways.  Inside a branch, and from the heavy child into its
+// parent (same lane, next step), the pair (f, b') stays in registers.  A
+// light child adds its contribution to the parent's LDS entry (ds_add_f64)
+// at its last step, at least two steps before the parent's first one.  The
+// group is one wave and the LDS executes a wave's operations in order, so
+// every read sees the additions issued in earlier steps.  The forward sweep
+// replays the steps backwards: x of the parent is in registers (heavy child)
+// or in LDS, written in an earlier forward step (light child).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int sched_itlen(int len) {
-  const int k = (len - 1 + kChunk - 1) / kChunk;
-  return k > 1 ? k : 1;
+using hines::flow_lds_bytes;
+using hines::flow_mask_offset;
+
+__device__ __forceinline__ int tri(int p) { return (int)__umul24((unsigned)p, 3u); }  // 3 p, p < 2^24
+__device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+__device__ __forceinline__ int rank_in(uint64_t m, int base) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)base));
+}
+typedef __attribute__((address_space(3))) double lds_f64;
+typedef __attribute__((address_space(3))) int16_t lds_i16;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) u32x4 lds_u4;
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+
+__device__ __forceinline__ void lds_add(lds_f64* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__global__ __launch_bounds__(64) void k_solve_sched(DevTables tb, RhsSpec rs, const double* __restrict__ d,
-                                                    const double* __restrict__ u, double* x) {
-  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+// Right-hand side forms of the flow kernel, fixed at compile time: given,
+// c v, c v + i, c v + sigma Z.
+enum : int { kFlowGiven = 0, kFlowCV = 1, kFlowCVI = 2, kFlowNoise = 3 };
+
+// Element e of a user range (user index lo + e) -> its position.  A lane
+// handles elements lane, lane + 64, ...; the loads of kStageUnroll of them are
+// issued before any is used.  Indices past the range are clamped to its last
+// element, so every load is unconditional (the repeated element is written
+// twice with the same value).
+constexpr int kStageUnroll = 16;
+
+template <int RHS>
+__device__ __forceinline__ void flow_stage_range(const RhsSpec& rs, const double* __restrict__ d,
+                                                 const double* __restrict__ u, int64_t lo, int n,
+                                                 const uint16_t* __restrict__ pos, lds_f64* img, int lane) {
+  for (int e0 = 0; e0 < n; e0 += 64 * kStageUnroll) {
+    uint32_t pw[kStageUnroll];
+    double dv[kStageUnroll], uv[kStageUnroll], bv[kStageUnroll], cv[kStageUnroll], iv[kStageUnroll];
+#pragma unroll
+    for (int k = 0; k < kStageUnroll; ++k) {
+      const int e = min(e0 + 64 * k + lane, n - 1);
+      pw[k] = pos[e];
+      dv[k] = d[lo + e];
+      uv[k] = u[lo + e];
+      if constexpr (RHS == kFlowGiven) {
+        bv[k] = rs.rhs[lo + e];
+      } else {
+        cv[k] = rs.c[lo + e];
+        bv[k] = rs.v[lo + e];
+        if constexpr (RHS == kFlowCVI) iv[k] = rs.icur[lo + e];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kStageUnroll; ++k) {
+      const int e = min(e0 + 64 * k + lane, n - 1);
+      double b = bv[k];
+      if constexpr (RHS != kFlowGiven) b = cv[k] * bv[k];
+      if constexpr (RHS == kFlowCVI) b = b + iv[k];
+      if constexpr (RHS == kFlowNoise) b = b + noise_draw(rs.seed, rs.step, (uint64_t)(lo + e), rs.sigma);
+      lds_f64* q = img + tri((int)(pw[k] & 0x7fffu));
+      q[0] = dv[k];
+      q[1] = (pw[k] & 0x8000u) ? 0.0 : uv[k];
+      q[2] = b;
+    }
+  }
+}
+
+__device__ __forceinline__ void flow_store_range(double* x, int64_t lo, int n, const uint16_t* __restrict__ pos,
+                                                 const lds_f64* img, int lane) {
+  for (int e0 = 0; e0 < n; e0 += 64 * kStageUnroll) {
+    uint32_t pw[kStageUnroll];
+#pragma unroll
+    for (int k = 0; k < kStageUnroll; ++k) pw[k] = pos[min(e0 + 64 * k + lane, n - 1)];
+#pragma unroll
+    for (int k = 0; k < kStageUnroll; ++k) {
+      const int e = e0 + 64 * k + lane;
+      if (e < n) x[lo + e] = img[tri((int)(pw[k] & 0x7fffu)) + 2];
+    }
+  }
+}
+
+// Step masks: staged into LDS with the group (16 bytes per step: active and
+// push masks); a step's masks are read one step ahead with a broadcast LDS
+// read and moved to scalar registers.
+__device__ __forceinline__ uint64_t first_u64(uint32_t lo, uint32_t hi) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)hi) << 32) |
+         (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)lo);
+}
+
+// Both sweeps run the same straight-line code for every lane in every step:
+// a lane that is idle in a step reads the constant entry `nelem` (d = 1, u = 0,
+// b = 0, which eliminates to zeros) and writes and pushes into its own sink
+// entry nelem + 1 + lane, which is never read.  Without branches the number
+// of LDS operations per step is fixed, so the wait at the top of a step covers
+// only the reads issued one step earlier.
+template <int RHS>
+__global__ __launch_bounds__(64) void k_solve_flow(DevTables tb, RhsSpec rs, const double* __restrict__ d,
+                                                   const double* __restrict__ u, double* x) {
+  extern __shared__ __attribute__((aligned(16))) double img_raw[];
+  lds_f64* img = (lds_f64*)img_raw;
   const int g = tb.glist[blockIdx.x];
   const KGroup G = tb.grp[g];
-  const LdsLayout L{G.nunk, (G.nbr + 1) & ~1, G.nlev};
-  double* D = (double*)lds_raw;
-  double* U = D + L.u_off();
-  double* B = D + L.b_off();
-  double* CD = D + L.cd_off();
-  double* CB = D + L.cb_off();
-  const KBranch* BR = (const KBranch*)(lds_raw + L.br_off_bytes());
-  const int* LO = (const int*)(lds_raw + L.tab_off_bytes());
+  const hines::KFlow W = tb.flow[g];
   const int lane = threadIdx.x;
-
-  stage_group<64, false>(tb, G, L, rs, d, u, D, U, B, lds_raw, lane,
-                         tb.lanes + (int64_t)g * (hines::kSchedLanes + 1));
-
-  const int q0 = LO[lane], q1 = LO[lane + 1];
-  const int F = G.makespan;
-  {
-    int q = q0, js = 0x7fffffff, i = 0, rem = -1;
-    KBranch rec{};
-    if (q < q1) {
-      rec = BR[q];
-      js = rec.pad;
-    }
-    double dl = 0.0, bl = 0.0;
-    for (int it = 0; it < F; ++it) {
-      if (q < q1 && it >= js) {
-        if (it == js) {
-          i = rec.start + rec.lendir - 1;
-          dl = D[i];
-          bl = B[i];
-          for (int k = rec.nchild - 1; k >= 0; --k) {
-            dl = dl - CD[rec.child0 + k];
-            bl = bl - CB[rec.child0 + k];
-          }
-          rem = rec.lendir - 1;
-        }
-        if (rem > 0) {
-          const int n = rem < kChunk ? rem : kChunk;
-          backward_chunk_asc(i, n, dl, bl, D, U, B);
-          rem -= n;
-        }
-        if (rem == 0) {
-          finish_backward(rec, i, dl, bl, D, U, B, CD, CB);
-          ++q;
-          rem = -1;
-          if (q < q1) {
-            rec = BR[q];
-            js = rec.pad;
-          }
-        }
-      }
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  const uint16_t* pos = tb.fpos + W.pos_off;
+  const int F = W.nstep;
+  const int idle = W.nelem, sink = W.nelem + 1 + lane;
+  lds_i16* aux = (lds_i16*)(img + tri(W.nelem + 1 + 64));
+  // masks of steps 0 .. F-1, then one zero record on each side (steps -1 and F)
+  lds_u4* msk = (lds_u4*)((lds_u8*)img + flow_mask_offset(W)) + 1;
+  // masks and push targets by global->LDS DMA (16- and 4-byte units; the push
+  // targets of a group start 4-byte aligned and the table is padded)
+  dma16<64>(tb.fmask + 2 * W.step_off, (void*)(msk), F, lane);
+  dma4<64>(tb.faux + W.aux_off, (void*)aux, (W.naux + 1) >> 1, lane);
+  if (lane == 0) {
+    msk[-1] = u32x4{0u, 0u, 0u, 0u};
+    msk[F] = u32x4{0u, 0u, 0u, 0u};
+    if (W.naux == 0) aux[0] = 0;  // the clamped push-target read stays defined
+    img[tri(idle)] = 1.0;
+    img[tri(idle) + 1] = 0.0;
+    img[tri(idle) + 2] = 0.0;
+  }
+  if (G.contig) {
+    flow_stage_range<RHS>(rs, d, u, G.user_base + G.user_lo, G.user_n, pos, img, lane);
+  } else {
+    int e0 = 0;
+    for (int c = 0; c < G.ncell; ++c) {
+      const KCell C = tb.cell[G.cell_begin + c];
+      flow_stage_range<RHS>(rs, d, u, C.user_lo, C.n, pos + e0, img, lane);
+      e0 += C.n;
     }
   }
-  __syncthreads();
+  __builtin_amdgcn_s_waitcnt(0);  // every DMA of this wave has landed
+  __syncthreads();  // staged
+  const int last_aux = W.naux > 0 ? W.naux - 1 : 0;
+
+  // Backward sweep.  During step t: the masks of t + 1 move to scalar
+  // registers, the masks of t + 2, the operands of t + 1 and the push target
+  // of t + 1 are read from LDS, and step t is eliminated.
   {
-    int q = q1 - 1, je = -1, i = 0, rem = -1;
-    KBranch rec{};
-    if (q >= q0) {
-      rec = BR[q];
-      je = rec.pad + sched_itlen(rec.lendir) - 1;
+    const u32x4 m0 = msk[0];
+    uint64_t M = first_u64(m0.x, m0.y), E = first_u64(m0.z, m0.w);
+    u32x4 mv = msk[1];
+    int R = 0, A = 0;
+    int pc = lane_in(M) ? rank_in(M, 0) : idle;
+    double Dn = img[tri(pc)], Un = img[tri(pc) + 1], Bn = img[tri(pc) + 2];
+    int qn = aux[min(rank_in(E, 0), last_aux)];
+    double fin = 0.0, uin = 0.0, bin = 0.0;
+    for (int t = 0; t < F; ++t) {
+      const uint64_t M1 = first_u64(mv.x, mv.y), E1 = first_u64(mv.z, mv.w);
+      mv = msk[t + 2 <= F ? t + 2 : F];
+      const int R1 = R + __builtin_popcountll(M), A1 = A + __builtin_popcountll(E);
+      const double Dc = Dn, Uc = Un, Bc = Bn;
+      const int qp = qn, pw = pc;
+      pc = lane_in(M1) ? rank_in(M1, R1) : idle;
+      Dn = img[tri(pc)];
+      Un = img[tri(pc) + 1];
+      Bn = img[tri(pc) + 2];
+      qn = aux[min(rank_in(E1, A1), last_aux)];
+      const double dl = __builtin_fma(-fin, uin, Dc);
+      const double bl = __builtin_fma(-fin, bin, Bc);
+      const double r = rcp_nr(dl);
+      const double f = Uc * r;
+      const int w = lane_in(M) ? pw : sink;
+      img[tri(w)] = f;
+      img[tri(w) + 2] = bl * r;
+      const int wq = lane_in(E) ? (int)qp : sink;
+      lds_add(img + tri(wq), -(f * Uc));
+      lds_add(img + tri(wq) + 2, -(f * bl));
+      fin = lane_in(M & ~E) ? f : 0.0;
+      uin = Uc;
+      bin = bl;
+      M = M1;
+      E = E1;
+      R = R1;
+      A = A1;
     }
+  }
+  __syncthreads();  // backward done
+
+  // Forward sweep, steps in reverse.  During step t: the masks of t - 2 move
+  // to scalar registers, the masks of t - 3 are read, the operands of t - 1,
+  // the parent x of the pushing lanes of t - 1 and the push target of t - 2
+  // are read from LDS, and step t is solved.
+  {
+    const u32x4 ma = msk[F - 1], mb = msk[F - 2];
+    uint64_t M = first_u64(ma.x, ma.y), E = first_u64(ma.z, ma.w);
+    uint64_t M1 = first_u64(mb.x, mb.y), E1 = first_u64(mb.z, mb.w);
+    u32x4 mv = msk[F - 3 >= -1 ? F - 3 : -1];
+    int R = W.nelem - __builtin_popcountll(M), A = W.naux - __builtin_popcountll(E);
+    int R1 = R - __builtin_popcountll(M1), A1 = A - __builtin_popcountll(E1);
+    int pc = lane_in(M) ? rank_in(M, R) : idle;
+    double fn = img[tri(pc)], yn = img[tri(pc) + 2];
+    double xqn = img[tri(aux[min(rank_in(E, A), last_aux)]) + 2];
+    int q1 = aux[min(rank_in(E1, A1), last_aux)];
     double xp = 0.0;
-    for (int it = F - 1; it >= 0; --it) {
-      if (q >= q0 && it <= je) {
-        if (it == je) {
-          i = rec.start;
-          if (rec.u0 >= 0) {
-            xp = __builtin_fma(-D[i], B[rec.pslot], B[i]);
-            B[i] = xp;
-          } else {
-            xp = B[i];
-          }
-          rem = rec.lendir - 1;
-        }
-        if (rem > 0) {
-          const int n = rem < kChunk ? rem : kChunk;
-          forward_chunk_asc(i, n, xp, D, B);
-          rem -= n;
-        }
-        if (rem == 0) {
-          --q;
-          rem = -1;
-          if (q >= q0) {
-            rec = BR[q];
-            je = rec.pad + sched_itlen(rec.lendir) - 1;
-          }
-        }
-      }
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    for (int t = F - 1; t >= 0; --t) {
+      const uint64_t M2 = first_u64(mv.x, mv.y), E2 = first_u64(mv.z, mv.w);
+      mv = msk[t - 3 >= -1 ? t - 3 : -1];
+      const int R2 = R1 - __builtin_popcountll(M2), A2 = A1 - __builtin_popcountll(E2);
+      const double f = fn, y = yn, xq = xqn;
+      const int pw = pc;
+      pc = lane_in(M1) ? rank_in(M1, R1) : idle;
+      fn = img[tri(pc)];
+      yn = img[tri(pc) + 2];
+      xqn = img[tri(q1) + 2];
+      q1 = aux[min(rank_in(E2, A2), last_aux)];
+      const double xv = __builtin_fma(-f, lane_in(E) ? xq : xp, y);
+      img[tri(lane_in(M) ? pw : sink) + 2] = xv;
+      xp = lane_in(M) ? xv : xp;
+      M = M1;
+      E = E1;
+      M1 = M2;
+      E1 = E2;
+      R1 = R2;
+      A1 = A2;
     }
   }
-  __syncthreads();
-  store_group<64>(tb, G, B, x, lane);
+  __syncthreads();  // forward done
+  if (G.contig) {
+    flow_store_range(x, G.user_base + G.user_lo, G.user_n, pos, img, lane);
+  } else {
+    int e0 = 0;
+    for (int c = 0; c < G.ncell; ++c) {
+      const KCell C = tb.cell[G.cell_begin + c];
+      flow_store_range(x, C.user_lo, C.n, pos + e0, img, lane);
+      e0 += C.n;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -825,7 +954,7 @@ __global__ __launch_bounds__(T) void k_solve_mixed(DevTables tb, const float* __
   int* seg = (int*)(lds_raw + L.tab_off_bytes());
   const int tid = threadIdx.x;
 
-  dma16<T>(tb.br_level + G.br_begin, lds_raw + L.br_off_bytes(), G.nbr, tid);
+  dma16<T>(tb.br + G.br_begin, lds_raw + L.br_off_bytes(), G.nbr, tid);
   dma4<T>(tb.seg + G.seg_begin, seg, G.nlev + 1, tid);
   if (G.contig) {
     stage_mixed_range<T>(d32, u32, b, G.user_base, G.user_lo + G.user_n, kLdsPad, D, U, B, tid);

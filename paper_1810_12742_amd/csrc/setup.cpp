@@ -23,48 +23,56 @@
 namespace hines {
 namespace {
 
-// Heavy-path lane schedule of one group.  Input: the group's branches in
-// group-local breadth-first order (children after parents), with length,
-// parent and children ranges.  Output: start iteration and lane per branch,
-// and the makespan.  Returns false if no schedule was found.
+// Static step schedule of one group (the flow kernel).  One lane eliminates
+// one compartment per step; a branch of length L occupies L consecutive steps
+// of one lane, its far end first.  Input: the group's branches in group-local
+// breadth-first order (children after parents) with length and child range.
+// A branch may start once its children are done: the child that finishes
+// last (the heavy child) runs on the same lane right before it and hands its
+// contribution over in registers; every other child must end at least one
+// step earlier, because it adds its contribution into the parent's LDS entry
+// and the parent's operands are read one step ahead.  Heavy chains are placed
+// as whole paths, latest deadline first, each on the lane where it can end
+// latest (as late as possible), so light subtrees fill the gaps of the lanes.
+// Output: start step, lane and "carried" flag per branch, and the makespan.
 struct SchedIn {
   int32_t len, parent, child0, nchild;
 };
 
-static bool schedule_group(const std::vector<SchedIn>& br, std::vector<int32_t>& start, std::vector<int32_t>& lane_of,
-                           int32_t& makespan) {
+static bool schedule_flow(const std::vector<SchedIn>& br, std::vector<int32_t>& start, std::vector<int32_t>& lane_of,
+                          std::vector<uint8_t>& carried, int32_t& makespan) {
   const int32_t nb = (int32_t)br.size();
-  std::vector<int32_t> itl(nb), fin(nb), heavy(nb, -1), plen(nb, 0);
+  std::vector<int32_t> fin(nb), heavy(nb, -1), plen(nb, 0);
   int64_t total = 0;
-  for (int32_t b = 0; b < nb; ++b) {
-    itl[b] = std::max<int32_t>(1, (br[b].len - 1 + kSchedChunk - 1) / kSchedChunk);
-    total += itl[b];
-  }
-  // as soon as possible: a branch starts when its last child finishes
-  for (int32_t b = nb - 1; b >= 0; --b) {
+  for (int32_t b = 0; b < nb; ++b) total += br[b].len;
+  for (int32_t b = nb - 1; b >= 0; --b) {  // as soon as possible
     int32_t hf = 0, h = -1;
     for (int32_t c = br[b].child0; c < br[b].child0 + br[b].nchild; ++c)
       if (h < 0 || fin[c] > hf) {  // the child finishing last; the smallest id on ties
         hf = fin[c];
         h = c;
       }
+    int32_t st = hf;
+    for (int32_t c = br[b].child0; c < br[b].child0 + br[b].nchild; ++c)
+      if (c != h) st = std::max(st, fin[c] + 1);
     heavy[b] = h;
-    fin[b] = hf + itl[b];
+    fin[b] = st + br[b].len;
   }
-  // path length from each branch down its heavy chain
-  for (int32_t b = nb - 1; b >= 0; --b) plen[b] = itl[b] + (heavy[b] >= 0 ? plen[heavy[b]] : 0);
+  for (int32_t b = nb - 1; b >= 0; --b) plen[b] = br[b].len + (heavy[b] >= 0 ? plen[heavy[b]] : 0);
   int32_t F = 0;
   for (int32_t b = 0; b < nb; ++b)
     if (br[b].parent < 0) F = std::max(F, fin[b]);
   start.assign(nb, 0);
   lane_of.assign(nb, 0);
+  carried.assign(nb, 0);
   std::vector<std::vector<std::pair<int32_t, int32_t>>> busy(kSchedLanes);
   struct Item {
     int32_t deadline, top;
   };
-  for (int64_t tries = 0; F <= total + 1 && F < 32000; ++tries, ++F) {
+  std::vector<Item> work;
+  for (; F <= total + nb + 1 && F <= kMaxSteps; ++F) {
     for (auto& v : busy) v.clear();
-    std::vector<Item> work;
+    work.clear();
     for (int32_t b = nb - 1; b >= 0; --b)
       if (br[b].parent < 0) work.push_back({F, b});
     bool ok = true;
@@ -85,9 +93,9 @@ static bool schedule_group(const std::vector<SchedIn>& br, std::vector<int32_t>&
         int32_t end = it.deadline;
         const auto& iv = busy[ln];  // sorted by start
         for (int64_t k = (int64_t)iv.size() - 1; k >= 0; --k) {
-          if (iv[k].first >= end) continue;           // entirely after the window end
-          if (iv[k].second <= end - L) break;         // gap [iv.second, end) fits
-          end = iv[k].first;                          // move the window before this interval
+          if (iv[k].first >= end) continue;    // entirely after the window end
+          if (iv[k].second <= end - L) break;  // gap [iv.second, end) fits
+          end = iv[k].first;                   // move the window before this interval
         }
         if (end - L >= 0 && end > best_end) {
           best_end = end;
@@ -101,14 +109,14 @@ static bool schedule_group(const std::vector<SchedIn>& br, std::vector<int32_t>&
       auto& iv = busy[best_lane];
       iv.push_back({best_end - L, best_end});
       std::sort(iv.begin(), iv.end());
-      // branches of the path from the top down
-      int32_t t = best_end;
+      int32_t t = best_end;  // branches of the path from the top down
       for (int32_t b = it.top; b >= 0; b = heavy[b]) {
-        t -= itl[b];
+        t -= br[b].len;
         start[b] = t;
         lane_of[b] = best_lane;
+        if (heavy[b] >= 0) carried[heavy[b]] = 1;
         for (int32_t c = br[b].child0; c < br[b].child0 + br[b].nchild; ++c)
-          if (c != heavy[b]) work.push_back({t, c});
+          if (c != heavy[b]) work.push_back({t - 1, c});
       }
     }
     if (ok) {
@@ -118,6 +126,8 @@ static bool schedule_group(const std::vector<SchedIn>& br, std::vector<int32_t>&
   }
   return false;
 }
+
+static inline int popc64(uint64_t m) { return __builtin_popcountll(m); }
 
 struct Builder {
   const int32_t* parent;
@@ -645,20 +655,46 @@ struct Builder {
       }
     }
 
-    // ---- static lane schedule (ascending fast path, groups staged in LDS) ----
-    if (opt.scheduler && !opt.bitwise && P.all_ascending && P.kernel_tables_fit && !opt.host_only) {
-      P.klane.assign((size_t)ng * (kSchedLanes + 1), 0);
+    // ---- static step schedule and flow tables (ascending plans, LDS groups) ----
+    // Every child branch must hang off the far end of its parent (always true
+    // for maximal chains and splits; user layouts may attach mid-branch).
+    bool tips_only = true;
+    for (int64_t g = 0; g < ng && tips_only; ++g) {
+      const KGroup& G = P.kgroup[g];
+      std::vector<int32_t> rec_of(G.nbr, -1);
+      for (int32_t r = 0; r < G.nbr; ++r) rec_of[P.kbranch[G.br_begin + r].self] = r;
+      for (int32_t r = 0; r < G.nbr && tips_only; ++r) {
+        const KBranch& B = P.kbranch[G.br_begin + r];
+        for (int32_t c = B.child0; c < B.child0 + B.nchild; ++c)
+          if (P.kbranch[G.br_begin + rec_of[c]].pslot != B.start + B.lendir - 1) tips_only = false;
+      }
+    }
+    if (opt.scheduler && !opt.bitwise && P.all_ascending && P.kernel_tables_fit && tips_only) {
+      P.kflow.assign(ng, KFlow{});
       std::vector<SchedIn> sin;
-      std::vector<int32_t> st, ln, order;
-      std::vector<KBranch> tmp;
-      std::vector<KBranch> sched(P.kbranch);  // committed only if every group is scheduled
+      std::vector<int32_t> st, ln, slot_elem;
+      std::vector<uint8_t> car;
+      std::vector<uint64_t> M, E;
+      std::vector<int32_t> R;
       bool all_ok = true;
+      int64_t steps = 0, elems = 0;
       for (int64_t g = 0; g < ng && all_ok; ++g) {
-        KGroup& G = P.kgroup[g];
-        if (G.ws_off >= 0) continue;  // level-synchronous from the workspace
+        const KGroup& G = P.kgroup[g];
+        KFlow& W = P.kflow[g];
+        W.step_off = steps;
+        W.pos_off = elems;
+        if (P.faux.size() & 1) P.faux.push_back(0);  // 4-byte aligned start of the group's push targets
+        W.aux_off = (int64_t)P.faux.size();
+        W.nelem = G.user_n;
+        if (G.ws_off >= 0) {  // level-synchronous from the workspace
+          W.nstep = 0;
+          W.naux = 0;
+          W.nelem = 0;
+          continue;
+        }
         const int32_t nbg = G.nbr;
         sin.assign(nbg, SchedIn{0, -1, 0, 0});
-        std::vector<int32_t> rec_of(nbg, -1);  // group-local BFS id -> record index in the group
+        std::vector<int32_t> rec_of(nbg, -1);  // group-local BFS id -> record
         for (int32_t r = 0; r < nbg; ++r) {
           const KBranch& B = P.kbranch[G.br_begin + r];
           rec_of[B.self] = r;
@@ -667,37 +703,84 @@ struct Builder {
         for (int32_t b = 0; b < nbg; ++b)
           for (int32_t c = sin[b].child0; c < sin[b].child0 + sin[b].nchild; ++c) sin[c].parent = b;
         int32_t F = 0;
-        if (!schedule_group(sin, st, ln, F)) {
+        if (!schedule_flow(sin, st, ln, car, F)) {
           all_ok = false;
           break;
         }
-        G.makespan = F;
-        order.resize(nbg);
-        std::iota(order.begin(), order.end(), 0);
-        std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-          if (ln[a] != ln[b]) return ln[a] < ln[b];
-          return st[a] < st[b];
-        });
-        tmp.resize(nbg);
-        int32_t* lo = &P.klane[(size_t)g * (kSchedLanes + 1)];
-        int32_t cur = 0;
-        for (int32_t lane_id = 0; lane_id <= kSchedLanes; ++lane_id) {
-          while (cur < nbg && ln[order[cur]] < lane_id) ++cur;
-          lo[lane_id] = cur;
+        const int32_t Fp = (F + 3) & ~3;  // whole 64-byte blocks of step records
+        M.assign(Fp, 0);
+        E.assign(Fp, 0);
+        for (int32_t b = 0; b < nbg; ++b) {
+          for (int32_t k = 0; k < sin[b].len; ++k) M[st[b] + k] |= 1ull << ln[b];
+          if (sin[b].parent >= 0 && !car[b]) E[st[b] + sin[b].len - 1] |= 1ull << ln[b];
         }
-        for (int32_t k = 0; k < nbg; ++k) {
-          const int32_t b = order[k];
-          tmp[k] = P.kbranch[G.br_begin + rec_of[b]];
-          tmp[k].pad = (int16_t)st[b];
+        R.assign(Fp + 1, 0);
+        for (int32_t t = 0; t < Fp; ++t) R[t + 1] = R[t] + popc64(M[t]);
+        auto pos_at = [&](int32_t t, int32_t lane_id) {
+          return R[t] + popc64(M[t] & ((1ull << lane_id) - 1));
+        };
+        // slot of the user-order image -> element index of the staging order
+        slot_elem.assign(G.nunk, -1);
+        int32_t cum = 0;
+        for (int c = 0; c < G.ncell; ++c) {
+          const KCell& C = P.kcell[G.cell_begin + c];
+          for (int32_t k = 0; k < C.n; ++k) slot_elem[C.lds + k] = cum + k;
+          cum += C.n;
         }
-        std::copy(tmp.begin(), tmp.end(), sched.begin() + G.br_begin);
+        if (R[Fp] != cum || cum != G.user_n) {
+          all_ok = false;
+          break;
+        }
+        P.fpos.resize(elems + cum);
+        for (int32_t b = 0; b < nbg; ++b) {
+          const KBranch& B = P.kbranch[G.br_begin + rec_of[b]];
+          for (int32_t k = 0; k < sin[b].len; ++k) {
+            const int32_t e = slot_elem[B.start + k];
+            uint32_t p = (uint32_t)pos_at(st[b] + sin[b].len - 1 - k, ln[b]);
+            if (k == 0 && sin[b].parent < 0) p |= 0x8000u;  // the cell's root: no coupling
+            P.fpos[elems + e] = (uint16_t)p;
+          }
+        }
+        // push targets in (step, lane) order: the parent's far end, eliminated
+        // at the parent's first step on the parent's lane
+        std::vector<int32_t> end_br(Fp * (int64_t)kSchedLanes, -1);
+        for (int32_t b = 0; b < nbg; ++b)
+          if (sin[b].parent >= 0 && !car[b]) end_br[(int64_t)(st[b] + sin[b].len - 1) * kSchedLanes + ln[b]] = b;
+        for (int32_t t = 0; t < Fp; ++t)
+          for (int32_t l = 0; l < kSchedLanes; ++l) {
+            const int32_t b = end_br[(int64_t)t * kSchedLanes + l];
+            if (b < 0) continue;
+            const int32_t pb = sin[b].parent;
+            P.faux.push_back((int16_t)pos_at(st[pb], ln[pb]));
+          }
+        for (int32_t t = 0; t < Fp; ++t) {
+          P.fmask.push_back(M[t]);
+          P.fmask.push_back(E[t]);
+        }
+        W.nstep = Fp;
+        W.naux = (int32_t)((int64_t)P.faux.size() - W.aux_off);
+        W.makespan = F;
+        if (flow_lds_bytes(W) > kLdsLimitBytes) {  // e.g. very long single branches: level kernel
+          P.fmask.resize(2 * steps);
+          P.fpos.resize(elems);
+          P.faux.resize(W.aux_off);
+          W = KFlow{};
+          W.step_off = steps;
+          W.pos_off = elems;
+          W.aux_off = (int64_t)P.faux.size();
+          continue;
+        }
+        P.kgroup[g].makespan = F;
+        steps += Fp;
+        elems += cum;
       }
       if (all_ok) {
-        P.kbranch_level.swap(P.kbranch);
-        P.kbranch.swap(sched);
-        P.scheduled = true;
-      } else {
-        std::vector<int32_t>().swap(P.klane);  // level-synchronous kernel instead
+        P.flow = true;
+      } else {  // level-synchronous kernel instead
+        std::vector<KFlow>().swap(P.kflow);
+        std::vector<uint64_t>().swap(P.fmask);
+        std::vector<uint16_t>().swap(P.fpos);
+        std::vector<int16_t>().swap(P.faux);
       }
     }
     P.seg_offsets.assign(P.kseg.begin(), P.kseg.end());
@@ -743,7 +826,9 @@ int64_t export_table(const HostPlan& p, int32_t id, int64_t* out, int64_t capaci
     }
     return cnt;
   };
-  if (!p.opt.keep_tables && (id == T_NODE_PLAN || id == T_BRANCHES || id == T_U_SRC)) return -1;
+  if (!p.opt.keep_tables && (id == T_NODE_PLAN || id == T_BRANCHES || id == T_U_SRC || id == T_FLOW_MASKS ||
+                             id == T_FLOW_POS || id == T_FLOW_AUX))
+    return -1;
   switch (id) {
     case T_NODE_PLAN: return put(p.node_plan);
     case T_U_SRC: return put(p.u_src);
@@ -770,6 +855,26 @@ int64_t export_table(const HostPlan& p, int32_t id, int64_t* out, int64_t capaci
     case T_GROUP_SEG_OFFSETS: return put(p.group_seg_offsets);
     case T_SEG_OFFSETS: return put(p.seg_offsets);
     case T_LANES: return put(p.lanes);
+    case T_FLOW_GROUPS: {
+      const int64_t cnt = p.flow ? 6 * (int64_t)p.kflow.size() : 0;
+      if (out) {
+        if (capacity < cnt) return -1;
+        for (int64_t g = 0; g < cnt / 6; ++g) {
+          const KFlow& w = p.kflow[g];
+          int64_t* r = out + 6 * g;
+          r[0] = w.step_off;
+          r[1] = w.pos_off;
+          r[2] = w.aux_off;
+          r[3] = w.nstep;
+          r[4] = w.nelem;
+          r[5] = w.naux;
+        }
+      }
+      return cnt;
+    }
+    case T_FLOW_MASKS: return put(p.fmask);
+    case T_FLOW_POS: return put(p.fpos);
+    case T_FLOW_AUX: return put(p.faux);
     default: return -1;
   }
 }

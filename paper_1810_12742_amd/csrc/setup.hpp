@@ -39,16 +39,10 @@ struct Options {
                                    // 0: level-synchronous sweeps (paper §3)
 };
 
-// Static lane schedule of one group (used by the scheduled solve kernel).
-// Time is counted in iterations; in one iteration a lane eliminates up to
-// kSchedChunk compartments of one branch.  A branch b occupies
-// it_len(b) = max(1, ceil((len_b - 1) / kSchedChunk)) consecutive iterations on
-// one lane and may start only after all its child branches have finished.  A
-// lane continues from a branch into its parent when that child finishes last
-// (the heavy path); the other children are placed as late as their deadline
-// allows on any free lane.
-constexpr int32_t kSchedChunk = 8;
+// Static step schedule (flow kernel): one lane eliminates one compartment per
+// step; kSchedLanes lanes per group; at most kMaxSteps steps per sweep.
 constexpr int32_t kSchedLanes = 64;
+constexpr int32_t kMaxSteps = 16384;
 
 // LDS image of a group: d, u, b per slot (nimg slots; 0 when the compartment
 // arrays live in the global workspace), two elimination contributions per
@@ -79,7 +73,11 @@ enum TableId : int32_t {
   T_GROUP_SEG_OFFSETS = 5,  // int64[ngroups+1]
   T_SEG_OFFSETS = 6,      // int64[nseg+1]
   T_LANES = 7,            // int64[nb]
-  T_NUM = 8,
+  T_FLOW_GROUPS = 8,      // int64[ngroups*6]: step_off, pos_off, aux_off, nstep, nelem, naux
+  T_FLOW_MASKS = 9,       // int64[2*steps]: active and push masks (bit patterns)
+  T_FLOW_POS = 10,        // int64[elements]: position | 0x8000 for cell roots
+  T_FLOW_AUX = 11,        // int64[pushes]: parent position
+  T_NUM = 12,
 };
 
 // Per-branch record of the LDS-staged solve kernel, in (group, level, lane)
@@ -95,7 +93,7 @@ struct KBranch {
   int16_t self;    // group-local breadth-first id (slot of its elimination contribution)
   int16_t child0;  // group-local id of the first child branch
   int16_t nchild;  // number of child branches (ids child0 .. child0+nchild-1)
-  int16_t pad;     // scheduled kernel: first iteration of the branch
+  int16_t pad;     // unused (0)
 };
 static_assert(sizeof(KBranch) == 16, "one DMA lane per record");
 
@@ -120,7 +118,7 @@ struct KGroup {
   int32_t contig;      // 1: cells are one user range; LDS slot kLdsPad + k <-> user index user_base + k
   int32_t user_lo;     // contiguous groups: first user index relative to user_base (0 or 1)
   int32_t user_n;      // contiguous groups: compartments in the range
-  int32_t makespan;    // scheduled kernel: iterations of each sweep
+  int32_t makespan;    // flow kernel: steps of each sweep (0: not scheduled)
 };
 static_assert(sizeof(KGroup) == 64, "layout");
 
@@ -129,6 +127,35 @@ struct KCell {
   int32_t n;        // compartments
   int32_t lds;      // offset of the cell in the group's LDS image
 };
+
+// Flow kernel tables of one group.  The group's compartments get "positions"
+// in step order: the compartment that lane l eliminates at step t sits at
+// R[t] + (number of active lanes below l at step t), R[t] the number of
+// eliminations before step t.  Per step the table holds two 64-bit lane masks
+// (active, push: the lane ends a branch whose contribution goes to LDS); per
+// element of the group's staging order its position (bit 15: the cell root,
+// whose coupling is ignored); per push, in (step, lane) order, the position
+// of the parent compartment.
+struct KFlow {
+  int64_t step_off;  // first step record (two uint64 masks) of the group
+  int64_t pos_off;   // first element position
+  int64_t aux_off;   // first push target
+  int32_t nstep;     // steps per sweep (a multiple of 4; 0 for workspace groups)
+  int32_t nelem;     // compartments = positions
+  int32_t naux;      // pushes
+  int32_t makespan;  // steps before padding to a multiple of 4
+  int32_t pad0, pad1;
+};
+static_assert(sizeof(KFlow) == 48, "layout");
+
+// LDS layout of a flow group: image (24 bytes per position: d, u, b; then one
+// constant entry for idle lanes and 64 write-only sink entries), push targets
+// (int16, at least one entry), step masks (16 bytes per step plus a zero
+// record before and after).
+constexpr int64_t flow_mask_offset(const KFlow& w) {
+  return (24 * ((int64_t)w.nelem + 65) + 2 * ((int64_t)w.naux + 1) + 15) & ~(int64_t)15;
+}
+constexpr int64_t flow_lds_bytes(const KFlow& w) { return flow_mask_offset(w) + 16 * ((int64_t)w.nstep + 2); }
 
 struct HostPlan {
   int64_t n = 0, ncells = 0, nbranches = 0, ngroups = 0, nseg = 0;
@@ -149,9 +176,11 @@ struct HostPlan {
   std::vector<KCell> kcell;       // [ncells] group order
   bool kernel_tables_fit = true;  // every group addressable by the int16 records
   bool all_ascending = true;      // every branch runs toward higher user indices
-  bool scheduled = false;         // kbranch is in (group, lane, start) order with start in KBranch::pad
-  std::vector<int32_t> klane;     // scheduled: per group kSchedLanes + 1 record offsets (group-relative)
-  std::vector<KBranch> kbranch_level;  // scheduled: the records in level order (kbranch holds lane order)
+  bool flow = false;              // every LDS group has a step schedule (flow kernel)
+  std::vector<KFlow> kflow;       // [ngroups]
+  std::vector<uint64_t> fmask;    // [2 * total steps]: active and push masks per step
+  std::vector<uint16_t> fpos;     // [elements of LDS groups]: position, bit 15 = cell root
+  std::vector<int16_t> faux;      // [pushes]: parent position
   int64_t ws_doubles = 0;         // global workspace for groups that exceed LDS
 };
 
