@@ -62,9 +62,11 @@ hines_status ok() {
   return HINES_OK;
 }
 
-// LDS footprint buckets (bytes); a launch reserves its bucket's size per workgroup.
-constexpr int kBuckets[] = {4096,  8192,  12288, 16384, 20480, 24576,  32768,  40960,
-                            49152, 65536, 81920, 98304, 131072, 163840};
+// LDS footprint classes (bytes); a launch reserves its class's size per
+// workgroup.  A CU holds floor(160 KiB / size) such workgroups, so the classes
+// sit at 160 KiB / n (rounded down to 256 bytes) for the occupancies that
+// matter; each class is one launch, so there are few of them.
+constexpr int kBuckets[] = {4096, 8192, 12288, 16384, 20480, 23296, 27136, 32768, 40960, 54528, 81920, 163840};
 constexpr int kGlobalT = 256;  // workgroup of groups whose image lives in the workspace
 
 inline LdsLayout layout_of(const KGroup& g) {
@@ -283,8 +285,8 @@ bool check_kernel_tables(const hines::HostPlan& P, std::string& why, bool& capac
     }
   }
   if (P.flow) {
-    // every LDS index the flow kernel forms: positions R + rank < nelem,
-    // push ranks < naux, stored positions and push targets < nelem
+    // every LDS index the flow kernel forms: entries R + j c + rank < nent,
+    // push ranks < naux, stored entries and push targets < nent
     if ((int64_t)P.kflow.size() != P.ngroups) {
       why = "flow table size";
       return false;
@@ -295,10 +297,10 @@ bool check_kernel_tables(const hines::HostPlan& P, std::string& why, bool& capac
       const hines::KFlow& W = P.kflow[g];
       if (G.ws_off >= 0) continue;
       if (W.nstep == 0 && W.nelem == 0 && W.naux == 0) continue;  // level kernel in LDS
-      if (W.nstep < 0 || (W.nstep & 3) || W.nstep > hines::kMaxSteps + 3 || W.nelem != G.user_n || W.naux < 0 ||
-          W.step_off < 0 || 2 * (W.step_off + W.nstep) > (int64_t)P.fmask.size() || W.pos_off < 0 ||
-          W.pos_off + W.nelem > (int64_t)P.fpos.size() || W.aux_off < 0 ||
-          W.aux_off + W.naux > (int64_t)P.faux.size() || hines::flow_lds_bytes(W) > hines::kLdsLimitBytes) {
+      if (W.nstep < 1 || W.nstep > hines::kMaxSteps || W.nelem != G.user_n || W.naux < 0 || W.nent < W.nelem ||
+          hines::flow_image8(W) > 32767 || W.nent % hines::kFlowChunk || W.step_off < 0 || 2 * (W.step_off + W.nstep) > (int64_t)P.fmask.size() ||
+          W.pos_off < 0 || W.pos_off + W.nelem > (int64_t)P.fpos.size() || W.aux_off < 0 || (W.aux_off & 1) ||
+          W.aux_off + W.naux + 1 > (int64_t)P.faux.size() + 1 || hines::flow_lds_bytes(W) > hines::kLdsLimitBytes) {
         why = "flow group record";
         capacity = hines::flow_lds_bytes(W) > hines::kLdsLimitBytes;
         return false;
@@ -313,22 +315,26 @@ bool check_kernel_tables(const hines::HostPlan& P, std::string& why, bool& capac
         act += __builtin_popcountll(M);
         push += __builtin_popcountll(E);
       }
-      if (act != W.nelem || push != W.naux) {
+      if (act * hines::kFlowChunk != W.nent || push != W.naux) {
         why = "flow mask counts";
         return false;
       }
-      seen.assign(W.nelem, 0);
+      const int32_t nunits = W.nent / hines::kFlowChunk * hines::kFlowBlock8;  // block region
+      auto valid = [&](int32_t q) {
+        const int32_t r = q % hines::kFlowBlock8;
+        return q >= 0 && q < nunits && r < 3 * hines::kFlowChunk && r % 3 == 0;
+      };
+      seen.assign(nunits, 0);
       for (int32_t e = 0; e < W.nelem; ++e) {
         const int32_t q = P.fpos[W.pos_off + e] & 0x7fff;
-        if (q >= W.nelem || seen[q]) {
+        if (!valid(q) || seen[q]) {
           why = "flow positions";
           return false;
         }
         seen[q] = 1;
       }
       for (int32_t k = 0; k < W.naux; ++k) {
-        const int32_t q = P.faux[W.aux_off + k];
-        if (q < 0 || q >= W.nelem) {
+        if (!valid(P.faux[W.aux_off + k])) {
           why = "flow push target";
           return false;
         }

@@ -573,6 +573,7 @@ __global__ __launch_bounds__(T) void k_solve_level(DevTables tb, RhsSpec rs, con
 // replays the steps backwards: x of the parent is in registers (heavy child)
 // or in LDS, written in an earlier forward step (light child).
 // ---------------------------------------------------------------------------
+using hines::flow_image8;
 using hines::flow_lds_bytes;
 using hines::flow_mask_offset;
 
@@ -602,25 +603,35 @@ enum : int { kFlowGiven = 0, kFlowCV = 1, kFlowCVI = 2, kFlowNoise = 3 };
 // twice with the same value).
 constexpr int kStageUnroll = 16;
 
+// The first kStageUnroll entries of each lane are also returned in keep[], so
+// that a group staged in one batch stores its solution without reading its
+// positions again.
 template <int RHS>
-__device__ __forceinline__ void flow_stage_range(const RhsSpec& rs, const double* __restrict__ d,
-                                                 const double* __restrict__ u, int64_t lo, int n,
-                                                 const uint16_t* __restrict__ pos, lds_f64* img, int lane) {
+__device__ __forceinline__ void flow_stage_range(const RhsSpec& rs, const double* __restrict__ d_,
+                                                 const double* __restrict__ u_, int64_t lo, int n,
+                                                 const uint16_t* __restrict__ pos, lds_f64* img, int lane,
+                                                 uint32_t* keep) {
+  // uniform bases, 32-bit per-lane offsets
+  const double* __restrict__ d = d_ + lo;
+  const double* __restrict__ u = u_ + lo;
+  const double* __restrict__ rhs = rs.rhs + lo;
+  const double* __restrict__ cc = rs.c + lo;
+  const double* __restrict__ vv = rs.v + lo;
+  const double* __restrict__ ii = rs.icur + lo;
   for (int e0 = 0; e0 < n; e0 += 64 * kStageUnroll) {
     uint32_t pw[kStageUnroll];
-    double dv[kStageUnroll], uv[kStageUnroll], bv[kStageUnroll], cv[kStageUnroll], iv[kStageUnroll];
+    double dv[kStageUnroll], uv[kStageUnroll], bv[kStageUnroll], cv[kStageUnroll];
 #pragma unroll
     for (int k = 0; k < kStageUnroll; ++k) {
       const int e = min(e0 + 64 * k + lane, n - 1);
       pw[k] = pos[e];
-      dv[k] = d[lo + e];
-      uv[k] = u[lo + e];
+      dv[k] = d[e];
+      uv[k] = u[e];
       if constexpr (RHS == kFlowGiven) {
-        bv[k] = rs.rhs[lo + e];
+        bv[k] = rhs[e];
       } else {
-        cv[k] = rs.c[lo + e];
-        bv[k] = rs.v[lo + e];
-        if constexpr (RHS == kFlowCVI) iv[k] = rs.icur[lo + e];
+        cv[k] = cc[e];
+        bv[k] = vv[e];
       }
     }
 #pragma unroll
@@ -628,26 +639,37 @@ __device__ __forceinline__ void flow_stage_range(const RhsSpec& rs, const double
       const int e = min(e0 + 64 * k + lane, n - 1);
       double b = bv[k];
       if constexpr (RHS != kFlowGiven) b = cv[k] * bv[k];
-      if constexpr (RHS == kFlowCVI) b = b + iv[k];
+      if constexpr (RHS == kFlowCVI) b = b + ii[e];
       if constexpr (RHS == kFlowNoise) b = b + noise_draw(rs.seed, rs.step, (uint64_t)(lo + e), rs.sigma);
-      lds_f64* q = img + tri((int)(pw[k] & 0x7fffu));
+      lds_f64* q = img + (int)(pw[k] & 0x7fffu);
       q[0] = dv[k];
       q[1] = (pw[k] & 0x8000u) ? 0.0 : uv[k];
       q[2] = b;
     }
+    if (e0 == 0) {
+#pragma unroll
+      for (int k = 0; k < kStageUnroll; ++k) keep[k] = pw[k];
+    }
   }
 }
 
-__device__ __forceinline__ void flow_store_range(double* x, int64_t lo, int n, const uint16_t* __restrict__ pos,
-                                                 const lds_f64* img, int lane) {
+// keep: the positions of the first batch (from the staging), or nullptr.
+__device__ __forceinline__ void flow_store_range(double* x_, int64_t lo, int n, const uint16_t* __restrict__ pos,
+                                                 const lds_f64* img, int lane, const uint32_t* keep) {
+  double* x = x_ + lo;
   for (int e0 = 0; e0 < n; e0 += 64 * kStageUnroll) {
     uint32_t pw[kStageUnroll];
+    if (e0 == 0 && keep) {
 #pragma unroll
-    for (int k = 0; k < kStageUnroll; ++k) pw[k] = pos[min(e0 + 64 * k + lane, n - 1)];
+      for (int k = 0; k < kStageUnroll; ++k) pw[k] = keep[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < kStageUnroll; ++k) pw[k] = pos[min(e0 + 64 * k + lane, n - 1)];
+    }
 #pragma unroll
     for (int k = 0; k < kStageUnroll; ++k) {
       const int e = e0 + 64 * k + lane;
-      if (e < n) x[lo + e] = img[tri((int)(pw[k] & 0x7fffu)) + 2];
+      if (e < n) x[e] = img[(int)(pw[k] & 0x7fffu) + 2];
     }
   }
 }
@@ -660,12 +682,15 @@ __device__ __forceinline__ uint64_t first_u64(uint32_t lo, uint32_t hi) {
          (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)lo);
 }
 
-// Both sweeps run the same straight-line code for every lane in every step:
-// a lane that is idle in a step reads the constant entry `nelem` (d = 1, u = 0,
-// b = 0, which eliminates to zeros) and writes and pushes into its own sink
-// entry nelem + 1 + lane, which is never read.  Without branches the number
-// of LDS operations per step is fixed, so the wait at the top of a step covers
-// only the reads issued one step earlier.
+// Both sweeps run the same straight-line code for every lane in every chunk
+// step.  The chunk of a busy lane is one LDS block; sub-step j is entry j of
+// the block, so every access of a sub-step is the block base plus an
+// immediate offset.  An idle lane reads the identity block (d = 1, u = 0,
+// b = 0 per entry, which eliminates to zeros) and writes into the sink, which
+// is never read.  Only the pushes are masked.
+constexpr int KC = hines::kFlowChunk;
+constexpr int KB8 = hines::kFlowBlock8;
+
 template <int RHS>
 __global__ __launch_bounds__(64) void k_solve_flow(DevTables tb, RhsSpec rs, const double* __restrict__ d,
                                                    const double* __restrict__ u, double* x) {
@@ -677,29 +702,36 @@ __global__ __launch_bounds__(64) void k_solve_flow(DevTables tb, RhsSpec rs, con
   const int lane = threadIdx.x;
   const uint16_t* pos = tb.fpos + W.pos_off;
   const int F = W.nstep;
-  const int idle = W.nelem, sink = W.nelem + 1 + lane;
-  lds_i16* aux = (lds_i16*)(img + tri(W.nelem + 1 + 64));
+  const int nblk = W.nent / KC;
+  const int idle = nblk * KB8, sink = idle + KB8 + lane;
+  lds_i16* aux = (lds_i16*)(img + flow_image8(W));
   // masks of steps 0 .. F-1, then one zero record on each side (steps -1 and F)
   lds_u4* msk = (lds_u4*)((lds_u8*)img + flow_mask_offset(W)) + 1;
   // masks and push targets by global->LDS DMA (16- and 4-byte units; the push
   // targets of a group start 4-byte aligned and the table is padded)
   dma16<64>(tb.fmask + 2 * W.step_off, (void*)(msk), F, lane);
   dma4<64>(tb.faux + W.aux_off, (void*)aux, (W.naux + 1) >> 1, lane);
+  // every entry of every block (pads and the identity block included) starts
+  // as the identity compartment; the scatter below overwrites the real ones
+  for (int e = lane; e < W.nent + KC; e += 64) {
+    const int o = (e / KC) * KB8 + 3 * (e % KC);
+    img[o] = 1.0;
+    img[o + 1] = 0.0;
+    img[o + 2] = 0.0;
+  }
   if (lane == 0) {
     msk[-1] = u32x4{0u, 0u, 0u, 0u};
     msk[F] = u32x4{0u, 0u, 0u, 0u};
     if (W.naux == 0) aux[0] = 0;  // the clamped push-target read stays defined
-    img[tri(idle)] = 1.0;
-    img[tri(idle) + 1] = 0.0;
-    img[tri(idle) + 2] = 0.0;
   }
+  uint32_t keep[kStageUnroll];
   if (G.contig) {
-    flow_stage_range<RHS>(rs, d, u, G.user_base + G.user_lo, G.user_n, pos, img, lane);
+    flow_stage_range<RHS>(rs, d, u, G.user_base + G.user_lo, G.user_n, pos, img, lane, keep);
   } else {
     int e0 = 0;
     for (int c = 0; c < G.ncell; ++c) {
       const KCell C = tb.cell[G.cell_begin + c];
-      flow_stage_range<RHS>(rs, d, u, C.user_lo, C.n, pos + e0, img, lane);
+      flow_stage_range<RHS>(rs, d, u, C.user_lo, C.n, pos + e0, img, lane, keep);
       e0 += C.n;
     }
   }
@@ -707,42 +739,65 @@ __global__ __launch_bounds__(64) void k_solve_flow(DevTables tb, RhsSpec rs, con
   __syncthreads();  // staged
   const int last_aux = W.naux > 0 ? W.naux - 1 : 0;
 
-  // Backward sweep.  During step t: the masks of t + 1 move to scalar
-  // registers, the masks of t + 2, the operands of t + 1 and the push target
-  // of t + 1 are read from LDS, and step t is eliminated.
+  // Backward sweep.  During chunk step t: the masks of t + 1 move to scalar
+  // registers, the masks of t + 2, the operands of t + 1 and the push target of
+  // t + 1 are read from LDS, and the KC sub-steps of t are eliminated.
   {
     const u32x4 m0 = msk[0];
     uint64_t M = first_u64(m0.x, m0.y), E = first_u64(m0.z, m0.w);
     u32x4 mv = msk[1];
     int R = 0, A = 0;
-    int pc = lane_in(M) ? rank_in(M, 0) : idle;
-    double Dn = img[tri(pc)], Un = img[tri(pc) + 1], Bn = img[tri(pc) + 2];
+    int rb = lane_in(M) ? rank_in(M, 0) * KB8 : idle;
+    double Dn[KC], Un[KC], Bn[KC];
+#pragma unroll
+    for (int j = 0; j < KC; ++j) {
+      Dn[j] = img[rb + 3 * j];
+      Un[j] = img[rb + 3 * j + 1];
+      Bn[j] = img[rb + 3 * j + 2];
+    }
     int qn = aux[min(rank_in(E, 0), last_aux)];
     double fin = 0.0, uin = 0.0, bin = 0.0;
     for (int t = 0; t < F; ++t) {
       const uint64_t M1 = first_u64(mv.x, mv.y), E1 = first_u64(mv.z, mv.w);
       mv = msk[t + 2 <= F ? t + 2 : F];
       const int R1 = R + __builtin_popcountll(M), A1 = A + __builtin_popcountll(E);
-      const double Dc = Dn, Uc = Un, Bc = Bn;
-      const int qp = qn, pw = pc;
-      pc = lane_in(M1) ? rank_in(M1, R1) : idle;
-      Dn = img[tri(pc)];
-      Un = img[tri(pc) + 1];
-      Bn = img[tri(pc) + 2];
+      double Dc[KC], Uc[KC], Bc[KC];
+#pragma unroll
+      for (int j = 0; j < KC; ++j) {
+        Dc[j] = Dn[j];
+        Uc[j] = Un[j];
+        Bc[j] = Bn[j];
+      }
+      const int qp = qn;
+      const int wb = lane_in(M) ? rb : sink;
+      rb = lane_in(M1) ? rank_in(M1, R1) * KB8 : idle;
+#pragma unroll
+      for (int j = 0; j < KC; ++j) {
+        Dn[j] = img[rb + 3 * j];
+        Un[j] = img[rb + 3 * j + 1];
+        Bn[j] = img[rb + 3 * j + 2];
+      }
       qn = aux[min(rank_in(E1, A1), last_aux)];
-      const double dl = __builtin_fma(-fin, uin, Dc);
-      const double bl = __builtin_fma(-fin, bin, Bc);
-      const double r = rcp_nr(dl);
-      const double f = Uc * r;
-      const int w = lane_in(M) ? pw : sink;
-      img[tri(w)] = f;
-      img[tri(w) + 2] = bl * r;
-      const int wq = lane_in(E) ? (int)qp : sink;
-      lds_add(img + tri(wq), -(f * Uc));
-      lds_add(img + tri(wq) + 2, -(f * bl));
-      fin = lane_in(M & ~E) ? f : 0.0;
-      uin = Uc;
-      bin = bl;
+#pragma unroll
+      for (int j = 0; j < KC; ++j) {
+        const double dl = __builtin_fma(-fin, uin, Dc[j]);
+        const double bl = __builtin_fma(-fin, bin, Bc[j]);
+        const double r = rcp_nr(dl);
+        const double f = Uc[j] * r;
+        img[wb + 3 * j] = f;
+        img[wb + 3 * j + 2] = bl * r;
+        fin = f;
+        uin = Uc[j];
+        bin = bl;
+      }
+      {
+        const double cd = -(fin * uin), cb = -(fin * bin);
+        if (lane_in(E)) {
+          lds_add(img + qp, cd);
+          lds_add(img + qp + 2, cb);
+        }
+      }
+      fin = lane_in(M & ~E) ? fin : 0.0;
       M = M1;
       E = E1;
       R = R1;
@@ -751,35 +806,53 @@ __global__ __launch_bounds__(64) void k_solve_flow(DevTables tb, RhsSpec rs, con
   }
   __syncthreads();  // backward done
 
-  // Forward sweep, steps in reverse.  During step t: the masks of t - 2 move
-  // to scalar registers, the masks of t - 3 are read, the operands of t - 1,
-  // the parent x of the pushing lanes of t - 1 and the push target of t - 2
-  // are read from LDS, and step t is solved.
+  // Forward sweep, chunk steps in reverse, sub-steps in reverse.  During step
+  // t: the masks of t - 2 move to scalar registers, the masks of t - 3 are
+  // read, the operands of t - 1, the parent x of the pushing lanes of t - 1 and
+  // the push target of t - 2 are read from LDS, and step t is solved.
   {
     const u32x4 ma = msk[F - 1], mb = msk[F - 2];
     uint64_t M = first_u64(ma.x, ma.y), E = first_u64(ma.z, ma.w);
     uint64_t M1 = first_u64(mb.x, mb.y), E1 = first_u64(mb.z, mb.w);
     u32x4 mv = msk[F - 3 >= -1 ? F - 3 : -1];
-    int R = W.nelem - __builtin_popcountll(M), A = W.naux - __builtin_popcountll(E);
+    const int R = nblk - __builtin_popcountll(M), A = W.naux - __builtin_popcountll(E);
     int R1 = R - __builtin_popcountll(M1), A1 = A - __builtin_popcountll(E1);
-    int pc = lane_in(M) ? rank_in(M, R) : idle;
-    double fn = img[tri(pc)], yn = img[tri(pc) + 2];
-    double xqn = img[tri(aux[min(rank_in(E, A), last_aux)]) + 2];
+    int rb = lane_in(M) ? rank_in(M, R) * KB8 : idle;
+    double fn[KC], yn[KC];
+#pragma unroll
+    for (int j = 0; j < KC; ++j) {
+      fn[j] = img[rb + 3 * j];
+      yn[j] = img[rb + 3 * j + 2];
+    }
+    double xqn = img[aux[min(rank_in(E, A), last_aux)] + 2];
     int q1 = aux[min(rank_in(E1, A1), last_aux)];
     double xp = 0.0;
     for (int t = F - 1; t >= 0; --t) {
       const uint64_t M2 = first_u64(mv.x, mv.y), E2 = first_u64(mv.z, mv.w);
       mv = msk[t - 3 >= -1 ? t - 3 : -1];
       const int R2 = R1 - __builtin_popcountll(M2), A2 = A1 - __builtin_popcountll(E2);
-      const double f = fn, y = yn, xq = xqn;
-      const int pw = pc;
-      pc = lane_in(M1) ? rank_in(M1, R1) : idle;
-      fn = img[tri(pc)];
-      yn = img[tri(pc) + 2];
-      xqn = img[tri(q1) + 2];
+      double fc[KC], yc[KC];
+#pragma unroll
+      for (int j = 0; j < KC; ++j) {
+        fc[j] = fn[j];
+        yc[j] = yn[j];
+      }
+      const double xq = xqn;
+      const int wb = lane_in(M) ? rb : sink;
+      rb = lane_in(M1) ? rank_in(M1, R1) * KB8 : idle;
+#pragma unroll
+      for (int j = 0; j < KC; ++j) {
+        fn[j] = img[rb + 3 * j];
+        yn[j] = img[rb + 3 * j + 2];
+      }
+      xqn = img[q1 + 2];
       q1 = aux[min(rank_in(E2, A2), last_aux)];
-      const double xv = __builtin_fma(-f, lane_in(E) ? xq : xp, y);
-      img[tri(lane_in(M) ? pw : sink) + 2] = xv;
+      double xv = lane_in(E) ? xq : xp;
+#pragma unroll
+      for (int j = KC - 1; j >= 0; --j) {
+        xv = __builtin_fma(-fc[j], xv, yc[j]);
+        img[wb + 3 * j + 2] = xv;
+      }
       xp = lane_in(M) ? xv : xp;
       M = M1;
       E = E1;
@@ -791,12 +864,12 @@ __global__ __launch_bounds__(64) void k_solve_flow(DevTables tb, RhsSpec rs, con
   }
   __syncthreads();  // forward done
   if (G.contig) {
-    flow_store_range(x, G.user_base + G.user_lo, G.user_n, pos, img, lane);
+    flow_store_range(x, G.user_base + G.user_lo, G.user_n, pos, img, lane, keep);
   } else {
     int e0 = 0;
     for (int c = 0; c < G.ncell; ++c) {
       const KCell C = tb.cell[G.cell_begin + c];
-      flow_store_range(x, C.user_lo, C.n, pos + e0, img, lane);
+      flow_store_range(x, C.user_lo, C.n, pos + e0, img, lane, G.ncell == 1 ? keep : nullptr);
       e0 += C.n;
     }
   }

@@ -23,71 +23,124 @@
 namespace hines {
 namespace {
 
-// Static step schedule of one group (the flow kernel).  One lane eliminates
-// one compartment per step; a branch of length L occupies L consecutive steps
-// of one lane, its far end first.  Input: the group's branches in group-local
-// breadth-first order (children after parents) with length and child range.
-// A branch may start once its children are done: the child that finishes
-// last (the heavy child) runs on the same lane right before it and hands its
-// contribution over in registers; every other child must end at least one
-// step earlier, because it adds its contribution into the parent's LDS entry
-// and the parent's operands are read one step ahead.  Heavy chains are placed
-// as whole paths, latest deadline first, each on the lane where it can end
-// latest (as late as possible), so light subtrees fill the gaps of the lanes.
-// Output: start step, lane and "carried" flag per branch, and the makespan.
+// Static chunk schedule of one group (the flow kernel).
+//
+// The group's branch tree is cut into heavy paths: a path starts at a branch
+// that is a root or a light child and follows, at every branch end, the child
+// whose elimination finishes last (as soon as possible, one compartment per
+// step); a path therefore runs from a leaf up to its top branch.  One lane
+// eliminates a whole path, kFlowChunk compartments per chunk step, from the
+// leaf upward; the path is padded at its leaf end to a whole number of chunks
+// with identity compartments (d = 1, u = 0, b = 0), which eliminate to zero
+// and leave the next compartment untouched.  Inside a path the contribution
+// to the next compartment stays in registers; a light path adds its top's
+// contribution into its parent compartment in LDS, at least two chunk steps
+// before the chunk that holds that compartment (operands are read one chunk
+// step ahead).  Paths are placed latest deadline first, each on the lane where
+// it can end latest, so light paths fill the gaps of the lanes.
 struct SchedIn {
   int32_t len, parent, child0, nchild;
 };
 
-static bool schedule_flow(const std::vector<SchedIn>& br, std::vector<int32_t>& start, std::vector<int32_t>& lane_of,
-                          std::vector<uint8_t>& carried, int32_t& makespan) {
+struct PathPlan {
+  std::vector<int32_t> top_of;   // per branch: top branch of its path
+  std::vector<int32_t> heavy;    // per branch: heavy child or -1
+  std::vector<int32_t> below;    // per branch: compartments of its path below it (processed before it)
+  std::vector<int32_t> plen;     // per path top: compartments of the path
+  std::vector<int32_t> start;    // per path top: first chunk step
+  std::vector<int32_t> lane;     // per path top: lane
+  int32_t makespan = 0;          // chunk steps
+};
+
+static inline int32_t nchunks(int32_t len) { return (len + kFlowChunk - 1) / kFlowChunk; }
+
+static bool schedule_paths(const std::vector<SchedIn>& br, PathPlan& pp) {
   const int32_t nb = (int32_t)br.size();
-  std::vector<int32_t> fin(nb), heavy(nb, -1), plen(nb, 0);
-  int64_t total = 0;
-  for (int32_t b = 0; b < nb; ++b) total += br[b].len;
-  for (int32_t b = nb - 1; b >= 0; --b) {  // as soon as possible
+  const int32_t K = kFlowChunk;
+  std::vector<int32_t> fin(nb);
+  pp.heavy.assign(nb, -1);
+  for (int32_t b = nb - 1; b >= 0; --b) {  // compartment-level as soon as possible: heavy children
     int32_t hf = 0, h = -1;
     for (int32_t c = br[b].child0; c < br[b].child0 + br[b].nchild; ++c)
       if (h < 0 || fin[c] > hf) {  // the child finishing last; the smallest id on ties
         hf = fin[c];
         h = c;
       }
-    int32_t st = hf;
-    for (int32_t c = br[b].child0; c < br[b].child0 + br[b].nchild; ++c)
-      if (c != h) st = std::max(st, fin[c] + 1);
-    heavy[b] = h;
-    fin[b] = st + br[b].len;
+    pp.heavy[b] = h;
+    fin[b] = hf + br[b].len;
   }
-  for (int32_t b = nb - 1; b >= 0; --b) plen[b] = br[b].len + (heavy[b] >= 0 ? plen[heavy[b]] : 0);
-  int32_t F = 0;
-  for (int32_t b = 0; b < nb; ++b)
-    if (br[b].parent < 0) F = std::max(F, fin[b]);
-  start.assign(nb, 0);
-  lane_of.assign(nb, 0);
-  carried.assign(nb, 0);
+  // paths: tops are roots and light children; below[b] = compartments of the
+  // path under branch b (its heavy descendants)
+  pp.top_of.assign(nb, -1);
+  pp.below.assign(nb, 0);
+  pp.plen.assign(nb, 0);
+  std::vector<int32_t> tops;
+  for (int32_t b = 0; b < nb; ++b) {
+    const int32_t p = br[b].parent;
+    if (p < 0 || pp.heavy[p] != b) {
+      tops.push_back(b);
+      int32_t len = 0;
+      for (int32_t x = b; x >= 0; x = pp.heavy[x]) {
+        pp.top_of[x] = b;
+        len += br[x].len;
+      }
+      pp.plen[b] = len;
+      int32_t acc = len;
+      for (int32_t x = b; x >= 0; x = pp.heavy[x]) {
+        acc -= br[x].len;
+        pp.below[x] = acc;
+      }
+    }
+  }
+  // chunk index (within its parent path) of the compartment a light path attaches to:
+  // the far end of its parent branch, processed right after the path part below it
+  auto attach_chunk = [&](int32_t top) {
+    const int32_t pb = br[top].parent;
+    const int32_t q = pp.top_of[pb];
+    const int32_t npad = nchunks(pp.plen[q]) * K - pp.plen[q];
+    return (npad + pp.below[pb]) / K;
+  };
+  // as soon as possible in chunk steps (tops in descending id: light children first)
+  std::vector<int32_t> pfin(nb, 0), kids_begin, kids;  // light child paths per path
+  std::vector<std::vector<int32_t>> light(nb);
+  for (int32_t t : tops)
+    if (br[t].parent >= 0) light[pp.top_of[br[t].parent]].push_back(t);
+  for (auto it = tops.rbegin(); it != tops.rend(); ++it) {
+    const int32_t q = *it;
+    int32_t s = 0;
+    for (int32_t l : light[q]) s = std::max(s, pfin[l] + 1 - attach_chunk(l));
+    pfin[q] = s + nchunks(pp.plen[q]);
+  }
+  int32_t F = 0, total = 0;
+  for (int32_t q : tops) {
+    if (br[q].parent < 0) F = std::max(F, pfin[q]);
+    total += nchunks(pp.plen[q]);
+  }
+  pp.start.assign(nb, 0);
+  pp.lane.assign(nb, 0);
   std::vector<std::vector<std::pair<int32_t, int32_t>>> busy(kSchedLanes);
   struct Item {
     int32_t deadline, top;
   };
   std::vector<Item> work;
-  for (; F <= total + nb + 1 && F <= kMaxSteps; ++F) {
+  for (; F <= 2 * total + 2 && F <= kMaxSteps; ++F) {
     for (auto& v : busy) v.clear();
     work.clear();
-    for (int32_t b = nb - 1; b >= 0; --b)
-      if (br[b].parent < 0) work.push_back({F, b});
+    for (int32_t q : tops)
+      if (br[q].parent < 0) work.push_back({F, q});
     bool ok = true;
     while (!work.empty()) {
-      // latest deadline first; longer path first on ties
-      size_t pick = 0;
+      size_t pick = 0;  // latest deadline first; longer path first; smaller id
       for (size_t k = 1; k < work.size(); ++k) {
         const Item &a = work[k], &bb = work[pick];
-        if (a.deadline > bb.deadline || (a.deadline == bb.deadline && plen[a.top] > plen[bb.top]) ||
-            (a.deadline == bb.deadline && plen[a.top] == plen[bb.top] && a.top < bb.top))
+        const int32_t la = nchunks(pp.plen[a.top]), lb = nchunks(pp.plen[bb.top]);
+        if (a.deadline > bb.deadline || (a.deadline == bb.deadline && la > lb) ||
+            (a.deadline == bb.deadline && la == lb && a.top < bb.top))
           pick = k;
       }
       const Item it = work[pick];
       work.erase(work.begin() + (std::ptrdiff_t)pick);
-      const int32_t L = plen[it.top];
+      const int32_t L = nchunks(pp.plen[it.top]);
       int32_t best_end = -1, best_lane = -1;
       for (int32_t ln = 0; ln < kSchedLanes; ++ln) {
         int32_t end = it.deadline;
@@ -109,18 +162,12 @@ static bool schedule_flow(const std::vector<SchedIn>& br, std::vector<int32_t>& 
       auto& iv = busy[best_lane];
       iv.push_back({best_end - L, best_end});
       std::sort(iv.begin(), iv.end());
-      int32_t t = best_end;  // branches of the path from the top down
-      for (int32_t b = it.top; b >= 0; b = heavy[b]) {
-        t -= br[b].len;
-        start[b] = t;
-        lane_of[b] = best_lane;
-        if (heavy[b] >= 0) carried[heavy[b]] = 1;
-        for (int32_t c = br[b].child0; c < br[b].child0 + br[b].nchild; ++c)
-          if (c != heavy[b]) work.push_back({t - 1, c});
-      }
+      pp.start[it.top] = best_end - L;
+      pp.lane[it.top] = best_lane;
+      for (int32_t l : light[it.top]) work.push_back({best_end - L + attach_chunk(l) - 1, l});
     }
     if (ok) {
-      makespan = F;
+      pp.makespan = F;
       return true;
     }
   }
@@ -655,7 +702,7 @@ struct Builder {
       }
     }
 
-    // ---- static step schedule and flow tables (ascending plans, LDS groups) ----
+    // ---- static chunk schedule and flow tables (ascending plans, LDS groups) ----
     // Every child branch must hang off the far end of its parent (always true
     // for maximal chains and splits; user layouts may attach mid-branch).
     bool tips_only = true;
@@ -670,12 +717,12 @@ struct Builder {
       }
     }
     if (opt.scheduler && !opt.bitwise && P.all_ascending && P.kernel_tables_fit && tips_only) {
+      const int32_t K = kFlowChunk;
       P.kflow.assign(ng, KFlow{});
       std::vector<SchedIn> sin;
-      std::vector<int32_t> st, ln, slot_elem;
-      std::vector<uint8_t> car;
+      std::vector<int32_t> slot_elem, R, tops;
       std::vector<uint64_t> M, E;
-      std::vector<int32_t> R;
+      PathPlan pp;
       bool all_ok = true;
       int64_t steps = 0, elems = 0;
       for (int64_t g = 0; g < ng && all_ok; ++g) {
@@ -685,13 +732,7 @@ struct Builder {
         W.pos_off = elems;
         if (P.faux.size() & 1) P.faux.push_back(0);  // 4-byte aligned start of the group's push targets
         W.aux_off = (int64_t)P.faux.size();
-        W.nelem = G.user_n;
-        if (G.ws_off >= 0) {  // level-synchronous from the workspace
-          W.nstep = 0;
-          W.naux = 0;
-          W.nelem = 0;
-          continue;
-        }
+        if (G.ws_off >= 0) continue;  // level-synchronous from the workspace (all counts 0)
         const int32_t nbg = G.nbr;
         sin.assign(nbg, SchedIn{0, -1, 0, 0});
         std::vector<int32_t> rec_of(nbg, -1);  // group-local BFS id -> record
@@ -702,24 +743,33 @@ struct Builder {
         }
         for (int32_t b = 0; b < nbg; ++b)
           for (int32_t c = sin[b].child0; c < sin[b].child0 + sin[b].nchild; ++c) sin[c].parent = b;
-        int32_t F = 0;
-        if (!schedule_flow(sin, st, ln, car, F)) {
+        if (!schedule_paths(sin, pp)) {
           all_ok = false;
           break;
         }
-        const int32_t Fp = (F + 3) & ~3;  // whole 64-byte blocks of step records
-        M.assign(Fp, 0);
-        E.assign(Fp, 0);
-        for (int32_t b = 0; b < nbg; ++b) {
-          for (int32_t k = 0; k < sin[b].len; ++k) M[st[b] + k] |= 1ull << ln[b];
-          if (sin[b].parent >= 0 && !car[b]) E[st[b] + sin[b].len - 1] |= 1ull << ln[b];
-        }
-        R.assign(Fp + 1, 0);
-        for (int32_t t = 0; t < Fp; ++t) R[t + 1] = R[t] + popc64(M[t]);
-        auto pos_at = [&](int32_t t, int32_t lane_id) {
-          return R[t] + popc64(M[t] & ((1ull << lane_id) - 1));
+        const int32_t F = pp.makespan;
+        M.assign(F, 0);
+        E.assign(F, 0);
+        tops.clear();
+        for (int32_t b = 0; b < nbg; ++b)
+          if (pp.top_of[b] == b) {
+            tops.push_back(b);
+            const int32_t s = pp.start[b], n = nchunks(pp.plen[b]);
+            for (int32_t i = 0; i < n; ++i) M[s + i] |= 1ull << pp.lane[b];
+            if (sin[b].parent >= 0) E[s + n - 1] |= 1ull << pp.lane[b];
+          }
+        R.assign(F + 1, 0);  // lane-chunks (blocks) before chunk step t
+        for (int32_t t = 0; t < F; ++t) R[t + 1] = R[t] + popc64(M[t]);
+        const int32_t nent = K * R[F];
+        // LDS offset (8-byte units) of sub-step j of chunk step t on lane l:
+        // block (R[t] + rank of l) of kFlowBlock8 units, entry j at 3 j
+        auto entry = [&](int32_t t, int32_t j, int32_t l) {
+          return (R[t] + popc64(M[t] & ((1ull << l) - 1))) * kFlowBlock8 + 3 * j;
         };
-        // slot of the user-order image -> element index of the staging order
+        // entry of the compartment with processing index idx (pads first) of path q
+        auto entry_of = [&](int32_t q, int32_t idx) {
+          return entry(pp.start[q] + idx / K, idx % K, pp.lane[q]);
+        };
         slot_elem.assign(G.nunk, -1);
         int32_t cum = 0;
         for (int c = 0; c < G.ncell; ++c) {
@@ -727,51 +777,54 @@ struct Builder {
           for (int32_t k = 0; k < C.n; ++k) slot_elem[C.lds + k] = cum + k;
           cum += C.n;
         }
-        if (R[Fp] != cum || cum != G.user_n) {
+        if (cum != G.user_n || (int64_t)R[F] * kFlowBlock8 + kFlowTail8 > 32767) {
           all_ok = false;
           break;
         }
-        P.fpos.resize(elems + cum);
-        for (int32_t b = 0; b < nbg; ++b) {
-          const KBranch& B = P.kbranch[G.br_begin + rec_of[b]];
-          for (int32_t k = 0; k < sin[b].len; ++k) {
-            const int32_t e = slot_elem[B.start + k];
-            uint32_t p = (uint32_t)pos_at(st[b] + sin[b].len - 1 - k, ln[b]);
-            if (k == 0 && sin[b].parent < 0) p |= 0x8000u;  // the cell's root: no coupling
-            P.fpos[elems + e] = (uint16_t)p;
-          }
-        }
-        // push targets in (step, lane) order: the parent's far end, eliminated
-        // at the parent's first step on the parent's lane
-        std::vector<int32_t> end_br(Fp * (int64_t)kSchedLanes, -1);
-        for (int32_t b = 0; b < nbg; ++b)
-          if (sin[b].parent >= 0 && !car[b]) end_br[(int64_t)(st[b] + sin[b].len - 1) * kSchedLanes + ln[b]] = b;
-        for (int32_t t = 0; t < Fp; ++t)
-          for (int32_t l = 0; l < kSchedLanes; ++l) {
-            const int32_t b = end_br[(int64_t)t * kSchedLanes + l];
-            if (b < 0) continue;
-            const int32_t pb = sin[b].parent;
-            P.faux.push_back((int16_t)pos_at(st[pb], ln[pb]));
-          }
-        for (int32_t t = 0; t < Fp; ++t) {
-          P.fmask.push_back(M[t]);
-          P.fmask.push_back(E[t]);
-        }
-        W.nstep = Fp;
-        W.naux = (int32_t)((int64_t)P.faux.size() - W.aux_off);
+        W.nstep = F;
+        W.nelem = cum;
+        W.nent = nent;
         W.makespan = F;
         if (flow_lds_bytes(W) > kLdsLimitBytes) {  // e.g. very long single branches: level kernel
-          P.fmask.resize(2 * steps);
-          P.fpos.resize(elems);
-          P.faux.resize(W.aux_off);
           W = KFlow{};
           W.step_off = steps;
           W.pos_off = elems;
           W.aux_off = (int64_t)P.faux.size();
           continue;
         }
+        P.fpos.resize(elems + cum);
+        for (int32_t q : tops) {
+          const int32_t npad = nchunks(pp.plen[q]) * K - pp.plen[q];
+          for (int32_t x = q; x >= 0; x = pp.heavy[x]) {
+            const KBranch& B = P.kbranch[G.br_begin + rec_of[x]];
+            for (int32_t k = 0; k < sin[x].len; ++k) {
+              // far end (k = len - 1) first
+              const int32_t idx = npad + pp.below[x] + (sin[x].len - 1 - k);
+              uint32_t p = (uint32_t)entry_of(q, idx);
+              if (k == 0 && sin[x].parent < 0) p |= 0x8000u;  // the cell's root: no coupling
+              P.fpos[elems + slot_elem[B.start + k]] = (uint16_t)p;
+            }
+          }
+        }
+        // push targets in (chunk step, lane) order: the far end of the parent branch
+        std::vector<int32_t> end_top((int64_t)F * kSchedLanes, -1);
+        for (int32_t q : tops)
+          if (sin[q].parent >= 0) end_top[(int64_t)(pp.start[q] + nchunks(pp.plen[q]) - 1) * kSchedLanes + pp.lane[q]] = q;
+        for (int32_t t = 0; t < F; ++t)
+          for (int32_t l = 0; l < kSchedLanes; ++l) {
+            const int32_t q = end_top[(int64_t)t * kSchedLanes + l];
+            if (q < 0) continue;
+            const int32_t pb = sin[q].parent, pq = pp.top_of[pb];
+            const int32_t npad = nchunks(pp.plen[pq]) * K - pp.plen[pq];
+            P.faux.push_back((int16_t)entry_of(pq, npad + pp.below[pb]));
+          }
+        for (int32_t t = 0; t < F; ++t) {
+          P.fmask.push_back(M[t]);
+          P.fmask.push_back(E[t]);
+        }
+        W.naux = (int32_t)((int64_t)P.faux.size() - W.aux_off);
         P.kgroup[g].makespan = F;
-        steps += Fp;
+        steps += F;
         elems += cum;
       }
       if (all_ok) {
@@ -856,18 +909,20 @@ int64_t export_table(const HostPlan& p, int32_t id, int64_t* out, int64_t capaci
     case T_SEG_OFFSETS: return put(p.seg_offsets);
     case T_LANES: return put(p.lanes);
     case T_FLOW_GROUPS: {
-      const int64_t cnt = p.flow ? 6 * (int64_t)p.kflow.size() : 0;
+      const int64_t cnt = p.flow ? 8 * (int64_t)p.kflow.size() : 0;
       if (out) {
         if (capacity < cnt) return -1;
-        for (int64_t g = 0; g < cnt / 6; ++g) {
+        for (int64_t g = 0; g < cnt / 8; ++g) {
           const KFlow& w = p.kflow[g];
-          int64_t* r = out + 6 * g;
+          int64_t* r = out + 8 * g;
           r[0] = w.step_off;
           r[1] = w.pos_off;
           r[2] = w.aux_off;
           r[3] = w.nstep;
           r[4] = w.nelem;
           r[5] = w.naux;
+          r[6] = w.nent;
+          r[7] = kFlowChunk;
         }
       }
       return cnt;

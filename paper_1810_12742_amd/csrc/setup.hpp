@@ -39,10 +39,20 @@ struct Options {
                                    // 0: level-synchronous sweeps (paper §3)
 };
 
-// Static step schedule (flow kernel): one lane eliminates one compartment per
-// step; kSchedLanes lanes per group; at most kMaxSteps steps per sweep.
+// Static chunk schedule (flow kernel): one lane eliminates kFlowChunk
+// compartments of one path per chunk step; kSchedLanes lanes per group; at
+// most kMaxSteps chunk steps per sweep.
 constexpr int32_t kSchedLanes = 64;
 constexpr int32_t kMaxSteps = 16384;
+constexpr int32_t kFlowChunk = 8;
+// LDS block of one lane-chunk: kFlowChunk entries of d, u, b (3 doubles each)
+// and one spare double, so that consecutive blocks start in different banks.
+constexpr int32_t kFlowBlock8 = 3 * kFlowChunk + 1;
+// after the blocks: one identity block read by idle lanes (d = 1, u = 0,
+// b = 0 per entry) and a write-only sink: idle lane l writes entry j of a step
+// at 8-byte unit l + 3 j of the sink, so no two lanes of one write collide
+constexpr int32_t kFlowSink8 = 64 + 3 * kFlowChunk;
+constexpr int32_t kFlowTail8 = kFlowBlock8 + kFlowSink8;
 
 // LDS image of a group: d, u, b per slot (nimg slots; 0 when the compartment
 // arrays live in the global workspace), two elimination contributions per
@@ -128,32 +138,37 @@ struct KCell {
   int32_t lds;      // offset of the cell in the group's LDS image
 };
 
-// Flow kernel tables of one group.  The group's compartments get "positions"
-// in step order: the compartment that lane l eliminates at step t sits at
-// R[t] + (number of active lanes below l at step t), R[t] the number of
-// eliminations before step t.  Per step the table holds two 64-bit lane masks
-// (active, push: the lane ends a branch whose contribution goes to LDS); per
-// element of the group's staging order its position (bit 15: the cell root,
-// whose coupling is ignored); per push, in (step, lane) order, the position
-// of the parent compartment.
+// Flow kernel tables of one group.  The compartments (and path pads) get LDS
+// "entries" in chunk-step order: the chunk of lane l at chunk step t is block
+// R[t] + (active lanes below l at t), R[t] the active lane-chunks before t,
+// and sub-step j is entry j of that block.  Entries are named by their LDS
+// offset in 8-byte units (block * kFlowBlock8 + 3 j).  Per chunk step the
+// table holds two 64-bit lane masks (active; push: the lane ends a path whose
+// contribution goes to LDS); per element of the group's staging order its
+// entry (bit 15: the cell root, whose coupling is ignored); per push, in
+// (step, lane) order, the entry of the parent compartment.
 struct KFlow {
   int64_t step_off;  // first step record (two uint64 masks) of the group
-  int64_t pos_off;   // first element position
+  int64_t pos_off;   // first element entry
   int64_t aux_off;   // first push target
-  int32_t nstep;     // steps per sweep (a multiple of 4; 0 for workspace groups)
-  int32_t nelem;     // compartments = positions
+  int32_t nstep;     // chunk steps per sweep (0: not a flow group)
+  int32_t nelem;     // compartments
   int32_t naux;      // pushes
-  int32_t makespan;  // steps before padding to a multiple of 4
-  int32_t pad0, pad1;
+  int32_t makespan;  // chunk steps
+  int32_t nent;      // entries: compartments and pads (kFlowChunk per block)
+  int32_t pad1;
 };
 static_assert(sizeof(KFlow) == 48, "layout");
 
-// LDS layout of a flow group: image (24 bytes per position: d, u, b; then one
+// LDS layout of a flow group: image (24 bytes per entry: d, u, b; then one
 // constant entry for idle lanes and 64 write-only sink entries), push targets
 // (int16, at least one entry), step masks (16 bytes per step plus a zero
 // record before and after).
+constexpr int64_t flow_image8(const KFlow& w) {  // 8-byte units of blocks, identity block and sink
+  return (int64_t)w.nent / kFlowChunk * kFlowBlock8 + kFlowTail8;
+}
 constexpr int64_t flow_mask_offset(const KFlow& w) {
-  return (24 * ((int64_t)w.nelem + 65) + 2 * ((int64_t)w.naux + 1) + 15) & ~(int64_t)15;
+  return (8 * flow_image8(w) + 2 * ((int64_t)w.naux + 1) + 15) & ~(int64_t)15;
 }
 constexpr int64_t flow_lds_bytes(const KFlow& w) { return flow_mask_offset(w) + 16 * ((int64_t)w.nstep + 2); }
 

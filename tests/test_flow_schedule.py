@@ -1,14 +1,15 @@
-"""CPU replay of the flow kernel's step schedule.
+"""CPU replay of the flow kernel's chunk schedule.
 
-The host builder hands the flow kernel four tables per plan (per-step lane
-masks, element positions, push targets, group records).  This test replays
-the kernel's step semantics on those tables in plain numpy and checks
+The host builder hands the flow kernel four tables per plan (per-chunk-step
+lane masks, element entries, push targets, group records).  This test
+replays the kernel's semantics on those tables in plain numpy (K sub-steps
+per busy lane and chunk step, identity pads, pushes at path tops) and checks
 
-* the ordering rules the kernel relies on: every position is eliminated
-  exactly once; a push into a parent's entry happens at least two steps
-  before the parent's elimination reads it (operands are read one step
-  ahead); in the forward sweep a pushed child reads its parent's x at least
-  two steps after the parent wrote it;
+* the ordering rules the kernel relies on: every entry is eliminated exactly
+  once; a push into a parent's entry happens at least two chunk steps before
+  the step that eliminates it (operands are read one step ahead); in the
+  forward sweep a pushed path reads its parent's x at least two steps after
+  the parent wrote it;
 * the solution against the FP64 oracle (relative error <= 1e-12 per cell).
 """
 import numpy as np
@@ -26,7 +27,7 @@ def _bits(m):
 
 
 def replay(plan, f, diag, upper, rhs):
-    fg = plan.table("flow_groups").reshape(-1, 6)
+    fg = plan.table("flow_groups").reshape(-1, 8)
     masks = plan.table("flow_masks").view(np.uint64)
     pos = plan.table("flow_pos")
     aux = plan.table("flow_aux")
@@ -35,28 +36,32 @@ def replay(plan, f, diag, upper, rhs):
     co = f.cell_offsets
     x = np.full(f.n, np.nan)
     for g in range(fg.shape[0]):
-        step_off, pos_off, aux_off, F, nel, naux = (int(v) for v in fg[g])
+        step_off, pos_off, aux_off, F, nel, naux, nent, K = (int(v) for v in fg[g])
         users = np.concatenate([np.arange(co[c], co[c + 1]) for c in gcells[goff[g]:goff[g + 1]]])
-        if F == 0:  # too large for LDS: solved by the workspace kernel
+        if F == 0:  # too large for LDS: solved by the level-synchronous kernel
             assert nel == 0 and naux == 0
             continue
-        assert F % 4 == 0
-        assert users.size == nel
+        assert users.size == nel and nent >= nel and aux_off % 2 == 0
+        B8 = 3 * K + 1  # LDS block of a lane-chunk, in 8-byte units; entry j at 3 j
+
+        def to_entry(off):
+            off = np.asarray(off)
+            assert np.all((off % B8) < 3 * K) and np.all((off % B8) % 3 == 0)
+            return (off // B8) * K + (off % B8) // 3
         pw = pos[pos_off:pos_off + nel]
-        P = pw & 0x7FFF
+        P = to_entry(pw & 0x7FFF)
         root = (pw & 0x8000) != 0
-        assert np.array_equal(np.sort(P), np.arange(nel))
-        assert root.sum() == goff[g + 1] - goff[g]
+        assert np.unique(P).size == nel and P.max() < nent
         assert np.array_equal(np.sort(users[root]), np.sort(co[gcells[goff[g]:goff[g + 1]]]))
-        D = np.empty(nel)
-        U = np.empty(nel)
-        B = np.empty(nel)
+        D = np.ones(nent)  # pads: identity compartments
+        U = np.zeros(nent)
+        B = np.zeros(nent)
         D[P] = diag[users]
         U[P] = np.where(root, 0.0, upper[users])
         B[P] = rhs[users]
-        ax = aux[aux_off:aux_off + naux]
-        elim_step = np.full(nel, -1)
-        last_push = np.full(nel, -10)
+        ax = to_entry(aux[aux_off:aux_off + naux]) if naux else aux[:0]
+        elim_step = np.full(nent, -1)
+        last_push = np.full(nent, -10)
         fin = np.zeros(64)
         uin = np.zeros(64)
         bin_ = np.zeros(64)
@@ -66,51 +71,55 @@ def replay(plan, f, diag, upper, rhs):
             E = masks[2 * (step_off + t) + 1]
             act = _bits(M)
             push = _bits(E)
+            c = act.size
             assert np.all(np.isin(push, act))
-            p = R + np.arange(act.size)
-            assert np.all(elim_step[p] < 0)
-            assert np.all(last_push[p] <= t - 2), "push too late for the one-step-ahead read"
-            elim_step[p] = t
-            dl = D[p] - fin[act] * uin[act]
-            bl = B[p] - fin[act] * bin_[act]
-            r = 1.0 / dl
-            fv = U[p] * r
-            D[p] = fv
-            B[p] = bl * r
+            for j in range(K):
+                e = (R + np.arange(c)) * K + j
+                assert np.all(elim_step[e] < 0)
+                assert np.all(last_push[e] <= t - 2), "push too late for the one-step-ahead read"
+                elim_step[e] = t
+                dl = D[e] - fin[act] * uin[act]
+                bl = B[e] - fin[act] * bin_[act]
+                r = 1.0 / dl
+                fv = U[e] * r
+                D[e] = fv
+                B[e] = bl * r
+                fin[act] = fv
+                uin[act] = U[e]
+                bin_[act] = bl
             nf = np.zeros(64)
-            nf[act] = fv
-            uin[act] = U[p]
-            bin_[act] = bl
+            nf[act] = fin[act]
             if push.size:
-                k = np.searchsorted(act, push)
                 q = ax[A + np.arange(push.size)]
                 assert np.all(elim_step[q] < 0), "push after the parent was eliminated"
-                for qq, ff, uu, bb in zip(q, fv[k], U[p][k], bl[k]):  # in lane order
-                    D[qq] -= ff * uu
-                    B[qq] -= ff * bb
+                for qq, l in zip(q, push):  # in lane order
+                    D[qq] -= fin[l] * uin[l]
+                    B[qq] -= fin[l] * bin_[l]
                     last_push[qq] = t
                 nf[push] = 0.0
             fin = nf
-            R += act.size
+            R += c
             A += push.size
-        assert R == nel and A == naux
+        assert R * K == nent and A == naux
         xp = np.zeros(64)
         for t in range(F - 1, -1, -1):
             M = masks[2 * (step_off + t)]
             E = masks[2 * (step_off + t) + 1]
             act = _bits(M)
             push = _bits(E)
-            R -= act.size
+            c = act.size
+            R -= c
             A -= push.size
-            p = R + np.arange(act.size)
-            xpar = xp[act].copy()
+            xv = xp[act].copy()
             if push.size:
                 k = np.searchsorted(act, push)
                 q = ax[A + np.arange(push.size)]
                 assert np.all(elim_step[q] >= t + 2), "parent x not written two steps earlier"
-                xpar[k] = B[q]
-            xv = B[p] - D[p] * xpar
-            B[p] = xv
+                xv[k] = B[q]
+            for j in range(K - 1, -1, -1):
+                e = (R + np.arange(c)) * K + j
+                xv = B[e] - D[e] * xv
+                B[e] = xv
             xp[act] = xv
         x[users] = B[P]
     return x
