@@ -72,7 +72,14 @@ typedef struct hines_options {
                                  0 (default): when every branch runs toward higher user indices
                                  and bitwise is 0, a static per-lane schedule computed at setup
                                  (each branch starts once its children are done; no barriers) */
-  int32_t reserved[7];        /* must be 0 */
+  int32_t cell_lanes;         /* 1: hines_solve and hines_timestep run one lane per cell (paper
+                                 §2's elimination in a depth-first order of each cell, 64 cells
+                                 of similar size per wave, elimination factors kept in a device
+                                 scratch of 16 bytes per compartment owned by the plan); needs
+                                 bitwise 0, cells of at most 65535 compartments and a stack need
+                                 of at most 12 (HINES_ERR_TOO_BIG otherwise).  hines_solve_mixed
+                                 keeps using the groups.  0 (default): groups (§3-§4)        */
+  int32_t reserved[6];        /* must be 0 */
 } hines_options;
 
 /* Plan summary. */
@@ -82,7 +89,8 @@ typedef struct hines_plan_info {
   int32_t nclasses;           /* LDS size classes (kernel launches per solve) */
   int64_t device_table_bytes; /* device memory held by the plan */
   int64_t max_group_lds_bytes;
-  int32_t kernel;             /* 0 level-synchronous, 1 flow (static step schedule), 2 bitwise */
+  int32_t kernel;             /* 0 level-synchronous, 1 flow (static step schedule), 2 bitwise,
+                                 3 cell lanes                                                 */
   int32_t max_makespan;       /* scheduled plans: longest schedule, in iterations */
   int64_t workspace_groups;   /* groups too large for LDS, solved from a global workspace */
 } hines_plan_info;
@@ -109,7 +117,16 @@ enum {
                                         (64-bit patterns stored in int64)                    */
   HINES_TABLE_FLOW_POS = 10,         /* [elements] LDS position of each element of a group's
                                         staging order; 0x8000 marks a cell root              */
-  HINES_TABLE_FLOW_AUX = 11          /* [pushes] position receiving each push, step order     */
+  HINES_TABLE_FLOW_AUX = 11,         /* [pushes] position receiving each push, step order     */
+  /* Cell-lane plans (hines_plan_info.kernel == 3): 64 lanes per wave, chunks of 16 steps.  */
+  HINES_TABLE_CELL_WAVES = 12,       /* [nwaves*3] first chunk, chunks per sweep, cells       */
+  HINES_TABLE_CELL_LANES = 13,       /* [nwaves*64] cell of each lane, -1 if empty            */
+  HINES_TABLE_CELL_POS = 14,         /* [chunks*1024] per chunk, lane j, slot r: position of
+                                        element (j % 16) of lane (4 r + j / 16)'s cell relative
+                                        to its first compartment in backward step order, 65535
+                                        for padding                                           */
+  HINES_TABLE_CELL_FLAGS = 15        /* [chunks*1024] per chunk, lane c, element e: flags
+                                        1 tip, 2 pop, 4 push, 8 merge, 16 padding, 32 root    */
 };
 
 /* Fill *opt with the defaults: no re-rooting, no splitting, group_width 64,

@@ -31,12 +31,16 @@ def _run(cmd, verbose):
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    setup_o = os.path.join(BUILD, "setup.o")
+    objs = []
+    for src in ("setup.cpp", "cells.cpp"):
+        o = os.path.join(BUILD, src.replace(".cpp", ".o"))
+        _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", o], verbose)
+        objs.append(o)
     hines_o = os.path.join(BUILD, "hines.o")
-    _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "setup.cpp"), "-o", setup_o], verbose)
     _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "hines.hip"), "-o", hines_o], verbose)
+    objs.append(hines_o)
     tmp = LIB + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-o", tmp, setup_o, hines_o], verbose)
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-o", tmp, *objs], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -79,6 +79,7 @@ struct hines_plan {
   hines::HostPlan host;
   int device = -1;
   void* dev_mem = nullptr;
+  void* scr_mem = nullptr;  // cell-lane kernel: (f, y) scratch
   int64_t dev_bytes = 0;
   DevTables t{};
   struct Bucket {
@@ -143,6 +144,18 @@ void launch_bucket(const hines_plan* p, const hines_plan::Bucket& bk, const RhsS
 
 hipError_t launch_solve(const hines_plan* p, const RhsSpec& rs, const double* d, const double* u, double* x,
                         hipStream_t s) {
+  if (p->host.cl.built) {
+    const dim3 grid((unsigned)p->host.cl.nwaves);
+    if (rs.mode == hdev::kRhsGiven)
+      hipLaunchKernelGGL(hdev::k_solve_cells<hdev::kFlowGiven>, grid, dim3(64), 0, s, p->t, rs, d, u, x);
+    else if (rs.mode == hdev::kRhsNoise)
+      hipLaunchKernelGGL(hdev::k_solve_cells<hdev::kFlowNoise>, grid, dim3(64), 0, s, p->t, rs, d, u, x);
+    else if (rs.icur)
+      hipLaunchKernelGGL(hdev::k_solve_cells<hdev::kFlowCVI>, grid, dim3(64), 0, s, p->t, rs, d, u, x);
+    else
+      hipLaunchKernelGGL(hdev::k_solve_cells<hdev::kFlowCV>, grid, dim3(64), 0, s, p->t, rs, d, u, x);
+    return hipGetLastError();
+  }
   for (const auto& bk : p->buckets) {
     if (bk.count == 0) continue;
     switch (p->host.opt.group_width) {
@@ -344,6 +357,69 @@ bool check_kernel_tables(const hines::HostPlan& P, std::string& why, bool& capac
   return true;
 }
 
+// Cell-lane tables: every wave's chunks inside the tables, every position
+// inside its lane's cell, and per lane a stack that never underflows nor
+// leaves its kCellStack LDS slots, in both sweeps, so that no kernel access
+// leaves its buffers whatever the tables hold.
+bool check_cell_tables(const hines::HostPlan& P, const int64_t* cell_offsets, std::string& why) {
+  const hines::CellLanes& C = P.cl;
+  for (int64_t w = 0; w < C.nwaves; ++w) {
+    const hines::KCellWave& W = C.waves[w];
+    if (W.chunk_off < 0 || W.nchunk < 0 || W.chunk_off + W.nchunk > C.nchunks || W.ncell < 1 || W.ncell > 64) {
+      why = "wave " + std::to_string(w) + " record out of range";
+      return false;
+    }
+    for (int c = 0; c < 64; ++c) {
+      const int32_t cell = C.lane_cell[w * 64 + c];
+      const int64_t lo = C.base[w * 64 + c];
+      int64_t size = 0;
+      if (cell >= 0) {
+        if (cell >= P.ncells || lo != cell_offsets[cell]) {
+          why = "wave " + std::to_string(w) + " lane cell out of range";
+          return false;
+        }
+        size = cell_offsets[cell + 1] - lo;
+      } else if (lo != 0) {
+        why = "empty lane with a base";
+        return false;
+      }
+      // stack entries per sweep (the top in registers, the rest in slots 1..)
+      int m = 0;
+      bool ok_b = true;
+      for (int64_t k = 0; k < W.nchunk && ok_b; ++k)
+        for (int e = 0; e < hines::kCellChunk && ok_b; ++e) {
+          const int64_t g = W.chunk_off + k;
+          const uint8_t f = C.flags[g * 1024 + c * 16 + e];
+          const uint16_t ps = C.pos[g * 1024 + (((c & 3) << 4) | e) * 16 + (c >> 2)];
+          if ((ps == hines::kCellPadPos) != ((f & hines::CF_PAD) != 0) || (ps != hines::kCellPadPos && ps >= size)) {
+            why = "wave " + std::to_string(w) + " position out of range";
+            return false;
+          }
+          if (f & hines::CF_POP) ok_b = m-- >= 1;
+          if ((f & hines::CF_MERGE) && m < 1) ok_b = false;
+          if (f & hines::CF_PUSH) ok_b = ok_b && m++ < hines::kCellStack;
+        }
+      if (!ok_b || m != 0) {
+        why = "wave " + std::to_string(w) + " lane " + std::to_string(c) + " backward stack unbalanced";
+        return false;
+      }
+      bool ok_f = true;
+      for (int64_t k = W.nchunk - 1; k >= 0 && ok_f; --k)
+        for (int e = hines::kCellChunk - 1; e >= 0 && ok_f; --e) {
+          const uint8_t f = C.flags[(W.chunk_off + k) * 1024 + c * 16 + e];
+          if ((f & (hines::CF_PUSH | hines::CF_MERGE)) && m < 1) ok_f = false;
+          if (f & hines::CF_PUSH) --m;
+          if (f & hines::CF_POP) ok_f = ok_f && m++ < hines::kCellStack;
+        }
+      if (!ok_f || m != 0) {
+        why = "wave " + std::to_string(w) + " lane " + std::to_string(c) + " forward stack unbalanced";
+        return false;
+      }
+    }
+  }
+  return true;
+}
+
 hines_status check_call(const hines_plan* p, int32_t ncells) {
   if (!p) return set_err(HINES_ERR_NULL, "plan is NULL");
   if (p->host.opt.host_only) return set_err(HINES_ERR_STATE, "plan was built host_only");
@@ -432,8 +508,10 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
     opt = *opt_in;
   else
     hines_default_options(&opt);
-  for (int k = 0; k < 7; ++k)
+  for (int k = 0; k < 6; ++k)
     if (opt.reserved[k] != 0) return set_err(HINES_ERR_OPTION, "reserved option fields must be 0");
+  if (opt.cell_lanes && opt.bitwise)
+    return set_err(HINES_ERR_OPTION, "cell_lanes needs the fast arithmetic form (bitwise 0)");
   hines::Options o;
   o.rebalance_root = opt.rebalance_root != 0;
   o.split_branches = opt.split_branches != 0;
@@ -444,6 +522,8 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   o.keep_tables = opt.keep_tables != 0;
   o.bitwise = opt.bitwise != 0;
   o.scheduler = opt.level_sync ? 0 : 1;
+  o.cell_lanes = opt.cell_lanes != 0;
+  if (o.cell_lanes) o.scheduler = 0;  // the groups serve hines_solve_mixed only
   hines_plan* p = new (std::nothrow) hines_plan();
   if (!p) return set_err(HINES_ERR_OOM, "host allocation failed");
   std::string why;
@@ -451,6 +531,14 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   if (s != hines::OK) {
     delete p;
     return set_err((hines_status)s, "%s", why.c_str());
+  }
+  if (o.cell_lanes) {
+    s = hines::build_cell_lanes(parent, n, cell_offsets, ncells, p->host.cl, why);
+    if (s == hines::OK && !check_cell_tables(p->host, cell_offsets, why)) s = hines::ERR_STATE;
+    if (s != hines::OK) {
+      delete p;
+      return set_err((hines_status)s, "cell lanes: %s", why.c_str());
+    }
   }
   bool capacity = false;
   if (!o.host_only && !check_kernel_tables(p->host, why, capacity)) {
@@ -528,7 +616,14 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   const int64_t sz_fm = al((int64_t)P.fmask.size() * sizeof(uint64_t));
   const int64_t sz_fp = al((int64_t)P.fpos.size() * sizeof(uint16_t));
   const int64_t sz_fa = al((int64_t)P.faux.size() * sizeof(int16_t));
-  const int64_t total = sz_br + sz_grp + sz_seg + sz_cell + sz_gl + sz_ws + sz_fl + sz_fm + sz_fp + sz_fa + 256;
+  const hines::CellLanes& CL = P.cl;
+  const int64_t sz_cw = al((int64_t)CL.waves.size() * sizeof(hines::KCellWave));
+  const int64_t sz_cb = al((int64_t)CL.base.size() * sizeof(int64_t));
+  const int64_t sz_cp = al((int64_t)CL.pos.size() * sizeof(uint16_t));
+  const int64_t sz_cf = al((int64_t)CL.flags.size());
+  const int64_t total = sz_br + sz_grp + sz_seg + sz_cell + sz_gl + sz_ws + sz_fl + sz_fm + sz_fp + sz_fa + sz_cw +
+                        sz_cb + sz_cp + sz_cf + 256;
+  const int64_t scr_bytes = CL.nchunks * hines::kCellChunk * 64 * 16;
   hipError_t e = hipGetDevice(&p->device);
   if (e == hipSuccess) e = allow_lds(o.group_width);
   if (e != hipSuccess) {
@@ -541,7 +636,17 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
     delete p;
     return set_err(HINES_ERR_OOM, "hipMalloc(%lld): %s", (long long)total, hipGetErrorString(e));
   }
-  p->dev_bytes = total;
+  if (scr_bytes > 0) {
+    e = hipMalloc(&p->scr_mem, scr_bytes);
+    if (e != hipSuccess) {
+      p->scr_mem = nullptr;
+      hipFree(p->dev_mem);
+      delete p;
+      return set_err(HINES_ERR_OOM, "hipMalloc(%lld) for the cell-lane scratch: %s", (long long)scr_bytes,
+                     hipGetErrorString(e));
+    }
+  }
+  p->dev_bytes = total + scr_bytes;
   char* base = (char*)p->dev_mem;
   auto up = [&](const void* src, int64_t bytes, int64_t slot) -> hipError_t {
     if (bytes == 0) return hipSuccess;
@@ -577,7 +682,21 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   p->t.faux = (const int16_t*)(base + off);
   if (e == hipSuccess) e = up(P.faux.data(), (int64_t)P.faux.size() * sizeof(int16_t), off);
   off += sz_fa;
+  p->t.cwave = (const hines::KCellWave*)(base + off);
+  if (e == hipSuccess) e = up(CL.waves.data(), (int64_t)CL.waves.size() * sizeof(hines::KCellWave), off);
+  off += sz_cw;
+  p->t.cbase = (const int64_t*)(base + off);
+  if (e == hipSuccess) e = up(CL.base.data(), (int64_t)CL.base.size() * sizeof(int64_t), off);
+  off += sz_cb;
+  p->t.cpos = (const uint16_t*)(base + off);
+  if (e == hipSuccess) e = up(CL.pos.data(), (int64_t)CL.pos.size() * sizeof(uint16_t), off);
+  off += sz_cp;
+  p->t.cflag = (const uint8_t*)(base + off);
+  if (e == hipSuccess) e = up(CL.flags.data(), (int64_t)CL.flags.size(), off);
+  off += sz_cf;
+  p->t.cscr = (double*)p->scr_mem;
   if (e != hipSuccess) {
+    if (p->scr_mem) hipFree(p->scr_mem);
     hipFree(p->dev_mem);
     delete p;
     return set_err(HINES_ERR_HIP, "table upload: %s", hipGetErrorString(e));
@@ -588,6 +707,8 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
     std::vector<uint64_t>().swap(p->host.fmask);
     std::vector<uint16_t>().swap(p->host.fpos);
     std::vector<int16_t>().swap(p->host.faux);
+    std::vector<uint16_t>().swap(p->host.cl.pos);
+    std::vector<uint8_t>().swap(p->host.cl.flags);
   }
   *out = p;
   return ok();
@@ -779,7 +900,8 @@ hines_status hines_plan_info_get(const hines_plan* p, hines_plan_info* info) {
   info->nclasses = nb;
   info->device_table_bytes = p->dev_bytes;
   info->max_group_lds_bytes = p->max_lds;
-  info->kernel = p->host.flow ? 1 : (p->host.opt.bitwise ? 2 : 0);
+  info->kernel = p->host.cl.built ? 3 : (p->host.flow ? 1 : (p->host.opt.bitwise ? 2 : 0));
+  if (p->host.cl.built) info->nclasses = 1;
   int32_t mk = 0;
   int64_t ng_ws = 0;
   for (const auto& G : p->host.kgroup) {
@@ -806,12 +928,13 @@ hines_status hines_get_table(const hines_plan* p, int32_t which, int64_t* host_o
 hines_status hines_destroy(hines_plan* p) {
   if (!p) return ok();
   hines_status st = HINES_OK;
-  if (p->dev_mem || p->adj_mem) {
+  if (p->dev_mem || p->adj_mem || p->scr_mem) {
     int prev = -1;
     hipGetDevice(&prev);
     if (prev != p->device) hipSetDevice(p->device);
     hipError_t e = hipDeviceSynchronize();
     if (e == hipSuccess && p->dev_mem) e = hipFree(p->dev_mem);
+    if (e == hipSuccess && p->scr_mem) e = hipFree(p->scr_mem);
     if (e == hipSuccess && p->adj_mem) e = hipFree(p->adj_mem);
     if (e != hipSuccess) st = set_err(HINES_ERR_HIP, "destroy: %s", hipGetErrorString(e));
     if (prev != p->device && prev >= 0) hipSetDevice(prev);

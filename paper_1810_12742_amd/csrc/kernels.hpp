@@ -32,6 +32,11 @@ struct DevTables {
   const uint64_t* fmask;     // flow kernel: active and push masks per step
   const uint16_t* fpos;      // flow kernel: position of every element
   const int16_t* faux;       // flow kernel: parent position of every push
+  const hines::KCellWave* cwave;  // cell-lane kernel: per wave
+  const int64_t* cbase;           // cell-lane kernel: first user index of each lane's cell
+  const uint16_t* cpos;           // cell-lane kernel: positions, staging order
+  const uint8_t* cflag;           // cell-lane kernel: flags, cell-lane order
+  double* cscr;                   // cell-lane kernel: (f, y) per step and lane
 };
 
 // Right-hand side of a solve: given (kRhsGiven), c v + i (kRhsCV; i may be
@@ -871,6 +876,235 @@ __global__ __launch_bounds__(64) void k_solve_flow(DevTables tb, RhsSpec rs, con
       const KCell C = tb.cell[G.cell_begin + c];
       flow_store_range(x, C.user_lo, C.n, pos + e0, img, lane, G.ncell == 1 ? keep : nullptr);
       e0 += C.n;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cell-lane solve: one lane per cell, 64 cells of similar size per wave.  Lane
+// c walks its cell in the order of the setup tables (the reverse of a depth-
+// first order in the backward sweep, that order in the forward sweep),
+// kCellChunk steps per chunk.
+//
+// The inputs of a chunk are gathered by the whole wave: in slot r, lane j
+// loads element j % 16 of the cell of lane 4 r + j / 16, so 16 lanes read one
+// run of a cell's compartments.  They pass through two LDS planes (d, u and b;
+// rows padded so that both the gathering writes and the per-lane reads are
+// free of bank conflicts) to the lane that eliminates them.  The factors
+// (f, y) of each step go to a device scratch in lane-major order (one 1 KiB
+// store per step) and return in the forward sweep, whose x values pass back
+// through LDS to the gather mapping for the store in user order.
+//
+// Contributions to a parent (paper §2: d_p -= u_i f_i, b_p -= u_i y_i) stay in
+// registers when the parent is eliminated next.  The contributions of its
+// other children wait in one merged stack entry per pending parent; the top
+// entry lives in registers, the ones below in LDS slots (slot 0 is a dummy
+// that lanes without an entry to spill write into).  The forward sweep keeps
+// x of a compartment with several children on the same kind of stack.
+// ---------------------------------------------------------------------------
+constexpr int CK = hines::kCellChunk;
+constexpr int kCellRowDU = 64 * 16 + 16;  // bytes per element row of the (d, u) plane
+constexpr int kCellRowB = 64 * 8 + 16;    // bytes per element row of the b plane (x in the forward sweep)
+constexpr int kCellLdsB = CK * kCellRowDU;                 // byte offset of the b plane
+constexpr int kCellLdsStack = kCellLdsB + CK * kCellRowB;  // byte offset of the stack slots
+constexpr int kCellLds = kCellLdsStack + hines::kCellStack * 64 * 16;
+
+typedef double double2_t __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) double2_t lds_d2;
+typedef __attribute__((address_space(3))) char lds_char;
+
+__device__ __forceinline__ unsigned cell_byte(const u32x4& v, int e) { return (v[e >> 2] >> (8 * (e & 3))) & 0xffu; }
+// position of slot r (0..15) from the lane's two 16-byte position words;
+// padding reads the cell's first compartment (its value is replaced later)
+__device__ __forceinline__ unsigned cell_pos(const u32x4& p0, const u32x4& p1, int r) {
+  const unsigned w = r < 8 ? p0[(r & 7) >> 1] : p1[(r & 7) >> 1];
+  return (w >> (16 * (r & 1))) & 0xffffu;
+}
+
+template <int RHS>
+struct CellBatch {
+  double dv[CK], uv[CK], bv[CK];
+  double cv[RHS == kFlowGiven ? 1 : CK];
+  double iv[RHS == kFlowCVI ? CK : 1];
+};
+
+template <int RHS>
+__device__ __forceinline__ void cell_load(CellBatch<RHS>& B, const RhsSpec& rs, const double* __restrict__ d,
+                                          const double* __restrict__ u, const int64_t* base, const u32x4& p0,
+                                          const u32x4& p1) {
+#pragma unroll
+  for (int r = 0; r < CK; ++r) {
+    const unsigned p = cell_pos(p0, p1, r);
+    const int64_t i = base[r] + (p == hines::kCellPadPos ? 0u : p);
+    B.dv[r] = d[i];
+    B.uv[r] = u[i];
+    if constexpr (RHS == kFlowGiven) {
+      B.bv[r] = rs.rhs[i];
+    } else {
+      B.cv[r] = rs.c[i];
+      B.bv[r] = rs.v[i];
+      if constexpr (RHS == kFlowCVI) B.iv[r] = rs.icur[i];
+    }
+  }
+}
+
+template <int RHS>
+__device__ __forceinline__ void cell_put(const CellBatch<RHS>& B, const RhsSpec& rs, const int64_t* base,
+                                         const u32x4& p0, const u32x4& p1, lds_char* lds, int lane) {
+  const int e = lane & 15;
+#pragma unroll
+  for (int r = 0; r < CK; ++r) {
+    const int c = 4 * r + (lane >> 4);
+    double b = B.bv[r];
+    if constexpr (RHS != kFlowGiven) b = B.cv[r] * B.bv[r];
+    if constexpr (RHS == kFlowCVI) b = b + B.iv[r];
+    if constexpr (RHS == kFlowNoise) {
+      const unsigned p = cell_pos(p0, p1, r);
+      b = b + noise_draw(rs.seed, rs.step, (uint64_t)(base[r] + (p == hines::kCellPadPos ? 0u : p)), rs.sigma);
+    }
+    *(lds_d2*)(lds + e * kCellRowDU + c * 16) = double2_t{B.dv[r], B.uv[r]};
+    *(lds_f64*)(lds + kCellLdsB + e * kCellRowB + c * 8) = b;
+  }
+}
+
+template <int RHS>
+__global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, const double* __restrict__ d,
+                                                    const double* __restrict__ u, double* x) {
+  __shared__ __attribute__((aligned(16))) char cl_raw[kCellLds];
+  lds_char* lds = (lds_char*)cl_raw;
+  const int lane = threadIdx.x;
+  const hines::KCellWave W = tb.cwave[blockIdx.x];
+  const int nk = W.nchunk;
+  int64_t base[CK];
+#pragma unroll
+  for (int r = 0; r < CK; ++r) base[r] = tb.cbase[(int64_t)blockIdx.x * 64 + 4 * r + (lane >> 4)];
+  const u32x4* posv = (const u32x4*)(tb.cpos + W.chunk_off * 1024) + 2 * lane;  // + 128 per chunk
+  const u32x4* flv = (const u32x4*)(tb.cflag + W.chunk_off * 1024) + lane;      // + 64 per chunk
+  double2_t* scr = (double2_t*)tb.cscr + W.chunk_off * (CK * 64) + lane;       // + CK * 64 per chunk
+  lds_d2* stk = (lds_d2*)(lds + kCellLdsStack) + lane;                            // slot s at stk[64 s]
+  const lds_d2* pdu = (const lds_d2*)lds + lane;
+  lds_f64* pb = (lds_f64*)(lds + kCellLdsB) + lane;
+
+  // ---- backward sweep ----
+  u32x4 p0 = posv[0], p1 = posv[1], fl = flv[0];
+  CellBatch<RHS> B;
+  cell_load<RHS>(B, rs, d, u, base, p0, p1);
+  u32x4 q0 = p0, q1 = p1;
+  if (nk > 1) {
+    q0 = posv[128];
+    q1 = posv[129];
+  }
+  double cd = 0.0, cb = 0.0, td = 0.0, tb_ = 0.0;
+  int m = 0;
+  for (int k = 0; k < nk; ++k) {
+    cell_put<RHS>(B, rs, base, p0, p1, lds, lane);
+    const u32x4 f = fl;
+    if (k + 1 < nk) {
+      fl = flv[64 * (k + 1)];
+      cell_load<RHS>(B, rs, d, u, base, q0, q1);
+      p0 = q0;
+      p1 = q1;
+      const int k2 = min(k + 2, nk - 1);
+      q0 = posv[128 * k2];
+      q1 = posv[128 * k2 + 1];
+    }
+    double2_t* sk = scr + k * (CK * 64);
+#pragma unroll
+    for (int e = 0; e < CK; ++e) {
+      const unsigned fe = cell_byte(f, e);
+      const double2_t du = pdu[e * (kCellRowDU / 16)];
+      const double bv = pb[e * (kCellRowB / 8)];
+      const bool pad = fe & hines::CF_PAD;
+      double dd = pad ? 1.0 : du.x;
+      const double uu = (fe & (hines::CF_PAD | hines::CF_ROOT)) ? 0.0 : du.y;
+      double bb = pad ? 0.0 : bv;
+      if (fe & hines::CF_TIP) {
+        cd = 0.0;
+        cb = 0.0;
+      }
+      dd = dd - cd;
+      bb = bb - cb;
+      if (fe & hines::CF_POP) {
+        dd = dd - td;
+        bb = bb - tb_;
+        m -= 1;
+        const double2_t t = stk[64 * m];
+        td = t.x;
+        tb_ = t.y;
+      }
+      const double rr = rcp_nr(dd);
+      const double fv = uu * rr, yv = bb * rr;
+      cd = uu * fv;
+      cb = uu * yv;
+      if (fe & hines::CF_PUSH) {
+        stk[64 * m] = double2_t{td, tb_};
+        m += 1;
+        td = cd;
+        tb_ = cb;
+      }
+      if (fe & hines::CF_MERGE) {
+        td = td + cd;
+        tb_ = tb_ + cb;
+      }
+      sk[e * 64] = double2_t{fv, yv};
+    }
+  }
+  // the forward sweep reads back this wave's own scratch stores
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+
+  // ---- forward sweep ----
+  lds_f64* stx = (lds_f64*)(lds + kCellLdsStack) + lane;  // slot s at stx[64 s]
+  double2_t fy[CK];
+  {
+    const double2_t* sk = scr + (nk - 1) * (CK * 64);
+#pragma unroll
+    for (int e = 0; e < CK; ++e) fy[e] = sk[e * 64];
+  }
+  p0 = posv[128 * (nk - 1)];
+  p1 = posv[128 * (nk - 1) + 1];
+  fl = flv[64 * (nk - 1)];
+  double xc = 0.0, xt = 0.0;
+  m = 0;
+  const lds_f64* xrd = (const lds_f64*)(lds + kCellLdsB + (lane & 15) * kCellRowB) + (lane >> 4);
+  for (int k = nk - 1; k >= 0; --k) {
+    const u32x4 f = fl, c0 = p0, c1 = p1;
+    double2_t fyn[CK];
+    if (k > 0) {
+      const double2_t* sk = scr + (k - 1) * (CK * 64);
+#pragma unroll
+      for (int e = 0; e < CK; ++e) fyn[e] = sk[e * 64];
+      p0 = posv[128 * (k - 1)];
+      p1 = posv[128 * (k - 1) + 1];
+      fl = flv[64 * (k - 1)];
+    }
+#pragma unroll
+    for (int e = CK - 1; e >= 0; --e) {
+      const unsigned fe = cell_byte(f, e);
+      double xp = xc;
+      if (fe & (hines::CF_PUSH | hines::CF_MERGE)) xp = xt;
+      if (fe & hines::CF_PUSH) {
+        m -= 1;
+        xt = stx[64 * m];
+      }
+      const double xv = __builtin_fma(-fy[e].x, xp, fy[e].y);
+      if (fe & hines::CF_POP) {
+        stx[64 * m] = xt;
+        m += 1;
+        xt = xv;
+      }
+      xc = xv;
+      pb[e * (kCellRowB / 8)] = xv;
+    }
+#pragma unroll
+    for (int r = 0; r < CK; ++r) {
+      const double xv = xrd[4 * r];
+      const unsigned p = cell_pos(c0, c1, r);
+      if (p != hines::kCellPadPos) x[base[r] + p] = xv;
+    }
+    if (k > 0) {
+#pragma unroll
+      for (int e = 0; e < CK; ++e) fy[e] = fyn[e];
     }
   }
 }

@@ -880,7 +880,7 @@ int64_t export_table(const HostPlan& p, int32_t id, int64_t* out, int64_t capaci
     return cnt;
   };
   if (!p.opt.keep_tables && (id == T_NODE_PLAN || id == T_BRANCHES || id == T_U_SRC || id == T_FLOW_MASKS ||
-                             id == T_FLOW_POS || id == T_FLOW_AUX))
+                             id == T_FLOW_POS || id == T_FLOW_AUX || id == T_CELL_POS || id == T_CELL_FLAGS))
     return -1;
   switch (id) {
     case T_NODE_PLAN: return put(p.node_plan);
@@ -930,6 +930,21 @@ int64_t export_table(const HostPlan& p, int32_t id, int64_t* out, int64_t capaci
     case T_FLOW_MASKS: return put(p.fmask);
     case T_FLOW_POS: return put(p.fpos);
     case T_FLOW_AUX: return put(p.faux);
+    case T_CELL_WAVES: {
+      const int64_t cnt = 3 * (int64_t)p.cl.waves.size();
+      if (out) {
+        if (capacity < cnt) return -1;
+        for (int64_t w = 0; w < cnt / 3; ++w) {
+          out[3 * w] = p.cl.waves[w].chunk_off;
+          out[3 * w + 1] = p.cl.waves[w].nchunk;
+          out[3 * w + 2] = p.cl.waves[w].ncell;
+        }
+      }
+      return cnt;
+    }
+    case T_CELL_LANES: return put(p.cl.lane_cell);
+    case T_CELL_POS: return put(p.cl.pos);
+    case T_CELL_FLAGS: return put(p.cl.flags);
     default: return -1;
   }
 }

@@ -37,6 +37,7 @@ struct Options {
   int32_t bitwise = 0;             // IEEE divisions, unfused updates: equal to the plain algorithm bit for bit
   int32_t scheduler = 1;           // 1: static heavy-path lane schedule when every branch ascends;
                                    // 0: level-synchronous sweeps (paper §3)
+  int32_t cell_lanes = 0;          // 1: one lane per cell (streaming kernel) for hines_solve / timestep
 };
 
 // Static chunk schedule (flow kernel): one lane eliminates kFlowChunk
@@ -87,8 +88,58 @@ enum TableId : int32_t {
   T_FLOW_MASKS = 9,       // int64[2*steps]: active and push masks (bit patterns)
   T_FLOW_POS = 10,        // int64[elements]: position | 0x8000 for cell roots
   T_FLOW_AUX = 11,        // int64[pushes]: parent position
-  T_NUM = 12,
+  T_CELL_WAVES = 12,      // int64[nwaves*3]: chunk_off, nchunk, ncell
+  T_CELL_LANES = 13,      // int64[nwaves*64]: cell of each lane (-1: empty)
+  T_CELL_POS = 14,        // int64[nchunks*1024]: [chunk][staging lane][slot] relative position
+  T_CELL_FLAGS = 15,      // int64[nchunks*1024]: [chunk][cell lane][element] flags
+  T_NUM = 16,
 };
+
+// Cell-lane kernel (one lane per cell).  Each cell is processed in a depth-
+// first order of its compartments in which the children of a compartment are
+// visited with the child needing the deepest contribution stack last (paper
+// §2's elimination needs only that children precede parents in the backward
+// sweep).  Backward sweep: reverse of that order; forward sweep: the order.
+// A wave holds 64 cells of similar size; lane c walks cell c.  Per chunk of
+// kCellChunk consecutive steps the table gives, for the staging mapping (lane
+// j, slot r) -> (cell lane 4 r + j / 16, element j % 16), the position of the
+// element relative to its cell's first compartment, and per (cell lane,
+// element) the flags below.
+constexpr int32_t kCellChunk = 16;
+constexpr int32_t kCellStack = 12;           // LDS stack slots per lane; slot 0 is a dummy
+constexpr uint16_t kCellPadPos = 0xFFFF;     // padding element: no user compartment
+constexpr int64_t kCellMaxSize = 65535;      // positions fit 16 bits below kCellPadPos
+enum : uint8_t {
+  CF_TIP = 1,     // no children: the elimination carry does not enter
+  CF_POP = 2,     // two or more children: the stacked contributions of all but the first enter
+  CF_PUSH = 4,    // last child of its parent (two or more children): its contribution opens a stack entry
+  CF_MERGE = 8,   // middle child: its contribution is added to the top entry
+  CF_PAD = 16,    // padding: identity row
+  CF_ROOT = 32,   // cell root: no coupling to a parent
+};
+struct KCellWave {
+  int64_t chunk_off;  // first chunk of the wave in the pos / flags / scratch tables
+  int32_t nchunk;     // chunks per sweep
+  int32_t ncell;      // occupied lanes
+};
+static_assert(sizeof(KCellWave) == 16, "layout");
+
+struct CellLanes {
+  bool built = false;
+  int64_t nwaves = 0, nchunks = 0;
+  int32_t max_need = 0;             // deepest stack of any cell (entries)
+  std::vector<KCellWave> waves;     // [nwaves], largest cells first
+  std::vector<int32_t> lane_cell;   // [nwaves*64] cell of each lane, -1 for empty lanes
+  std::vector<int64_t> base;        // [nwaves*64] first user index of the lane's cell (0: empty)
+  std::vector<uint16_t> pos;        // [nchunks*1024] staging order
+  std::vector<uint8_t> flags;       // [nchunks*1024] cell-lane order
+};
+
+// Build the cell-lane tables.  parent / cell_offsets must already be valid.
+// ERR_TOO_BIG if a cell has more than kCellMaxSize compartments or needs more
+// than kCellStack stack entries.
+Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_offsets, int64_t ncells,
+                        CellLanes& out, std::string& err);
 
 // Per-branch record of the LDS-staged solve kernel, in (group, level, lane)
 // order; 16 bytes so that one DMA lane moves one record.  All indices are
@@ -197,6 +248,7 @@ struct HostPlan {
   std::vector<uint16_t> fpos;     // [elements of LDS groups]: position, bit 15 = cell root
   std::vector<int16_t> faux;      // [pushes]: parent position
   int64_t ws_doubles = 0;         // global workspace for groups that exceed LDS
+  CellLanes cl;                   // cell-lane kernel tables (opt.cell_lanes)
 };
 
 Status build_plan(const int32_t* parent, int64_t n, const int64_t* branch_offsets, int64_t nbranches,

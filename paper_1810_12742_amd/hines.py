@@ -18,6 +18,7 @@ TABLES = {
     "node_plan": 0, "branches": 1, "u_src": 2, "group_offsets": 3, "group_cells": 4,
     "group_seg_offsets": 5, "seg_offsets": 6, "lanes": 7,
     "flow_groups": 8, "flow_masks": 9, "flow_pos": 10, "flow_aux": 11,
+    "cell_waves": 12, "cell_lanes": 13, "cell_pos": 14, "cell_flags": 15,
 }
 STATUS = {0: "OK", 1: "NULL", 2: "BAD_OFFSETS", 3: "BAD_PARENT", 4: "BAD_BRANCHES", 5: "TOO_WIDE",
           6: "NCELLS", 7: "OPTION", 8: "OOM", 9: "HIP", 10: "TOO_BIG", 11: "NOT_SDD", 12: "STATE"}
@@ -35,7 +36,8 @@ class _Options(ctypes.Structure):
                 ("group_width", ctypes.c_int32), ("cell_order", ctypes.c_int32),
                 ("max_group_unknowns", ctypes.c_int32), ("host_only", ctypes.c_int32),
                 ("keep_tables", ctypes.c_int32), ("bitwise", ctypes.c_int32),
-                ("level_sync", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("level_sync", ctypes.c_int32), ("cell_lanes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class _Info(ctypes.Structure):
@@ -113,7 +115,7 @@ class Plan:
 
     def __init__(self, parent, cell_offsets, branch_offsets=None, *, rebalance_root=False,
                  split_branches=False, group_width=64, cell_order=0, max_group_unknowns=None,
-                 host_only=False, keep_tables=True, bitwise=False, level_sync=False):
+                 host_only=False, keep_tables=True, bitwise=False, level_sync=False, cell_lanes=False):
         lib = load()
         opt = _Options()
         lib.hines_default_options(ctypes.byref(opt))
@@ -127,6 +129,7 @@ class Plan:
         opt.keep_tables = int(bool(keep_tables))
         opt.bitwise = int(bool(bitwise))
         opt.level_sync = int(bool(level_sync))
+        opt.cell_lanes = int(bool(cell_lanes))
         self._par = _host(parent, np.int32)
         self._coff = _host(cell_offsets, np.int64)
         bo = None if branch_offsets is None else _host(branch_offsets, np.int64)

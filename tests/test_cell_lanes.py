@@ -1,0 +1,261 @@
+"""CPU replay of the cell-lane kernel's tables.
+
+The host builder hands the cell-lane kernel, per wave of 64 cells, chunks of
+16 steps: for the gather mapping (lane j, slot r) -> (cell lane 4 r + j // 16,
+element j % 16) the position of each element relative to its cell's first
+compartment, and per (cell lane, element) the flags that steer the register
+carry and the per-lane contribution stack.  This test replays the kernel's
+semantics on those tables in numpy, lane-parallel like the kernel, and checks
+
+* that every compartment of every cell is eliminated once and substituted
+  once, and the stack never underflows or leaves its slots;
+* the solution against the FP64 oracle (relative error <= 1e-12 per cell),
+  on the workload families and on trees with many children per compartment,
+  which exercise the merge of middle children.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import configs
+from workloads.configs import random_system
+from workloads.trees import Forest
+
+TIP, POP, PUSH, MERGE, PAD, ROOT = 1, 2, 4, 8, 16, 32
+K = 16
+STACK = 12
+
+
+def replay(plan, f, diag, upper, rhs):
+    waves = plan.table("cell_waves").reshape(-1, 3)
+    lane_cell = plan.table("cell_lanes").reshape(-1, 64)
+    pos = plan.table("cell_pos").reshape(-1, 64, 16)     # [chunk][j][r]
+    flags = plan.table("cell_flags").reshape(-1, 64, 16)  # [chunk][c][e]
+    co = f.cell_offsets
+    x = np.full(f.n, np.nan)
+    seen_b = np.zeros(f.n, dtype=np.int64)
+    seen_f = np.zeros(f.n, dtype=np.int64)
+    jj = np.arange(64)
+    lanes = np.arange(64)
+    for w in range(waves.shape[0]):
+        off, nk, ncell = (int(v) for v in waves[w])
+        cells = lane_cell[w]
+        assert np.all(cells[:ncell] >= 0) and np.all(cells[ncell:] == -1)
+        base = np.where(cells >= 0, co[np.maximum(cells, 0)], 0)
+        scr = np.zeros((nk, K, 64, 2))
+        cd = np.zeros(64)
+        cb = np.zeros(64)
+        td = np.zeros(64)
+        tb = np.zeros(64)
+        m = np.zeros(64, dtype=np.int64)
+        stk = np.zeros((STACK, 64, 2))
+        for k in range(nk):
+            g = off + k
+            D = np.empty((K, 64))
+            U = np.empty((K, 64))
+            B = np.empty((K, 64))
+            for r in range(16):  # gather: slot r of every lane j
+                c = 4 * r + jj // 16
+                e = jj % 16
+                p = pos[g, jj, r]
+                idx = base[c] + np.where(p == 0xFFFF, 0, p)
+                D[e, c] = diag[idx]
+                U[e, c] = upper[idx]
+                B[e, c] = rhs[idx]
+                real = p != 0xFFFF
+                seen_b[idx[real]] += 1
+            for e in range(K):
+                fe = flags[g, :, e]
+                pad = (fe & PAD) != 0
+                dd = np.where(pad, 1.0, D[e])
+                uu = np.where((fe & (PAD | ROOT)) != 0, 0.0, U[e])
+                bb = np.where(pad, 0.0, B[e])
+                tip = (fe & TIP) != 0
+                cd[tip] = 0.0
+                cb[tip] = 0.0
+                dd = dd - cd
+                bb = bb - cb
+                pop = (fe & POP) != 0
+                dd = np.where(pop, dd - td, dd)
+                bb = np.where(pop, bb - tb, bb)
+                m[pop] -= 1
+                assert np.all(m >= 0), "stack underflow"
+                td = np.where(pop, stk[np.maximum(m, 0), lanes, 0], td)
+                tb = np.where(pop, stk[np.maximum(m, 0), lanes, 1], tb)
+                rr = 1.0 / dd
+                fv = uu * rr
+                yv = bb * rr
+                cd = uu * fv
+                cb = uu * yv
+                push = (fe & PUSH) != 0
+                assert np.all(m[push] < STACK), "stack overflow"
+                stk[m[push], lanes[push], 0] = td[push]
+                stk[m[push], lanes[push], 1] = tb[push]
+                m[push] += 1
+                td = np.where(push, cd, td)
+                tb = np.where(push, cb, tb)
+                merge = (fe & MERGE) != 0
+                assert np.all(m[merge] >= 1), "merge into an empty stack"
+                td = np.where(merge, td + cd, td)
+                tb = np.where(merge, tb + cb, tb)
+                scr[k, e, :, 0] = fv
+                scr[k, e, :, 1] = yv
+        assert np.all(m == 0), "backward stack not empty at the end"
+        xc = np.zeros(64)
+        xt = np.zeros(64)
+        stx = np.zeros((STACK, 64))
+        for k in range(nk - 1, -1, -1):
+            g = off + k
+            X = np.empty((K, 64))
+            for e in range(K - 1, -1, -1):
+                fe = flags[g, :, e]
+                use = (fe & (PUSH | MERGE)) != 0
+                xp = np.where(use, xt, xc)
+                push = (fe & PUSH) != 0
+                m[push] -= 1
+                assert np.all(m >= 0), "forward stack underflow"
+                xt = np.where(push, stx[np.maximum(m, 0), lanes], xt)
+                xv = scr[k, e, :, 1] - scr[k, e, :, 0] * xp
+                pop = (fe & POP) != 0
+                assert np.all(m[pop] < STACK), "forward stack overflow"
+                stx[m[pop], lanes[pop]] = xt[pop]
+                m[pop] += 1
+                xt = np.where(pop, xv, xt)
+                xc = xv
+                X[e] = xv
+            for r in range(16):  # scatter through the gather mapping
+                c = 4 * r + jj // 16
+                e = jj % 16
+                p = pos[g, jj, r]
+                real = p != 0xFFFF
+                idx = base[c] + p
+                x[idx[real]] = X[e[real], c[real]]
+                seen_f[idx[real]] += 1
+        assert np.all(m == 0), "forward stack not empty at the end"
+    assert np.all(seen_b == 1) and np.all(seen_f == 1), "each compartment once per sweep"
+    return x
+
+
+def cell_err(f, x, xo):
+    e = np.maximum.reduceat(np.abs(x - xo), f.cell_offsets[:-1])
+    s = np.maximum.reduceat(np.abs(xo), f.cell_offsets[:-1])
+    return float(np.max(e / s))
+
+
+def bushy_system(ncells, seed, max_children=6, size=(1, 400)):
+    """Random trees where a compartment may have up to max_children children
+    (parent drawn among the last few compartments), so that merges of middle
+    children and deep stacks occur."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(size[0], size[1], ncells)
+    off = np.zeros(ncells + 1, dtype=np.int64)
+    np.cumsum(sizes, out=off[1:])
+    par = np.full(off[-1], -1, dtype=np.int32)
+    for c in range(ncells):
+        lo, m = off[c], sizes[c]
+        nch = np.zeros(m, dtype=np.int64)
+        for i in range(1, m):
+            for _ in range(8):
+                p = int(rng.integers(max(0, i - 12), i))
+                if nch[p] < max_children:
+                    break
+            nch[p] += 1
+            par[lo + i] = lo + p
+    a = rng.uniform(0.5, 2.0, off[-1])
+    cc = rng.uniform(0.1, 1.0, off[-1])
+    roots = off[:-1]
+    a[roots] = 0.0
+    diag = cc + a
+    np.add.at(diag, par[par >= 0], a[par >= 0])
+    upper = -a
+    return Forest(par, off, None), diag, upper
+
+
+CASES = {
+    "random_small": lambda: random_system(300, 5),
+    "c2_cells": lambda: configs.c2(70),
+    "c1_cells": lambda: configs.c1(64),
+    "c3_cells": lambda: configs.c3(60),
+}
+
+
+def _check(f, diag, upper, seed=3):
+    from paper_1810_12742_amd import Plan
+    rhs = np.random.default_rng(seed).standard_normal(f.n)
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets, host_only=1, cell_lanes=1)
+    assert p.info["kernel"] == 3
+    x = replay(p, f, diag, upper, rhs)
+    xo = oracle.solve(f, diag, upper, rhs)
+    assert cell_err(f, x, xo) <= 1e-12
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_cell_replay_matches_oracle(name):
+    s = CASES[name]()
+    _check(s.forest, s.diag, s.upper)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_cell_replay_bushy_trees(seed):
+    f, diag, upper = bushy_system(90, seed)
+    _check(f, diag, upper, seed)
+
+
+def test_cell_flags_of_a_small_tree():
+    """Hand-checked flags of one tree: root 0 with children 1 (a leaf) and 2;
+    2 has children 3, 4, 5 (leaves); 6 hangs off 5.  Stack needs: node 5
+    (one child) 0; node 2: three children with needs 0, 0, 0 -> 1; root: 0 and
+    1 -> max(1, 0 + 1) = 1.  Heavy child of 2 is its first maximal one (3),
+    its light children 4, 5 come first in ascending order, so the preorder is
+    0, 1, 2, 4, 5, 6, 3 and the backward sweep runs it backwards: 3 (tip, last
+    child of 2: push), 6 (tip, carries into 5), 5 (middle child of 2: merge),
+    4 (tip, first child of 2: carries), 2 (pop; the root's heavy child: push),
+    1 (tip, first child of 0: carries), 0 (root, pop)."""
+    from paper_1810_12742_amd import Plan
+    par = np.array([-1, 0, 0, 2, 2, 2, 5], dtype=np.int32)
+    off = np.array([0, 7], dtype=np.int64)
+    p = Plan(par, off, None, host_only=1, cell_lanes=1)
+    waves = p.table("cell_waves").reshape(-1, 3)
+    assert waves.tolist() == [[0, 1, 1]]
+    pos = p.table("cell_pos").reshape(-1, 64, 16)
+    flags = p.table("cell_flags").reshape(-1, 64, 16)
+    # lane 0's elements e = 0..15 sit at gather lanes j = e, slot r = 0
+    order = [int(v) for v in pos[0, :16, 0]]
+    fl = [int(v) for v in flags[0, 0, :16]]
+    assert order[:9] == [0xFFFF] * 9 and fl[:9] == [PAD | TIP] * 9
+    assert order[9:] == [3, 6, 5, 4, 2, 1, 0]
+    assert fl[9:] == [TIP | PUSH, TIP, MERGE, TIP, POP | PUSH, TIP, POP | ROOT]
+    # every other lane is empty
+    assert np.all(flags[0, 1:] == PAD | TIP) and np.all(pos[0, 16:] == 0xFFFF)
+
+
+def test_cell_lane_setup_errors():
+    from paper_1810_12742_amd import HinesError, Plan
+    par = np.r_[-1, np.arange(70000 - 1)].astype(np.int32)
+    with pytest.raises(HinesError) as ei:
+        Plan(par, np.array([0, 70000], dtype=np.int64), None, host_only=1, cell_lanes=1)
+    assert ei.value.code == "TOO_BIG"
+    s = random_system(5, 1)
+    f = s.forest
+    with pytest.raises(HinesError) as ei:
+        Plan(f.parent, f.cell_offsets, f.branch_offsets, host_only=1, cell_lanes=1, bitwise=1)
+    assert ei.value.code == "OPTION"
+
+
+def test_stack_need_of_a_full_binary_tree():
+    """A full binary tree of compartments of height h needs h stack entries
+    at the root (a node whose two children need a entries each needs a + 1:
+    one child's entry waits while the other subtree runs), so height 12
+    (4096 tips) is the tallest that fits 12 entries."""
+    from paper_1810_12742_amd import HinesError, Plan
+
+    def full(h):
+        n = 2 ** (h + 1) - 1
+        par = np.r_[-1, (np.arange(1, n) - 1) // 2].astype(np.int32)
+        return par, np.array([0, n], dtype=np.int64)
+
+    p = Plan(*full(12), None, host_only=1, cell_lanes=1)
+    assert p.info["kernel"] == 3
+    with pytest.raises(HinesError) as ei:
+        Plan(*full(13), None, host_only=1, cell_lanes=1)
+    assert ei.value.code == "TOO_BIG"

@@ -1,0 +1,123 @@
+"""GPU parity of the cell-lane kernel (hines_solve / hines_timestep with
+cell_lanes = 1, through the C-ABI) against the FP64 oracle: relative error
+<= 1e-12 per cell (max norm), results independent of the run and of aliasing
+x with the right-hand side."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import Forest, cable_values, configs, grow_random_forest
+
+from test_cell_lanes import bushy_system
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    return torch, torch.device("cuda")
+
+
+def cell_rel_err(f, x, xo):
+    err = np.maximum.reduceat(np.abs(x - xo), f.cell_offsets[:-1])
+    scale = np.maximum.reduceat(np.abs(xo), f.cell_offsets[:-1])
+    return float(np.max(err / np.maximum(scale, 1e-300)))
+
+
+def solve_cells(torch_dev, f, diag, upper, rhs, alias=False):
+    torch, dev = torch_dev
+    from paper_1810_12742_amd import Plan
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets, cell_lanes=1)
+    assert p.info["kernel"] == 3
+    d = torch.from_numpy(np.ascontiguousarray(diag)).to(dev)
+    u = torch.from_numpy(np.ascontiguousarray(upper)).to(dev)
+    b = torch.from_numpy(np.ascontiguousarray(rhs)).to(dev)
+    x = b if alias else torch.empty_like(b)
+    p.solve(d, u, b, out=x)
+    torch.cuda.synchronize()
+    out = x.cpu().numpy()
+    p.close()
+    return out
+
+
+def test_c2_slice(torch_dev):
+    s = configs.c2(1536)
+    f = s.forest
+    print("cells: c2 slice 1536", flush=True)
+    xo = oracle.solve(f, s.diag, s.upper, s.rhs)
+    x1 = solve_cells(torch_dev, f, s.diag, s.upper, s.rhs)
+    assert cell_rel_err(f, x1, xo) <= TOL
+    x2 = solve_cells(torch_dev, f, s.diag, s.upper, s.rhs, alias=True)
+    assert np.array_equal(x1, x2)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_bushy_trees_and_ragged_waves(torch_dev, seed):
+    """Up to 6 children per compartment (middle-child merges, deeper stacks);
+    90 cells, so the second wave is partly empty."""
+    f, diag, upper = bushy_system(90, seed)
+    print(f"cells: bushy seed {seed}", flush=True)
+    rhs = np.random.default_rng(seed + 7).standard_normal(f.n)
+    xo = oracle.solve(f, diag, upper, rhs)
+    assert cell_rel_err(f, solve_cells(torch_dev, f, diag, upper, rhs), xo) <= TOL
+
+
+def test_mixed_sizes_long_cable_and_single_compartments(torch_dev):
+    """Cells of 1 to 20,000 compartments in one plan, an unbranched
+    5,000-compartment cable among them."""
+    rng = np.random.default_rng(21)
+    sizes = np.array([1, 50, 500, 5000, 20000, 1, 2, 3, 500, 50] * 4)
+    g = grow_random_forest(rng, len(sizes), target_size=sizes)
+    n0 = g.n
+    cab = 5000
+    par = np.concatenate([g.parent, np.r_[-1, np.arange(n0, n0 + cab - 1)].astype(np.int32)])
+    off = np.r_[g.cell_offsets, n0 + cab]
+    f = Forest(par.astype(np.int32), off.astype(np.int64), None)
+    s = cable_values(f, np.random.default_rng(22), a_kind="uniform", rhs=True)
+    print("cells: mixed sizes", flush=True)
+    xo = oracle.solve(f, s.diag, s.upper, s.rhs)
+    assert cell_rel_err(f, solve_cells(torch_dev, f, s.diag, s.upper, s.rhs), xo) <= TOL
+
+
+def test_timestep_forms_and_graph(torch_dev):
+    """c V + I, c V + sigma Z and plain c V right-hand sides formed in the
+    kernel; a captured multi-step graph equals the eager steps."""
+    torch, dev = torch_dev
+    from paper_1810_12742_amd import Plan
+    s = configs.c3(300)
+    f = s.forest
+    print("cells: timestep forms", flush=True)
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets, cell_lanes=1)
+    d = torch.from_numpy(s.diag).to(dev)
+    u = torch.from_numpy(s.upper).to(dev)
+    c = torch.from_numpy(s.c).to(dev)
+    steps = 3
+    V = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    for k in range(steps):
+        p.timestep(d, u, c, V, V, noise_sigma=0.1, noise_seed=5, step=k)
+    Vo = oracle.timeloop(f, s.diag, s.upper, s.c, steps, noise_seed=5, noise_sigma=0.1)
+    assert cell_rel_err(f, V.cpu().numpy(), Vo) <= TOL
+    I = 0.1 * np.random.default_rng(4).standard_normal(f.n)
+    It = torch.from_numpy(I).to(dev)
+    Va = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    for k in range(steps):
+        Va = p.timestep(d, u, c, Va, i_inj=It, step=k)
+    Vo = oracle.timeloop(f, s.diag, s.upper, s.c, steps, I_const=I)
+    assert cell_rel_err(f, Va.cpu().numpy(), Vo) <= TOL
+    V0 = np.random.default_rng(6).standard_normal(f.n)
+    Vc = p.timestep(d, u, c, torch.from_numpy(V0).to(dev), step=0)
+    Voc = oracle.timeloop(f, s.diag, s.upper, s.c, 1, V0=V0, I_const=np.zeros(f.n))
+    assert cell_rel_err(f, Vc.cpu().numpy(), Voc) <= TOL
+    Vg = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    loop = p.timeloop(d, u, c, Vg, steps, i_inj=It)
+    for rep in range(2):
+        Vg.zero_()
+        loop.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(Vg.cpu().numpy(), Va.cpu().numpy()), rep
+        _ = (d * 2).sum().item()
+    loop.close()
+    p.close()
