@@ -36,7 +36,7 @@ METRIC = "Hines unknowns solved/s and % HBM roofline, plain FP64 vs batched/FP32
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UNKNOWN = 32  # read diag, upper, rhs; write x (FP64)
 # Launch configuration of the timed solve (setup options of the plan).
-C2_OPTIONS = dict(max_group_unknowns=1536, split_branches=0, cell_order=0, group_width=64)
+C2_OPTIONS = dict(cell_lanes=1)
 CALIB_BYTES = 512 << 20  # bytes read (and written) by one calibration copy
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hines_solve_c2.json")
 KERNEL_SRC_DIR = os.path.join(ROOT, "paper_1810_12742_amd", "csrc")
@@ -198,6 +198,7 @@ def run_c2(args, torch, dev):
             "workload": "c2: 65,536 random dendritic cells, 16-256 branches, geometric(12) branch "
                         "lengths, dt=0.025, one FP64 solve per step",
             "ncells": f.ncells, "unknowns": n, "groups": info["ngroups"], "launches_per_step": launches,
+            "kernel": {3: "cell lanes", 1: "flow", 2: "bitwise"}.get(info["kernel"], "level-synchronous"),
             "options": C2_OPTIONS, "setup_s": round(setup_s, 3),
         },
         "roofline": {
@@ -207,7 +208,7 @@ def run_c2(args, torch, dev):
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": _traffic(launches),
-            "kernel": "k_solve_flow" if info["kernel"] == 1 else "k_solve_level",
+            "kernel": {3: "k_solve_cells", 1: "k_solve_flow"}.get(info["kernel"], "k_solve_level"),
             "bytes_per_launch": bytes_per_solve / launches,
             "avg_launch_us": ms * 1e3 / launches,
         },
@@ -236,7 +237,7 @@ def run_c3(args, torch, dev):
     fs = smp.forest
     ds, us, cs = (torch.from_numpy(a).to(dev) for a in (smp.diag, smp.upper, smp.c))
     vs = torch.zeros(fs.n, dtype=torch.float64, device=dev)
-    cands = [dict(max_group_unknowns=m, level_sync=l) for m in (1536, 3000) for l in (0, 1)]
+    cands = [dict(max_group_unknowns=m, level_sync=l) for m in (1536, 3000) for l in (0, 1)] + [dict(cell_lanes=1)]
     best, tried = autotune(fs.parent, fs.cell_offsets, fs.branch_offsets,
                            lambda p: p.timestep(ds, us, cs, vs, vs, noise_sigma=0.1, noise_seed=3),
                            candidates=cands, reps=3, cache_path=None)
@@ -278,7 +279,8 @@ def run_c3(args, torch, dev):
                    "autotune_ms": [[o, round(t, 4)] for o, t in tried], "setup_s": round(setup_s, 2),
                    "groups": plan.info["ngroups"], "workspace_groups": plan.info["workspace_groups"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "time step (flow/level)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": {3: "k_solve_cells", 1: "k_solve_flow"}.get(plan.info["kernel"], "k_solve_level"),
                      "bytes_per_step": bytes_per_step},
         "charge_conservation_max_rel_err_step0": check,
     }
