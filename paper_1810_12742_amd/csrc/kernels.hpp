@@ -948,6 +948,9 @@ __device__ __forceinline__ void cell_load(CellBatch<RHS>& B, const RhsSpec& rs, 
   }
 }
 
+// Into the LDS planes.  A padding element reads its cell's first compartment
+// and a cell root has no coupling: both get u = 0, so they contribute nothing
+// (d > 0 and b of the first compartment keep every value finite).
 template <int RHS>
 __device__ __forceinline__ void cell_put(const CellBatch<RHS>& B, const RhsSpec& rs, const int64_t* base,
                                          const u32x4& p0, const u32x4& p1, lds_char* lds, int lane) {
@@ -955,15 +958,84 @@ __device__ __forceinline__ void cell_put(const CellBatch<RHS>& B, const RhsSpec&
 #pragma unroll
   for (int r = 0; r < CK; ++r) {
     const int c = 4 * r + (lane >> 4);
+    const unsigned p = cell_pos(p0, p1, r);
     double b = B.bv[r];
     if constexpr (RHS != kFlowGiven) b = B.cv[r] * B.bv[r];
     if constexpr (RHS == kFlowCVI) b = b + B.iv[r];
-    if constexpr (RHS == kFlowNoise) {
-      const unsigned p = cell_pos(p0, p1, r);
+    if constexpr (RHS == kFlowNoise)
       b = b + noise_draw(rs.seed, rs.step, (uint64_t)(base[r] + (p == hines::kCellPadPos ? 0u : p)), rs.sigma);
-    }
-    *(lds_d2*)(lds + e * kCellRowDU + c * 16) = double2_t{B.dv[r], B.uv[r]};
+    const double uu = (p == 0u || p == hines::kCellPadPos) ? 0.0 : B.uv[r];
+    *(lds_d2*)(lds + e * kCellRowDU + c * 16) = double2_t{B.dv[r], uu};
     *(lds_f64*)(lds + kCellLdsB + e * kCellRowB + c * 8) = b;
+  }
+}
+
+// Backward elimination of one chunk from the LDS planes; (f, y) per step into fy.
+__device__ __forceinline__ void cell_backward(const u32x4& f, const lds_d2* pdu, const lds_f64* pb, lds_d2* stk,
+                                              double& cd, double& cb, double& td, double& tb, int& m,
+                                              double2_t* fy) {
+#pragma unroll
+  for (int e = 0; e < CK; ++e) {
+    const unsigned fe = cell_byte(f, e);
+    const double2_t du = pdu[e * (kCellRowDU / 16)];
+    double dd = du.x, bb = pb[e * (kCellRowB / 8)];
+    const double uu = du.y;
+    const double kc = (fe & hines::CF_TIP) ? 0.0 : 1.0;  // the carry enters unless this is a tip
+    dd = __builtin_fma(-kc, cd, dd);
+    bb = __builtin_fma(-kc, cb, bb);
+    if (fe & hines::CF_POP) {  // the merged entry of the other children; refill the top
+      dd = dd - td;
+      bb = bb - tb;
+      m -= 1;
+      const double2_t t = stk[64 * m];
+      td = t.x;
+      tb = t.y;
+    }
+    const double rr = rcp_nr(dd);
+    const double fv = uu * rr, yv = bb * rr;
+    cd = uu * fv;
+    cb = uu * yv;
+    if (fe & hines::CF_PUSH) {
+      stk[64 * m] = double2_t{td, tb};
+      m += 1;
+      td = cd;
+      tb = cb;
+    }
+    if (fe & hines::CF_MERGE) {
+      td = td + cd;
+      tb = tb + cb;
+    }
+    fy[e] = double2_t{fv, yv};
+  }
+}
+
+// Forward substitution of one chunk (steps in reverse); x per step into the
+// b plane, then through the gather mapping to the user order.
+__device__ __forceinline__ void cell_forward(const u32x4& f, const u32x4& c0, const u32x4& c1, const double2_t* fy,
+                                             lds_f64* pb, const lds_f64* xrd, lds_f64* stx, double& xc, double& xt,
+                                             int& m, double* x, const int64_t* base) {
+#pragma unroll
+  for (int e = CK - 1; e >= 0; --e) {
+    const unsigned fe = cell_byte(f, e);
+    const double xp = (fe & (hines::CF_PUSH | hines::CF_MERGE)) ? xt : xc;
+    if (fe & hines::CF_PUSH) {
+      m -= 1;
+      xt = stx[64 * m];
+    }
+    const double xv = __builtin_fma(-fy[e].x, xp, fy[e].y);
+    if (fe & hines::CF_POP) {
+      stx[64 * m] = xt;
+      m += 1;
+      xt = xv;
+    }
+    xc = xv;
+    pb[e * (kCellRowB / 8)] = xv;
+  }
+#pragma unroll
+  for (int r = 0; r < CK; ++r) {
+    const double xv = xrd[4 * r];
+    const unsigned p = cell_pos(c0, c1, r);
+    if (p != hines::kCellPadPos) x[base[r] + p] = xv;
   }
 }
 
@@ -985,19 +1057,23 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
   const lds_d2* pdu = (const lds_d2*)lds + lane;
   lds_f64* pb = (lds_f64*)(lds + kCellLdsB) + lane;
 
-  // ---- backward sweep ----
+  // ---- backward sweep: the gather of chunk k + 1 and the stores of chunk
+  // k - 1 overlap the elimination of chunk k ----
   u32x4 p0 = posv[0], p1 = posv[1], fl = flv[0];
   CellBatch<RHS> B;
   cell_load<RHS>(B, rs, d, u, base, p0, p1);
-  u32x4 q0 = p0, q1 = p1;
-  if (nk > 1) {
-    q0 = posv[128];
-    q1 = posv[129];
-  }
+  const int k1 = min(1, nk - 1);
+  u32x4 q0 = posv[128 * k1], q1 = posv[128 * k1 + 1];
   double cd = 0.0, cb = 0.0, td = 0.0, tb_ = 0.0;
   int m = 0;
+  double2_t fy[CK];
   for (int k = 0; k < nk; ++k) {
     cell_put<RHS>(B, rs, base, p0, p1, lds, lane);
+    if (k > 0) {
+      double2_t* sk = scr + (k - 1) * (CK * 64);
+#pragma unroll
+      for (int e = 0; e < CK; ++e) sk[e * 64] = fy[e];
+    }
     const u32x4 f = fl;
     if (k + 1 < nk) {
       fl = flv[64 * (k + 1)];
@@ -1008,104 +1084,43 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
       q0 = posv[128 * k2];
       q1 = posv[128 * k2 + 1];
     }
-    double2_t* sk = scr + k * (CK * 64);
-#pragma unroll
-    for (int e = 0; e < CK; ++e) {
-      const unsigned fe = cell_byte(f, e);
-      const double2_t du = pdu[e * (kCellRowDU / 16)];
-      const double bv = pb[e * (kCellRowB / 8)];
-      const bool pad = fe & hines::CF_PAD;
-      double dd = pad ? 1.0 : du.x;
-      const double uu = (fe & (hines::CF_PAD | hines::CF_ROOT)) ? 0.0 : du.y;
-      double bb = pad ? 0.0 : bv;
-      if (fe & hines::CF_TIP) {
-        cd = 0.0;
-        cb = 0.0;
-      }
-      dd = dd - cd;
-      bb = bb - cb;
-      if (fe & hines::CF_POP) {
-        dd = dd - td;
-        bb = bb - tb_;
-        m -= 1;
-        const double2_t t = stk[64 * m];
-        td = t.x;
-        tb_ = t.y;
-      }
-      const double rr = rcp_nr(dd);
-      const double fv = uu * rr, yv = bb * rr;
-      cd = uu * fv;
-      cb = uu * yv;
-      if (fe & hines::CF_PUSH) {
-        stk[64 * m] = double2_t{td, tb_};
-        m += 1;
-        td = cd;
-        tb_ = cb;
-      }
-      if (fe & hines::CF_MERGE) {
-        td = td + cd;
-        tb_ = tb_ + cb;
-      }
-      sk[e * 64] = double2_t{fv, yv};
-    }
+    cell_backward(f, pdu, pb, stk, cd, cb, td, tb_, m, fy);
   }
-  // the forward sweep reads back this wave's own scratch stores
+  // chunk nk - 1 stays in registers: it is the first one of the forward sweep.
+  // The forward sweep reads back this wave's own scratch stores.
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 
-  // ---- forward sweep ----
+  // ---- forward sweep: two register sets, the loads of the next chunk overlap
+  // the substitution of this one ----
   lds_f64* stx = (lds_f64*)(lds + kCellLdsStack) + lane;  // slot s at stx[64 s]
-  double2_t fy[CK];
-  {
-    const double2_t* sk = scr + (nk - 1) * (CK * 64);
-#pragma unroll
-    for (int e = 0; e < CK; ++e) fy[e] = sk[e * 64];
-  }
-  p0 = posv[128 * (nk - 1)];
-  p1 = posv[128 * (nk - 1) + 1];
-  fl = flv[64 * (nk - 1)];
+  const lds_f64* xrd = (const lds_f64*)(lds + kCellLdsB + (lane & 15) * kCellRowB) + (lane >> 4);
   double xc = 0.0, xt = 0.0;
   m = 0;
-  const lds_f64* xrd = (const lds_f64*)(lds + kCellLdsB + (lane & 15) * kCellRowB) + (lane >> 4);
-  for (int k = nk - 1; k >= 0; --k) {
-    const u32x4 f = fl, c0 = p0, c1 = p1;
-    double2_t fyn[CK];
-    if (k > 0) {
+  u32x4 a0 = posv[128 * (nk - 1)], a1 = posv[128 * (nk - 1) + 1], af = flv[64 * (nk - 1)];
+  double2_t fb[CK];
+  u32x4 b0 = a0, b1 = a1, bf = af;
+  for (int k = nk - 1;; k -= 2) {
+    if (k >= 1) {
       const double2_t* sk = scr + (k - 1) * (CK * 64);
 #pragma unroll
-      for (int e = 0; e < CK; ++e) fyn[e] = sk[e * 64];
-      p0 = posv[128 * (k - 1)];
-      p1 = posv[128 * (k - 1) + 1];
-      fl = flv[64 * (k - 1)];
+      for (int e = 0; e < CK; ++e) fb[e] = sk[e * 64];
+      b0 = posv[128 * (k - 1)];
+      b1 = posv[128 * (k - 1) + 1];
+      bf = flv[64 * (k - 1)];
     }
+    cell_forward(af, a0, a1, fy, pb, xrd, stx, xc, xt, m, x, base);
+    if (k < 1) break;
+    if (k >= 2) {
+      const double2_t* sk = scr + (k - 2) * (CK * 64);
 #pragma unroll
-    for (int e = CK - 1; e >= 0; --e) {
-      const unsigned fe = cell_byte(f, e);
-      double xp = xc;
-      if (fe & (hines::CF_PUSH | hines::CF_MERGE)) xp = xt;
-      if (fe & hines::CF_PUSH) {
-        m -= 1;
-        xt = stx[64 * m];
-      }
-      const double xv = __builtin_fma(-fy[e].x, xp, fy[e].y);
-      if (fe & hines::CF_POP) {
-        stx[64 * m] = xt;
-        m += 1;
-        xt = xv;
-      }
-      xc = xv;
-      pb[e * (kCellRowB / 8)] = xv;
+      for (int e = 0; e < CK; ++e) fy[e] = sk[e * 64];
+      a0 = posv[128 * (k - 2)];
+      a1 = posv[128 * (k - 2) + 1];
+      af = flv[64 * (k - 2)];
     }
-#pragma unroll
-    for (int r = 0; r < CK; ++r) {
-      const double xv = xrd[4 * r];
-      const unsigned p = cell_pos(c0, c1, r);
-      if (p != hines::kCellPadPos) x[base[r] + p] = xv;
-    }
-    if (k > 0) {
-#pragma unroll
-      for (int e = 0; e < CK; ++e) fy[e] = fyn[e];
-    }
+    cell_forward(bf, b0, b1, fb, pb, xrd, stx, xc, xt, m, x, base);
+    if (k < 2) break;
   }
 }
 
