@@ -12,7 +12,9 @@ refinement form on the same cells at dt in {0.001, 0.025, 1.0}.
 Other workloads (``--workload``): ``c3`` the batched implicit-Euler time loop
 (200,000 cells of 50/500/5,000/20,000 compartments, noise current, K steps per
 captured graph), ``c5`` the adjoint (16,384 cells x 1,000 compartments, 100
-steps, checkpoints every 10).
+steps, checkpoints every 10), ``scaling`` the paper's comparison of the
+one-thread-per-cell solver with the fine-grained one (Figure 7.1's axes): solve
+time of both kernels on the first 64 ... 65,536 cells of the headline workload.
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: the solve is per cell
 and needs no communication; this build measures one GPU.
@@ -37,6 +39,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_UNKNOWN = 32  # read diag, upper, rhs; write x (FP64)
 # Launch configuration of the timed solve (setup options of the plan).
 C2_OPTIONS = dict(cell_lanes=1)
+# The fine-grained (flow kernel) plan used for comparisons.
+C2_FLOW_OPTIONS = dict(max_group_unknowns=1536, split_branches=0, cell_order=0, group_width=64)
 CALIB_BYTES = 512 << 20  # bytes read (and written) by one calibration copy
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hines_solve_c2.json")
 KERNEL_SRC_DIR = os.path.join(ROOT, "paper_1810_12742_amd", "csrc")
@@ -349,12 +353,58 @@ def run_c5(args, torch, dev):
     }
 
 
+SCALING_CELLS = (64, 256, 1024, 4096, 16384, 65536)
+
+
+def run_scaling(args, torch, dev):
+    """Solve time against the number of cells for the cell-lane kernel (one
+    lane per cell, the paper's "old" solver) and the flow kernel (branch-level
+    parallelism, the "fine" solver): the first n cells of the headline
+    workload, each plan timed with HIP events."""
+    from workloads import configs
+    from paper_1810_12742_amd import Plan
+
+    s = configs.c2()
+    f = s.forest
+    d = torch.from_numpy(s.diag).to(dev)
+    u = torch.from_numpy(s.upper).to(dev)
+    b = torch.from_numpy(s.rhs).to(dev)
+    stream = torch.cuda.current_stream()
+    kernels = {"cell_lanes": dict(cell_lanes=1), "flow": dict(C2_FLOW_OPTIONS)}
+    rows = []
+    for nc in SCALING_CELLS:
+        sub = f.subset(np.arange(nc)) if nc < f.ncells else f
+        n = sub.n
+        row = {"ncells": nc, "unknowns": n}
+        x = torch.empty(n, dtype=torch.float64, device=dev)
+        for name, opts in kernels.items():
+            p = Plan(sub.parent, sub.cell_offsets, sub.branch_offsets, **opts)
+            ms = _time(torch, lambda: p.solve(d[:n], u[:n], b[:n], out=x, stream=stream), args.steps, args.warmup,
+                       stream)
+            row[name + "_ms"] = ms
+            p.close()
+        row["fine_speedup_over_old"] = row["cell_lanes_ms"] / row["flow_ms"]
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    last = rows[-1]
+    best = min(last["cell_lanes_ms"], last["flow_ms"])
+    return {
+        "metric": METRIC, "value": last["unknowns"] / (best * 1e-3), "unit": "unknowns/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": best, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "scaling: first n cells of c2, n = " + ", ".join(map(str, SCALING_CELLS)) +
+                               "; value is the faster kernel at the largest n",
+                   "kernels": {k: v for k, v in kernels.items()}},
+        "rows": rows,
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("c2", "c3", "c5"), default="c2")
+    ap.add_argument("--workload", choices=("c2", "c3", "c5", "scaling"), default="c2")
     ap.add_argument("--cells", type=int, default=0, help="c3/c5: number of cells (default: the full workload)")
     ap.add_argument("--graph-steps", type=int, default=100, help="c3: time steps per captured graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -372,7 +422,7 @@ def main(argv=None):
     import torch
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    run = {"c2": run_c2, "c3": run_c3, "c5": run_c5}[args.workload]
+    run = {"c2": run_c2, "c3": run_c3, "c5": run_c5, "scaling": run_scaling}[args.workload]
     print(json.dumps(run(args, torch, dev)), flush=True)
     return 0
 

@@ -921,6 +921,10 @@ __device__ __forceinline__ unsigned cell_pos(const u32x4& p0, const u32x4& p1, i
   return (w >> (16 * (r & 1))) & 0xffffu;
 }
 
+// Table and scratch traffic is read once per sweep: non-temporal, so that it
+// does not push the gathered lines of d, u, b out of L2.
+__device__ __forceinline__ u32x4 stream_ld(const u32x4* p) { return __builtin_nontemporal_load(p); }
+
 template <int RHS>
 struct CellBatch {
   double dv[CK], uv[CK], bv[CK];
@@ -1059,11 +1063,11 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
 
   // ---- backward sweep: the gather of chunk k + 1 and the stores of chunk
   // k - 1 overlap the elimination of chunk k ----
-  u32x4 p0 = posv[0], p1 = posv[1], fl = flv[0];
+  u32x4 p0 = stream_ld(posv), p1 = stream_ld(posv + 1), fl = stream_ld(flv);
   CellBatch<RHS> B;
   cell_load<RHS>(B, rs, d, u, base, p0, p1);
   const int k1 = min(1, nk - 1);
-  u32x4 q0 = posv[128 * k1], q1 = posv[128 * k1 + 1];
+  u32x4 q0 = stream_ld(posv + 128 * k1), q1 = stream_ld(posv + 128 * k1 + 1);
   double cd = 0.0, cb = 0.0, td = 0.0, tb_ = 0.0;
   int m = 0;
   double2_t fy[CK];
@@ -1072,17 +1076,17 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
     if (k > 0) {
       double2_t* sk = scr + (k - 1) * (CK * 64);
 #pragma unroll
-      for (int e = 0; e < CK; ++e) sk[e * 64] = fy[e];
+      for (int e = 0; e < CK; ++e) __builtin_nontemporal_store(fy[e], sk + e * 64);
     }
     const u32x4 f = fl;
     if (k + 1 < nk) {
-      fl = flv[64 * (k + 1)];
+      fl = stream_ld(flv + 64 * (k + 1));
       cell_load<RHS>(B, rs, d, u, base, q0, q1);
       p0 = q0;
       p1 = q1;
       const int k2 = min(k + 2, nk - 1);
-      q0 = posv[128 * k2];
-      q1 = posv[128 * k2 + 1];
+      q0 = stream_ld(posv + 128 * k2);
+      q1 = stream_ld(posv + 128 * k2 + 1);
     }
     cell_backward(f, pdu, pb, stk, cd, cb, td, tb_, m, fy);
   }
@@ -1097,27 +1101,28 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
   const lds_f64* xrd = (const lds_f64*)(lds + kCellLdsB + (lane & 15) * kCellRowB) + (lane >> 4);
   double xc = 0.0, xt = 0.0;
   m = 0;
-  u32x4 a0 = posv[128 * (nk - 1)], a1 = posv[128 * (nk - 1) + 1], af = flv[64 * (nk - 1)];
+  u32x4 a0 = stream_ld(posv + 128 * (nk - 1)), a1 = stream_ld(posv + 128 * (nk - 1) + 1),
+        af = stream_ld(flv + 64 * (nk - 1));
   double2_t fb[CK];
   u32x4 b0 = a0, b1 = a1, bf = af;
   for (int k = nk - 1;; k -= 2) {
     if (k >= 1) {
       const double2_t* sk = scr + (k - 1) * (CK * 64);
 #pragma unroll
-      for (int e = 0; e < CK; ++e) fb[e] = sk[e * 64];
-      b0 = posv[128 * (k - 1)];
-      b1 = posv[128 * (k - 1) + 1];
-      bf = flv[64 * (k - 1)];
+      for (int e = 0; e < CK; ++e) fb[e] = __builtin_nontemporal_load(sk + e * 64);
+      b0 = stream_ld(posv + 128 * (k - 1));
+      b1 = stream_ld(posv + 128 * (k - 1) + 1);
+      bf = stream_ld(flv + 64 * (k - 1));
     }
     cell_forward(af, a0, a1, fy, pb, xrd, stx, xc, xt, m, x, base);
     if (k < 1) break;
     if (k >= 2) {
       const double2_t* sk = scr + (k - 2) * (CK * 64);
 #pragma unroll
-      for (int e = 0; e < CK; ++e) fy[e] = sk[e * 64];
-      a0 = posv[128 * (k - 2)];
-      a1 = posv[128 * (k - 2) + 1];
-      af = flv[64 * (k - 2)];
+      for (int e = 0; e < CK; ++e) fy[e] = __builtin_nontemporal_load(sk + e * 64);
+      a0 = stream_ld(posv + 128 * (k - 2));
+      a1 = stream_ld(posv + 128 * (k - 2) + 1);
+      af = stream_ld(flv + 64 * (k - 2));
     }
     cell_forward(bf, b0, b1, fb, pb, xrd, stx, xc, xt, m, x, base);
     if (k < 2) break;
