@@ -1,5 +1,5 @@
-// Tables of the cell-lane solve kernel: one lane per cell, 64 cells of similar
-// size per wave.  Pure C++17; no HIP.
+// Tables of the cell-lane solve kernel: one lane per cell (or per half of a
+// large cell), 64 lanes of similar length per wave.  Pure C++17; no HIP.
 //
 // The Hines elimination (paper §2) needs only that every compartment is
 // eliminated after all its children and substituted after its parent.  A
@@ -12,6 +12,14 @@
 // the deepest stack bounds the depth by a Strahler-like number, O(log) of the
 // number of tips.  The forward sweep mirrors this: x of a compartment with two
 // or more children waits on the stack for its later children.
+//
+// A cell much longer than the average is cut at one edge (v, p(v)) into the
+// subtree S of v and the rest P, walked by the paired lanes c and c + 32 of
+// one wave.  S starts at step 0 and ends with v; P ends with the cell root and
+// visits the path from the root to p(v) first in its preorder, so p(v) comes
+// late in its backward walk.  The contribution of v crosses through an LDS
+// mailbox at a strictly later step, and x of p(v) crosses back in the forward
+// sweep, which runs the steps in reverse.
 #include <algorithm>
 #include <numeric>
 
@@ -21,133 +29,262 @@ namespace hines {
 
 namespace {
 
-// Preorder of one cell (relative indices 0..m-1, root 0) with the deepest-
-// stack child last; fills flags per relative index and returns the stack need.
-int32_t cell_order(const int32_t* par, int64_t lo, int32_t m, std::vector<int32_t>& pre,
-                   std::vector<uint8_t>& fl, std::vector<int32_t>& ch_off, std::vector<int32_t>& ch,
-                   std::vector<int32_t>& need, std::vector<int32_t>& heavy) {
-  ch_off.assign(m + 1, 0);
-  for (int32_t i = 1; i < m; ++i) ch_off[par[lo + i] - lo + 1]++;
-  for (int32_t i = 0; i < m; ++i) ch_off[i + 1] += ch_off[i];
-  ch.resize(std::max(m - 1, 0));
-  {
-    std::vector<int32_t> fill(ch_off.begin(), ch_off.end() - 1);
-    for (int32_t i = 1; i < m; ++i) ch[fill[par[lo + i] - lo]++] = i;  // ascending per parent
-  }
-  need.assign(m, 0);
-  heavy.assign(m, -1);
-  for (int32_t v = m - 1; v >= 0; --v) {
-    int32_t b1 = -1, b2 = -1, h = -1;
-    for (int32_t k = ch_off[v]; k < ch_off[v + 1]; ++k) {
-      const int32_t c = ch[k], nc = need[c];
-      if (nc > b1) {
-        b2 = b1;
-        b1 = nc;
-        h = c;
-      } else if (nc > b2) {
-        b2 = nc;
-      }
-    }
-    const int32_t nch = ch_off[v + 1] - ch_off[v];
-    need[v] = nch == 0 ? 0 : (nch == 1 ? b1 : std::max(b1, b2 + 1));
-    heavy[v] = h;
-  }
-  // preorder: light children in ascending index, the heavy child last
-  pre.clear();
-  fl.assign(m, 0);
-  std::vector<int32_t> st;
-  st.push_back(0);
-  while (!st.empty()) {
-    const int32_t v = st.back();
-    st.pop_back();
-    pre.push_back(v);
-    const int32_t b = ch_off[v], e = ch_off[v + 1], nch = e - b;
-    uint8_t f = 0;
-    if (nch == 0) f |= CF_TIP;
-    if (nch >= 2) f |= CF_POP;
-    if (v == 0) f |= CF_ROOT;
-    fl[v] |= f;
-    if (nch == 0) continue;
-    const int32_t h = heavy[v];
-    st.push_back(h);
-    // the light children, popped in ascending order
-    for (int32_t k = e - 1; k >= b; --k)
-      if (ch[k] != h) st.push_back(ch[k]);
-    if (nch >= 2) {
-      fl[h] |= CF_PUSH;
-      bool first = true;
-      for (int32_t k = b; k < e; ++k) {
-        if (ch[k] == h) continue;
-        if (first) first = false;  // the first light child carries in registers
-        else fl[ch[k]] |= CF_MERGE;
-      }
-    }
-  }
-  return m > 0 ? need[0] : 0;
+struct CellTree {
+  std::vector<int32_t> ch_off, ch;  // children CSR (relative indices, ascending)
+  std::vector<int32_t> size;        // subtree sizes
+};
+
+void cell_tree(const int32_t* par, int64_t lo, int32_t m, CellTree& T) {
+  T.ch_off.assign(m + 1, 0);
+  for (int32_t i = 1; i < m; ++i) T.ch_off[par[lo + i] - lo + 1]++;
+  for (int32_t i = 0; i < m; ++i) T.ch_off[i + 1] += T.ch_off[i];
+  T.ch.resize(std::max(m - 1, 0));
+  std::vector<int32_t> fill(T.ch_off.begin(), T.ch_off.end() - 1);
+  for (int32_t i = 1; i < m; ++i) T.ch[fill[par[lo + i] - lo]++] = i;
+  T.size.assign(m, 1);
+  for (int32_t i = m - 1; i >= 1; --i) T.size[par[lo + i] - lo] += T.size[i];
 }
+
+// Walk of the subtree of `root` without the subtree of `cut` (-1: none).
+// `forced[a]` (-1: none) is put first among a's children; among the others
+// the child with the deepest stack need goes last.  Appends the preorder to
+// `pre`, sets the flags of the visited nodes in `fl` (indexed by relative
+// node) and returns the stack need of the walk.
+int32_t walk(const CellTree& T, int32_t root, int32_t cut, const std::vector<int32_t>& forced,
+             std::vector<int32_t>& pre, std::vector<uint8_t>& fl, std::vector<int32_t>& need,
+             std::vector<int32_t>& seen, std::vector<int32_t>& st) {
+  // the visited set in some preorder, then the needs in reverse (children first)
+  seen.clear();
+  st.clear();
+  st.push_back(root);
+  while (!st.empty()) {
+    const int32_t a = st.back();
+    st.pop_back();
+    seen.push_back(a);
+    for (int32_t k = T.ch_off[a]; k < T.ch_off[a + 1]; ++k)
+      if (T.ch[k] != cut) st.push_back(T.ch[k]);
+  }
+  // children of a in walk order: forced child, the others ascending, the deepest-need child last
+  auto ordered = [&](int32_t a, std::vector<int32_t>& out) {
+    out.clear();
+    int32_t h = -1, hn = -1;
+    const int32_t f = forced[a];
+    for (int32_t k = T.ch_off[a]; k < T.ch_off[a + 1]; ++k) {
+      const int32_t c = T.ch[k];
+      if (c == cut || c == f) continue;
+      if (need[c] > hn) {
+        hn = need[c];
+        h = c;
+      }
+    }
+    if (f >= 0) out.push_back(f);
+    for (int32_t k = T.ch_off[a]; k < T.ch_off[a + 1]; ++k) {
+      const int32_t c = T.ch[k];
+      if (c != cut && c != f && c != h) out.push_back(c);
+    }
+    if (h >= 0) out.push_back(h);
+  };
+  std::vector<int32_t> kids;
+  for (size_t i = seen.size(); i-- > 0;) {
+    const int32_t a = seen[i];
+    ordered(a, kids);
+    const int32_t nk = (int32_t)kids.size();
+    int32_t nd = 0;
+    if (nk == 1) {
+      nd = need[kids[0]];
+    } else if (nk >= 2) {
+      int32_t early = 0;
+      for (int32_t j = 0; j + 1 < nk; ++j) early = std::max(early, need[kids[j]]);
+      nd = std::max(need[kids[nk - 1]], early + 1);
+    }
+    need[a] = nd;
+  }
+  // preorder with the chosen child orders, and the flags
+  st.clear();
+  st.push_back(root);
+  while (!st.empty()) {
+    const int32_t a = st.back();
+    st.pop_back();
+    pre.push_back(a);
+    ordered(a, kids);
+    const int32_t nk = (int32_t)kids.size();
+    uint8_t f = 0;
+    if (nk == 0) f |= CF_TIP;
+    if (nk >= 2) f |= CF_POP;
+    fl[a] |= f;
+    for (int32_t j = nk - 1; j >= 0; --j) st.push_back(kids[j]);
+    if (nk >= 2) {
+      fl[kids[nk - 1]] |= CF_PUSH;
+      for (int32_t j = 1; j + 1 < nk; ++j) fl[kids[j]] |= CF_MERGE;
+    }
+  }
+  return need[root];
+}
+
+// One lane's work: relative positions in backward order (padding excluded),
+// their flags, and whether the padding goes after the walk.
+struct LaneWork {
+  int64_t cell = -1;
+  std::vector<int32_t> back;  // backward order
+  std::vector<uint8_t> bfl;
+  bool pad_after = false;
+};
 
 }  // namespace
 
 Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_offsets, int64_t ncells,
                         CellLanes& out, std::string& err) {
   out = CellLanes{};
-  std::vector<int64_t> order(ncells);
-  std::iota(order.begin(), order.end(), 0);
+  auto size_of = [&](int64_t c) { return cell_offsets[c + 1] - cell_offsets[c]; };
   for (int64_t c = 0; c < ncells; ++c) {
-    const int64_t m = cell_offsets[c + 1] - cell_offsets[c];
-    if (m > kCellMaxSize) {
-      err = "cell " + std::to_string(c) + " has " + std::to_string(m) + " compartments; the cell-lane kernel takes " +
-            std::to_string(kCellMaxSize) + " at most";
+    if (size_of(c) > kCellMaxSize) {
+      err = "cell " + std::to_string(c) + " has " + std::to_string(size_of(c)) +
+            " compartments; the cell-lane kernel takes " + std::to_string(kCellMaxSize) + " at most";
       return ERR_TOO_BIG;
     }
   }
-  auto size_of = [&](int64_t c) { return cell_offsets[c + 1] - cell_offsets[c]; };
-  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return size_of(a) > size_of(b); });
-  const int64_t nw = (ncells + 63) / 64;
+  // cells longer than 0.8 times the mean are cut in two (when the pieces fit): shorter
+  // lanes and more waves than wave slots, so that short waves fill in behind long ones
+  const double mean = ncells ? (double)n / (double)ncells : 0.0;
+  const int64_t split_above = std::max<int64_t>(4 * kCellChunk, (int64_t)(0.8 * mean));
+
+  CellTree T;
+  std::vector<int32_t> forced, need, pre, seen, st;
+  std::vector<uint8_t> fl;
+  std::vector<LaneWork> whole, halves;  // halves: S, P, S, P, ...
+  std::vector<int64_t> pair_span;        // per pair: the shortest span that keeps the mailbox order
+  auto to_back = [](const std::vector<int32_t>& pre_, const std::vector<uint8_t>& fl_, LaneWork& w) {
+    w.back.assign(pre_.rbegin(), pre_.rend());
+    w.bfl.resize(w.back.size());
+    for (size_t i = 0; i < w.back.size(); ++i) w.bfl[i] = fl_[w.back[i]];
+  };
+  for (int64_t c = 0; c < ncells; ++c) {
+    const int64_t lo = cell_offsets[c];
+    const int32_t m = (int32_t)size_of(c);
+    cell_tree(parent, lo, m, T);
+    forced.assign(m, -1);
+    need.assign(m, 0);
+    bool done = false;
+    if (m > split_above) {
+      // cut vertex: subtree size closest to m / 2 from below
+      int32_t v = -1;
+      for (int32_t i = 1; i < m; ++i)
+        if (2 * T.size[i] <= m && (v < 0 || T.size[i] > T.size[v])) v = i;
+      if (v > 0 && 4 * T.size[v] >= m) {
+        const int32_t pv = parent[lo + v] - (int32_t)lo;
+        int32_t depth = 0;
+        for (int32_t a = pv; a != 0; a = parent[lo + a] - (int32_t)lo) {
+          forced[parent[lo + a] - lo] = a;
+          ++depth;
+        }
+        LaneWork S, P;
+        S.cell = P.cell = c;
+        fl.assign(m, 0);
+        pre.clear();
+        const int32_t ns = walk(T, v, -1, forced, pre, fl, need, seen, st);
+        fl[v] |= CF_MBOUT;
+        to_back(pre, fl, S);
+        S.pad_after = true;
+        pre.clear();
+        const int32_t np = walk(T, 0, v, forced, pre, fl, need, seen, st);
+        fl[pv] |= CF_MBIN;
+        fl[0] |= CF_ROOT;
+        to_back(pre, fl, P);
+        if (ns <= kCellStack && np <= kCellStack && pre.size() > (size_t)depth && pre[depth] == pv) {
+          out.max_need = std::max(out.max_need, std::max(ns, np));
+          pair_span.push_back(std::max<int64_t>((int64_t)P.back.size(), (int64_t)S.back.size() + depth + 1));
+          halves.push_back(std::move(S));
+          halves.push_back(std::move(P));
+          done = true;
+        }
+        forced.assign(m, -1);
+      }
+    }
+    if (!done) {
+      LaneWork W;
+      W.cell = c;
+      fl.assign(m, 0);
+      pre.clear();
+      const int32_t nd = walk(T, 0, -1, forced, pre, fl, need, seen, st);
+      if (nd > kCellStack) {
+        err = "cell " + std::to_string(c) + " needs " + std::to_string(nd) +
+              " contribution stack entries; the cell-lane kernel holds " + std::to_string(kCellStack);
+        return ERR_TOO_BIG;
+      }
+      fl[0] |= CF_ROOT;
+      out.max_need = std::max(out.max_need, nd);
+      to_back(pre, fl, W);
+      whole.push_back(std::move(W));
+    }
+  }
+  // waves: 32 cut cells (lanes c and c + 32) or 64 whole cells, longest first
+  struct WavePlan {
+    int64_t span;
+    std::vector<const LaneWork*> lanes;  // 64 entries, nullptr for empty lanes
+  };
+  std::vector<WavePlan> plans;
+  {
+    std::vector<int64_t> idx(whole.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](int64_t a, int64_t b) { return whole[a].back.size() > whole[b].back.size(); });
+    for (size_t w = 0; w < idx.size(); w += 64) {
+      WavePlan P{0, std::vector<const LaneWork*>(64, nullptr)};
+      for (size_t l = 0; l < 64 && w + l < idx.size(); ++l) {
+        P.lanes[l] = &whole[idx[w + l]];
+        P.span = std::max<int64_t>(P.span, (int64_t)whole[idx[w + l]].back.size());
+      }
+      plans.push_back(std::move(P));
+    }
+    std::vector<int64_t> pidx(pair_span.size());
+    std::iota(pidx.begin(), pidx.end(), 0);
+    std::stable_sort(pidx.begin(), pidx.end(), [&](int64_t a, int64_t b) { return pair_span[a] > pair_span[b]; });
+    for (size_t w = 0; w < pidx.size(); w += 32) {
+      WavePlan P{0, std::vector<const LaneWork*>(64, nullptr)};
+      for (size_t l = 0; l < 32 && w + l < pidx.size(); ++l) {
+        P.lanes[l] = &halves[2 * pidx[w + l]];
+        P.lanes[l + 32] = &halves[2 * pidx[w + l] + 1];
+        P.span = std::max(P.span, pair_span[pidx[w + l]]);
+      }
+      plans.push_back(std::move(P));
+    }
+    std::stable_sort(plans.begin(), plans.end(), [](const WavePlan& a, const WavePlan& b) { return a.span > b.span; });
+  }
+  const int64_t nw = (int64_t)plans.size();
   out.nwaves = nw;
   out.waves.resize(nw);
   out.lane_cell.assign(nw * 64, -1);
   out.base.assign(nw * 64, 0);
   int64_t chunks = 0;
   for (int64_t w = 0; w < nw; ++w) {
-    const int64_t first = order[w * 64];
-    const int32_t nk = (int32_t)((size_of(first) + kCellChunk - 1) / kCellChunk);
-    out.waves[w] = KCellWave{chunks, nk, (int32_t)std::min<int64_t>(64, ncells - w * 64)};
+    const int32_t nk = (int32_t)((plans[w].span + kCellChunk - 1) / kCellChunk);
+    int32_t nc = 0;
+    for (int l = 0; l < 64; ++l) nc += plans[w].lanes[l] && !plans[w].lanes[l]->pad_after;
+    out.waves[w] = KCellWave{chunks, nk, nc};
     chunks += nk;
   }
   out.nchunks = chunks;
   out.pos.assign(chunks * 1024, kCellPadPos);
   out.flags.assign(chunks * 1024, (uint8_t)(CF_PAD | CF_TIP));
-  std::vector<int32_t> pre, ch_off, ch, need, heavy;
-  std::vector<uint8_t> fl;
   for (int64_t w = 0; w < nw; ++w) {
     const KCellWave& W = out.waves[w];
     const int64_t span = (int64_t)W.nchunk * kCellChunk;
-    for (int32_t c = 0; c < W.ncell; ++c) {
-      const int64_t cell = order[w * 64 + c];
-      const int64_t lo = cell_offsets[cell];
-      const int32_t m = (int32_t)size_of(cell);
-      out.lane_cell[w * 64 + c] = (int32_t)cell;
-      out.base[w * 64 + c] = lo;
-      const int32_t nd = cell_order(parent, lo, m, pre, fl, ch_off, ch, need, heavy);
-      if (nd > kCellStack) {
-        err = "cell " + std::to_string(cell) + " needs " + std::to_string(nd) +
-              " contribution stack entries; the cell-lane kernel holds " + std::to_string(kCellStack);
-        return ERR_TOO_BIG;
-      }
-      out.max_need = std::max(out.max_need, nd);
-      // backward step q: padding for q < npad, then the reverse preorder
-      const int64_t npad = span - m;
-      for (int64_t q = npad; q < span; ++q) {
-        const int32_t v = pre[m - 1 - (q - npad)];
+    for (int c = 0; c < 64; ++c) {
+      const LaneWork* L = plans[w].lanes[c];
+      if (!L) continue;
+      out.lane_cell[w * 64 + c] = (int32_t)L->cell;
+      out.base[w * 64 + c] = cell_offsets[L->cell];
+      const int64_t len = (int64_t)L->back.size();
+      const int64_t q0 = L->pad_after ? 0 : span - len;
+      for (int64_t t = 0; t < len; ++t) {
+        const int64_t q = q0 + t;
         const int64_t k = q / kCellChunk, e = q % kCellChunk;
         const int64_t j = ((c & 3) << 4) | e, r = c >> 2;
-        out.pos[(W.chunk_off + k) * 1024 + j * 16 + r] = (uint16_t)v;
-        out.flags[(W.chunk_off + k) * 1024 + c * 16 + e] = fl[v];
+        out.pos[(W.chunk_off + k) * 1024 + j * 16 + r] = (uint16_t)L->back[t];
+        out.flags[(W.chunk_off + k) * 1024 + c * 16 + e] = L->bfl[t];
       }
     }
   }
-  (void)n;
   out.built = true;
   return OK;
 }

@@ -416,6 +416,31 @@ bool check_cell_tables(const hines::HostPlan& P, const int64_t* cell_offsets, st
         return false;
       }
     }
+    // mailboxes: lane c < 32 posts at most once (its half's root), lane c + 32
+    // takes it exactly then, at a strictly later step
+    for (int c = 0; c < 32; ++c) {
+      int64_t qo = -1, qi = -1;
+      int no = 0, ni = 0;
+      for (int64_t q = 0; q < (int64_t)W.nchunk * hines::kCellChunk; ++q) {
+        const int64_t g = W.chunk_off + q / hines::kCellChunk, e = q % hines::kCellChunk;
+        const uint8_t fo = C.flags[g * 1024 + c * 16 + e], fi = C.flags[g * 1024 + (c + 32) * 16 + e];
+        if (fo & hines::CF_MBIN) ni += 100;  // wrong side
+        if (fi & hines::CF_MBOUT) no += 100;
+        if (fo & hines::CF_MBOUT) {
+          ++no;
+          qo = q;
+        }
+        if (fi & hines::CF_MBIN) {
+          ++ni;
+          qi = q;
+        }
+      }
+      if (no != ni || no > 1 || (no == 1 && !(qo < qi)) ||
+          (no == 1 && C.lane_cell[w * 64 + c] != C.lane_cell[w * 64 + c + 32])) {
+        why = "wave " + std::to_string(w) + " lane " + std::to_string(c) + " mailbox unpaired or out of order";
+        return false;
+      }
+    }
   }
   return true;
 }

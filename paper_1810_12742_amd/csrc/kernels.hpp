@@ -895,6 +895,10 @@ __global__ __launch_bounds__(64) void k_solve_flow(DevTables tb, RhsSpec rs, con
 // store per step) and return in the forward sweep, whose x values pass back
 // through LDS to the gather mapping for the store in user order.
 //
+// A long cell may be cut in two halves walked by lanes c < 32 (the subtree)
+// and c + 32 (the rest); the cut edge's contribution and, in the forward
+// sweep, the parent's x cross through mailbox slot c at strictly ordered steps.
+//
 // Contributions to a parent (paper §2: d_p -= u_i f_i, b_p -= u_i y_i) stay in
 // registers when the parent is eliminated next.  The contributions of its
 // other children wait in one merged stack entry per pending parent; the top
@@ -907,7 +911,8 @@ constexpr int kCellRowDU = 64 * 16 + 16;  // bytes per element row of the (d, u)
 constexpr int kCellRowB = 64 * 8 + 16;    // bytes per element row of the b plane (x in the forward sweep)
 constexpr int kCellLdsB = CK * kCellRowDU;                 // byte offset of the b plane
 constexpr int kCellLdsStack = kCellLdsB + CK * kCellRowB;  // byte offset of the stack slots
-constexpr int kCellLds = kCellLdsStack + hines::kCellStack * 64 * 16;
+constexpr int kCellLdsMail = kCellLdsStack + hines::kCellStack * 64 * 16;  // byte offset of the mailboxes
+constexpr int kCellLds = kCellLdsMail + 64 * 16;
 
 typedef double double2_t __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) double2_t lds_d2;
@@ -975,9 +980,10 @@ __device__ __forceinline__ void cell_put(const CellBatch<RHS>& B, const RhsSpec&
 }
 
 // Backward elimination of one chunk from the LDS planes; (f, y) per step into fy.
+// mb: the mailboxes (slot c: the contribution of the cut-off half in lane c).
 __device__ __forceinline__ void cell_backward(const u32x4& f, const lds_d2* pdu, const lds_f64* pb, lds_d2* stk,
-                                              double& cd, double& cb, double& td, double& tb, int& m,
-                                              double2_t* fy) {
+                                              lds_d2* mb, int lane, double& cd, double& cb, double& td, double& tb,
+                                              int& m, double2_t* fy) {
 #pragma unroll
   for (int e = 0; e < CK; ++e) {
     const unsigned fe = cell_byte(f, e);
@@ -987,6 +993,11 @@ __device__ __forceinline__ void cell_backward(const u32x4& f, const lds_d2* pdu,
     const double kc = (fe & hines::CF_TIP) ? 0.0 : 1.0;  // the carry enters unless this is a tip
     dd = __builtin_fma(-kc, cd, dd);
     bb = __builtin_fma(-kc, cb, bb);
+    if (fe & hines::CF_MBIN) {  // the cut-off child's contribution, posted at an earlier step
+      const double2_t mv = mb[lane ^ 32];
+      dd = dd - mv.x;
+      bb = bb - mv.y;
+    }
     if (fe & hines::CF_POP) {  // the merged entry of the other children; refill the top
       dd = dd - td;
       bb = bb - tb;
@@ -1009,6 +1020,7 @@ __device__ __forceinline__ void cell_backward(const u32x4& f, const lds_d2* pdu,
       td = td + cd;
       tb = tb + cb;
     }
+    if (fe & hines::CF_MBOUT) mb[lane] = double2_t{cd, cb};
     fy[e] = double2_t{fv, yv};
   }
 }
@@ -1016,12 +1028,13 @@ __device__ __forceinline__ void cell_backward(const u32x4& f, const lds_d2* pdu,
 // Forward substitution of one chunk (steps in reverse); x per step into the
 // b plane, then through the gather mapping to the user order.
 __device__ __forceinline__ void cell_forward(const u32x4& f, const u32x4& c0, const u32x4& c1, const double2_t* fy,
-                                             lds_f64* pb, const lds_f64* xrd, lds_f64* stx, double& xc, double& xt,
-                                             int& m, double* x, const int64_t* base) {
+                                             lds_f64* pb, const lds_f64* xrd, lds_f64* stx, lds_d2* mb, int lane,
+                                             double& xc, double& xt, int& m, double* x, const int64_t* base) {
 #pragma unroll
   for (int e = CK - 1; e >= 0; --e) {
     const unsigned fe = cell_byte(f, e);
-    const double xp = (fe & (hines::CF_PUSH | hines::CF_MERGE)) ? xt : xc;
+    double xp = (fe & (hines::CF_PUSH | hines::CF_MERGE)) ? xt : xc;
+    if (fe & hines::CF_MBOUT) xp = mb[lane].x;  // x of the parent, posted by the other half
     if (fe & hines::CF_PUSH) {
       m -= 1;
       xt = stx[64 * m];
@@ -1032,6 +1045,7 @@ __device__ __forceinline__ void cell_forward(const u32x4& f, const u32x4& c0, co
       m += 1;
       xt = xv;
     }
+    if (fe & hines::CF_MBIN) mb[lane ^ 32].x = xv;
     xc = xv;
     pb[e * (kCellRowB / 8)] = xv;
   }
@@ -1058,6 +1072,7 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
   const u32x4* flv = (const u32x4*)(tb.cflag + W.chunk_off * 1024) + lane;      // + 64 per chunk
   double2_t* scr = (double2_t*)tb.cscr + W.chunk_off * (CK * 64) + lane;       // + CK * 64 per chunk
   lds_d2* stk = (lds_d2*)(lds + kCellLdsStack) + lane;                            // slot s at stk[64 s]
+  lds_d2* mb = (lds_d2*)(lds + kCellLdsMail);
   const lds_d2* pdu = (const lds_d2*)lds + lane;
   lds_f64* pb = (lds_f64*)(lds + kCellLdsB) + lane;
 
@@ -1071,14 +1086,18 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
   double cd = 0.0, cb = 0.0, td = 0.0, tb_ = 0.0;
   int m = 0;
   double2_t fy[CK];
+  u32x4 fprev = fl;
   for (int k = 0; k < nk; ++k) {
     cell_put<RHS>(B, rs, base, p0, p1, lds, lane);
-    if (k > 0) {
+    if (k > 0) {  // padding steps store nothing; the forward sweep reads their slots but
+                  // uses no value of a padding step (no carry or stack leaves one)
       double2_t* sk = scr + (k - 1) * (CK * 64);
 #pragma unroll
-      for (int e = 0; e < CK; ++e) __builtin_nontemporal_store(fy[e], sk + e * 64);
+      for (int e = 0; e < CK; ++e)
+        if (!(cell_byte(fprev, e) & hines::CF_PAD)) __builtin_nontemporal_store(fy[e], sk + e * 64);
     }
     const u32x4 f = fl;
+    fprev = f;
     if (k + 1 < nk) {
       fl = stream_ld(flv + 64 * (k + 1));
       cell_load<RHS>(B, rs, d, u, base, q0, q1);
@@ -1088,7 +1107,7 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
       q0 = stream_ld(posv + 128 * k2);
       q1 = stream_ld(posv + 128 * k2 + 1);
     }
-    cell_backward(f, pdu, pb, stk, cd, cb, td, tb_, m, fy);
+    cell_backward(f, pdu, pb, stk, mb, lane, cd, cb, td, tb_, m, fy);
   }
   // chunk nk - 1 stays in registers: it is the first one of the forward sweep.
   // The forward sweep reads back this wave's own scratch stores.
@@ -1114,7 +1133,7 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
       b1 = stream_ld(posv + 128 * (k - 1) + 1);
       bf = stream_ld(flv + 64 * (k - 1));
     }
-    cell_forward(af, a0, a1, fy, pb, xrd, stx, xc, xt, m, x, base);
+    cell_forward(af, a0, a1, fy, pb, xrd, stx, mb, lane, xc, xt, m, x, base);
     if (k < 1) break;
     if (k >= 2) {
       const double2_t* sk = scr + (k - 2) * (CK * 64);
@@ -1124,7 +1143,7 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
       a1 = stream_ld(posv + 128 * (k - 2) + 1);
       af = stream_ld(flv + 64 * (k - 2));
     }
-    cell_forward(bf, b0, b1, fb, pb, xrd, stx, xc, xt, m, x, base);
+    cell_forward(bf, b0, b1, fb, pb, xrd, stx, mb, lane, xc, xt, m, x, base);
     if (k < 2) break;
   }
 }

@@ -95,7 +95,7 @@ enum TableId : int32_t {
   T_NUM = 16,
 };
 
-// Cell-lane kernel (one lane per cell).  Each cell is processed in a depth-
+// Cell-lane kernel (one lane per cell, or per half of a long cell).  Each cell is processed in a depth-
 // first order of its compartments in which the children of a compartment are
 // visited with the child needing the deepest contribution stack last (paper
 // §2's elimination needs only that children precede parents in the backward
@@ -116,6 +116,9 @@ enum : uint8_t {
   CF_MERGE = 8,   // middle child: its contribution is added to the top entry
   CF_PAD = 16,    // padding: identity row
   CF_ROOT = 32,   // cell root: no coupling to a parent
+  CF_MBOUT = 64,  // root of the cut-off half of a cell (lane c < 32): its contribution leaves through
+                  // mailbox c, x of its parent comes back through it
+  CF_MBIN = 128,  // parent of that root (lane c + 32): takes the contribution, returns its x
 };
 struct KCellWave {
   int64_t chunk_off;  // first chunk of the wave in the pos / flags / scratch tables

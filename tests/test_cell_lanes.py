@@ -21,7 +21,7 @@ from workloads import configs
 from workloads.configs import random_system
 from workloads.trees import Forest
 
-TIP, POP, PUSH, MERGE, PAD, ROOT = 1, 2, 4, 8, 16, 32
+TIP, POP, PUSH, MERGE, PAD, ROOT, MBOUT, MBIN = 1, 2, 4, 8, 16, 32, 64, 128
 K = 16
 STACK = 12
 
@@ -40,8 +40,10 @@ def replay(plan, f, diag, upper, rhs):
     for w in range(waves.shape[0]):
         off, nk, ncell = (int(v) for v in waves[w])
         cells = lane_cell[w]
-        assert np.all(cells[:ncell] >= 0) and np.all(cells[ncell:] == -1)
+        assert 1 <= ncell <= 64 and np.any(cells >= 0)
         base = np.where(cells >= 0, co[np.maximum(cells, 0)], 0)
+        mb = np.zeros((64, 2))
+        up = lanes ^ 32
         scr = np.zeros((nk, K, 64, 2))
         cd = np.zeros(64)
         cb = np.zeros(64)
@@ -75,13 +77,18 @@ def replay(plan, f, diag, upper, rhs):
                 cb[tip] = 0.0
                 dd = dd - cd
                 bb = bb - cb
+                mbin = (fe & MBIN) != 0
+                assert np.all(lanes[mbin] >= 32)
+                dd = np.where(mbin, dd - mb[up, 0], dd)
+                bb = np.where(mbin, bb - mb[up, 1], bb)
                 pop = (fe & POP) != 0
                 dd = np.where(pop, dd - td, dd)
                 bb = np.where(pop, bb - tb, bb)
                 m[pop] -= 1
                 assert np.all(m >= 0), "stack underflow"
-                td = np.where(pop, stk[np.maximum(m, 0), lanes, 0], td)
-                tb = np.where(pop, stk[np.maximum(m, 0), lanes, 1], tb)
+                top = np.clip(m, 0, STACK - 1)  # lanes that do not pop read nothing in the kernel
+                td = np.where(pop, stk[top, lanes, 0], td)
+                tb = np.where(pop, stk[top, lanes, 1], tb)
                 rr = 1.0 / dd
                 fv = uu * rr
                 yv = bb * rr
@@ -98,6 +105,10 @@ def replay(plan, f, diag, upper, rhs):
                 assert np.all(m[merge] >= 1), "merge into an empty stack"
                 td = np.where(merge, td + cd, td)
                 tb = np.where(merge, tb + cb, tb)
+                mbout = (fe & MBOUT) != 0
+                assert np.all(lanes[mbout] < 32)
+                mb[mbout, 0] = cd[mbout]
+                mb[mbout, 1] = cb[mbout]
                 scr[k, e, :, 0] = fv
                 scr[k, e, :, 1] = yv
         assert np.all(m == 0), "backward stack not empty at the end"
@@ -111,16 +122,19 @@ def replay(plan, f, diag, upper, rhs):
                 fe = flags[g, :, e]
                 use = (fe & (PUSH | MERGE)) != 0
                 xp = np.where(use, xt, xc)
+                xp = np.where((fe & MBOUT) != 0, mb[lanes, 0], xp)
                 push = (fe & PUSH) != 0
                 m[push] -= 1
                 assert np.all(m >= 0), "forward stack underflow"
-                xt = np.where(push, stx[np.maximum(m, 0), lanes], xt)
+                xt = np.where(push, stx[np.clip(m, 0, STACK - 1), lanes], xt)
                 xv = scr[k, e, :, 1] - scr[k, e, :, 0] * xp
                 pop = (fe & POP) != 0
                 assert np.all(m[pop] < STACK), "forward stack overflow"
                 stx[m[pop], lanes[pop]] = xt[pop]
                 m[pop] += 1
                 xt = np.where(pop, xv, xt)
+                mbin = (fe & MBIN) != 0
+                mb[up[mbin], 0] = xv[mbin]
                 xc = xv
                 X[e] = xv
             for r in range(16):  # scatter through the gather mapping
@@ -187,6 +201,7 @@ def _check(f, diag, upper, seed=3):
     x = replay(p, f, diag, upper, rhs)
     xo = oracle.solve(f, diag, upper, rhs)
     assert cell_err(f, x, xo) <= 1e-12
+    return p
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -254,8 +269,38 @@ def test_stack_need_of_a_full_binary_tree():
         par = np.r_[-1, (np.arange(1, n) - 1) // 2].astype(np.int32)
         return par, np.array([0, n], dtype=np.int64)
 
-    p = Plan(*full(12), None, host_only=1, cell_lanes=1)
+    def with_cable(par, off, n_cable=40000):
+        # a long unbranched cell beside the tree raises the mean size, so the tree
+        # stays whole (cells are cut only above 0.8 times the mean)
+        n = off[-1]
+        cab = np.r_[-1, np.arange(n, n + n_cable - 1)].astype(np.int32)
+        return np.r_[par, cab].astype(np.int32), np.r_[off, n + n_cable].astype(np.int64)
+
+    p = Plan(*with_cable(*full(12)), None, host_only=1, cell_lanes=1)
     assert p.info["kernel"] == 3
     with pytest.raises(HinesError) as ei:
-        Plan(*full(13), None, host_only=1, cell_lanes=1)
+        Plan(*with_cable(*full(13)), None, host_only=1, cell_lanes=1)
     assert ei.value.code == "TOO_BIG"
+    # alone, the same tree is cut in two halves whose stacks fit
+    assert Plan(*full(13), None, host_only=1, cell_lanes=1).info["kernel"] == 3
+
+
+def test_long_cells_are_cut_into_paired_halves():
+    """Cells longer than 1.25 times the mean are cut at one edge into two
+    halves walked by lanes c and c + 32: the wave holding them has mailbox
+    posts in lanes below 32 and takes in the lanes 32 above, and the solution
+    still matches the oracle.  The longest lane is shorter than the longest
+    cell."""
+    rng = np.random.default_rng(8)
+    from workloads import grow_random_forest, cable_values
+    sizes = np.r_[np.full(100, 300), np.full(28, 3000)]
+    f = grow_random_forest(rng, len(sizes), target_size=sizes)
+    s = cable_values(f, np.random.default_rng(9), a_kind="uniform", rhs=False)
+    p = _check(f, s.diag, s.upper)
+    fl = p.table("cell_flags").reshape(-1, 64, 16)
+    waves = p.table("cell_waves").reshape(-1, 3)
+    outs = np.nonzero(fl & MBOUT)
+    ins = np.nonzero(fl & MBIN)
+    assert outs[0].size == 28 and ins[0].size == 28
+    assert np.all(outs[1] < 32) and np.all(ins[1] >= 32)
+    assert waves[:, 1].max() * 16 < 3000
