@@ -264,8 +264,8 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
     chunks += nk;
   }
   out.nchunks = chunks;
-  out.pos.assign(chunks * 1024, kCellPadPos);
-  out.flags.assign(chunks * 1024, (uint8_t)(CF_PAD | CF_TIP));
+  out.pos.assign(chunks * kCellChunkElems, kCellPadPos);
+  out.flags.assign(chunks * kCellChunkElems, (uint8_t)(CF_PAD | CF_TIP));
   for (int64_t w = 0; w < nw; ++w) {
     const KCellWave& W = out.waves[w];
     const int64_t span = (int64_t)W.nchunk * kCellChunk;
@@ -278,10 +278,10 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
       const int64_t q0 = L->pad_after ? 0 : span - len;
       for (int64_t t = 0; t < len; ++t) {
         const int64_t q = q0 + t;
-        const int64_t k = q / kCellChunk, e = q % kCellChunk;
-        const int64_t j = ((c & 3) << 4) | e, r = c >> 2;
-        out.pos[(W.chunk_off + k) * 1024 + j * 16 + r] = (uint16_t)L->back[t];
-        out.flags[(W.chunk_off + k) * 1024 + c * 16 + e] = L->bfl[t];
+        const int64_t k = q / kCellChunk;
+        const int32_t e = (int32_t)(q % kCellChunk);
+        out.pos[cell_pos_index(W.chunk_off + k, c, e)] = (uint16_t)L->back[t];
+        out.flags[cell_flag_index(W.chunk_off + k, c, e)] = L->bfl[t];
       }
     }
   }

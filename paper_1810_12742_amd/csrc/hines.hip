@@ -389,8 +389,8 @@ bool check_cell_tables(const hines::HostPlan& P, const int64_t* cell_offsets, st
       for (int64_t k = 0; k < W.nchunk && ok_b; ++k)
         for (int e = 0; e < hines::kCellChunk && ok_b; ++e) {
           const int64_t g = W.chunk_off + k;
-          const uint8_t f = C.flags[g * 1024 + c * 16 + e];
-          const uint16_t ps = C.pos[g * 1024 + (((c & 3) << 4) | e) * 16 + (c >> 2)];
+          const uint8_t f = C.flags[hines::cell_flag_index(g, c, e)];
+          const uint16_t ps = C.pos[hines::cell_pos_index(g, c, e)];
           if ((ps == hines::kCellPadPos) != ((f & hines::CF_PAD) != 0) || (ps != hines::kCellPadPos && ps >= size)) {
             why = "wave " + std::to_string(w) + " position out of range";
             return false;
@@ -406,7 +406,7 @@ bool check_cell_tables(const hines::HostPlan& P, const int64_t* cell_offsets, st
       bool ok_f = true;
       for (int64_t k = W.nchunk - 1; k >= 0 && ok_f; --k)
         for (int e = hines::kCellChunk - 1; e >= 0 && ok_f; --e) {
-          const uint8_t f = C.flags[(W.chunk_off + k) * 1024 + c * 16 + e];
+          const uint8_t f = C.flags[hines::cell_flag_index(W.chunk_off + k, c, e)];
           if ((f & (hines::CF_PUSH | hines::CF_MERGE)) && m < 1) ok_f = false;
           if (f & hines::CF_PUSH) --m;
           if (f & hines::CF_POP) ok_f = ok_f && m++ < hines::kCellStack;
@@ -422,8 +422,9 @@ bool check_cell_tables(const hines::HostPlan& P, const int64_t* cell_offsets, st
       int64_t qo = -1, qi = -1;
       int no = 0, ni = 0;
       for (int64_t q = 0; q < (int64_t)W.nchunk * hines::kCellChunk; ++q) {
-        const int64_t g = W.chunk_off + q / hines::kCellChunk, e = q % hines::kCellChunk;
-        const uint8_t fo = C.flags[g * 1024 + c * 16 + e], fi = C.flags[g * 1024 + (c + 32) * 16 + e];
+        const int64_t g = W.chunk_off + q / hines::kCellChunk;
+        const int e = (int)(q % hines::kCellChunk);
+        const uint8_t fo = C.flags[hines::cell_flag_index(g, c, e)], fi = C.flags[hines::cell_flag_index(g, c + 32, e)];
         if (fo & hines::CF_MBIN) ni += 100;  // wrong side
         if (fi & hines::CF_MBOUT) no += 100;
         if (fo & hines::CF_MBOUT) {

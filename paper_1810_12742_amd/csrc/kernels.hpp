@@ -887,8 +887,8 @@ __global__ __launch_bounds__(64) void k_solve_flow(DevTables tb, RhsSpec rs, con
 // kCellChunk steps per chunk.
 //
 // The inputs of a chunk are gathered by the whole wave: in slot r, lane j
-// loads element j % 16 of the cell of lane 4 r + j / 16, so 16 lanes read one
-// run of a cell's compartments.  They pass through two LDS planes (d, u and b;
+// loads element j % K of the cell of lane (64 / K) r + j / K (K = kCellChunk,
+// 16: lane 4 r + j / 16), so K lanes read one run of a cell's compartments.  They pass through two LDS planes (d, u and b;
 // rows padded so that both the gathering writes and the per-lane reads are
 // free of bank conflicts) to the lane that eliminates them.  The factors
 // (f, y) of each step go to a device scratch in lane-major order (one 1 KiB
@@ -907,28 +907,43 @@ __global__ __launch_bounds__(64) void k_solve_flow(DevTables tb, RhsSpec rs, con
 // x of a compartment with several children on the same kind of stack.
 // ---------------------------------------------------------------------------
 constexpr int CK = hines::kCellChunk;
-constexpr int kCellRowDU = 64 * 16 + 16;  // bytes per element row of the (d, u) plane
-constexpr int kCellRowB = 64 * 8 + 16;    // bytes per element row of the b plane (x in the forward sweep)
+constexpr int CG = hines::kCellSlotCells;  // cells per gather slot (a run of CK lanes each)
+// Rows padded by 256 / CK bytes: the gathering writes (CK lanes of one cell,
+// consecutive elements, per phase of 16 or 32 lanes) and the per-lane reads
+// then fall into distinct banks.
+constexpr int kCellRowDU = 64 * 16 + 256 / CK;  // bytes per element row of the (d, u) plane
+constexpr int kCellRowB = 64 * 8 + 256 / CK;    // bytes per element row of the b plane (x in the forward sweep)
 constexpr int kCellLdsB = CK * kCellRowDU;                 // byte offset of the b plane
 constexpr int kCellLdsStack = kCellLdsB + CK * kCellRowB;  // byte offset of the stack slots
 constexpr int kCellLdsMail = kCellLdsStack + hines::kCellStack * 64 * 16;  // byte offset of the mailboxes
 constexpr int kCellLds = kCellLdsMail + 64 * 16;
+static_assert(CK == 8 || CK == 16, "chunk of 8 or 16 steps");
 
 typedef double double2_t __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) double2_t lds_d2;
 typedef __attribute__((address_space(3))) char lds_char;
+typedef unsigned int cflag_t __attribute__((ext_vector_type(CK / 4)));  // CK flag bytes of one lane
 
-__device__ __forceinline__ unsigned cell_byte(const u32x4& v, int e) { return (v[e >> 2] >> (8 * (e & 3))) & 0xffu; }
-// position of slot r (0..15) from the lane's two 16-byte position words;
-// padding reads the cell's first compartment (its value is replaced later)
-__device__ __forceinline__ unsigned cell_pos(const u32x4& p0, const u32x4& p1, int r) {
-  const unsigned w = r < 8 ? p0[(r & 7) >> 1] : p1[(r & 7) >> 1];
-  return (w >> (16 * (r & 1))) & 0xffffu;
+// The CK 16-bit positions of one lane's gather slots.
+struct CellPos {
+  u32x4 w[CK / 8];
+};
+
+__device__ __forceinline__ unsigned cell_byte(const cflag_t& v, int e) { return (v[e >> 2] >> (8 * (e & 3))) & 0xffu; }
+// position of slot r; padding reads the cell's first compartment (its value is replaced later)
+__device__ __forceinline__ unsigned cell_pos(const CellPos& p, int r) {
+  return (p.w[r >> 3][(r & 7) >> 1] >> (16 * (r & 1))) & 0xffffu;
 }
 
 // Table and scratch traffic is read once per sweep: non-temporal, so that it
 // does not push the gathered lines of d, u, b out of L2.
-__device__ __forceinline__ u32x4 stream_ld(const u32x4* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ CellPos pos_ld(const u32x4* p) {
+  CellPos r;
+#pragma unroll
+  for (int i = 0; i < CK / 8; ++i) r.w[i] = __builtin_nontemporal_load(p + i);
+  return r;
+}
+__device__ __forceinline__ cflag_t flag_ld(const cflag_t* p) { return __builtin_nontemporal_load(p); }
 
 template <int RHS>
 struct CellBatch {
@@ -939,11 +954,10 @@ struct CellBatch {
 
 template <int RHS>
 __device__ __forceinline__ void cell_load(CellBatch<RHS>& B, const RhsSpec& rs, const double* __restrict__ d,
-                                          const double* __restrict__ u, const int64_t* base, const u32x4& p0,
-                                          const u32x4& p1) {
+                                          const double* __restrict__ u, const int64_t* base, const CellPos& P) {
 #pragma unroll
   for (int r = 0; r < CK; ++r) {
-    const unsigned p = cell_pos(p0, p1, r);
+    const unsigned p = cell_pos(P, r);
     const int64_t i = base[r] + (p == hines::kCellPadPos ? 0u : p);
     B.dv[r] = d[i];
     B.uv[r] = u[i];
@@ -962,12 +976,12 @@ __device__ __forceinline__ void cell_load(CellBatch<RHS>& B, const RhsSpec& rs, 
 // (d > 0 and b of the first compartment keep every value finite).
 template <int RHS>
 __device__ __forceinline__ void cell_put(const CellBatch<RHS>& B, const RhsSpec& rs, const int64_t* base,
-                                         const u32x4& p0, const u32x4& p1, lds_char* lds, int lane) {
-  const int e = lane & 15;
+                                         const CellPos& P, lds_char* lds, int lane) {
+  const int e = lane % CK;
 #pragma unroll
   for (int r = 0; r < CK; ++r) {
-    const int c = 4 * r + (lane >> 4);
-    const unsigned p = cell_pos(p0, p1, r);
+    const int c = CG * r + lane / CK;
+    const unsigned p = cell_pos(P, r);
     double b = B.bv[r];
     if constexpr (RHS != kFlowGiven) b = B.cv[r] * B.bv[r];
     if constexpr (RHS == kFlowCVI) b = b + B.iv[r];
@@ -981,7 +995,7 @@ __device__ __forceinline__ void cell_put(const CellBatch<RHS>& B, const RhsSpec&
 
 // Backward elimination of one chunk from the LDS planes; (f, y) per step into fy.
 // mb: the mailboxes (slot c: the contribution of the cut-off half in lane c).
-__device__ __forceinline__ void cell_backward(const u32x4& f, const lds_d2* pdu, const lds_f64* pb, lds_d2* stk,
+__device__ __forceinline__ void cell_backward(const cflag_t& f, const lds_d2* pdu, const lds_f64* pb, lds_d2* stk,
                                               lds_d2* mb, int lane, double& cd, double& cb, double& td, double& tb,
                                               int& m, double2_t* fy) {
 #pragma unroll
@@ -1027,7 +1041,7 @@ __device__ __forceinline__ void cell_backward(const u32x4& f, const lds_d2* pdu,
 
 // Forward substitution of one chunk (steps in reverse); x per step into the
 // b plane, then through the gather mapping to the user order.
-__device__ __forceinline__ void cell_forward(const u32x4& f, const u32x4& c0, const u32x4& c1, const double2_t* fy,
+__device__ __forceinline__ void cell_forward(const cflag_t& f, const CellPos& P, const double2_t* fy,
                                              lds_f64* pb, const lds_f64* xrd, lds_f64* stx, lds_d2* mb, int lane,
                                              double& xc, double& xt, int& m, double* x, const int64_t* base) {
 #pragma unroll
@@ -1051,8 +1065,8 @@ __device__ __forceinline__ void cell_forward(const u32x4& f, const u32x4& c0, co
   }
 #pragma unroll
   for (int r = 0; r < CK; ++r) {
-    const double xv = xrd[4 * r];
-    const unsigned p = cell_pos(c0, c1, r);
+    const double xv = xrd[CG * r];
+    const unsigned p = cell_pos(P, r);
     if (p != hines::kCellPadPos) x[base[r] + p] = xv;
   }
 }
@@ -1067,28 +1081,29 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
   const int nk = W.nchunk;
   int64_t base[CK];
 #pragma unroll
-  for (int r = 0; r < CK; ++r) base[r] = tb.cbase[(int64_t)blockIdx.x * 64 + 4 * r + (lane >> 4)];
-  const u32x4* posv = (const u32x4*)(tb.cpos + W.chunk_off * 1024) + 2 * lane;  // + 128 per chunk
-  const u32x4* flv = (const u32x4*)(tb.cflag + W.chunk_off * 1024) + lane;      // + 64 per chunk
-  double2_t* scr = (double2_t*)tb.cscr + W.chunk_off * (CK * 64) + lane;       // + CK * 64 per chunk
-  lds_d2* stk = (lds_d2*)(lds + kCellLdsStack) + lane;                            // slot s at stk[64 s]
+  for (int r = 0; r < CK; ++r) base[r] = tb.cbase[(int64_t)blockIdx.x * 64 + CG * r + lane / CK];
+  constexpr int PS = 8 * CK;  // u32x4 words of positions per chunk
+  const u32x4* posv = (const u32x4*)(tb.cpos + W.chunk_off * hines::kCellChunkElems) + (CK / 8) * lane;
+  const cflag_t* flv = (const cflag_t*)(tb.cflag + W.chunk_off * hines::kCellChunkElems) + lane;  // + 64 per chunk
+  double2_t* scr = (double2_t*)tb.cscr + W.chunk_off * (CK * 64) + lane;  // + CK * 64 per chunk
+  lds_d2* stk = (lds_d2*)(lds + kCellLdsStack) + lane;                       // slot s at stk[64 s]
   lds_d2* mb = (lds_d2*)(lds + kCellLdsMail);
   const lds_d2* pdu = (const lds_d2*)lds + lane;
   lds_f64* pb = (lds_f64*)(lds + kCellLdsB) + lane;
 
   // ---- backward sweep: the gather of chunk k + 1 and the stores of chunk
   // k - 1 overlap the elimination of chunk k ----
-  u32x4 p0 = stream_ld(posv), p1 = stream_ld(posv + 1), fl = stream_ld(flv);
+  CellPos P = pos_ld(posv);
+  cflag_t fl = flag_ld(flv);
   CellBatch<RHS> B;
-  cell_load<RHS>(B, rs, d, u, base, p0, p1);
-  const int k1 = min(1, nk - 1);
-  u32x4 q0 = stream_ld(posv + 128 * k1), q1 = stream_ld(posv + 128 * k1 + 1);
+  cell_load<RHS>(B, rs, d, u, base, P);
+  CellPos Q = pos_ld(posv + PS * min(1, nk - 1));
   double cd = 0.0, cb = 0.0, td = 0.0, tb_ = 0.0;
   int m = 0;
   double2_t fy[CK];
-  u32x4 fprev = fl;
+  cflag_t fprev = fl;
   for (int k = 0; k < nk; ++k) {
-    cell_put<RHS>(B, rs, base, p0, p1, lds, lane);
+    cell_put<RHS>(B, rs, base, P, lds, lane);
     if (k > 0) {  // padding steps store nothing; the forward sweep reads their slots but
                   // uses no value of a padding step (no carry or stack leaves one)
       double2_t* sk = scr + (k - 1) * (CK * 64);
@@ -1096,16 +1111,13 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
       for (int e = 0; e < CK; ++e)
         if (!(cell_byte(fprev, e) & hines::CF_PAD)) __builtin_nontemporal_store(fy[e], sk + e * 64);
     }
-    const u32x4 f = fl;
+    const cflag_t f = fl;
     fprev = f;
     if (k + 1 < nk) {
-      fl = stream_ld(flv + 64 * (k + 1));
-      cell_load<RHS>(B, rs, d, u, base, q0, q1);
-      p0 = q0;
-      p1 = q1;
-      const int k2 = min(k + 2, nk - 1);
-      q0 = stream_ld(posv + 128 * k2);
-      q1 = stream_ld(posv + 128 * k2 + 1);
+      fl = flag_ld(flv + 64 * (k + 1));
+      cell_load<RHS>(B, rs, d, u, base, Q);
+      P = Q;
+      Q = pos_ld(posv + PS * min(k + 2, nk - 1));
     }
     cell_backward(f, pdu, pb, stk, mb, lane, cd, cb, td, tb_, m, fy);
   }
@@ -1117,33 +1129,30 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
   // ---- forward sweep: two register sets, the loads of the next chunk overlap
   // the substitution of this one ----
   lds_f64* stx = (lds_f64*)(lds + kCellLdsStack) + lane;  // slot s at stx[64 s]
-  const lds_f64* xrd = (const lds_f64*)(lds + kCellLdsB + (lane & 15) * kCellRowB) + (lane >> 4);
+  const lds_f64* xrd = (const lds_f64*)(lds + kCellLdsB + (lane % CK) * kCellRowB) + lane / CK;
   double xc = 0.0, xt = 0.0;
   m = 0;
-  u32x4 a0 = stream_ld(posv + 128 * (nk - 1)), a1 = stream_ld(posv + 128 * (nk - 1) + 1),
-        af = stream_ld(flv + 64 * (nk - 1));
+  CellPos PA = pos_ld(posv + PS * (nk - 1)), PB = PA;
+  cflag_t fa = flag_ld(flv + 64 * (nk - 1)), fb_ = fa;
   double2_t fb[CK];
-  u32x4 b0 = a0, b1 = a1, bf = af;
   for (int k = nk - 1;; k -= 2) {
     if (k >= 1) {
       const double2_t* sk = scr + (k - 1) * (CK * 64);
 #pragma unroll
       for (int e = 0; e < CK; ++e) fb[e] = __builtin_nontemporal_load(sk + e * 64);
-      b0 = stream_ld(posv + 128 * (k - 1));
-      b1 = stream_ld(posv + 128 * (k - 1) + 1);
-      bf = stream_ld(flv + 64 * (k - 1));
+      PB = pos_ld(posv + PS * (k - 1));
+      fb_ = flag_ld(flv + 64 * (k - 1));
     }
-    cell_forward(af, a0, a1, fy, pb, xrd, stx, mb, lane, xc, xt, m, x, base);
+    cell_forward(fa, PA, fy, pb, xrd, stx, mb, lane, xc, xt, m, x, base);
     if (k < 1) break;
     if (k >= 2) {
       const double2_t* sk = scr + (k - 2) * (CK * 64);
 #pragma unroll
       for (int e = 0; e < CK; ++e) fy[e] = __builtin_nontemporal_load(sk + e * 64);
-      a0 = stream_ld(posv + 128 * (k - 2));
-      a1 = stream_ld(posv + 128 * (k - 2) + 1);
-      af = stream_ld(flv + 64 * (k - 2));
+      PA = pos_ld(posv + PS * (k - 2));
+      fa = flag_ld(flv + 64 * (k - 2));
     }
-    cell_forward(bf, b0, b1, fb, pb, xrd, stx, mb, lane, xc, xt, m, x, base);
+    cell_forward(fb_, PB, fb, pb, xrd, stx, mb, lane, xc, xt, m, x, base);
     if (k < 2) break;
   }
 }

@@ -90,8 +90,8 @@ enum TableId : int32_t {
   T_FLOW_AUX = 11,        // int64[pushes]: parent position
   T_CELL_WAVES = 12,      // int64[nwaves*3]: chunk_off, nchunk, ncell
   T_CELL_LANES = 13,      // int64[nwaves*64]: cell of each lane (-1: empty)
-  T_CELL_POS = 14,        // int64[nchunks*1024]: [chunk][staging lane][slot] relative position
-  T_CELL_FLAGS = 15,      // int64[nchunks*1024]: [chunk][cell lane][element] flags
+  T_CELL_POS = 14,        // int64[nchunks*kCellChunkElems]: [chunk][staging lane][slot] relative position
+  T_CELL_FLAGS = 15,      // int64[nchunks*kCellChunkElems]: [chunk][cell lane][element] flags
   T_NUM = 16,
 };
 
@@ -102,10 +102,20 @@ enum TableId : int32_t {
 // sweep).  Backward sweep: reverse of that order; forward sweep: the order.
 // A wave holds 64 cells of similar size; lane c walks cell c.  Per chunk of
 // kCellChunk consecutive steps the table gives, for the staging mapping (lane
-// j, slot r) -> (cell lane 4 r + j / 16, element j % 16), the position of the
-// element relative to its cell's first compartment, and per (cell lane,
-// element) the flags below.
-constexpr int32_t kCellChunk = 16;
+// j, slot r) -> (cell lane kCellSlotCells r + j / kCellChunk, element
+// j % kCellChunk), the position of the element relative to its cell's first
+// compartment, and per (cell lane, element) the flags below.
+constexpr int32_t kCellChunk = 16;                     // steps per chunk (a power of two, <= 16)
+constexpr int32_t kCellSlotCells = 64 / kCellChunk;     // cells per gather slot
+constexpr int32_t kCellChunkElems = 64 * kCellChunk;    // table entries per chunk
+// Table index of element e of the cell in lane c: in the gather order (lane j,
+// slot r) and in the cell-lane order.
+constexpr int64_t cell_pos_index(int64_t chunk, int32_t c, int32_t e) {
+  return chunk * kCellChunkElems + (int64_t)((c % kCellSlotCells) * kCellChunk + e) * kCellChunk + c / kCellSlotCells;
+}
+constexpr int64_t cell_flag_index(int64_t chunk, int32_t c, int32_t e) {
+  return chunk * kCellChunkElems + (int64_t)c * kCellChunk + e;
+}
 constexpr int32_t kCellStack = 12;           // LDS stack slots per lane; slot 0 is a dummy
 constexpr uint16_t kCellPadPos = 0xFFFF;     // padding element: no user compartment
 constexpr int64_t kCellMaxSize = 65535;      // positions fit 16 bits below kCellPadPos
@@ -134,8 +144,8 @@ struct CellLanes {
   std::vector<KCellWave> waves;     // [nwaves], largest cells first
   std::vector<int32_t> lane_cell;   // [nwaves*64] cell of each lane, -1 for empty lanes
   std::vector<int64_t> base;        // [nwaves*64] first user index of the lane's cell (0: empty)
-  std::vector<uint16_t> pos;        // [nchunks*1024] staging order
-  std::vector<uint8_t> flags;       // [nchunks*1024] cell-lane order
+  std::vector<uint16_t> pos;        // [nchunks*kCellChunkElems] staging order
+  std::vector<uint8_t> flags;       // [nchunks*kCellChunkElems] cell-lane order
 };
 
 // Build the cell-lane tables.  parent / cell_offsets must already be valid.

