@@ -72,10 +72,12 @@ typedef struct hines_options {
                                  0 (default): when every branch runs toward higher user indices
                                  and bitwise is 0, a static per-lane schedule computed at setup
                                  (each branch starts once its children are done; no barriers) */
-  int32_t cell_lanes;         /* 1: hines_solve and hines_timestep run one lane per cell (paper
-                                 §2's elimination in a depth-first order of each cell, 64 cells
-                                 of similar size per wave, elimination factors kept in a device
-                                 scratch of 16 bytes per compartment owned by the plan); needs
+  int32_t cell_lanes;         /* 1: hines_solve and hines_timestep run one lane per cell, the
+                                 one-thread-per-matrix solver of §3 and §7 (§2's elimination in a
+                                 depth-first order of each cell, 64 lanes of similar length per
+                                 wave; a cell longer than 0.8 times the mean cell is cut at one
+                                 edge into two halves on two lanes; elimination factors kept in a
+                                 device scratch of 16 bytes per step owned by the plan).  Needs
                                  bitwise 0, cells of at most 65535 compartments and a stack need
                                  of at most 12 (HINES_ERR_TOO_BIG otherwise).  hines_solve_mixed
                                  keeps using the groups.  0 (default): groups (§3-§4)        */
@@ -118,15 +120,18 @@ enum {
   HINES_TABLE_FLOW_POS = 10,         /* [elements] LDS position of each element of a group's
                                         staging order; 0x8000 marks a cell root              */
   HINES_TABLE_FLOW_AUX = 11,         /* [pushes] position receiving each push, step order     */
-  /* Cell-lane plans (hines_plan_info.kernel == 3): 64 lanes per wave, chunks of 16 steps.  */
+  /* Cell-lane plans (hines_plan_info.kernel == 3): 64 lanes per wave, chunks of K = 16
+     steps (K * 64 entries per chunk).                                                       */
   HINES_TABLE_CELL_WAVES = 12,       /* [nwaves*3] first chunk, chunks per sweep, cells       */
   HINES_TABLE_CELL_LANES = 13,       /* [nwaves*64] cell of each lane, -1 if empty            */
-  HINES_TABLE_CELL_POS = 14,         /* [chunks*1024] per chunk, lane j, slot r: position of
-                                        element (j % 16) of lane (4 r + j / 16)'s cell relative
-                                        to its first compartment in backward step order, 65535
-                                        for padding                                           */
-  HINES_TABLE_CELL_FLAGS = 15        /* [chunks*1024] per chunk, lane c, element e: flags
-                                        1 tip, 2 pop, 4 push, 8 merge, 16 padding, 32 root    */
+  HINES_TABLE_CELL_POS = 14,         /* [chunks*K*64] per chunk, lane j, slot r: position of
+                                        element (j % K) of lane ((64 / K) r + j / K)'s walk,
+                                        relative to its cell's first compartment, in backward
+                                        step order; 65535 for padding                         */
+  HINES_TABLE_CELL_FLAGS = 15        /* [chunks*K*64] per chunk, lane c, element e: flags
+                                        1 tip, 2 pop, 4 push, 8 merge, 16 padding, 32 root,
+                                        64 root of a cut-off half (lane c < 32; its contribution
+                                        goes to lane c + 32), 128 parent of that root           */
 };
 
 /* Fill *opt with the defaults: no re-rooting, no splitting, group_width 64,
