@@ -93,7 +93,8 @@ typedef struct hines_plan_info {
   int64_t max_group_lds_bytes;
   int32_t kernel;             /* 0 level-synchronous, 1 flow (static step schedule), 2 bitwise,
                                  3 cell lanes                                                 */
-  int32_t max_makespan;       /* scheduled plans: longest schedule, in iterations */
+  int32_t max_makespan;       /* flow plans: longest schedule, in chunk steps; cell-lane plans:
+                                 chunks per sweep of the longest wave                        */
   int64_t workspace_groups;   /* groups too large for LDS, solved from a global workspace */
 } hines_plan_info;
 

@@ -47,7 +47,9 @@ void cell_tree(const int32_t* par, int64_t lo, int32_t m, CellTree& T) {
 
 // Walk of the subtree of `root` without the subtree of `cut` (-1: none).
 // `forced[a]` (-1: none) is put first among a's children; among the others
-// the child with the deepest stack need goes last.  Appends the preorder to
+// the child with the deepest stack need goes last (the highest index among
+// equal needs: breadth-first numbered siblings are adjacent in memory, so
+// the backward walk then runs down through them).  Appends the preorder to
 // `pre`, sets the flags of the visited nodes in `fl` (indexed by relative
 // node) and returns the stack need of the walk.
 int32_t walk(const CellTree& T, int32_t root, int32_t cut, const std::vector<int32_t>& forced,
@@ -72,7 +74,7 @@ int32_t walk(const CellTree& T, int32_t root, int32_t cut, const std::vector<int
     for (int32_t k = T.ch_off[a]; k < T.ch_off[a + 1]; ++k) {
       const int32_t c = T.ch[k];
       if (c == cut || c == f) continue;
-      if (need[c] > hn) {
+      if (need[c] >= hn) {
         hn = need[c];
         h = c;
       }

@@ -934,6 +934,8 @@ hines_status hines_plan_info_get(const hines_plan* p, hines_plan_info* info) {
     if (p->host.flow && G.ws_off < 0) mk = std::max(mk, G.makespan);
     ng_ws += G.ws_off >= 0;
   }
+  if (p->host.cl.built)
+    for (const auto& W : p->host.cl.waves) mk = std::max(mk, W.nchunk);
   info->max_makespan = mk;
   info->workspace_groups = ng_ws;
   return ok();

@@ -236,14 +236,15 @@ def test_cell_replay_bushy_trees(seed):
 
 def test_cell_flags_of_a_small_tree():
     """Hand-checked flags of one tree: root 0 with children 1 (a leaf) and 2;
-    2 has children 3, 4, 5 (leaves); 6 hangs off 5.  Stack needs: node 5
-    (one child) 0; node 2: three children with needs 0, 0, 0 -> 1; root: 0 and
-    1 -> max(1, 0 + 1) = 1.  Heavy child of 2 is its first maximal one (3),
-    its light children 4, 5 come first in ascending order, so the preorder is
-    0, 1, 2, 4, 5, 6, 3 and the backward sweep runs it backwards: 3 (tip, last
-    child of 2: push), 6 (tip, carries into 5), 5 (middle child of 2: merge),
-    4 (tip, first child of 2: carries), 2 (pop; the root's heavy child: push),
-    1 (tip, first child of 0: carries), 0 (root, pop)."""
+    2 has children 3, 4, 5; 6 hangs off 5.  Stack needs: 6, 5, 4, 3 need 0;
+    node 2 has three children of need 0 -> 1; the root has children of need 0
+    and 1 -> max(1, 0 + 1) = 1.  The child with the largest need goes last,
+    the highest index among equal needs (5 under 2; 2 under 0), the others in
+    ascending order, so the preorder is 0, 1, 2, 3, 4, 5, 6 and the backward
+    sweep runs 6 (tip, carries into 5), 5 (last child of 2: push), 4 (tip,
+    middle child of 2: merge), 3 (tip, first child of 2: carries), 2 (pop; the
+    root's last child: push), 1 (tip, first child of 0: carries), 0 (root,
+    pop)."""
     from paper_1810_12742_amd import Plan
     par = np.array([-1, 0, 0, 2, 2, 2, 5], dtype=np.int32)
     off = np.array([0, 7], dtype=np.int64)
@@ -255,8 +256,8 @@ def test_cell_flags_of_a_small_tree():
     fl = [int(v) for v in lane_view(p, "cell_flags", 0).reshape(-1)]
     npad = len(order) - 7
     assert npad == (-7) % K and order[:npad] == [0xFFFF] * npad and fl[:npad] == [PAD | TIP] * npad
-    assert order[npad:] == [3, 6, 5, 4, 2, 1, 0]
-    assert fl[npad:] == [TIP | PUSH, TIP, MERGE, TIP, POP | PUSH, TIP, POP | ROOT]
+    assert order[npad:] == [6, 5, 4, 3, 2, 1, 0]
+    assert fl[npad:] == [TIP, PUSH, TIP | MERGE, TIP, POP | PUSH, TIP, POP | ROOT]
     # every other lane is empty
     flags = p.table("cell_flags").reshape(-1, 64, K)
     pos = p.table("cell_pos").reshape(-1, 64, K)
@@ -324,3 +325,4 @@ def test_long_cells_are_cut_into_paired_halves():
     assert outs[0].size == 28 and ins[0].size == 28
     assert np.all(outs[1] < 32) and np.all(ins[1] >= 32)
     assert waves[:, 1].max() * K < 3000
+    assert p.info["max_makespan"] == waves[:, 1].max()
