@@ -272,7 +272,9 @@ def run_c3(args, torch, dev):
     stream = torch.cuda.current_stream()
     ms = _time(torch, loop.launch, args.steps, args.warmup, stream)
     n = f.n
-    bytes_per_step = 40 * n  # read d, u, c, V; write V
+    # read d, u, c, V; write V (a cell-lane plan factors A once per graph launch
+    # and then reads the pair (f, 1/d') in place of (d, u): the same 40 bytes)
+    bytes_per_step = 40 * n
     achieved = bytes_per_step * K / (ms * 1e-3) / 1e9
     out = {
         "metric": METRIC, "value": n * K / (ms * 1e-3), "unit": "unknown-steps/s", "n_gpus": 1,
@@ -285,7 +287,7 @@ def run_c3(args, torch, dev):
                    "groups": plan.info["ngroups"], "workspace_groups": plan.info["workspace_groups"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": {3: "k_solve_cells", 1: "k_solve_flow"}.get(plan.info["kernel"], "k_solve_level"),
+                     "kernel": {3: "k_cells_step", 1: "k_solve_flow"}.get(plan.info["kernel"], "k_solve_level"),
                      "bytes_per_step": bytes_per_step},
         "charge_conservation_max_rel_err_step0": check,
     }

@@ -194,7 +194,14 @@ hines_status hines_timestep(const hines_plan* plan, const double* diag, const do
  * steps first_step .. first_step + nsteps - 1, into a HIP graph (captured on
  * a private stream; nothing runs during creation).  Each
  * hines_timeloop_launch replays the same steps on `stream`; the arrays are
- * bound at creation and must stay valid.  The plan must outlive the loop. */
+ * bound at creation and must stay valid.  The plan must outlive the loop.
+ * On a cell-lane plan (option cell_lanes) the loop allocates, at creation,
+ * up to 40 bytes per walk slot (cell compartments plus padding) and each
+ * launch factors A once (f = u / d' and 1 / d' per compartment), moves c, the
+ * current and v into the lanes' walk order, runs the nsteps right-hand-side
+ * sweeps there and writes v back in user order at the end: the result equals
+ * nsteps hines_timestep calls bit for bit.  HINES_ERR_OOM if that allocation
+ * fails; hines_timeloop_destroy frees it. */
 hines_status hines_timeloop_create(const hines_plan* plan, const double* diag, const double* upper,
                                    const double* c, double* v, const double* i_inj, double noise_sigma,
                                    uint32_t noise_seed, uint32_t first_step, int32_t nsteps, int32_t ncells,

@@ -104,6 +104,7 @@ struct hines_timeloop {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int32_t nsteps = 0;
+  void* mem = nullptr;  // cell-lane plans: factors and walk-layout arrays of the loop
 };
 
 namespace {
@@ -721,6 +722,7 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   if (e == hipSuccess) e = up(CL.flags.data(), (int64_t)CL.flags.size(), off);
   off += sz_cf;
   p->t.cscr = (double*)p->scr_mem;
+  p->t.cslots = CL.nchunks * hines::kCellChunk * 64;
   if (e != hipSuccess) {
     if (p->scr_mem) hipFree(p->scr_mem);
     hipFree(p->dev_mem);
@@ -804,11 +806,59 @@ hines_status hines_timeloop_create(const hines_plan* p, const double* diag, cons
     return set_err(HINES_ERR_STATE, "v must not alias the matrix, c or the current");
   hines_timeloop* tl = new (std::nothrow) hines_timeloop();
   if (!tl) return set_err(HINES_ERR_OOM, "host allocation failed");
+  const bool noise = i_inj == nullptr && noise_sigma != 0.0;
+  // cell-lane plans keep the factors: per launch, factor A and move c, the
+  // current and V into the walk layout; K steps there; V back at the end
+  const bool factored = p->host.cl.built && p->host.n > 0;
+  hdev::CellLoop L{};
+  if (factored) {
+    const int64_t S = p->t.cslots;
+    // f, 1 / d', c, the current, V; positions for the draws
+    const int64_t bytes = 8 * S * (i_inj ? 5 : 4) + (noise ? 2 * S : 0) + 256;
+    hipError_t ea = hipMalloc(&tl->mem, bytes);
+    if (ea != hipSuccess) {
+      tl->mem = nullptr;
+      delete tl;
+      return set_err(HINES_ERR_OOM, "hipMalloc(%lld) for the time loop: %s", (long long)bytes, hipGetErrorString(ea));
+    }
+    double* m = (double*)tl->mem;
+    L.f = m;
+    L.r = m + S;
+    L.c = m + 2 * S;
+    L.v = m + 3 * S;
+    L.ci = i_inj ? m + 4 * S : nullptr;
+    L.lp = noise ? (const uint16_t*)(m + 4 * S) : nullptr;
+    L.sigma = noise_sigma;
+    L.seed = noise_seed;
+  }
   hipStream_t cs = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   const bool capturing = e == hipSuccess;
-  for (int32_t k = 0; k < nsteps && e == hipSuccess && p->host.n > 0; ++k) {
+  if (factored && e == hipSuccess) {
+    const dim3 grid((unsigned)p->host.cl.nwaves);
+    if (noise)
+      hipLaunchKernelGGL(hdev::k_cells_lane_pos, grid_for(p->t.cslots, 256), dim3(256), 0, cs, p->t,
+                         (uint16_t*)L.lp, p->host.cl.nchunks);
+    RhsSpec rs0{};
+    hipLaunchKernelGGL(hdev::k_solve_cells<hdev::kCellFactor>, grid, dim3(64), 0, cs, p->t, rs0, diag, upper,
+                       (double*)L.f);  // f at L.f, 1 / d' at L.f + slots = L.r
+    hipLaunchKernelGGL(hdev::k_cells_to_walk, grid, dim3(64), 0, cs, p->t, c, (double*)L.c);
+    if (i_inj) hipLaunchKernelGGL(hdev::k_cells_to_walk, grid, dim3(64), 0, cs, p->t, i_inj, (double*)L.ci);
+    hipLaunchKernelGGL(hdev::k_cells_to_walk, grid, dim3(64), 0, cs, p->t, (const double*)v, L.v);
+    for (int32_t k = 0; k < nsteps; ++k) {
+      L.step = first_step + (uint32_t)k;
+      if (noise)
+        hipLaunchKernelGGL(hdev::k_cells_step<hdev::kFlowNoise>, grid, dim3(64), 0, cs, p->t, L);
+      else if (i_inj)
+        hipLaunchKernelGGL(hdev::k_cells_step<hdev::kFlowCVI>, grid, dim3(64), 0, cs, p->t, L);
+      else
+        hipLaunchKernelGGL(hdev::k_cells_step<hdev::kFlowCV>, grid, dim3(64), 0, cs, p->t, L);
+    }
+    hipLaunchKernelGGL(hdev::k_cells_from_walk, grid, dim3(64), 0, cs, p->t, (const double*)L.v, v);
+    e = hipGetLastError();
+  }
+  for (int32_t k = 0; k < nsteps && e == hipSuccess && p->host.n > 0 && !factored; ++k) {
     RhsSpec rs{};
     rs.c = c;
     rs.v = v;
@@ -828,6 +878,7 @@ hines_status hines_timeloop_create(const hines_plan* p, const double* diag, cons
   if (e != hipSuccess) {
     if (tl->exec) hipGraphExecDestroy(tl->exec);
     if (tl->graph) hipGraphDestroy(tl->graph);
+    if (tl->mem) hipFree(tl->mem);
     delete tl;
     return set_err(HINES_ERR_HIP, "time loop capture: %s", hipGetErrorString(e));
   }
@@ -849,6 +900,10 @@ hines_status hines_timeloop_destroy(hines_timeloop* tl) {
   if (tl->exec) e = hipGraphExecDestroy(tl->exec);
   if (tl->graph) {
     hipError_t e2 = hipGraphDestroy(tl->graph);
+    if (e == hipSuccess) e = e2;
+  }
+  if (tl->mem) {
+    hipError_t e2 = hipFree(tl->mem);  // waits for the device
     if (e == hipSuccess) e = e2;
   }
   delete tl;

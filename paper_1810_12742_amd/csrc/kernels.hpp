@@ -37,6 +37,7 @@ struct DevTables {
   const uint16_t* cpos;           // cell-lane kernel: positions, staging order
   const uint8_t* cflag;           // cell-lane kernel: flags, cell-lane order
   double* cscr;                   // cell-lane kernel: (f, y) per step and lane
+  int64_t cslots;                 // cell-lane kernel: steps x lanes of all waves (walk-layout array length)
 };
 
 // Right-hand side of a solve: given (kRhsGiven), c v + i (kRhsCV; i may be
@@ -600,6 +601,8 @@ __device__ __forceinline__ void lds_add(lds_f64* p, double v) {
 // Right-hand side forms of the flow kernel, fixed at compile time: given,
 // c v, c v + i, c v + sigma Z.
 enum : int { kFlowGiven = 0, kFlowCV = 1, kFlowCVI = 2, kFlowNoise = 3 };
+// Cell-lane kernel only: eliminate the matrix alone and keep its factors.
+enum : int { kCellFactor = 4 };
 
 // Element e of a user range (user index lo + e) -> its position.  A lane
 // handles elements lane, lane + 64, ...; the loads of kStageUnroll of them are
@@ -948,7 +951,7 @@ __device__ __forceinline__ cflag_t flag_ld(const cflag_t* p) { return __builtin_
 template <int RHS>
 struct CellBatch {
   double dv[CK], uv[CK], bv[CK];
-  double cv[RHS == kFlowGiven ? 1 : CK];
+  double cv[(RHS == kFlowGiven || RHS == kCellFactor) ? 1 : CK];
   double iv[RHS == kFlowCVI ? CK : 1];
 };
 
@@ -961,7 +964,9 @@ __device__ __forceinline__ void cell_load(CellBatch<RHS>& B, const RhsSpec& rs, 
     const int64_t i = base[r] + (p == hines::kCellPadPos ? 0u : p);
     B.dv[r] = d[i];
     B.uv[r] = u[i];
-    if constexpr (RHS == kFlowGiven) {
+    if constexpr (RHS == kCellFactor) {
+      B.bv[r] = 0.0;
+    } else if constexpr (RHS == kFlowGiven) {
       B.bv[r] = rs.rhs[i];
     } else {
       B.cv[r] = rs.c[i];
@@ -983,7 +988,7 @@ __device__ __forceinline__ void cell_put(const CellBatch<RHS>& B, const RhsSpec&
     const int c = CG * r + lane / CK;
     const unsigned p = cell_pos(P, r);
     double b = B.bv[r];
-    if constexpr (RHS != kFlowGiven) b = B.cv[r] * B.bv[r];
+    if constexpr (RHS != kFlowGiven && RHS != kCellFactor) b = B.cv[r] * B.bv[r];
     if constexpr (RHS == kFlowCVI) b = b + B.iv[r];
     if constexpr (RHS == kFlowNoise)
       b = b + noise_draw(rs.seed, rs.step, (uint64_t)(base[r] + (p == hines::kCellPadPos ? 0u : p)), rs.sigma);
@@ -995,6 +1000,9 @@ __device__ __forceinline__ void cell_put(const CellBatch<RHS>& B, const RhsSpec&
 
 // Backward elimination of one chunk from the LDS planes; (f, y) per step into fy.
 // mb: the mailboxes (slot c: the contribution of the cut-off half in lane c).
+// FACTOR: keep (f, 1 / d') instead of (f, y).  The contribution to the parent
+// is (u f, f b'), the same products a solve with stored factors forms.
+template <bool FACTOR = false>
 __device__ __forceinline__ void cell_backward(const cflag_t& f, const lds_d2* pdu, const lds_f64* pb, lds_d2* stk,
                                               lds_d2* mb, int lane, double& cd, double& cb, double& td, double& tb,
                                               int& m, double2_t* fy) {
@@ -1023,7 +1031,7 @@ __device__ __forceinline__ void cell_backward(const cflag_t& f, const lds_d2* pd
     const double rr = rcp_nr(dd);
     const double fv = uu * rr, yv = bb * rr;
     cd = uu * fv;
-    cb = uu * yv;
+    cb = fv * bb;
     if (fe & hines::CF_PUSH) {
       stk[64 * m] = double2_t{td, tb};
       m += 1;
@@ -1035,7 +1043,7 @@ __device__ __forceinline__ void cell_backward(const cflag_t& f, const lds_d2* pd
       tb = tb + cb;
     }
     if (fe & hines::CF_MBOUT) mb[lane] = double2_t{cd, cb};
-    fy[e] = double2_t{fv, yv};
+    fy[e] = double2_t{fv, FACTOR ? rr : yv};
   }
 }
 
@@ -1068,6 +1076,25 @@ __device__ __forceinline__ void cell_forward(const cflag_t& f, const CellPos& P,
     const double xv = xrd[CG * r];
     const unsigned p = cell_pos(P, r);
     if (p != hines::kCellPadPos) x[base[r] + p] = xv;
+  }
+}
+
+// The walk layout of the time loop with kept factors: per (wave chunk, pair q
+// of steps 2q and 2q + 1, lane) one 16-byte unit, so a lane moves two steps
+// with one load and a wave instruction covers 1 KiB.  Index in 16-byte units.
+__device__ __forceinline__ int64_t walk_pair(int64_t chunk, int q, int lane) {
+  return (chunk * (CK / 2) + q) * 64 + lane;
+}
+
+// f into F and 1 / d' into F + slots, both in the walk layout
+__device__ __forceinline__ void factor_store(const double2_t* fy, double* F, int64_t slots, int64_t chunk, int lane) {
+  double2_t* f2 = (double2_t*)F;
+  double2_t* r2 = (double2_t*)(F + slots);
+#pragma unroll
+  for (int q = 0; q < CK / 2; ++q) {
+    const int64_t o = walk_pair(chunk, q, lane);
+    f2[o] = double2_t{fy[2 * q].x, fy[2 * q + 1].x};
+    r2[o] = double2_t{fy[2 * q].y, fy[2 * q + 1].y};
   }
 }
 
@@ -1106,10 +1133,14 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
     cell_put<RHS>(B, rs, base, P, lds, lane);
     if (k > 0) {  // padding steps store nothing; the forward sweep reads their slots but
                   // uses no value of a padding step (no carry or stack leaves one)
-      double2_t* sk = scr + (k - 1) * (CK * 64);
+      if constexpr (RHS == kCellFactor) {  // f and 1 / d' of every step at its walk slot
+        factor_store(fy, x, tb.cslots, W.chunk_off + k - 1, lane);
+      } else {
+        double2_t* sk = scr + (k - 1) * (CK * 64);
 #pragma unroll
-      for (int e = 0; e < CK; ++e)
-        if (!(cell_byte(fprev, e) & hines::CF_PAD)) __builtin_nontemporal_store(fy[e], sk + e * 64);
+        for (int e = 0; e < CK; ++e)
+          if (!(cell_byte(fprev, e) & hines::CF_PAD)) __builtin_nontemporal_store(fy[e], sk + e * 64);
+      }
     }
     const cflag_t f = fl;
     fprev = f;
@@ -1119,7 +1150,11 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
       P = Q;
       Q = pos_ld(posv + PS * min(k + 2, nk - 1));
     }
-    cell_backward(f, pdu, pb, stk, mb, lane, cd, cb, td, tb_, m, fy);
+    cell_backward<RHS == kCellFactor>(f, pdu, pb, stk, mb, lane, cd, cb, td, tb_, m, fy);
+  }
+  if constexpr (RHS == kCellFactor) {  // the last chunk's factors
+    factor_store(fy, x, tb.cslots, W.chunk_off + nk - 1, lane);
+    return;
   }
   // chunk nk - 1 stays in registers: it is the first one of the forward sweep.
   // The forward sweep reads back this wave's own scratch stores.
@@ -1153,6 +1188,241 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
       fa = flag_ld(flv + 64 * (k - 2));
     }
     cell_forward(fb_, PB, fb, pb, xrd, stx, mb, lane, xc, xt, m, x, base);
+    if (k < 2) break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Time loop with the factors kept (cell-lane plans).  The matrix of a time
+// loop does not change between steps, so the elimination of A (paper §2: the
+// pivots d' and f = u / d') is done once per loop launch and each step only
+// sweeps the right-hand side: y = (b - sum f_c b'_c) / d' backwards, x = y -
+// f x_p forwards.  Everything a step touches (f, 1 / d', c, the current, V)
+// lives in the walk layout (walk_pair): a lane moves two steps per 16-byte
+// access and each wave instruction is one coalesced KiB.  V enters the walk
+// layout at the start of a launch and returns to the user layout at its end.
+// ---------------------------------------------------------------------------
+struct CellLoop {
+  const double* f;   // f = u / d' per walk slot
+  const double* r;   // 1 / d'
+  const double* c;   // c
+  const double* ci;  // kFlowCVI: the current I
+  double* v;         // V, then y and x in place
+  const uint16_t* lp;  // kFlowNoise: positions, CK per lane and chunk (the user index of the draw)
+  double sigma;
+  uint32_t seed, step;
+};
+
+// user layout -> walk layout (padding slots get the cell's first compartment)
+__global__ __launch_bounds__(64) void k_cells_to_walk(DevTables tb, const double* __restrict__ src,
+                                                      double* __restrict__ dst) {
+  __shared__ __attribute__((aligned(16))) char raw[CK * kCellRowB];
+  lds_f64* pl = (lds_f64*)raw;
+  const int lane = threadIdx.x;
+  const hines::KCellWave W = tb.cwave[blockIdx.x];
+  int64_t base[CK];
+#pragma unroll
+  for (int r = 0; r < CK; ++r) base[r] = tb.cbase[(int64_t)blockIdx.x * 64 + CG * r + lane / CK];
+  constexpr int PS = 8 * CK;
+  const u32x4* posv = (const u32x4*)(tb.cpos + W.chunk_off * hines::kCellChunkElems) + (CK / 8) * lane;
+  const int wo = (lane % CK) * (kCellRowB / 8) + lane / CK;  // + CG r
+  double2_t* d2 = (double2_t*)dst;
+  for (int k = 0; k < W.nchunk; ++k) {
+    const CellPos P = pos_ld(posv + PS * k);
+    double v[CK];
+#pragma unroll
+    for (int r = 0; r < CK; ++r) {
+      const unsigned p = cell_pos(P, r);
+      v[r] = src[base[r] + (p == hines::kCellPadPos ? 0u : p)];
+    }
+#pragma unroll
+    for (int r = 0; r < CK; ++r) pl[wo + CG * r] = v[r];
+#pragma unroll
+    for (int q = 0; q < CK / 2; ++q)
+      d2[walk_pair(W.chunk_off + k, q, lane)] =
+          double2_t{pl[2 * q * (kCellRowB / 8) + lane], pl[(2 * q + 1) * (kCellRowB / 8) + lane]};
+  }
+}
+
+// walk layout -> user layout (padding slots are not stored)
+__global__ __launch_bounds__(64) void k_cells_from_walk(DevTables tb, const double* __restrict__ src,
+                                                        double* __restrict__ dst) {
+  __shared__ __attribute__((aligned(16))) char raw[CK * kCellRowB];
+  lds_f64* pl = (lds_f64*)raw;
+  const int lane = threadIdx.x;
+  const hines::KCellWave W = tb.cwave[blockIdx.x];
+  int64_t base[CK];
+#pragma unroll
+  for (int r = 0; r < CK; ++r) base[r] = tb.cbase[(int64_t)blockIdx.x * 64 + CG * r + lane / CK];
+  constexpr int PS = 8 * CK;
+  const u32x4* posv = (const u32x4*)(tb.cpos + W.chunk_off * hines::kCellChunkElems) + (CK / 8) * lane;
+  const lds_f64* rd = (const lds_f64*)((lds_char*)raw + (lane % CK) * kCellRowB) + lane / CK;
+  const double2_t* s2 = (const double2_t*)src;
+  for (int k = 0; k < W.nchunk; ++k) {
+    const CellPos P = pos_ld(posv + PS * k);
+#pragma unroll
+    for (int q = 0; q < CK / 2; ++q) {
+      const double2_t v = s2[walk_pair(W.chunk_off + k, q, lane)];
+      pl[2 * q * (kCellRowB / 8) + lane] = v.x;
+      pl[(2 * q + 1) * (kCellRowB / 8) + lane] = v.y;
+    }
+#pragma unroll
+    for (int r = 0; r < CK; ++r) {
+      const unsigned p = cell_pos(P, r);
+      const double v = rd[CG * r];
+      if (p != hines::kCellPadPos) dst[base[r] + p] = v;
+    }
+  }
+}
+
+// positions in lane order, CK per lane and chunk like the flags (for the draws)
+__global__ void k_cells_lane_pos(DevTables tb, uint16_t* __restrict__ lp, int64_t nchunks) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nchunks * 64 * CK) return;
+  const int64_t g = t / (64 * CK);
+  const int c = (int)((t / CK) % 64), e = (int)(t % CK);
+  lp[t] = tb.cpos[hines::cell_pos_index(g, c, e)];
+}
+
+// One implicit-Euler step with the factors kept: V <- A^-1 (c V + I) in the
+// walk layout.  Two register sets: the loads of the next chunk are in flight
+// while this one is swept.
+__device__ __forceinline__ double pair_at(const double2_t* a, int e) { return (e & 1) ? a[e >> 1].y : a[e >> 1].x; }
+
+template <int RHS>
+struct StepChunk {
+  double2_t f[CK / 2], r[CK / 2], c[CK / 2], i[RHS == kFlowCVI ? CK / 2 : 1], v[CK / 2];
+  cflag_t fl;
+  CellPos p;  // kFlowNoise: positions of the lane's steps
+};
+
+template <int RHS>
+__device__ __forceinline__ void step_load_b(StepChunk<RHS>& C, const CellLoop& L, const hines::KCellWave& W,
+                                            const cflag_t* flv, int k, int lane) {
+  C.fl = flag_ld(flv + 64 * k);
+  if constexpr (RHS == kFlowNoise)
+    C.p = pos_ld((const u32x4*)(L.lp + (W.chunk_off + k) * hines::kCellChunkElems) + (CK / 8) * lane);
+#pragma unroll
+  for (int q = 0; q < CK / 2; ++q) {
+    const int64_t o = walk_pair(W.chunk_off + k, q, lane);
+    C.f[q] = ((const double2_t*)L.f)[o];
+    C.r[q] = ((const double2_t*)L.r)[o];
+    C.c[q] = ((const double2_t*)L.c)[o];
+    if constexpr (RHS == kFlowCVI) C.i[q] = ((const double2_t*)L.ci)[o];
+    C.v[q] = ((const double2_t*)L.v)[o];
+  }
+}
+
+template <int RHS>
+__device__ __forceinline__ void step_load_f(StepChunk<RHS>& C, const CellLoop& L, const hines::KCellWave& W,
+                                            const cflag_t* flv, int k, int lane) {
+  C.fl = flag_ld(flv + 64 * k);
+#pragma unroll
+  for (int q = 0; q < CK / 2; ++q) {
+    const int64_t o = walk_pair(W.chunk_off + k, q, lane);
+    C.f[q] = ((const double2_t*)L.f)[o];
+    C.v[q] = ((const double2_t*)L.v)[o];  // y from the backward sweep
+  }
+}
+
+template <int RHS>
+__device__ __forceinline__ void step_backward(const StepChunk<RHS>& C, const CellLoop& L, const hines::KCellWave& W,
+                                              int k, int lane, int64_t base, lds_f64* stk, lds_f64* mb, double& cb,
+                                              double& tb, int& m) {
+  double y[CK];
+#pragma unroll
+  for (int e = 0; e < CK; ++e) {
+    const unsigned fe = cell_byte(C.fl, e);
+    double bb = pair_at(C.c, e) * pair_at(C.v, e);
+    if constexpr (RHS == kFlowCVI) bb = bb + pair_at(C.i, e);
+    if constexpr (RHS == kFlowNoise) {
+      const unsigned p = cell_pos(C.p, e);
+      bb = bb + noise_draw(L.seed, L.step, (uint64_t)(base + (p == hines::kCellPadPos ? 0u : p)), L.sigma);
+    }
+    const double kc = (fe & hines::CF_TIP) ? 0.0 : 1.0;
+    bb = __builtin_fma(-kc, cb, bb);
+    if (fe & hines::CF_MBIN) bb = bb - mb[lane ^ 32];
+    if (fe & hines::CF_POP) {
+      bb = bb - tb;
+      m -= 1;
+      tb = stk[64 * m];
+    }
+    y[e] = bb * pair_at(C.r, e);
+    cb = pair_at(C.f, e) * bb;
+    if (fe & hines::CF_PUSH) {
+      stk[64 * m] = tb;
+      m += 1;
+      tb = cb;
+    }
+    if (fe & hines::CF_MERGE) tb = tb + cb;
+    if (fe & hines::CF_MBOUT) mb[lane] = cb;
+    if (e & 1) ((double2_t*)L.v)[walk_pair(W.chunk_off + k, e >> 1, lane)] = double2_t{y[e - 1], y[e]};
+  }
+}
+
+template <int RHS>
+__device__ __forceinline__ void step_forward(const StepChunk<RHS>& C, const CellLoop& L, const hines::KCellWave& W,
+                                             int k, int lane, lds_f64* stk, lds_f64* mb, double& xc, double& xt,
+                                             int& m) {
+  double x[CK];
+#pragma unroll
+  for (int e = CK - 1; e >= 0; --e) {
+    const unsigned fe = cell_byte(C.fl, e);
+    double xp = (fe & (hines::CF_PUSH | hines::CF_MERGE)) ? xt : xc;
+    if (fe & hines::CF_MBOUT) xp = mb[lane];
+    if (fe & hines::CF_PUSH) {
+      m -= 1;
+      xt = stk[64 * m];
+    }
+    const double xv = __builtin_fma(-pair_at(C.f, e), xp, pair_at(C.v, e));
+    if (fe & hines::CF_POP) {
+      stk[64 * m] = xt;
+      m += 1;
+      xt = xv;
+    }
+    if (fe & hines::CF_MBIN) mb[lane ^ 32] = xv;
+    xc = xv;
+    x[e] = xv;
+    if (!(e & 1)) ((double2_t*)L.v)[walk_pair(W.chunk_off + k, e >> 1, lane)] = double2_t{x[e], x[e + 1]};
+  }
+}
+
+template <int RHS>
+__global__ __launch_bounds__(64) void k_cells_step(DevTables tb, CellLoop L) {
+  __shared__ __attribute__((aligned(16))) double sraw[hines::kCellStack * 64 + 64];
+  lds_f64* stk = (lds_f64*)sraw + threadIdx.x;  // slot s at stk[64 s]
+  lds_f64* mb = (lds_f64*)sraw + hines::kCellStack * 64;
+  const int lane = threadIdx.x;
+  const hines::KCellWave W = tb.cwave[blockIdx.x];
+  const int nk = W.nchunk;
+  const cflag_t* flv = (const cflag_t*)(tb.cflag + W.chunk_off * hines::kCellChunkElems) + lane;
+  int64_t base = 0;
+  if constexpr (RHS == kFlowNoise) base = tb.cbase[(int64_t)blockIdx.x * 64 + lane];
+  StepChunk<RHS> A, B;
+  // backward: y = (b - contributions) / d', in place of V
+  double cb = 0.0, tb_ = 0.0;
+  int m = 0;
+  step_load_b<RHS>(A, L, W, flv, 0, lane);
+  for (int k = 0;; k += 2) {
+    if (k + 1 < nk) step_load_b<RHS>(B, L, W, flv, k + 1, lane);
+    step_backward<RHS>(A, L, W, k, lane, base, stk, mb, cb, tb_, m);
+    if (k + 1 >= nk) break;
+    if (k + 2 < nk) step_load_b<RHS>(A, L, W, flv, k + 2, lane);
+    step_backward<RHS>(B, L, W, k + 1, lane, base, stk, mb, cb, tb_, m);
+    if (k + 2 >= nk) break;
+  }
+  // the forward sweep reads back this wave's own stores
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  double xc = 0.0, xt = 0.0;
+  m = 0;
+  step_load_f<RHS>(A, L, W, flv, nk - 1, lane);
+  for (int k = nk - 1;; k -= 2) {
+    if (k >= 1) step_load_f<RHS>(B, L, W, flv, k - 1, lane);
+    step_forward<RHS>(A, L, W, k, lane, stk, mb, xc, xt, m);
+    if (k < 1) break;
+    if (k >= 2) step_load_f<RHS>(A, L, W, flv, k - 2, lane);
+    step_forward<RHS>(B, L, W, k - 1, lane, stk, mb, xc, xt, m);
     if (k < 2) break;
   }
 }

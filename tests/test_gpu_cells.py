@@ -121,3 +121,36 @@ def test_timestep_forms_and_graph(torch_dev):
         _ = (d * 2).sum().item()
     loop.close()
     p.close()
+
+
+def test_factored_time_loop_with_noise(torch_dev):
+    """A captured loop on a cell-lane plan factors A once per launch and keeps
+    V in the walk layout: it equals the eager steps bit for bit and the
+    oracle's time loop to 1e-12, over two launches."""
+    torch, dev = torch_dev
+    from paper_1810_12742_amd import Plan
+    s = configs.c3(300, seed=5)
+    f = s.forest
+    print("cells: factored noise loop", flush=True)
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets, cell_lanes=1)
+    d = torch.from_numpy(s.diag).to(dev)
+    u = torch.from_numpy(s.upper).to(dev)
+    c = torch.from_numpy(s.c).to(dev)
+    steps = 4
+    Ve = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    for k in range(2 * steps):
+        p.timestep(d, u, c, Ve, Ve, noise_sigma=0.1, noise_seed=9, step=k)
+    Vg = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    loop = p.timeloop(d, u, c, Vg, steps, noise_sigma=0.1, noise_seed=9)
+    loop.launch()
+    torch.cuda.synchronize()
+    first = Vg.cpu().numpy().copy()
+    Vo = oracle.timeloop(f, s.diag, s.upper, s.c, steps, noise_seed=9, noise_sigma=0.1)
+    assert cell_rel_err(f, first, Vo) <= TOL
+    loop2 = p.timeloop(d, u, c, Vg, steps, first_step=steps, noise_sigma=0.1, noise_seed=9)
+    loop2.launch()
+    torch.cuda.synchronize()
+    assert np.array_equal(Vg.cpu().numpy(), Ve.cpu().numpy())
+    loop.close()
+    loop2.close()
+    p.close()
