@@ -75,8 +75,8 @@ typedef struct hines_options {
   int32_t cell_lanes;         /* 1: hines_solve and hines_timestep run one lane per cell, the
                                  one-thread-per-matrix solver of §3 and §7 (§2's elimination in a
                                  depth-first order of each cell, 64 lanes of similar length per
-                                 wave; a cell longer than 0.8 times the mean cell is cut at one
-                                 edge into two halves on two lanes; elimination factors kept in a
+                                 wave; a cell longer than 0.8 times the mean cell is cut into
+                                 pieces on two to four lanes of one wave; elimination factors kept in a
                                  device scratch of 16 bytes per step owned by the plan).  Needs
                                  bitwise 0, cells of at most 65535 compartments and a stack need
                                  of at most 12 (HINES_ERR_TOO_BIG otherwise).  hines_solve_mixed
@@ -129,10 +129,14 @@ enum {
                                         element (j % K) of lane ((64 / K) r + j / K)'s walk,
                                         relative to its cell's first compartment, in backward
                                         step order; 65535 for padding                         */
-  HINES_TABLE_CELL_FLAGS = 15        /* [chunks*K*64] per chunk, lane c, element e: flags
+  HINES_TABLE_CELL_FLAGS = 15,       /* [chunks*K*64] per chunk, lane c, element e: flags
                                         1 tip, 2 pop, 4 push, 8 merge, 16 padding, 32 root,
-                                        64 root of a cut-off half (lane c < 32; its contribution
-                                        goes to lane c + 32), 128 parent of that root           */
+                                        64 root of a cut-off subtree (its contribution leaves
+                                        through mailbox c), 128 parent of such a root (takes
+                                        the next mailbox of the lane's source list)           */
+  HINES_TABLE_CELL_MBSRC = 16        /* [nwaves*64] per lane: the mailbox (source lane) of each
+                                        take, 6 bits each, in backward order in bits 0-31 and
+                                        in forward order in bits 32-63; 0 without takes       */
 };
 
 /* Fill *opt with the defaults: no re-rooting, no splitting, group_width 64,

@@ -13,13 +13,18 @@
 // number of tips.  The forward sweep mirrors this: x of a compartment with two
 // or more children waits on the stack for its later children.
 //
-// A cell much longer than the average is cut at one edge (v, p(v)) into the
-// subtree S of v and the rest P, walked by the paired lanes c and c + 32 of
-// one wave.  S starts at step 0 and ends with v; P ends with the cell root and
-// visits the path from the root to p(v) first in its preorder, so p(v) comes
-// late in its backward walk.  The contribution of v crosses through an LDS
-// mailbox at a strictly later step, and x of p(v) crosses back in the forward
-// sweep, which runs the steps in reverse.
+// A cell much longer than the average is cut at edges (v_i, p(v_i)) into
+// subtrees S_i of v_i and the rest P, each walked by a lane of one wave.  All
+// receivers p(v_i) lie on one path from the root, which P visits first in its
+// preorder, so they come late in its backward walk.  S_i starts at step 0 and
+// ends with v_i, whose contribution crosses through the LDS mailbox of S_i's
+// lane at a strictly later step; P reads the mailboxes in the order its walk
+// meets the receivers (a per-lane list of source lanes).  x of p(v_i) crosses
+// back in the forward sweep, which runs the steps in reverse.  One cut takes
+// the subtree closest to half the cell; a cell that stays much longer than
+// the average is instead cut along its heavy path (the child with the most
+// compartments at every step from the root), up to kCellMaxCuts subtrees.
+
 #include <algorithm>
 #include <numeric>
 
@@ -45,14 +50,14 @@ void cell_tree(const int32_t* par, int64_t lo, int32_t m, CellTree& T) {
   for (int32_t i = m - 1; i >= 1; --i) T.size[par[lo + i] - lo] += T.size[i];
 }
 
-// Walk of the subtree of `root` without the subtree of `cut` (-1: none).
+// Walk of the subtree of `root` without the subtrees whose roots `excl` marks.
 // `forced[a]` (-1: none) is put first among a's children; among the others
 // the child with the deepest stack need goes last (the highest index among
 // equal needs: breadth-first numbered siblings are adjacent in memory, so
 // the backward walk then runs down through them).  Appends the preorder to
 // `pre`, sets the flags of the visited nodes in `fl` (indexed by relative
 // node) and returns the stack need of the walk.
-int32_t walk(const CellTree& T, int32_t root, int32_t cut, const std::vector<int32_t>& forced,
+int32_t walk(const CellTree& T, int32_t root, const std::vector<uint8_t>& excl, const std::vector<int32_t>& forced,
              std::vector<int32_t>& pre, std::vector<uint8_t>& fl, std::vector<int32_t>& need,
              std::vector<int32_t>& seen, std::vector<int32_t>& st) {
   // the visited set in some preorder, then the needs in reverse (children first)
@@ -64,7 +69,7 @@ int32_t walk(const CellTree& T, int32_t root, int32_t cut, const std::vector<int
     st.pop_back();
     seen.push_back(a);
     for (int32_t k = T.ch_off[a]; k < T.ch_off[a + 1]; ++k)
-      if (T.ch[k] != cut) st.push_back(T.ch[k]);
+      if (!excl[T.ch[k]]) st.push_back(T.ch[k]);
   }
   // children of a in walk order: forced child, the others ascending, the deepest-need child last
   auto ordered = [&](int32_t a, std::vector<int32_t>& out) {
@@ -73,7 +78,7 @@ int32_t walk(const CellTree& T, int32_t root, int32_t cut, const std::vector<int
     const int32_t f = forced[a];
     for (int32_t k = T.ch_off[a]; k < T.ch_off[a + 1]; ++k) {
       const int32_t c = T.ch[k];
-      if (c == cut || c == f) continue;
+      if (excl[c] || c == f) continue;
       if (need[c] >= hn) {
         hn = need[c];
         h = c;
@@ -82,7 +87,7 @@ int32_t walk(const CellTree& T, int32_t root, int32_t cut, const std::vector<int
     if (f >= 0) out.push_back(f);
     for (int32_t k = T.ch_off[a]; k < T.ch_off[a + 1]; ++k) {
       const int32_t c = T.ch[k];
-      if (c != cut && c != f && c != h) out.push_back(c);
+      if (!excl[c] && c != f && c != h) out.push_back(c);
     }
     if (h >= 0) out.push_back(h);
   };
@@ -145,20 +150,63 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
       return ERR_TOO_BIG;
     }
   }
-  // cells longer than 0.8 times the mean are cut in two (when the pieces fit): shorter
+  // cells longer than 0.8 times the mean are cut (when the pieces fit): shorter
   // lanes and more waves than wave slots, so that short waves fill in behind long ones
   const double mean = ncells ? (double)n / (double)ncells : 0.0;
   const int64_t split_above = std::max<int64_t>(4 * kCellChunk, (int64_t)(0.8 * mean));
+  // cutting a lane below the steps every wave slot of the device walks anyway
+  // only adds padding: 1,024 slots (256 compute units, 4 SIMDs, one wave each
+  // at this kernel's register use), 64 lanes, about 15% padding
+  const int64_t slot_steps = (int64_t)(1.15 * (double)n / (64.0 * 1024.0));
 
   CellTree T;
-  std::vector<int32_t> forced, need, pre, seen, st;
-  std::vector<uint8_t> fl;
-  std::vector<LaneWork> whole, halves;  // halves: S, P, S, P, ...
-  std::vector<int64_t> pair_span;        // per pair: the shortest span that keeps the mailbox order
+  std::vector<int32_t> forced, need, pre, seen, st, depth, path, pick;
+  std::vector<uint8_t> fl, excl, onpath;
+  // a group: the lanes of one cell, lanes[0] whole or P, then the S_i in the
+  // order P's backward walk takes their contributions
+  struct Group {
+    int64_t span = 0;
+    std::vector<LaneWork> lanes;
+  };
+  std::vector<Group> groups;
   auto to_back = [](const std::vector<int32_t>& pre_, const std::vector<uint8_t>& fl_, LaneWork& w) {
     w.back.assign(pre_.rbegin(), pre_.rend());
     w.bfl.resize(w.back.size());
     for (size_t i = 0; i < w.back.size(); ++i) w.bfl[i] = fl_[w.back[i]];
+  };
+  // span of cutting off the subtrees `vs` (receivers on one root path): P
+  // ends with the root and has receiver r at step span - 1 - depth(r)
+  auto cut_span = [&](int32_t m, const std::vector<int32_t>& vs, int32_t lo) {
+    int64_t rest = m, sp = 0;
+    for (int32_t v : vs) {
+      rest -= T.size[v];
+      sp = std::max<int64_t>(sp, (int64_t)T.size[v] + depth[parent[lo + v] - lo] + 1);
+    }
+    return std::max(rest, sp);
+  };
+  // cut along the heavy path: for a target span t, per receiver the largest
+  // off-path child that fits, largest first, until the rest fits
+  auto heavy_cut = [&](int32_t m, int64_t t, std::vector<int32_t>& out) {
+    std::vector<std::pair<int32_t, int32_t>> cand;  // (size, child)
+    for (size_t i = 0; i + 1 < path.size(); ++i) {
+      const int32_t a = path[i];
+      int32_t best = -1;
+      for (int32_t k = T.ch_off[a]; k < T.ch_off[a + 1]; ++k) {
+        const int32_t c = T.ch[k];
+        if (onpath[c] || (int64_t)T.size[c] + depth[a] + 1 > t) continue;
+        if (best < 0 || T.size[c] > T.size[best]) best = c;
+      }
+      if (best >= 0) cand.push_back({T.size[best], best});
+    }
+    std::sort(cand.begin(), cand.end(), [](auto x, auto y) { return x.first > y.first || (x.first == y.first && x.second < y.second); });
+    out.clear();
+    int64_t rest = m;
+    for (auto& cs : cand) {
+      if (rest <= t || (int)out.size() >= kCellMaxCuts) break;
+      out.push_back(cs.second);
+      rest -= cs.first;
+    }
+    return rest <= t;
   };
   for (int64_t c = 0; c < ncells; ++c) {
     const int64_t lo = cell_offsets[c];
@@ -166,48 +214,106 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
     cell_tree(parent, lo, m, T);
     forced.assign(m, -1);
     need.assign(m, 0);
+    excl.assign(m, 0);
     bool done = false;
     if (m > split_above) {
-      // cut vertex: subtree size closest to m / 2 from below
+      depth.assign(m, 0);
+      for (int32_t i = 1; i < m; ++i) depth[i] = depth[parent[lo + i] - lo] + 1;
+      // one cut: the subtree closest to m / 2 from below (at least a quarter)
+      std::vector<int32_t> vs;
       int32_t v = -1;
       for (int32_t i = 1; i < m; ++i)
         if (2 * T.size[i] <= m && (v < 0 || T.size[i] > T.size[v])) v = i;
+      int64_t span = m;
       if (v > 0 && 4 * T.size[v] >= m) {
-        const int32_t pv = parent[lo + v] - (int32_t)lo;
-        int32_t depth = 0;
-        for (int32_t a = pv; a != 0; a = parent[lo + a] - (int32_t)lo) {
-          forced[parent[lo + a] - lo] = a;
-          ++depth;
+        vs = {v};
+        span = cut_span(m, vs, (int32_t)lo);
+      }
+      if (span > 2 * split_above) {  // still much longer than the average: the heavy path
+        path.assign(1, 0);
+        onpath.assign(m, 0);
+        onpath[0] = 1;
+        for (;;) {
+          const int32_t a = path.back();
+          int32_t h = -1;
+          for (int32_t k = T.ch_off[a]; k < T.ch_off[a + 1]; ++k)
+            if (h < 0 || T.size[T.ch[k]] > T.size[h]) h = T.ch[k];
+          if (h < 0) break;
+          path.push_back(h);
+          onpath[h] = 1;
         }
-        LaneWork S, P;
-        S.cell = P.cell = c;
+        int64_t tl = std::max<int64_t>({(m + kCellMaxCuts) / (kCellMaxCuts + 1), split_above, slot_steps}), th = span;
+        if (tl < th && heavy_cut(m, th - 1, pick)) {
+          while (tl < th) {  // smallest feasible target
+            const int64_t mid = (tl + th) / 2;
+            if (heavy_cut(m, mid, pick)) th = mid;
+            else tl = mid + 1;
+          }
+          heavy_cut(m, th, pick);
+          if (!pick.empty() && cut_span(m, pick, (int32_t)lo) < span) {
+            vs = pick;
+            span = cut_span(m, vs, (int32_t)lo);
+          }
+        }
+      }
+      if (!vs.empty()) {
+        // P's forced path: from the root to the deepest receiver; every receiver on it
+        int32_t deep = -1;
+        for (int32_t x : vs) {
+          const int32_t r = parent[lo + x] - (int32_t)lo;
+          if (deep < 0 || depth[r] > depth[deep]) deep = r;
+        }
+        for (int32_t a = deep; a != 0; a = parent[lo + a] - (int32_t)lo) forced[parent[lo + a] - lo] = a;
+        // S_i in the order P's backward walk meets their receivers: deepest first
+        std::sort(vs.begin(), vs.end(), [&](int32_t x, int32_t y) {
+          const int32_t dx = depth[parent[lo + x] - lo], dy = depth[parent[lo + y] - lo];
+          return dx > dy || (dx == dy && x < y);
+        });
+        Group g;
+        g.lanes.resize(1 + vs.size());
         fl.assign(m, 0);
+        bool ok = true;
+        int32_t nd = 0;
+        for (size_t i = 0; i < vs.size(); ++i) {
+          pre.clear();
+          nd = std::max(nd, walk(T, vs[i], excl, forced, pre, fl, need, seen, st));
+          fl[vs[i]] |= CF_MBOUT;
+          LaneWork& S = g.lanes[1 + i];
+          S.cell = c;
+          S.pad_after = true;
+          to_back(pre, fl, S);
+          excl[vs[i]] = 1;
+        }
         pre.clear();
-        const int32_t ns = walk(T, v, -1, forced, pre, fl, need, seen, st);
-        fl[v] |= CF_MBOUT;
-        to_back(pre, fl, S);
-        S.pad_after = true;
-        pre.clear();
-        const int32_t np = walk(T, 0, v, forced, pre, fl, need, seen, st);
-        fl[pv] |= CF_MBIN;
+        nd = std::max(nd, walk(T, 0, excl, forced, pre, fl, need, seen, st));
+        for (size_t i = 0; i < vs.size(); ++i) {
+          const int32_t r = parent[lo + vs[i]] - (int32_t)lo;
+          fl[r] |= CF_MBIN;
+          ok = ok && pre.size() > (size_t)depth[r] && pre[depth[r]] == r;
+          ok = ok && (i == 0 || r != parent[lo + vs[i - 1]] - (int32_t)lo);  // one take per receiver
+        }
         fl[0] |= CF_ROOT;
+        LaneWork& P = g.lanes[0];
+        P.cell = c;
         to_back(pre, fl, P);
-        if (ns <= kCellStack && np <= kCellStack && pre.size() > (size_t)depth && pre[depth] == pv) {
-          out.max_need = std::max(out.max_need, std::max(ns, np));
-          pair_span.push_back(std::max<int64_t>((int64_t)P.back.size(), (int64_t)S.back.size() + depth + 1));
-          halves.push_back(std::move(S));
-          halves.push_back(std::move(P));
+        if (ok && nd <= kCellStack) {
+          out.max_need = std::max(out.max_need, nd);
+          g.span = span;
+          groups.push_back(std::move(g));
           done = true;
         }
         forced.assign(m, -1);
+        excl.assign(m, 0);
       }
     }
     if (!done) {
-      LaneWork W;
+      Group g;
+      g.lanes.resize(1);
+      LaneWork& W = g.lanes[0];
       W.cell = c;
       fl.assign(m, 0);
       pre.clear();
-      const int32_t nd = walk(T, 0, -1, forced, pre, fl, need, seen, st);
+      const int32_t nd = walk(T, 0, excl, forced, pre, fl, need, seen, st);
       if (nd > kCellStack) {
         err = "cell " + std::to_string(c) + " needs " + std::to_string(nd) +
               " contribution stack entries; the cell-lane kernel holds " + std::to_string(kCellStack);
@@ -216,39 +322,49 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
       fl[0] |= CF_ROOT;
       out.max_need = std::max(out.max_need, nd);
       to_back(pre, fl, W);
-      whole.push_back(std::move(W));
+      g.span = (int64_t)W.back.size();
+      groups.push_back(std::move(g));
     }
   }
-  // waves: 32 cut cells (lanes c and c + 32) or 64 whole cells, longest first
+  // waves: groups of the same lane count, longest first.  A wave holds 64
+  // whole cells, or 32 two-lane cells (the cut-off subtree in lane c, the rest
+  // in lane c + 32), or 64 / g cells of g lanes on consecutive lanes
   struct WavePlan {
     int64_t span;
     std::vector<const LaneWork*> lanes;  // 64 entries, nullptr for empty lanes
+    std::vector<uint64_t> src;           // per lane: mailbox source lanes, backward | forward order << 32
   };
   std::vector<WavePlan> plans;
   {
-    std::vector<int64_t> idx(whole.size());
+    std::vector<int64_t> idx(groups.size());
     std::iota(idx.begin(), idx.end(), 0);
-    std::stable_sort(idx.begin(), idx.end(),
-                     [&](int64_t a, int64_t b) { return whole[a].back.size() > whole[b].back.size(); });
-    for (size_t w = 0; w < idx.size(); w += 64) {
-      WavePlan P{0, std::vector<const LaneWork*>(64, nullptr)};
-      for (size_t l = 0; l < 64 && w + l < idx.size(); ++l) {
-        P.lanes[l] = &whole[idx[w + l]];
-        P.span = std::max<int64_t>(P.span, (int64_t)whole[idx[w + l]].back.size());
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+      const size_t la = groups[a].lanes.size(), lb = groups[b].lanes.size();
+      return la < lb || (la == lb && groups[a].span > groups[b].span);
+    });
+    size_t prev = 0;
+    int slot = 0, per = 0;
+    for (int64_t gi : idx) {
+      const Group& g = groups[gi];
+      const int nl = (int)g.lanes.size();
+      if ((size_t)nl != prev || slot == per) {
+        plans.push_back(WavePlan{0, std::vector<const LaneWork*>(64, nullptr), std::vector<uint64_t>(64, 0)});
+        prev = (size_t)nl;
+        per = 64 / nl;
+        slot = 0;
       }
-      plans.push_back(std::move(P));
-    }
-    std::vector<int64_t> pidx(pair_span.size());
-    std::iota(pidx.begin(), pidx.end(), 0);
-    std::stable_sort(pidx.begin(), pidx.end(), [&](int64_t a, int64_t b) { return pair_span[a] > pair_span[b]; });
-    for (size_t w = 0; w < pidx.size(); w += 32) {
-      WavePlan P{0, std::vector<const LaneWork*>(64, nullptr)};
-      for (size_t l = 0; l < 32 && w + l < pidx.size(); ++l) {
-        P.lanes[l] = &halves[2 * pidx[w + l]];
-        P.lanes[l + 32] = &halves[2 * pidx[w + l] + 1];
-        P.span = std::max(P.span, pair_span[pidx[w + l]]);
+      WavePlan& P = plans.back();
+      // lane of piece i: pairs split across the halves, larger groups consecutive
+      auto lane_of = [&](int i) { return nl == 2 ? (i == 0 ? slot + 32 : slot) : slot * nl + i; };
+      uint64_t bw = 0, fw = 0;
+      for (int i = 1; i < nl; ++i) {
+        bw |= (uint64_t)lane_of(i) << (6 * (i - 1));
+        fw |= (uint64_t)lane_of(i) << (6 * (nl - 1 - i));
       }
-      plans.push_back(std::move(P));
+      P.src[lane_of(0)] = bw | (fw << 32);
+      for (int i = 0; i < nl; ++i) P.lanes[lane_of(i)] = &g.lanes[i];
+      P.span = std::max(P.span, g.span);
+      ++slot;
     }
     std::stable_sort(plans.begin(), plans.end(), [](const WavePlan& a, const WavePlan& b) { return a.span > b.span; });
   }
@@ -257,6 +373,7 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
   out.waves.resize(nw);
   out.lane_cell.assign(nw * 64, -1);
   out.base.assign(nw * 64, 0);
+  out.mbsrc.assign(nw * 64, 0);
   int64_t chunks = 0;
   for (int64_t w = 0; w < nw; ++w) {
     const int32_t nk = (int32_t)((plans[w].span + kCellChunk - 1) / kCellChunk);
@@ -275,6 +392,7 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
       const LaneWork* L = plans[w].lanes[c];
       if (!L) continue;
       out.lane_cell[w * 64 + c] = (int32_t)L->cell;
+      out.mbsrc[w * 64 + c] = plans[w].src[c];
       out.base[w * 64 + c] = cell_offsets[L->cell];
       const int64_t len = (int64_t)L->back.size();
       const int64_t q0 = L->pad_after ? 0 : span - len;

@@ -417,32 +417,60 @@ bool check_cell_tables(const hines::HostPlan& P, const int64_t* cell_offsets, st
         return false;
       }
     }
-    // mailboxes: lane c < 32 posts at most once (its half's root), lane c + 32
-    // takes it exactly then, at a strictly later step
-    for (int c = 0; c < 32; ++c) {
-      int64_t qo = -1, qi = -1;
-      int no = 0, ni = 0;
-      for (int64_t q = 0; q < (int64_t)W.nchunk * hines::kCellChunk; ++q) {
-        const int64_t g = W.chunk_off + q / hines::kCellChunk;
-        const int e = (int)(q % hines::kCellChunk);
-        const uint8_t fo = C.flags[hines::cell_flag_index(g, c, e)], fi = C.flags[hines::cell_flag_index(g, c + 32, e)];
-        if (fo & hines::CF_MBIN) ni += 100;  // wrong side
-        if (fi & hines::CF_MBOUT) no += 100;
-        if (fo & hines::CF_MBOUT) {
+    // mailboxes: a lane posts at most once (the root of its cut-off subtree);
+    // every post is taken exactly once, by a lane of the same cell, at a
+    // strictly later step, from the mailbox its source list names next; the
+    // forward list is the backward list reversed
+    const int64_t steps = (int64_t)W.nchunk * hines::kCellChunk;
+    int64_t post_at[64];
+    int taken[64] = {0};
+    for (int c = 0; c < 64; ++c) {
+      post_at[c] = -1;
+      int no = 0;
+      for (int64_t q = 0; q < steps; ++q) {
+        const uint8_t f = C.flags[hines::cell_flag_index(W.chunk_off + q / hines::kCellChunk, c, (int)(q % hines::kCellChunk))];
+        if (f & hines::CF_MBOUT) {
           ++no;
-          qo = q;
-        }
-        if (fi & hines::CF_MBIN) {
-          ++ni;
-          qi = q;
+          post_at[c] = q;
         }
       }
-      if (no != ni || no > 1 || (no == 1 && !(qo < qi)) ||
-          (no == 1 && C.lane_cell[w * 64 + c] != C.lane_cell[w * 64 + c + 32])) {
-        why = "wave " + std::to_string(w) + " lane " + std::to_string(c) + " mailbox unpaired or out of order";
+      if (no > 1) {
+        why = "wave " + std::to_string(w) + " lane " + std::to_string(c) + " posts more than once";
         return false;
       }
     }
+    for (int c = 0; c < 64; ++c) {
+      const uint64_t ms = C.mbsrc[w * 64 + c];
+      const uint32_t bw = (uint32_t)ms, fw = (uint32_t)(ms >> 32);
+      int src[6], ni = 0;
+      bool ok = true;
+      for (int64_t q = 0; q < steps && ok; ++q) {
+        const uint8_t f = C.flags[hines::cell_flag_index(W.chunk_off + q / hines::kCellChunk, c, (int)(q % hines::kCellChunk))];
+        if (!(f & hines::CF_MBIN)) continue;
+        if (ni >= 5) {
+          ok = false;
+          break;
+        }
+        const int s = (int)((bw >> (6 * ni)) & 63u);
+        src[ni++] = s;
+        ok = s != c && post_at[s] >= 0 && post_at[s] < q && C.lane_cell[w * 64 + s] == C.lane_cell[w * 64 + c] &&
+             taken[s]++ == 0;
+      }
+      uint32_t bw2 = 0, fw2 = 0;
+      for (int i = 0; i < ni && ok; ++i) {
+        bw2 |= (uint32_t)src[i] << (6 * i);
+        fw2 |= (uint32_t)src[ni - 1 - i] << (6 * i);
+      }
+      if (!ok || bw != bw2 || fw != fw2) {
+        why = "wave " + std::to_string(w) + " lane " + std::to_string(c) + " mailbox takes unpaired or out of order";
+        return false;
+      }
+    }
+    for (int c = 0; c < 64; ++c)
+      if ((post_at[c] >= 0) != (taken[c] == 1)) {
+        why = "wave " + std::to_string(w) + " lane " + std::to_string(c) + " mailbox post not taken";
+        return false;
+      }
   }
   return true;
 }
@@ -648,8 +676,9 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   const int64_t sz_cb = al((int64_t)CL.base.size() * sizeof(int64_t));
   const int64_t sz_cp = al((int64_t)CL.pos.size() * sizeof(uint16_t));
   const int64_t sz_cf = al((int64_t)CL.flags.size());
+  const int64_t sz_cm = al((int64_t)CL.mbsrc.size() * sizeof(uint64_t));
   const int64_t total = sz_br + sz_grp + sz_seg + sz_cell + sz_gl + sz_ws + sz_fl + sz_fm + sz_fp + sz_fa + sz_cw +
-                        sz_cb + sz_cp + sz_cf + 256;
+                        sz_cb + sz_cp + sz_cf + sz_cm + 256;
   const int64_t scr_bytes = CL.nchunks * hines::kCellChunk * 64 * 16;
   hipError_t e = hipGetDevice(&p->device);
   if (e == hipSuccess) e = allow_lds(o.group_width);
@@ -721,6 +750,9 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   p->t.cflag = (const uint8_t*)(base + off);
   if (e == hipSuccess) e = up(CL.flags.data(), (int64_t)CL.flags.size(), off);
   off += sz_cf;
+  p->t.cmsrc = (const uint64_t*)(base + off);
+  if (e == hipSuccess) e = up(CL.mbsrc.data(), (int64_t)CL.mbsrc.size() * sizeof(uint64_t), off);
+  off += sz_cm;
   p->t.cscr = (double*)p->scr_mem;
   p->t.cslots = CL.nchunks * hines::kCellChunk * 64;
   if (e != hipSuccess) {

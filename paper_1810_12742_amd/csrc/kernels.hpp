@@ -36,6 +36,7 @@ struct DevTables {
   const int64_t* cbase;           // cell-lane kernel: first user index of each lane's cell
   const uint16_t* cpos;           // cell-lane kernel: positions, staging order
   const uint8_t* cflag;           // cell-lane kernel: flags, cell-lane order
+  const uint64_t* cmsrc;          // cell-lane kernel: mailbox source lists per lane
   double* cscr;                   // cell-lane kernel: (f, y) per step and lane
   int64_t cslots;                 // cell-lane kernel: steps x lanes of all waves (walk-layout array length)
 };
@@ -65,8 +66,10 @@ __device__ __forceinline__ double noise_draw(uint32_t seed, uint32_t step, uint6
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    // one 32 x 32 -> 64-bit product per multiplier (high and low halves together)
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
     const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
     c1 = lo1;
@@ -77,7 +80,9 @@ __device__ __forceinline__ double noise_draw(uint32_t seed, uint32_t step, uint6
   const uint64_t m2 = ((((uint64_t)c2) << 32) | c3) >> 12;
   const double u1 = ((double)m1 + 0.5) * 0x1p-52;
   const double u2 = ((double)m2 + 0.5) * 0x1p-52;
-  return sigma * (sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2));
+  // cos(2 pi u2) as cospi(2 u2): 2 u2 is exact, and the reduction by whole
+  // periods is exact too (no multi-word reduction of a rounded 2 pi u2)
+  return sigma * (sqrt(-2.0 * log(u1)) * cospi(2.0 * u2));
 }
 
 __device__ __forceinline__ double rhs_value(const RhsSpec& rs, int64_t i) {
@@ -999,13 +1004,14 @@ __device__ __forceinline__ void cell_put(const CellBatch<RHS>& B, const RhsSpec&
 }
 
 // Backward elimination of one chunk from the LDS planes; (f, y) per step into fy.
-// mb: the mailboxes (slot c: the contribution of the cut-off half in lane c).
+// mb: the mailboxes (slot c: the contribution of the cut-off subtree in lane c);
+// msrc: the lane's source list, the next take in its low 6 bits.
 // FACTOR: keep (f, 1 / d') instead of (f, y).  The contribution to the parent
 // is (u f, f b'), the same products a solve with stored factors forms.
 template <bool FACTOR = false>
 __device__ __forceinline__ void cell_backward(const cflag_t& f, const lds_d2* pdu, const lds_f64* pb, lds_d2* stk,
                                               lds_d2* mb, int lane, double& cd, double& cb, double& td, double& tb,
-                                              int& m, double2_t* fy) {
+                                              int& m, double2_t* fy, unsigned& msrc) {
 #pragma unroll
   for (int e = 0; e < CK; ++e) {
     const unsigned fe = cell_byte(f, e);
@@ -1015,8 +1021,9 @@ __device__ __forceinline__ void cell_backward(const cflag_t& f, const lds_d2* pd
     const double kc = (fe & hines::CF_TIP) ? 0.0 : 1.0;  // the carry enters unless this is a tip
     dd = __builtin_fma(-kc, cd, dd);
     bb = __builtin_fma(-kc, cb, bb);
-    if (fe & hines::CF_MBIN) {  // the cut-off child's contribution, posted at an earlier step
-      const double2_t mv = mb[lane ^ 32];
+    if (fe & hines::CF_MBIN) {  // a cut-off child's contribution, posted at an earlier step
+      const double2_t mv = mb[msrc & 63u];
+      msrc >>= 6;
       dd = dd - mv.x;
       bb = bb - mv.y;
     }
@@ -1051,7 +1058,8 @@ __device__ __forceinline__ void cell_backward(const cflag_t& f, const lds_d2* pd
 // b plane, then through the gather mapping to the user order.
 __device__ __forceinline__ void cell_forward(const cflag_t& f, const CellPos& P, const double2_t* fy,
                                              lds_f64* pb, const lds_f64* xrd, lds_f64* stx, lds_d2* mb, int lane,
-                                             double& xc, double& xt, int& m, double* x, const int64_t* base) {
+                                             double& xc, double& xt, int& m, double* x, const int64_t* base,
+                                             unsigned& msrc) {
 #pragma unroll
   for (int e = CK - 1; e >= 0; --e) {
     const unsigned fe = cell_byte(f, e);
@@ -1067,7 +1075,10 @@ __device__ __forceinline__ void cell_forward(const cflag_t& f, const CellPos& P,
       m += 1;
       xt = xv;
     }
-    if (fe & hines::CF_MBIN) mb[lane ^ 32].x = xv;
+    if (fe & hines::CF_MBIN) {
+      mb[msrc & 63u].x = xv;
+      msrc >>= 6;
+    }
     xc = xv;
     pb[e * (kCellRowB / 8)] = xv;
   }
@@ -1128,6 +1139,8 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
   double cd = 0.0, cb = 0.0, td = 0.0, tb_ = 0.0;
   int m = 0;
   double2_t fy[CK];
+  const uint64_t ms = tb.cmsrc[(int64_t)blockIdx.x * 64 + lane];
+  unsigned msb = (unsigned)ms, msf = (unsigned)(ms >> 32);
   cflag_t fprev = fl;
   for (int k = 0; k < nk; ++k) {
     cell_put<RHS>(B, rs, base, P, lds, lane);
@@ -1150,7 +1163,7 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
       P = Q;
       Q = pos_ld(posv + PS * min(k + 2, nk - 1));
     }
-    cell_backward<RHS == kCellFactor>(f, pdu, pb, stk, mb, lane, cd, cb, td, tb_, m, fy);
+    cell_backward<RHS == kCellFactor>(f, pdu, pb, stk, mb, lane, cd, cb, td, tb_, m, fy, msb);
   }
   if constexpr (RHS == kCellFactor) {  // the last chunk's factors
     factor_store(fy, x, tb.cslots, W.chunk_off + nk - 1, lane);
@@ -1178,7 +1191,7 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
       PB = pos_ld(posv + PS * (k - 1));
       fb_ = flag_ld(flv + 64 * (k - 1));
     }
-    cell_forward(fa, PA, fy, pb, xrd, stx, mb, lane, xc, xt, m, x, base);
+    cell_forward(fa, PA, fy, pb, xrd, stx, mb, lane, xc, xt, m, x, base, msf);
     if (k < 1) break;
     if (k >= 2) {
       const double2_t* sk = scr + (k - 2) * (CK * 64);
@@ -1187,7 +1200,7 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
       PA = pos_ld(posv + PS * (k - 2));
       fa = flag_ld(flv + 64 * (k - 2));
     }
-    cell_forward(fb_, PB, fb, pb, xrd, stx, mb, lane, xc, xt, m, x, base);
+    cell_forward(fb_, PB, fb, pb, xrd, stx, mb, lane, xc, xt, m, x, base, msf);
     if (k < 2) break;
   }
 }
@@ -1328,7 +1341,7 @@ __device__ __forceinline__ void step_load_f(StepChunk<RHS>& C, const CellLoop& L
 template <int RHS>
 __device__ __forceinline__ void step_backward(const StepChunk<RHS>& C, const CellLoop& L, const hines::KCellWave& W,
                                               int k, int lane, int64_t base, lds_f64* stk, lds_f64* mb, double& cb,
-                                              double& tb, int& m) {
+                                              double& tb, int& m, unsigned& msrc) {
   double y[CK];
 #pragma unroll
   for (int e = 0; e < CK; ++e) {
@@ -1341,7 +1354,10 @@ __device__ __forceinline__ void step_backward(const StepChunk<RHS>& C, const Cel
     }
     const double kc = (fe & hines::CF_TIP) ? 0.0 : 1.0;
     bb = __builtin_fma(-kc, cb, bb);
-    if (fe & hines::CF_MBIN) bb = bb - mb[lane ^ 32];
+    if (fe & hines::CF_MBIN) {
+      bb = bb - mb[msrc & 63u];
+      msrc >>= 6;
+    }
     if (fe & hines::CF_POP) {
       bb = bb - tb;
       m -= 1;
@@ -1363,7 +1379,7 @@ __device__ __forceinline__ void step_backward(const StepChunk<RHS>& C, const Cel
 template <int RHS>
 __device__ __forceinline__ void step_forward(const StepChunk<RHS>& C, const CellLoop& L, const hines::KCellWave& W,
                                              int k, int lane, lds_f64* stk, lds_f64* mb, double& xc, double& xt,
-                                             int& m) {
+                                             int& m, unsigned& msrc) {
   double x[CK];
 #pragma unroll
   for (int e = CK - 1; e >= 0; --e) {
@@ -1380,7 +1396,10 @@ __device__ __forceinline__ void step_forward(const StepChunk<RHS>& C, const Cell
       m += 1;
       xt = xv;
     }
-    if (fe & hines::CF_MBIN) mb[lane ^ 32] = xv;
+    if (fe & hines::CF_MBIN) {
+      mb[msrc & 63u] = xv;
+      msrc >>= 6;
+    }
     xc = xv;
     x[e] = xv;
     if (!(e & 1)) ((double2_t*)L.v)[walk_pair(W.chunk_off + k, e >> 1, lane)] = double2_t{x[e], x[e + 1]};
@@ -1399,16 +1418,18 @@ __global__ __launch_bounds__(64) void k_cells_step(DevTables tb, CellLoop L) {
   int64_t base = 0;
   if constexpr (RHS == kFlowNoise) base = tb.cbase[(int64_t)blockIdx.x * 64 + lane];
   StepChunk<RHS> A, B;
+  const uint64_t ms = tb.cmsrc[(int64_t)blockIdx.x * 64 + lane];
+  unsigned msb = (unsigned)ms, msf = (unsigned)(ms >> 32);
   // backward: y = (b - contributions) / d', in place of V
   double cb = 0.0, tb_ = 0.0;
   int m = 0;
   step_load_b<RHS>(A, L, W, flv, 0, lane);
   for (int k = 0;; k += 2) {
     if (k + 1 < nk) step_load_b<RHS>(B, L, W, flv, k + 1, lane);
-    step_backward<RHS>(A, L, W, k, lane, base, stk, mb, cb, tb_, m);
+    step_backward<RHS>(A, L, W, k, lane, base, stk, mb, cb, tb_, m, msb);
     if (k + 1 >= nk) break;
     if (k + 2 < nk) step_load_b<RHS>(A, L, W, flv, k + 2, lane);
-    step_backward<RHS>(B, L, W, k + 1, lane, base, stk, mb, cb, tb_, m);
+    step_backward<RHS>(B, L, W, k + 1, lane, base, stk, mb, cb, tb_, m, msb);
     if (k + 2 >= nk) break;
   }
   // the forward sweep reads back this wave's own stores
@@ -1419,10 +1440,10 @@ __global__ __launch_bounds__(64) void k_cells_step(DevTables tb, CellLoop L) {
   step_load_f<RHS>(A, L, W, flv, nk - 1, lane);
   for (int k = nk - 1;; k -= 2) {
     if (k >= 1) step_load_f<RHS>(B, L, W, flv, k - 1, lane);
-    step_forward<RHS>(A, L, W, k, lane, stk, mb, xc, xt, m);
+    step_forward<RHS>(A, L, W, k, lane, stk, mb, xc, xt, m, msf);
     if (k < 1) break;
     if (k >= 2) step_load_f<RHS>(A, L, W, flv, k - 2, lane);
-    step_forward<RHS>(B, L, W, k - 1, lane, stk, mb, xc, xt, m);
+    step_forward<RHS>(B, L, W, k - 1, lane, stk, mb, xc, xt, m, msf);
     if (k < 2) break;
   }
 }

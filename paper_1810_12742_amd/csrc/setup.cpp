@@ -945,6 +945,7 @@ int64_t export_table(const HostPlan& p, int32_t id, int64_t* out, int64_t capaci
     case T_CELL_LANES: return put(p.cl.lane_cell);
     case T_CELL_POS: return put(p.cl.pos);
     case T_CELL_FLAGS: return put(p.cl.flags);
+    case T_CELL_MBSRC: return put(p.cl.mbsrc);
     default: return -1;
   }
 }

@@ -92,7 +92,8 @@ enum TableId : int32_t {
   T_CELL_LANES = 13,      // int64[nwaves*64]: cell of each lane (-1: empty)
   T_CELL_POS = 14,        // int64[nchunks*kCellChunkElems]: [chunk][staging lane][slot] relative position
   T_CELL_FLAGS = 15,      // int64[nchunks*kCellChunkElems]: [chunk][cell lane][element] flags
-  T_NUM = 16,
+  T_CELL_MBSRC = 16,      // int64[nwaves*64]: mailbox source lanes (6 bits each), backward | forward << 32
+  T_NUM = 17,
 };
 
 // Cell-lane kernel (one lane per cell, or per half of a long cell).  Each cell is processed in a depth-
@@ -117,6 +118,7 @@ constexpr int64_t cell_flag_index(int64_t chunk, int32_t c, int32_t e) {
   return chunk * kCellChunkElems + (int64_t)c * kCellChunk + e;
 }
 constexpr int32_t kCellStack = 12;           // LDS stack slots per lane; slot 0 is a dummy
+constexpr int32_t kCellMaxCuts = 3;          // cut-off subtrees per cell (lanes per cell: up to 4)
 constexpr uint16_t kCellPadPos = 0xFFFF;     // padding element: no user compartment
 constexpr int64_t kCellMaxSize = 65535;      // positions fit 16 bits below kCellPadPos
 enum : uint8_t {
@@ -126,9 +128,10 @@ enum : uint8_t {
   CF_MERGE = 8,   // middle child: its contribution is added to the top entry
   CF_PAD = 16,    // padding: identity row
   CF_ROOT = 32,   // cell root: no coupling to a parent
-  CF_MBOUT = 64,  // root of the cut-off half of a cell (lane c < 32): its contribution leaves through
-                  // mailbox c, x of its parent comes back through it
-  CF_MBIN = 128,  // parent of that root (lane c + 32): takes the contribution, returns its x
+  CF_MBOUT = 64,  // root of a cut-off subtree (lane c): its contribution leaves through mailbox c,
+                  // x of its parent comes back through it
+  CF_MBIN = 128,  // parent of such a root: takes the contribution from the next mailbox of its
+                  // lane's source list and returns its x there
 };
 struct KCellWave {
   int64_t chunk_off;  // first chunk of the wave in the pos / flags / scratch tables
@@ -146,6 +149,9 @@ struct CellLanes {
   std::vector<int64_t> base;        // [nwaves*64] first user index of the lane's cell (0: empty)
   std::vector<uint16_t> pos;        // [nchunks*kCellChunkElems] staging order
   std::vector<uint8_t> flags;       // [nchunks*kCellChunkElems] cell-lane order
+  std::vector<uint64_t> mbsrc;      // [nwaves*64] mailbox source lanes in the order the lane's
+                                    // backward sweep takes them (6 bits each), and in the order
+                                    // of its forward sweep << 32; 0 for lanes without takes
 };
 
 // Build the cell-lane tables.  parent / cell_offsets must already be valid.
