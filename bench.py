@@ -14,10 +14,12 @@ Other workloads (``--workload``): ``c3`` the batched implicit-Euler time loop
 captured graph), ``c5`` the adjoint (16,384 cells x 1,000 compartments, 100
 steps, checkpoints every 10), ``scaling`` the paper's comparison of the
 one-thread-per-cell solver with the fine-grained one (Figure 7.1's axes): solve
-time of both kernels on the first 64 ... 65,536 cells of the headline workload.
+time of both kernels on the first 64 ... 65,536 cells of the headline workload,
+``branching`` the same comparison against the branching probability of
+paper-style trees (Figure 7.2's axes).
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: the solve is per cell
-and needs no communication; this build measures one GPU.
+and needs no communication, and the bench measures one GPU.
 """
 from __future__ import annotations
 
@@ -402,12 +404,60 @@ def run_scaling(args, torch, dev):
     }
 
 
+BRANCHING_P = (0.25, 0.5, 0.75, 1.0)
+BRANCHING_CELLS = (4096, 65536)
+
+
+def run_branching(args, torch, dev):
+    """Speed-up of the fine solver (flow kernel, without and with branch
+    splitting) over the old one-lane-per-cell solver against the branching
+    probability of the trees: paper-style trees of 8 levels in which a branch
+    splits in two with probability p on every level and otherwise continues,
+    branches 40 * 0.8^level compartments long."""
+    from workloads import cable_values, grow_level_forest
+    from paper_1810_12742_amd import Plan
+
+    stream = torch.cuda.current_stream()
+    kernels = {"old_cell_lanes": dict(cell_lanes=1), "fine_flow": dict(C2_FLOW_OPTIONS),
+               "fine_flow_split": dict(C2_FLOW_OPTIONS, split_branches=1)}
+    rows = []
+    for pr in BRANCHING_P:
+        for nc in BRANCHING_CELLS:
+            f = grow_level_forest(np.random.default_rng(11), nc, levels=8, p_split=pr)
+            s = cable_values(f, np.random.default_rng(12), a_kind="cable", rhs=True)
+            d, u, b = (torch.from_numpy(a).to(dev) for a in (s.diag, s.upper, s.rhs))
+            x = torch.empty_like(b)
+            row = {"p_split": pr, "ncells": nc, "unknowns": f.n}
+            for name, opts in kernels.items():
+                p = Plan(f.parent, f.cell_offsets, f.branch_offsets, **opts)
+                row[name + "_ms"] = _time(torch, lambda: p.solve(d, u, b, out=x, stream=stream), args.steps,
+                                          args.warmup, stream)
+                p.close()
+            fine = min(row["fine_flow_ms"], row["fine_flow_split_ms"])
+            row["fine_speedup_over_old"] = row["old_cell_lanes_ms"] / fine
+            rows.append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
+            del d, u, b, x
+    last = rows[-1]
+    best = min(last["old_cell_lanes_ms"], last["fine_flow_ms"], last["fine_flow_split_ms"])
+    return {
+        "metric": METRIC, "value": last["unknowns"] / (best * 1e-3), "unit": "unknowns/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": best, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "branching: 8-level trees, split probability p = " +
+                               ", ".join(map(str, BRANCHING_P)) + ", cells = " + ", ".join(map(str, BRANCHING_CELLS)) +
+                               "; value is the fastest kernel on the last row",
+                   "kernels": kernels},
+        "rows": rows,
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("c2", "c3", "c5", "scaling"), default="c2")
+    ap.add_argument("--workload", choices=("c2", "c3", "c5", "scaling", "branching"), default="c2")
     ap.add_argument("--cells", type=int, default=0, help="c3/c5: number of cells (default: the full workload)")
     ap.add_argument("--graph-steps", type=int, default=100, help="c3: time steps per captured graph")
     ap.add_argument("--options", default="", help="c3: plan options as JSON instead of the autotuner's pick")
@@ -426,7 +476,8 @@ def main(argv=None):
     import torch
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    run = {"c2": run_c2, "c3": run_c3, "c5": run_c5, "scaling": run_scaling}[args.workload]
+    run = {"c2": run_c2, "c3": run_c3, "c5": run_c5, "scaling": run_scaling,
+           "branching": run_branching}[args.workload]
     print(json.dumps(run(args, torch, dev)), flush=True)
     return 0
 

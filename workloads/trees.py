@@ -262,6 +262,43 @@ def grow_random_forest(rng: np.random.Generator, ncells: int, *, max_branches=No
     return forest
 
 
+def grow_level_forest(rng: np.random.Generator, ncells: int, *, levels: int, p_split: float,
+                      len0: int = 40, decay: float = 0.8) -> Forest:
+    """Trees shaped like the paper's benchmark networks (§7): every cell has
+    ``levels`` levels of branches; on each level every branch splits into two
+    child branches with probability ``p_split`` and otherwise continues as a
+    single branch on the next level; branches of level l have
+    ``max(1, round(len0 * decay**l))`` compartments, so they get shorter away
+    from the soma.  A full binary tree for ``p_split = 1``, one chain for 0."""
+    lens = np.array([max(1, int(round(len0 * decay ** l))) for l in range(levels)], dtype=np.int64)
+    cell = [np.arange(ncells, dtype=np.int64)]
+    par = [np.full(ncells, -1, dtype=np.int64)]
+    lev = [np.zeros(ncells, dtype=np.int64)]
+    tip_id = np.arange(ncells, dtype=np.int64)
+    tip_cell = np.arange(ncells, dtype=np.int64)
+    nextid = ncells
+    for l in range(1, levels):
+        reps = np.where(rng.random(len(tip_id)) < p_split, 2, 1)
+        new_par = np.repeat(tip_id, reps)
+        new_cell = np.repeat(tip_cell, reps)
+        ids = nextid + np.arange(len(new_par), dtype=np.int64)
+        nextid += len(new_par)
+        cell.append(new_cell)
+        par.append(new_par)
+        lev.append(np.full(len(new_par), l, dtype=np.int64))
+        tip_id, tip_cell = ids, new_cell
+    cell = np.concatenate(cell)
+    par = np.concatenate(par)
+    lev = np.concatenate(lev)
+    nb = len(cell)
+    # creation order inside a level is already breadth first per cell
+    order = np.lexsort((np.arange(nb), lev, cell))
+    rank = np.empty(nb, dtype=np.int64)
+    rank[order] = np.arange(nb)
+    pb = np.where(par[order] >= 0, rank[np.maximum(par[order], 0)], -1)
+    return _layout(cell[order], pb, lens[lev[order]], ncells)
+
+
 def cable_values(forest: Forest, rng: np.random.Generator, *, a_kind: str, dt: float = 0.025,
                  sigma_cm=None, rhs: bool = True) -> CableSystem:
     """Coefficients of the implicit-Euler cable system on ``forest``.
