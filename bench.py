@@ -119,7 +119,8 @@ def cpu_baseline(system, budget_s: float = 12.0):
 def fp32_refine(torch, dev, plan, s, fp64_ms, reps, check):
     """FP32 storage + FP64 refinement on the same cells at each dt: errors
     after 0..3 sweeps against the FP64 solution of the FP32-rounded matrix, and
-    throughput with 3 sweeps against the FP64 solve."""
+    throughput with 3 sweeps against the FP64 solve.  On a cell-lane plan also
+    the FP32-stored matrix eliminated in FP64 (one sweep, no refinement)."""
     import oracle
     f = s.forest
     out = {}
@@ -147,6 +148,14 @@ def fp32_refine(torch, dev, plan, s, fp64_ms, reps, check):
         rec["ms_3_sweeps"] = ms
         rec["unknowns_per_s"] = f.n / (ms * 1e-3)
         rec["speed_vs_fp64"] = fp64_ms / ms
+        if plan.info["kernel"] == 3:
+            st = {}
+            if check:
+                plan.solve_stored32(D, U, b, out=x)
+                st["max_rel_err"] = cell_rel_err(f, x.cpu().numpy(), xs)
+            ms32 = _time(torch, lambda: plan.solve_stored32(D, U, b, out=x, stream=stream), reps, 2, stream)
+            st.update(ms=ms32, unknowns_per_s=f.n / (ms32 * 1e-3), speed_vs_fp64=fp64_ms / ms32)
+            rec["fp32_storage_fp64_elimination"] = st
         out[str(dt)] = rec
         del D, U
     return out

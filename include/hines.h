@@ -177,6 +177,17 @@ hines_status hines_solve(const hines_plan* plan, const double* diag, const doubl
  * so HBM sees 24 bytes per compartment whatever the number of sweeps.
  * HINES_ERR_TOO_BIG if a group does not fit this kernel's LDS image.
  * x may alias rhs.  Async on stream. */
+/* FP32 storage, FP64 elimination (cell-lane plans only).  The matrix is the
+ * FP32 one (diag32, upper32: device float arrays, user numbering); the kernel
+ * widens each entry exactly on load and runs §2's elimination in FP64, so one
+ * sweep solves A x = rhs to FP64 rounding and no refinement is needed: on this
+ * hardware FP64 and FP32 vector arithmetic issue at the same rate, and the
+ * FP32 storage only cuts the bytes of the matrix (24 instead of 32 bytes per
+ * compartment, with rhs and x in FP64).  HINES_ERR_STATE on a plan without
+ * cell lanes.  x may alias rhs.  Async on stream. */
+hines_status hines_solve_stored32(const hines_plan* plan, const float* diag32, const float* upper32,
+                                  const double* rhs, double* x, int32_t ncells, void* stream);
+
 hines_status hines_solve_mixed(const hines_plan* plan, const float* diag32, const float* upper32,
                                const double* rhs, double* x, int32_t sweeps, int32_t ncells, void* stream);
 

@@ -220,14 +220,15 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
       depth.assign(m, 0);
       for (int32_t i = 1; i < m; ++i) depth[i] = depth[parent[lo + i] - lo] + 1;
       // one cut: the subtree closest to m / 2 from below (at least a quarter)
-      std::vector<int32_t> vs;
+      // candidate cuts, preferred first: (subtree roots, span)
+      std::vector<std::pair<std::vector<int32_t>, int64_t>> cands;
       int32_t v = -1;
       for (int32_t i = 1; i < m; ++i)
         if (2 * T.size[i] <= m && (v < 0 || T.size[i] > T.size[v])) v = i;
       int64_t span = m;
       if (v > 0 && 4 * T.size[v] >= m) {
-        vs = {v};
-        span = cut_span(m, vs, (int32_t)lo);
+        cands.push_back({{v}, cut_span(m, {v}, (int32_t)lo)});
+        span = cands.back().second;
       }
       if (span > 2 * split_above) {  // still much longer than the average: the heavy path
         path.assign(1, 0);
@@ -250,13 +251,15 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
             else tl = mid + 1;
           }
           heavy_cut(m, th, pick);
-          if (!pick.empty() && cut_span(m, pick, (int32_t)lo) < span) {
-            vs = pick;
-            span = cut_span(m, vs, (int32_t)lo);
-          }
+          if (!pick.empty() && cut_span(m, pick, (int32_t)lo) < span)
+            cands.insert(cands.begin(), {pick, cut_span(m, pick, (int32_t)lo)});
         }
       }
-      if (!vs.empty()) {
+      // the first candidate whose walks fit the stack and keep every receiver in place
+      for (auto& cand : cands) {
+        if (done) break;
+        std::vector<int32_t> vs = cand.first;
+        span = cand.second;
         // P's forced path: from the root to the deepest receiver; every receiver on it
         int32_t deep = -1;
         for (int32_t x : vs) {

@@ -803,6 +803,25 @@ hines_status hines_solve_mixed(const hines_plan* p, const float* diag32, const f
   return ok();
 }
 
+hines_status hines_solve_stored32(const hines_plan* p, const float* diag32, const float* upper32, const double* rhs,
+                                 double* x, int32_t ncells, void* stream) {
+  hines_status st = check_call(p, ncells);
+  if (st != HINES_OK) return st;
+  if (!p->host.cl.built) return set_err(HINES_ERR_STATE, "hines_solve_stored32 needs a cell-lane plan");
+  if (p->host.n == 0) return ok();
+  if (!diag32 || !upper32 || !rhs || !x) return set_err(HINES_ERR_NULL, "a device array is NULL");
+  if ((const void*)x == (const void*)diag32 || (const void*)x == (const void*)upper32)
+    return set_err(HINES_ERR_STATE, "x must not alias diag or upper");
+  RhsSpec rs{};
+  rs.rhs = rhs;
+  rs.mode = hdev::kRhsGiven;
+  hipLaunchKernelGGL((hdev::k_solve_cells<hdev::kFlowGiven, float>), dim3((unsigned)p->host.cl.nwaves), dim3(64), 0,
+                     (hipStream_t)stream, p->t, rs, diag32, upper32, x);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_err(HINES_ERR_HIP, "launch: %s", hipGetErrorString(e));
+  return ok();
+}
+
 hines_status hines_timestep(const hines_plan* p, const double* diag, const double* upper, const double* c,
                             const double* v_in, double* v_out, const double* i_inj, double noise_sigma,
                             uint32_t noise_seed, uint32_t step, int32_t ncells, void* stream) {

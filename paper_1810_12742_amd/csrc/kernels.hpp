@@ -960,15 +960,16 @@ struct CellBatch {
   double iv[RHS == kFlowCVI ? CK : 1];
 };
 
-template <int RHS>
-__device__ __forceinline__ void cell_load(CellBatch<RHS>& B, const RhsSpec& rs, const double* __restrict__ d,
-                                          const double* __restrict__ u, const int64_t* base, const CellPos& P) {
+// MT: the storage type of the matrix (double, or float widened exactly)
+template <int RHS, typename MT>
+__device__ __forceinline__ void cell_load(CellBatch<RHS>& B, const RhsSpec& rs, const MT* __restrict__ d,
+                                          const MT* __restrict__ u, const int64_t* base, const CellPos& P) {
 #pragma unroll
   for (int r = 0; r < CK; ++r) {
     const unsigned p = cell_pos(P, r);
     const int64_t i = base[r] + (p == hines::kCellPadPos ? 0u : p);
-    B.dv[r] = d[i];
-    B.uv[r] = u[i];
+    B.dv[r] = (double)d[i];
+    B.uv[r] = (double)u[i];
     if constexpr (RHS == kCellFactor) {
       B.bv[r] = 0.0;
     } else if constexpr (RHS == kFlowGiven) {
@@ -1109,9 +1110,11 @@ __device__ __forceinline__ void factor_store(const double2_t* fy, double* F, int
   }
 }
 
-template <int RHS>
-__global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, const double* __restrict__ d,
-                                                    const double* __restrict__ u, double* x) {
+// MT = float: the matrix is stored in FP32 and widened exactly on load; the
+// elimination and everything after it stay in FP64.
+template <int RHS, typename MT = double>
+__global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, const MT* __restrict__ d,
+                                                    const MT* __restrict__ u, double* x) {
   __shared__ __attribute__((aligned(16))) char cl_raw[kCellLds];
   lds_char* lds = (lds_char*)cl_raw;
   const int lane = threadIdx.x;
@@ -1134,7 +1137,7 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
   CellPos P = pos_ld(posv);
   cflag_t fl = flag_ld(flv);
   CellBatch<RHS> B;
-  cell_load<RHS>(B, rs, d, u, base, P);
+  cell_load<RHS, MT>(B, rs, d, u, base, P);
   CellPos Q = pos_ld(posv + PS * min(1, nk - 1));
   double cd = 0.0, cb = 0.0, td = 0.0, tb_ = 0.0;
   int m = 0;
@@ -1159,7 +1162,7 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
     fprev = f;
     if (k + 1 < nk) {
       fl = flag_ld(flv + 64 * (k + 1));
-      cell_load<RHS>(B, rs, d, u, base, Q);
+      cell_load<RHS, MT>(B, rs, d, u, base, Q);
       P = Q;
       Q = pos_ld(posv + PS * min(k + 2, nk - 1));
     }

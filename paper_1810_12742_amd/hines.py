@@ -76,6 +76,7 @@ def load():
     U32, D = ctypes.c_uint32, ctypes.c_double
     lib.hines_timestep.argtypes = [P, P, P, P, P, P, P, D, U32, U32, I32, P]
     lib.hines_solve_mixed.argtypes = [P, P, P, P, P, I32, I32, P]
+    lib.hines_solve_stored32.argtypes = [P, P, P, P, P, I32, P]
     lib.hines_timeloop_create.argtypes = [P, P, P, P, P, P, D, U32, U32, I32, I32, ctypes.POINTER(P)]
     lib.hines_timeloop_launch.argtypes = [P, P]
     lib.hines_timeloop_destroy.argtypes = [P]
@@ -83,7 +84,8 @@ def load():
     lib.hines_gather_roots.argtypes = [P, P, P, P]
     lib.hines_adjoint_rhs.argtypes = [P, P, P, P, P, P]
     lib.hines_adjoint_accumulate.argtypes = [P, P, P, P, P, P, P, P]
-    for name in ("hines_setup", "hines_solve", "hines_solve_mixed", "hines_plan_info_get", "hines_get_table",
+    for name in ("hines_setup", "hines_solve", "hines_solve_mixed", "hines_solve_stored32", "hines_plan_info_get",
+                 "hines_get_table",
                  "hines_destroy",
                  "hines_timestep", "hines_timeloop_create", "hines_timeloop_launch", "hines_timeloop_destroy",
                  "hines_assemble", "hines_gather_roots", "hines_adjoint_rhs", "hines_adjoint_accumulate"):
@@ -199,6 +201,20 @@ class Plan:
                                         _dev(rhs, self.n, torch.float64, "rhs"),
                                         _dev(out, self.n, torch.float64, "out"), int(sweeps), self.ncells,
                                         ctypes.c_void_p(st.cuda_stream)))
+        return out
+
+    def solve_stored32(self, diag32, upper32, rhs, out=None, stream=None):
+        """FP32-stored matrix, FP64 elimination on a cell-lane plan
+        (``hines_solve_stored32``); returns ``out``."""
+        import torch
+        if out is None:
+            out = torch.empty_like(rhs)
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(load().hines_solve_stored32(self._h, _dev(diag32, self.n, torch.float32, "diag32"),
+                                           _dev(upper32, self.n, torch.float32, "upper32"),
+                                           _dev(rhs, self.n, torch.float64, "rhs"),
+                                           _dev(out, self.n, torch.float64, "out"), self.ncells,
+                                           ctypes.c_void_p(st.cuda_stream)))
         return out
 
     # ---- time loop (paper §1: one implicit-Euler system per step) ----------

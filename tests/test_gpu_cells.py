@@ -54,6 +54,37 @@ def test_c2_slice(torch_dev):
     assert np.array_equal(x1, x2)
 
 
+def test_fp32_storage_fp64_elimination(torch_dev):
+    """hines_solve_stored32: the FP32 matrix widened on load and eliminated in
+    FP64 equals the oracle's FP64 solve of the widened matrix to 1e-12, in
+    place too; a plan without cell lanes is refused."""
+    torch, dev = torch_dev
+    from paper_1810_12742_amd import Plan
+    from paper_1810_12742_amd.hines import HinesError
+    s = configs.c2(1536)
+    f = s.forest
+    print("cells: fp32 storage", flush=True)
+    d32 = s.diag.astype(np.float32)
+    u32 = s.upper.astype(np.float32)
+    xo = oracle.solve(f, d32.astype(np.float64), u32.astype(np.float64), s.rhs)
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets, cell_lanes=1)
+    D = torch.from_numpy(d32).to(dev)
+    U = torch.from_numpy(u32).to(dev)
+    b = torch.from_numpy(s.rhs).to(dev)
+    x = p.solve_stored32(D, U, b)
+    torch.cuda.synchronize()
+    x1 = x.cpu().numpy()
+    assert cell_rel_err(f, x1, xo) <= TOL
+    p.solve_stored32(D, U, b, out=b)
+    torch.cuda.synchronize()
+    assert np.array_equal(b.cpu().numpy(), x1)
+    p.close()
+    g = Plan(f.parent, f.cell_offsets, f.branch_offsets)
+    with pytest.raises(HinesError):
+        g.solve_stored32(D, U, torch.from_numpy(s.rhs).to(dev))
+    g.close()
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 def test_bushy_trees_and_ragged_waves(torch_dev, seed):
     """Up to 6 children per compartment (middle-child merges, deeper stacks);
