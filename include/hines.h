@@ -175,7 +175,9 @@ hines_status hines_solve(const hines_plan* plan, const double* diag, const doubl
  * forms r = rhs - A x in FP64, solves A d = fl32(r) in FP32 and adds d to x
  * in FP64.  The group's matrix, rhs and solution stay in LDS across sweeps,
  * so HBM sees 24 bytes per compartment whatever the number of sweeps.
- * HINES_ERR_TOO_BIG if a group does not fit this kernel's LDS image.
+ * HINES_ERR_TOO_BIG if a group does not fit this kernel's LDS image (or, on a
+ * cell-lane plan, the groups' 16-bit branch records: a cell-lane plan is
+ * still built then, and only this call is refused).
  * x may alias rhs.  Async on stream. */
 /* FP32 storage, FP64 elimination (cell-lane plans only).  The matrix is the
  * FP32 one (diag32, upper32: device float arrays, user numbering); the kernel
@@ -216,7 +218,8 @@ hines_status hines_timestep(const hines_plan* plan, const double* diag, const do
  * current and v into the lanes' walk order, runs the nsteps right-hand-side
  * sweeps there and writes v back in user order at the end: the result equals
  * nsteps hines_timestep calls bit for bit.  HINES_ERR_OOM if that allocation
- * fails; hines_timeloop_destroy frees it. */
+ * fails; hines_timeloop_destroy frees it.  On a plan with no compartments the
+ * loop holds no graph and its launch does nothing (the arrays may be NULL). */
 hines_status hines_timeloop_create(const hines_plan* plan, const double* diag, const double* upper,
                                    const double* c, double* v, const double* i_inj, double noise_sigma,
                                    uint32_t noise_seed, uint32_t first_step, int32_t nsteps, int32_t ncells,

@@ -596,9 +596,16 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
     }
   }
   bool capacity = false;
+  bool groups_usable = true;
   if (!o.host_only && !check_kernel_tables(p->host, why, capacity)) {
-    delete p;
-    return set_err(capacity ? HINES_ERR_TOO_BIG : HINES_ERR_STATE, "kernel tables: %s", why.c_str());
+    if (o.cell_lanes && capacity) {
+      // the cell-lane kernels never read the group tables; only the groups'
+      // FP32+refinement solve needs them, and it is refused on this plan
+      groups_usable = false;
+    } else {
+      delete p;
+      return set_err(capacity ? HINES_ERR_TOO_BIG : HINES_ERR_STATE, "kernel tables: %s", why.c_str());
+    }
   }
   const hines::HostPlan& P = p->host;
   // buckets by LDS footprint and kernel: flow groups, level-synchronous LDS
@@ -637,7 +644,7 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   // buckets of the FP32+refinement kernel (its LDS image holds 32 bytes per slot)
   {
     std::vector<std::vector<int32_t>> mm(nbk);
-    p->mixed_ok = true;
+    p->mixed_ok = groups_usable;
     for (int64_t g = 0; g < P.ngroups && p->mixed_ok; ++g) {
       const int64_t bytes = hdev::mixed_layout(P.kgroup[g]).bytes();
       int k = 0;
@@ -795,7 +802,8 @@ hines_status hines_solve_mixed(const hines_plan* p, const float* diag32, const f
   if (sweeps < 0 || sweeps > 8) return set_err(HINES_ERR_OPTION, "sweeps must be in [0, 8]");
   if (p->host.n == 0) return ok();
   if (!diag32 || !upper32 || !rhs || !x) return set_err(HINES_ERR_NULL, "a device array is NULL");
-  if (!p->mixed_ok) return set_err(HINES_ERR_TOO_BIG, "a group does not fit the FP32+refinement LDS image");
+  if (!p->mixed_ok)
+    return set_err(HINES_ERR_TOO_BIG, "a group does not fit the FP32+refinement LDS image or the branch records");
   if ((const void*)x == (const void*)diag32 || (const void*)x == (const void*)upper32)
     return set_err(HINES_ERR_STATE, "x must not alias diag or upper");
   hipError_t e = launch_mixed(p, diag32, upper32, rhs, x, sweeps, (hipStream_t)stream);
@@ -851,6 +859,12 @@ hines_status hines_timeloop_create(const hines_plan* p, const double* diag, cons
   hines_status st = check_call(p, ncells);
   if (st != HINES_OK) return st;
   if (nsteps < 1) return set_err(HINES_ERR_OPTION, "nsteps must be >= 1");
+  if (p->host.n == 0) {  // nothing to step: a loop without a graph, launch does nothing
+    *out = new (std::nothrow) hines_timeloop();
+    if (!*out) return set_err(HINES_ERR_OOM, "host allocation failed");
+    (*out)->nsteps = nsteps;
+    return ok();
+  }
   if (!diag || !upper || !c || !v) return set_err(HINES_ERR_NULL, "a device array is NULL");
   const void* vo = v;
   if (vo == diag || vo == upper || vo == c || (i_inj && vo == i_inj))
@@ -940,6 +954,7 @@ hines_status hines_timeloop_create(const hines_plan* p, const double* diag, cons
 
 hines_status hines_timeloop_launch(hines_timeloop* tl, void* stream) {
   if (!tl) return set_err(HINES_ERR_NULL, "time loop is NULL");
+  if (!tl->exec) return ok();  // empty plan
   hipError_t e = hipGraphLaunch(tl->exec, (hipStream_t)stream);
   if (e != hipSuccess) return set_err(HINES_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
   return ok();

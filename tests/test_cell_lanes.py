@@ -385,3 +385,26 @@ def test_heavy_path_cut_into_four_lanes():
     assert len(lists) == 1 and lists[0] >> 12 != 0 and lists[0] >> 18 == 0  # three takes
     K = chunk_steps(p)
     assert 2250 <= p.info["max_makespan"] * K < 2250 + K
+
+
+def test_largest_cell_and_single_compartment_cells():
+    """A cell of kCellMaxSize = 65,535 compartments among small ones is cut
+    over several lanes and replays to the oracle; so do 100 one-compartment
+    cells (every lane a lone tip that is also its cell's root); one more
+    compartment is refused."""
+    from paper_1810_12742_amd import HinesError, Plan
+    from workloads import Forest, cable_values, grow_random_forest
+    rng = np.random.default_rng(30)
+    sizes = np.r_[65535, np.full(40, 300)]
+    f = grow_random_forest(rng, len(sizes), target_size=sizes)
+    s = cable_values(f, np.random.default_rng(31), a_kind="cable", rhs=False)
+    p = _check(f, s.diag, s.upper)
+    assert np.count_nonzero(p.table("cell_lanes") == 0) >= 2
+    one = Forest(np.full(100, -1, dtype=np.int32), np.arange(101, dtype=np.int64), None)
+    s1 = cable_values(one, np.random.default_rng(2), a_kind="uniform", rhs=False)
+    p1 = _check(one, s1.diag, s1.upper)
+    fl = p1.table("cell_flags")
+    real = fl[(fl & PAD) == 0]
+    assert real.size == 100 and np.all(real == (TIP | ROOT))
+    with pytest.raises(HinesError):
+        Plan(np.r_[-1, np.arange(65535)].astype(np.int32), np.array([0, 65536]), None, host_only=1, cell_lanes=1)

@@ -185,3 +185,49 @@ def test_factored_time_loop_with_noise(torch_dev):
     loop.close()
     loop2.close()
     p.close()
+
+
+def test_edge_cases_empty_single_compartments_and_largest_cell(torch_dev):
+    """An empty forest (solve, time step, time loop, FP32 storage: nothing to
+    do); 100 one-compartment cells; a cell of 65,535 compartments (the
+    largest a cell lane takes, cut over several lanes) among 40 small ones.
+    Solves and a kept-factor loop of 3 steps against the oracle."""
+    torch, dev = torch_dev
+    from paper_1810_12742_amd import Plan
+    from workloads import Forest, cable_values, grow_random_forest
+    print("cells: empty forest", flush=True)
+    pe = Plan(np.zeros(0, dtype=np.int32), np.zeros(1, dtype=np.int64), None, cell_lanes=1)
+    e = torch.zeros(0, dtype=torch.float64, device=dev)
+    e32 = torch.zeros(0, dtype=torch.float32, device=dev)
+    pe.solve(e, e, e, out=e)
+    pe.timestep(e, e, e, e, e, noise_sigma=0.1, noise_seed=1)
+    pe.solve_stored32(e32, e32, e, out=e)
+    le = pe.timeloop(e, e, e, e, 3, noise_sigma=0.1, noise_seed=1)
+    le.launch()
+    torch.cuda.synchronize()
+    le.close()
+    pe.close()
+    singles = Forest(np.full(100, -1, dtype=np.int32), np.arange(101, dtype=np.int64), np.arange(101, dtype=np.int64))
+    rng = np.random.default_rng(30)
+    sizes = np.r_[65535, np.full(40, 300)]
+    big = grow_random_forest(rng, len(sizes), target_size=sizes)
+    for name, f in (("singles", singles), ("largest cell", big)):
+        print(f"cells: {name}", flush=True)
+        s = cable_values(f, np.random.default_rng(31), a_kind="cable", rhs=True)
+        p = Plan(f.parent, f.cell_offsets, f.branch_offsets, cell_lanes=1)
+        d, u, c, b = (torch.from_numpy(a).to(dev) for a in (s.diag, s.upper, s.c, s.rhs))
+        x = p.solve(d, u, b)
+        torch.cuda.synchronize()
+        assert cell_rel_err(f, x.cpu().numpy(), oracle.solve(f, s.diag, s.upper, s.rhs)) <= TOL
+        V = torch.zeros(f.n, dtype=torch.float64, device=dev)
+        loop = p.timeloop(d, u, c, V, 3, noise_sigma=0.1, noise_seed=4)
+        loop.launch()
+        torch.cuda.synchronize()
+        Vo = oracle.timeloop(f, s.diag, s.upper, s.c, 3, noise_seed=4, noise_sigma=0.1)
+        assert cell_rel_err(f, V.cpu().numpy(), Vo) <= TOL
+        loop.close()
+        if name == "largest cell":  # its groups exceed the 16-bit branch records: only the FP32+refinement solve refuses
+            from paper_1810_12742_amd.hines import HinesError
+            with pytest.raises(HinesError):
+                p.solve_mixed(d.float(), u.float(), b)
+        p.close()
