@@ -217,8 +217,9 @@ hines_status hines_timestep(const hines_plan* plan, const double* diag, const do
  * launch factors A once (f = u / d' and 1 / d' per compartment), moves c, the
  * current and v into the lanes' walk order, runs the nsteps right-hand-side
  * sweeps there and writes v back in user order at the end: the result equals
- * nsteps hines_timestep calls bit for bit.  HINES_ERR_OOM if that allocation
- * fails; hines_timeloop_destroy frees it.  On a plan with no compartments the
+ * nsteps hines_timestep calls bit for bit.  If that allocation fails, the
+ * loop captures nsteps plain hines_timestep launches instead (same results);
+ * hines_timeloop_destroy frees what was allocated.  On a plan with no compartments the
  * loop holds no graph and its launch does nothing (the arrays may be NULL). */
 hines_status hines_timeloop_create(const hines_plan* plan, const double* diag, const double* upper,
                                    const double* c, double* v, const double* i_inj, double noise_sigma,

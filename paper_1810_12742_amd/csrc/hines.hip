@@ -874,18 +874,20 @@ hines_status hines_timeloop_create(const hines_plan* p, const double* diag, cons
   const bool noise = i_inj == nullptr && noise_sigma != 0.0;
   // cell-lane plans keep the factors: per launch, factor A and move c, the
   // current and V into the walk layout; K steps there; V back at the end
-  const bool factored = p->host.cl.built && p->host.n > 0;
+  bool factored = p->host.cl.built && p->host.n > 0;
   hdev::CellLoop L{};
   if (factored) {
     const int64_t S = p->t.cslots;
     // f, 1 / d', c, the current, V; positions for the draws
     const int64_t bytes = 8 * S * (i_inj ? 5 : 4) + (noise ? 2 * S : 0) + 256;
-    hipError_t ea = hipMalloc(&tl->mem, bytes);
-    if (ea != hipSuccess) {
+    if (hipMalloc(&tl->mem, bytes) != hipSuccess) {
+      (void)hipGetLastError();  // no room for the factors: capture the plain steps instead
       tl->mem = nullptr;
-      delete tl;
-      return set_err(HINES_ERR_OOM, "hipMalloc(%lld) for the time loop: %s", (long long)bytes, hipGetErrorString(ea));
+      factored = false;
     }
+  }
+  if (factored) {
+    const int64_t S = p->t.cslots;
     double* m = (double*)tl->mem;
     L.f = m;
     L.r = m + S;
