@@ -9,8 +9,8 @@ simulation that sets up the same cells again reuses the choice.
 
 The candidates cover the knobs of paper §4-§6 that change the kernel tables:
 the cap on compartments per group (LDS image size, hence occupancy), branch
-splitting, cell order for packing, and the kernel (static lane schedule or
-level-synchronous sweeps).
+splitting, cell order for packing, and the kernel (static lane schedule,
+level-synchronous sweeps, or one lane per cell, which wins on large networks).
 """
 from __future__ import annotations
 
@@ -26,7 +26,7 @@ DEFAULT_CANDIDATES = [
     for sp in (0, 1)
     for co in (0, 1)
     for ls in (0, 1)
-]
+] + [dict(cell_lanes=1)]
 
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "hines_mi355x_autotune.json")
 
