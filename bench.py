@@ -282,6 +282,28 @@ def run_c3(args, torch, dev):
     loop = plan.timeloop(d, u, c, V, K, first_step=1, noise_sigma=0.1, noise_seed=3)
     stream = torch.cuda.current_stream()
     ms = _time(torch, loop.launch, args.steps, args.warmup, stream)
+    assembled = None
+    if plan.info["kernel"] == 3:
+        # a step whose diagonal changes (linearised current g (V - E)): the
+        # matrix assembled inside the solve against hines_assemble + a step
+        rng = np.random.default_rng(5)
+        g = torch.from_numpy(rng.uniform(0.0, 1.0, f.n)).to(dev)
+        ge = torch.from_numpy(-65.0 * rng.uniform(0.0, 1.0, f.n)).to(dev)
+        a = -u
+        cg = c + g
+        d2, u2 = torch.empty_like(c), torch.empty_like(c)
+        Vs = torch.zeros_like(c)
+        fused = _time(torch, lambda: plan.timestep_assembled(g, u, c, ge, Vs, Vs, stream=stream), max(3, args.steps),
+                      1, stream)
+
+        def two_kernels():
+            plan.assemble(a, cg, d2, u2, stream=stream)
+            plan.timestep(d2, u2, c, Vs, Vs, i_inj=ge, stream=stream)
+
+        unfused = _time(torch, two_kernels, max(3, args.steps), 1, stream)
+        assembled = {"fused_ms": fused, "assemble_then_step_ms": unfused, "speedup": unfused / fused,
+                     "bytes_per_unknown": {"fused": 48, "assemble_then_step": 80}}
+        del g, ge, a, cg, d2, u2, Vs
     n = f.n
     # read d, u, c, V; write V (a cell-lane plan factors A once per graph launch
     # and then reads the pair (f, 1/d') in place of (d, u): the same 40 bytes)
@@ -301,6 +323,7 @@ def run_c3(args, torch, dev):
                      "kernel": {3: "k_cells_step", 1: "k_solve_flow"}.get(plan.info["kernel"], "k_solve_level"),
                      "bytes_per_step": bytes_per_step},
         "charge_conservation_max_rel_err_step0": check,
+        "assembled_step": assembled,
     }
     loop.close()
     plan.close()

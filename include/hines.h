@@ -207,6 +207,21 @@ hines_status hines_timestep(const hines_plan* plan, const double* diag, const do
                             const double* v_in, double* v_out, const double* i_inj, double noise_sigma,
                             uint32_t noise_seed, uint32_t step, int32_t ncells, void* stream);
 
+/* One implicit-Euler step whose matrix is assembled in the solve (paper §1:
+ * the discrete cable equation, diagonal = capacitive term plus the
+ * conductances meeting at the compartment), for models whose diagonal
+ * changes every step through a linearised membrane current g (V - E):
+ *     A v_out = c * v_in + ge,
+ *     A_ii = c_i + g_i + a_i + sum_{k: parent[k] = i} a_k,   A_{i,parent(i)} = -a_i,
+ * with the edge conductances given as upper = -a (upper[root] is ignored, as
+ * in hines_solve), g and ge = g * E per compartment (device arrays, user
+ * numbering).  The diagonal is formed while the cell-lane kernel eliminates,
+ * so no diag array is written or read.  Cell-lane plans only
+ * (HINES_ERR_STATE otherwise).  v_out may alias v_in.  Async on stream. */
+hines_status hines_timestep_assembled(const hines_plan* plan, const double* g, const double* upper, const double* c,
+                                      const double* ge, const double* v_in, double* v_out, int32_t ncells,
+                                      void* stream);
+
 /* Capture nsteps consecutive hines_timestep calls, updating v in place with
  * steps first_step .. first_step + nsteps - 1, into a HIP graph (captured on
  * a private stream; nothing runs during creation).  Each

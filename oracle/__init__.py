@@ -155,6 +155,19 @@ def timeloop(forest, diag, upper, c, steps: int, *, V0=None, I_const=None, noise
     return (V, hist) if keep_all else V
 
 
+def timestep_assembled(forest, upper, c, g, ge, v, nthreads: int = 0):
+    """One implicit-Euler step with a linearised membrane current (paper §1):
+    the diagonal is the capacitive term plus g plus the conductances of every
+    edge meeting the compartment (a = -upper, none above a root); the right-
+    hand side is c v + g E, given as ``ge``.  Returns A^-1 (c v + ge)."""
+    par = np.asarray(forest.parent)
+    nonroot = par >= 0
+    a = np.where(nonroot, -np.asarray(upper, dtype=np.float64), 0.0)
+    diag = np.asarray(c, dtype=np.float64) + np.asarray(g, dtype=np.float64) + a
+    diag = diag + np.bincount(par[nonroot], weights=a[nonroot], minlength=forest.n)
+    return solve(forest, diag, np.where(nonroot, upper, 0.0), np.asarray(c) * np.asarray(v) + np.asarray(ge), nthreads)
+
+
 def refine(forest, diag32, upper32, rhs, sweeps: int = 3, nthreads: int = 0):
     """FP32 solves with FP64 residuals and FP64 accumulation.
 

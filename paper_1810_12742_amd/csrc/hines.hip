@@ -830,6 +830,28 @@ hines_status hines_solve_stored32(const hines_plan* p, const float* diag32, cons
   return ok();
 }
 
+hines_status hines_timestep_assembled(const hines_plan* p, const double* g, const double* upper, const double* c,
+                                     const double* ge, const double* v_in, double* v_out, int32_t ncells,
+                                     void* stream) {
+  hines_status st = check_call(p, ncells);
+  if (st != HINES_OK) return st;
+  if (!p->host.cl.built) return set_err(HINES_ERR_STATE, "hines_timestep_assembled needs a cell-lane plan");
+  if (p->host.n == 0) return ok();
+  if (!g || !upper || !c || !ge || !v_in || !v_out) return set_err(HINES_ERR_NULL, "a device array is NULL");
+  const void* o = v_out;
+  if (o == g || o == upper || o == c || o == ge) return set_err(HINES_ERR_STATE, "v_out may alias only v_in");
+  RhsSpec rs{};
+  rs.c = c;
+  rs.v = v_in;
+  rs.icur = ge;
+  rs.mode = hdev::kRhsCV;
+  hipLaunchKernelGGL((hdev::k_solve_cells<hdev::kCellCond, double>), dim3((unsigned)p->host.cl.nwaves), dim3(64), 0,
+                     (hipStream_t)stream, p->t, rs, g, upper, v_out);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_err(HINES_ERR_HIP, "launch: %s", hipGetErrorString(e));
+  return ok();
+}
+
 hines_status hines_timestep(const hines_plan* p, const double* diag, const double* upper, const double* c,
                             const double* v_in, double* v_out, const double* i_inj, double noise_sigma,
                             uint32_t noise_seed, uint32_t step, int32_t ncells, void* stream) {

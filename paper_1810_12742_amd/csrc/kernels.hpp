@@ -608,6 +608,12 @@ __device__ __forceinline__ void lds_add(lds_f64* p, double v) {
 enum : int { kFlowGiven = 0, kFlowCV = 1, kFlowCVI = 2, kFlowNoise = 3 };
 // Cell-lane kernel only: eliminate the matrix alone and keep its factors.
 enum : int { kCellFactor = 4 };
+// kCellCond: the step of a model whose diagonal changes every step (a
+// linearised membrane current g V - g E): the kernel assembles
+// d_i = c_i + g_i + a_i + sum over children a_k from the edge conductances
+// a = -u (paper §1) while it eliminates, with b = c v + g E.  The d argument
+// carries g and rs.icur carries g E.
+enum : int { kCellCond = 5 };
 
 // Element e of a user range (user index lo + e) -> its position.  A lane
 // handles elements lane, lane + 64, ...; the loads of kStageUnroll of them are
@@ -957,7 +963,7 @@ template <int RHS>
 struct CellBatch {
   double dv[CK], uv[CK], bv[CK];
   double cv[(RHS == kFlowGiven || RHS == kCellFactor) ? 1 : CK];
-  double iv[RHS == kFlowCVI ? CK : 1];
+  double iv[(RHS == kFlowCVI || RHS == kCellCond) ? CK : 1];
 };
 
 // MT: the storage type of the matrix (double, or float widened exactly)
@@ -977,7 +983,7 @@ __device__ __forceinline__ void cell_load(CellBatch<RHS>& B, const RhsSpec& rs, 
     } else {
       B.cv[r] = rs.c[i];
       B.bv[r] = rs.v[i];
-      if constexpr (RHS == kFlowCVI) B.iv[r] = rs.icur[i];
+      if constexpr (RHS == kFlowCVI || RHS == kCellCond) B.iv[r] = rs.icur[i];
     }
   }
 }
@@ -995,11 +1001,13 @@ __device__ __forceinline__ void cell_put(const CellBatch<RHS>& B, const RhsSpec&
     const unsigned p = cell_pos(P, r);
     double b = B.bv[r];
     if constexpr (RHS != kFlowGiven && RHS != kCellFactor) b = B.cv[r] * B.bv[r];
-    if constexpr (RHS == kFlowCVI) b = b + B.iv[r];
+    if constexpr (RHS == kFlowCVI || RHS == kCellCond) b = b + B.iv[r];
     if constexpr (RHS == kFlowNoise)
       b = b + noise_draw(rs.seed, rs.step, (uint64_t)(base[r] + (p == hines::kCellPadPos ? 0u : p)), rs.sigma);
     const double uu = (p == 0u || p == hines::kCellPadPos) ? 0.0 : B.uv[r];
-    *(lds_d2*)(lds + e * kCellRowDU + c * 16) = double2_t{B.dv[r], uu};
+    double dd = B.dv[r];
+    if constexpr (RHS == kCellCond) dd = (B.cv[r] + dd) - uu;  // c + g + a of the edge to the parent
+    *(lds_d2*)(lds + e * kCellRowDU + c * 16) = double2_t{dd, uu};
     *(lds_f64*)(lds + kCellLdsB + e * kCellRowB + c * 8) = b;
   }
 }
@@ -1009,7 +1017,9 @@ __device__ __forceinline__ void cell_put(const CellBatch<RHS>& B, const RhsSpec&
 // msrc: the lane's source list, the next take in its low 6 bits.
 // FACTOR: keep (f, 1 / d') instead of (f, y).  The contribution to the parent
 // is (u f, f b'), the same products a solve with stored factors forms.
-template <bool FACTOR = false>
+// COND: the parent's diagonal also takes the child's edge conductance a = -u,
+// so the diagonal contribution is u f + u.
+template <bool FACTOR = false, bool COND = false>
 __device__ __forceinline__ void cell_backward(const cflag_t& f, const lds_d2* pdu, const lds_f64* pb, lds_d2* stk,
                                               lds_d2* mb, int lane, double& cd, double& cb, double& td, double& tb,
                                               int& m, double2_t* fy, unsigned& msrc) {
@@ -1038,7 +1048,7 @@ __device__ __forceinline__ void cell_backward(const cflag_t& f, const lds_d2* pd
     }
     const double rr = rcp_nr(dd);
     const double fv = uu * rr, yv = bb * rr;
-    cd = uu * fv;
+    cd = COND ? __builtin_fma(uu, fv, uu) : uu * fv;
     cb = fv * bb;
     if (fe & hines::CF_PUSH) {
       stk[64 * m] = double2_t{td, tb};
@@ -1166,7 +1176,7 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
       P = Q;
       Q = pos_ld(posv + PS * min(k + 2, nk - 1));
     }
-    cell_backward<RHS == kCellFactor>(f, pdu, pb, stk, mb, lane, cd, cb, td, tb_, m, fy, msb);
+    cell_backward<RHS == kCellFactor, RHS == kCellCond>(f, pdu, pb, stk, mb, lane, cd, cb, td, tb_, m, fy, msb);
   }
   if constexpr (RHS == kCellFactor) {  // the last chunk's factors
     factor_store(fy, x, tb.cslots, W.chunk_off + nk - 1, lane);

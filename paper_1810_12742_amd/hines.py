@@ -77,6 +77,7 @@ def load():
     lib.hines_timestep.argtypes = [P, P, P, P, P, P, P, D, U32, U32, I32, P]
     lib.hines_solve_mixed.argtypes = [P, P, P, P, P, I32, I32, P]
     lib.hines_solve_stored32.argtypes = [P, P, P, P, P, I32, P]
+    lib.hines_timestep_assembled.argtypes = [P, P, P, P, P, P, P, I32, P]
     lib.hines_timeloop_create.argtypes = [P, P, P, P, P, P, D, U32, U32, I32, I32, ctypes.POINTER(P)]
     lib.hines_timeloop_launch.argtypes = [P, P]
     lib.hines_timeloop_destroy.argtypes = [P]
@@ -84,7 +85,8 @@ def load():
     lib.hines_gather_roots.argtypes = [P, P, P, P]
     lib.hines_adjoint_rhs.argtypes = [P, P, P, P, P, P]
     lib.hines_adjoint_accumulate.argtypes = [P, P, P, P, P, P, P, P]
-    for name in ("hines_setup", "hines_solve", "hines_solve_mixed", "hines_solve_stored32", "hines_plan_info_get",
+    for name in ("hines_setup", "hines_solve", "hines_solve_mixed", "hines_solve_stored32", "hines_timestep_assembled",
+                 "hines_plan_info_get",
                  "hines_get_table",
                  "hines_destroy",
                  "hines_timestep", "hines_timeloop_create", "hines_timeloop_launch", "hines_timeloop_destroy",
@@ -216,6 +218,20 @@ class Plan:
                                            _dev(out, self.n, torch.float64, "out"), self.ncells,
                                            ctypes.c_void_p(st.cuda_stream)))
         return out
+
+    def timestep_assembled(self, g, upper, c, ge, v_in, v_out=None, stream=None):
+        """v_out = A^-1 (c v_in + ge) with A assembled from upper = -a, c and g in
+        the solve (``hines_timestep_assembled``, cell-lane plans); v_out may be v_in."""
+        import torch
+        if v_out is None:
+            v_out = torch.empty_like(v_in)
+        st = stream if stream is not None else torch.cuda.current_stream()
+        f64 = torch.float64
+        _check(load().hines_timestep_assembled(
+            self._h, _dev(g, self.n, f64, "g"), _dev(upper, self.n, f64, "upper"), _dev(c, self.n, f64, "c"),
+            _dev(ge, self.n, f64, "ge"), _dev(v_in, self.n, f64, "v_in"), _dev(v_out, self.n, f64, "v_out"),
+            self.ncells, ctypes.c_void_p(st.cuda_stream)))
+        return v_out
 
     # ---- time loop (paper §1: one implicit-Euler system per step) ----------
     def timestep(self, diag, upper, c, v_in, v_out=None, i_inj=None, noise_sigma=0.0, noise_seed=0, step=0,

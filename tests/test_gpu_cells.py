@@ -231,3 +231,41 @@ def test_edge_cases_empty_single_compartments_and_largest_cell(torch_dev):
             with pytest.raises(HinesError):
                 p.solve_mixed(d.float(), u.float(), b)
         p.close()
+
+
+@pytest.mark.parametrize("which", ["c3", "bushy"])
+def test_assembled_step(torch_dev, which):
+    """hines_timestep_assembled: the diagonal c + g + incident edge
+    conductances formed inside the cell-lane solve equals the oracle's
+    assembled step to 1e-12 (cells cut over several lanes included), in place
+    too; a plan without cell lanes is refused."""
+    torch, dev = torch_dev
+    from paper_1810_12742_amd import Plan
+    from paper_1810_12742_amd.hines import HinesError
+    if which == "c3":
+        s = configs.c3(300, seed=7)
+        f, upper = s.forest, s.upper
+    else:
+        f, _, upper = bushy_system(90, 3)
+    print(f"cells: assembled step {which}", flush=True)
+    rng = np.random.default_rng(17)
+    n = f.n
+    c = rng.uniform(0.1, 1.0, n)
+    g = rng.uniform(0.0, 3.0, n)
+    ge = rng.standard_normal(n)
+    v = rng.standard_normal(n)
+    want = oracle.timestep_assembled(f, upper, c, g, ge, v)
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets, cell_lanes=1)
+    G, U, C, GE, V = (torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (g, upper, c, ge, v))
+    out = p.timestep_assembled(G, U, C, GE, V)
+    torch.cuda.synchronize()
+    x1 = out.cpu().numpy()
+    assert cell_rel_err(f, x1, want) <= TOL
+    p.timestep_assembled(G, U, C, GE, V, V)
+    torch.cuda.synchronize()
+    assert np.array_equal(V.cpu().numpy(), x1)
+    p.close()
+    q = Plan(f.parent, f.cell_offsets, f.branch_offsets)
+    with pytest.raises(HinesError):
+        q.timestep_assembled(G, U, C, GE, V, V)
+    q.close()

@@ -148,3 +148,29 @@ def test_adjoint_vs_central_differences():
             fd = (L(h) - L(-h)) / (2 * h)
             g = {"a": ga, "c": gc, "I": gI}[kind][i]
             assert abs(fd - g) <= 1e-5 * max(abs(g), 1e-3), (kind, i, fd, g)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_assembled_step_vs_dense_matrix_from_edges(seed):
+    """The assembled step against a dense matrix built edge by edge from the
+    cable equation's definition (each edge adds a to both diagonal ends and
+    -a off the diagonal; c + g on the diagonal), solved by LAPACK; the value
+    stored at a root's upper entry plays no part."""
+    rng = np.random.default_rng(seed)
+    f = configs.random_system(6, seed).forest
+    n = f.n
+    a = rng.uniform(0.1, 2.0, n)
+    upper = -a
+    upper[f.parent < 0] = 123.0  # ignored
+    c, g = rng.uniform(0.1, 1.0, n), rng.uniform(0.0, 3.0, n)
+    ge, v = rng.standard_normal(n), rng.standard_normal(n)
+    A = np.diag(c + g)
+    for i in range(n):
+        p = f.parent[i]
+        if p >= 0:
+            A[i, i] += a[i]
+            A[p, p] += a[i]
+            A[i, p] = A[p, i] = -a[i]
+    want = np.linalg.solve(A, c * v + ge)
+    got = oracle.timestep_assembled(f, upper, c, g, ge, v)
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-13)
