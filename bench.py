@@ -340,7 +340,8 @@ def run_c5(args, torch, dev):
     f = s.forest
     steps = s.meta["steps"]
     every = s.meta["checkpoint_every"]
-    plan = Plan(f.parent, f.cell_offsets, f.branch_offsets)
+    opts = json.loads(args.options) if args.options else {}
+    plan = Plan(f.parent, f.cell_offsets, f.branch_offsets, **opts)
     a = torch.from_numpy(s.a).to(dev).requires_grad_(True)
     c = torch.from_numpy(s.c).to(dev).requires_grad_(True)
     I = torch.from_numpy(s.meta["I"]).to(dev).requires_grad_(True)
@@ -385,7 +386,7 @@ def run_c5(args, torch, dev):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"c5: {f.ncells} cells x ~1000 compartments, {steps} implicit-Euler steps, "
                                f"loss sum (V_soma - target)^2, checkpoints every {every}",
-                   "ncells": f.ncells, "unknowns": n, "forward_ms": tf, "backward_ms": tb},
+                   "ncells": f.ncells, "unknowns": n, "forward_ms": tf, "backward_ms": tb, "options": opts},
         "max_rel_err_vs_oracle_adjoint": err,
     }
 
@@ -492,7 +493,7 @@ def main(argv=None):
     ap.add_argument("--workload", choices=("c2", "c3", "c5", "scaling", "branching"), default="c2")
     ap.add_argument("--cells", type=int, default=0, help="c3/c5: number of cells (default: the full workload)")
     ap.add_argument("--graph-steps", type=int, default=100, help="c3: time steps per captured graph")
-    ap.add_argument("--options", default="", help="c3: plan options as JSON instead of the autotuner's pick")
+    ap.add_argument("--options", default="", help="c3/c5: plan options as JSON (c3: instead of the autotuner's pick)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="c2: skip the FP32+refinement measurement")
