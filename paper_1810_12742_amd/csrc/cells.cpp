@@ -158,6 +158,12 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
   // only adds padding: 1,024 slots (256 compute units, 4 SIMDs, one wave each
   // at this kernel's register use), 64 lanes, about 15% padding
   const int64_t slot_steps = (int64_t)(1.15 * (double)n / (64.0 * 1024.0));
+  // too few cells to give every wave slot's lanes work (two lanes per cell or
+  // more fit): cut every cell longer than a slot's share, whatever the mean
+  const bool underfull = 2 * ncells <= 64 * 1024;
+  const int64_t cut_above = underfull ? std::max<int64_t>(4 * kCellChunk, slot_steps) : split_above;
+  const int64_t heavy_above = underfull ? cut_above : 2 * split_above;
+  const int64_t target_floor = underfull ? cut_above : std::max(split_above, slot_steps);
 
   CellTree T;
   std::vector<int32_t> forced, need, pre, seen, st, depth, path, pick;
@@ -216,7 +222,7 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
     need.assign(m, 0);
     excl.assign(m, 0);
     bool done = false;
-    if (m > split_above) {
+    if (m > cut_above) {
       depth.assign(m, 0);
       for (int32_t i = 1; i < m; ++i) depth[i] = depth[parent[lo + i] - lo] + 1;
       // one cut: the subtree closest to m / 2 from below (at least a quarter)
@@ -230,7 +236,7 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
         cands.push_back({{v}, cut_span(m, {v}, (int32_t)lo)});
         span = cands.back().second;
       }
-      if (span > 2 * split_above) {  // still much longer than the average: the heavy path
+      if (span > heavy_above) {  // still much longer than the average (or a slot's share): the heavy path
         path.assign(1, 0);
         onpath.assign(m, 0);
         onpath[0] = 1;
@@ -243,7 +249,7 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
           path.push_back(h);
           onpath[h] = 1;
         }
-        int64_t tl = std::max<int64_t>({(m + kCellMaxCuts) / (kCellMaxCuts + 1), split_above, slot_steps}), th = span;
+        int64_t tl = std::max<int64_t>((m + kCellMaxCuts) / (kCellMaxCuts + 1), target_floor), th = span;
         if (tl < th && heavy_cut(m, th - 1, pick)) {
           while (tl < th) {  // smallest feasible target
             const int64_t mid = (tl + th) / 2;

@@ -284,8 +284,10 @@ def test_cell_lane_setup_errors():
 def test_stack_need_of_a_full_binary_tree():
     """A full binary tree of compartments of height h needs h stack entries
     at the root (a node whose two children need a entries each needs a + 1:
-    one child's entry waits while the other subtree runs), so height 12
-    (4096 tips) is the tallest that fits 12 entries."""
+    one child's entry waits while the other subtree runs).  Heights 12 and 13
+    fit once cut into pieces; at height 14 every cut leaves a piece of height
+    13 or a remainder whose walk needs more than 12 entries, so setup refuses
+    the cell."""
     from paper_1810_12742_amd import HinesError, Plan
 
     def full(h):
@@ -293,20 +295,11 @@ def test_stack_need_of_a_full_binary_tree():
         par = np.r_[-1, (np.arange(1, n) - 1) // 2].astype(np.int32)
         return par, np.array([0, n], dtype=np.int64)
 
-    def with_cable(par, off, n_cable=40000):
-        # a long unbranched cell beside the tree raises the mean size, so the tree
-        # stays whole (cells are cut only above 0.8 times the mean)
-        n = off[-1]
-        cab = np.r_[-1, np.arange(n, n + n_cable - 1)].astype(np.int32)
-        return np.r_[par, cab].astype(np.int32), np.r_[off, n + n_cable].astype(np.int64)
-
-    p = Plan(*with_cable(*full(12)), None, host_only=1, cell_lanes=1)
-    assert p.info["kernel"] == 3
+    for h in (12, 13):
+        assert Plan(*full(h), None, host_only=1, cell_lanes=1).info["kernel"] == 3
     with pytest.raises(HinesError) as ei:
-        Plan(*with_cable(*full(13)), None, host_only=1, cell_lanes=1)
+        Plan(*full(14), None, host_only=1, cell_lanes=1)
     assert ei.value.code == "TOO_BIG"
-    # alone, the same tree is cut in two halves whose stacks fit
-    assert Plan(*full(13), None, host_only=1, cell_lanes=1).info["kernel"] == 3
 
 
 def test_long_cells_are_cut_into_pieces_on_lanes_of_one_wave():
