@@ -401,3 +401,18 @@ def test_largest_cell_and_single_compartment_cells():
     assert real.size == 100 and np.all(real == (TIP | ROOT))
     with pytest.raises(HinesError):
         Plan(np.r_[-1, np.arange(65535)].astype(np.int32), np.array([0, 65536]), None, host_only=1, cell_lanes=1)
+
+
+def test_small_networks_are_cut_to_fill_the_lanes():
+    """With too few cells to give the device's 64 x 1,024 wave-slot lanes
+    work, every cell longer than a slot's share is cut along its heavy path
+    (cells of one size included, which no cut relative to the mean would
+    touch): more lanes than cells, a shorter longest lane, same solution."""
+    from workloads import cable_values, grow_random_forest
+    rng = np.random.default_rng(40)
+    f = grow_random_forest(rng, 100, target_size=np.full(100, 1000))
+    s = cable_values(f, np.random.default_rng(41), a_kind="cable", rhs=False)
+    p = _check(f, s.diag, s.upper)
+    lanes = p.table("cell_lanes")
+    assert np.count_nonzero(lanes >= 0) >= 2 * f.ncells
+    assert p.info["max_makespan"] * chunk_steps(p) < 1000
