@@ -45,6 +45,7 @@ C2_OPTIONS = dict(cell_lanes=1)
 C2_FLOW_OPTIONS = dict(max_group_unknowns=1536, split_branches=0, cell_order=0, group_width=64)
 CALIB_BYTES = 512 << 20  # bytes read (and written) by one calibration copy
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hines_solve_c2.json")
+TRAFFIC_FILE_C3 = os.path.join(ROOT, "profiles", "traffic_k_cells_step_c3.json")
 KERNEL_SRC_DIR = os.path.join(ROOT, "paper_1810_12742_amd", "csrc")
 C4_DTS = (0.001, 0.025, 1.0)
 
@@ -61,11 +62,11 @@ def _kernel_sha() -> str:
     return h.hexdigest()
 
 
-def _traffic(n_launches_per_solve: int):
+def _traffic(n_launches_per_solve: int, path: str = TRAFFIC_FILE):
     """HBM bytes per launch from the committed PMC measurement, if it was taken
     on the current kernel source; else None."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -319,7 +320,9 @@ def run_c3(args, torch, dev):
                    "autotune_ms": [[o, round(t, 4)] for o, t in tried], "setup_s": round(setup_s, 2),
                    "groups": plan.info["ngroups"], "workspace_groups": plan.info["workspace_groups"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": _traffic(1, TRAFFIC_FILE_C3) if plan.info["kernel"] == 3 and ncells == configs.C3_CELLS
+                     else None,
                      "kernel": {3: "k_cells_step", 1: "k_solve_flow"}.get(plan.info["kernel"], "k_solve_level"),
                      "bytes_per_step": bytes_per_step},
         "charge_conservation_max_rel_err_step0": check,
