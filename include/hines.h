@@ -46,13 +46,14 @@ typedef enum hines_status {
   HINES_ERR_BAD_OFFSETS = 2,   /* cell_offsets not 0 < ... < n, or sizes out of range */
   HINES_ERR_BAD_PARENT = 3,    /* a root's parent is not -1, or parent[i] outside [cell start, i) */
   HINES_ERR_BAD_BRANCHES = 4,  /* branch layout invalid (see hines_setup) */
-  HINES_ERR_TOO_WIDE = 5,      /* reserved */
+  /* 5 is not used: a level wider than a group is walked by lanes that take
+     several branches each, so no width is ever refused */
   HINES_ERR_NCELLS = 6,        /* ncells differs from the plan's */
   HINES_ERR_OPTION = 7,        /* an option value is out of range */
   HINES_ERR_OOM = 8,           /* host or device allocation failed */
   HINES_ERR_HIP = 9,           /* a HIP runtime call or kernel launch failed */
   HINES_ERR_TOO_BIG = 10,      /* a group does not fit the device's LDS */
-  HINES_ERR_NOT_SDD = 11,      /* reserved for matrix checks */
+  HINES_ERR_NOT_SDD = 11,      /* hines_check_matrix: a row is not strictly diagonally dominant */
   HINES_ERR_STATE = 12         /* the plan was built host_only, or similar misuse */
 } hines_status;
 
@@ -168,17 +169,6 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
 hines_status hines_solve(const hines_plan* plan, const double* diag, const double* upper,
                          const double* rhs, double* x, int32_t ncells, void* stream);
 
-/* FP32 storage and elimination with FP64 refinement.  The matrix is the FP32
- * one (diag32, upper32: device float arrays, user numbering), widened exactly
- * where FP64 arithmetic is used; rhs and x are FP64.  Sweep 0 solves
- * A x = fl32(rhs) in FP32; each further sweep (up to `sweeps`, at most 8)
- * forms r = rhs - A x in FP64, solves A d = fl32(r) in FP32 and adds d to x
- * in FP64.  The group's matrix, rhs and solution stay in LDS across sweeps,
- * so HBM sees 24 bytes per compartment whatever the number of sweeps.
- * HINES_ERR_TOO_BIG if a group does not fit this kernel's LDS image (or, on a
- * cell-lane plan, the groups' 16-bit branch records: a cell-lane plan is
- * still built then, and only this call is refused).
- * x may alias rhs.  Async on stream. */
 /* FP32 storage, FP64 elimination (cell-lane plans only).  The matrix is the
  * FP32 one (diag32, upper32: device float arrays, user numbering); the kernel
  * widens each entry exactly on load and runs §2's elimination in FP64, so one
@@ -190,6 +180,17 @@ hines_status hines_solve(const hines_plan* plan, const double* diag, const doubl
 hines_status hines_solve_stored32(const hines_plan* plan, const float* diag32, const float* upper32,
                                   const double* rhs, double* x, int32_t ncells, void* stream);
 
+/* FP32 storage and elimination with FP64 refinement.  The matrix is the FP32
+ * one (diag32, upper32: device float arrays, user numbering), widened exactly
+ * where FP64 arithmetic is used; rhs and x are FP64.  Sweep 0 solves
+ * A x = fl32(rhs) in FP32; each further sweep (up to `sweeps`, at most 8)
+ * forms r = rhs - A x in FP64, solves A d = fl32(r) in FP32 and adds d to x
+ * in FP64.  The group's matrix, rhs and solution stay in LDS across sweeps,
+ * so HBM sees 24 bytes per compartment whatever the number of sweeps.
+ * HINES_ERR_TOO_BIG if a group does not fit this kernel's LDS image (or, on a
+ * cell-lane plan, the groups' 16-bit branch records: a cell-lane plan is
+ * still built then, and only this call is refused).
+ * x may alias rhs.  Async on stream. */
 hines_status hines_solve_mixed(const hines_plan* plan, const float* diag32, const float* upper32,
                                const double* rhs, double* x, int32_t sweeps, int32_t ncells, void* stream);
 
@@ -262,6 +263,20 @@ hines_status hines_adjoint_rhs(hines_plan* plan, const double* c, const double* 
                                double* mu, void* stream);
 hines_status hines_adjoint_accumulate(hines_plan* plan, const double* lam, const double* v, const double* v_prev,
                                       double* grad_a, double* grad_c, double* grad_i, void* stream);
+
+/* Check that (diag, upper) is a matrix the solver is defined for (paper §1:
+ * A is symmetric, which the storage of one coupling per edge guarantees, and
+ * strictly diagonally dominant with a positive diagonal, so elimination
+ * without pivoting keeps every pivot positive).  Row i passes when
+ *     diag[i] > |upper[i]| (not for a root) + sum over children k of |upper[k]|,
+ * the sum taken over the children in ascending index; a NaN entry fails.
+ *   diag, upper: device arrays of n doubles in the user numbering.
+ *   first_bad: NULL, or set to the smallest failing user index (-1 if none).
+ * The first call uploads the plan's parent array and child lists.  The call
+ * is synchronous: it returns after the check has run on `stream`.
+ * HINES_ERR_NOT_SDD if some row fails, HINES_OK otherwise. */
+hines_status hines_check_matrix(hines_plan* plan, const double* diag, const double* upper, int64_t* first_bad,
+                                void* stream);
 
 /* Summary counts of a plan. */
 hines_status hines_plan_info_get(const hines_plan* plan, hines_plan_info* info);

@@ -98,6 +98,7 @@ struct hines_plan {
   const int32_t* d_ch_off = nullptr;
   const int32_t* d_ch = nullptr;
   const int64_t* d_cell_off = nullptr;
+  unsigned long long* d_flag = nullptr;  // result word of hines_check_matrix
 };
 
 struct hines_timeloop {
@@ -510,7 +511,7 @@ hines_status ensure_adjoint_tables(hines_plan* p) {
   const int64_t sp = al(4 * std::max<int64_t>(n, 1)), so = al(4 * (n + 1)), sc = al(4 * std::max<int64_t>(n, 1)),
                 sf = al(8 * (int64_t)p->cell_off_host.size());
   void* mem = nullptr;
-  hipError_t e = hipMalloc(&mem, sp + so + sc + sf);
+  hipError_t e = hipMalloc(&mem, sp + so + sc + sf + 256);
   if (e != hipSuccess) return set_err(HINES_ERR_OOM, "element-wise tables: %s", hipGetErrorString(e));
   char* b = (char*)mem;
   if (n > 0) e = hipMemcpy(b, par.data(), 4 * n, hipMemcpyHostToDevice);
@@ -527,6 +528,7 @@ hines_status ensure_adjoint_tables(hines_plan* p) {
   p->d_ch_off = (const int32_t*)(b + sp);
   p->d_ch = (const int32_t*)(b + sp + so);
   p->d_cell_off = (const int64_t*)(b + sp + so + sc);
+  p->d_flag = (unsigned long long*)(b + sp + so + sc + sf);
   return HINES_OK;
 }
 
@@ -1057,6 +1059,32 @@ hines_status hines_adjoint_accumulate(hines_plan* p, const double* lam, const do
   return launched();
 }
 
+hines_status hines_check_matrix(hines_plan* p, const double* diag, const double* upper, int64_t* first_bad,
+                                void* stream) {
+  if (first_bad) *first_bad = -1;
+  hines_status st = check_call(p, p ? (int32_t)p->host.ncells : 0);
+  if (st != HINES_OK) return st;
+  if (p->host.n == 0) return ok();
+  if (!diag || !upper) return set_err(HINES_ERR_NULL, "a device array is NULL");
+  st = ensure_adjoint_tables(p);
+  if (st != HINES_OK) return st;
+  const int64_t n = p->host.n;
+  const hipStream_t s = (hipStream_t)stream;
+  const unsigned long long none = ~0ull;
+  hipLaunchKernelGGL(hdev::k_fill_u64, dim3(1), dim3(64), 0, s, p->d_flag, none);
+  hipLaunchKernelGGL(hdev::k_check_sdd, grid_for(n, 256), dim3(256), 0, s, n, p->d_parent, p->d_ch_off, p->d_ch,
+                     diag, upper, p->d_flag);
+  unsigned long long bad = none;
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, p->d_flag, sizeof bad, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return set_err(HINES_ERR_HIP, "matrix check: %s", hipGetErrorString(e));
+  if (bad == none) return ok();
+  if (first_bad) *first_bad = (int64_t)bad;
+  return set_err(HINES_ERR_NOT_SDD, "row %lld is not strictly diagonally dominant with a positive diagonal",
+                 (long long)bad);
+}
+
 hines_status hines_plan_info_get(const hines_plan* p, hines_plan_info* info) {
   if (!p || !info) return set_err(HINES_ERR_NULL, "NULL argument");
   std::memset(info, 0, sizeof *info);
@@ -1123,7 +1151,6 @@ const char* hines_status_str(hines_status s) {
     case HINES_ERR_BAD_OFFSETS: return "bad cell offsets";
     case HINES_ERR_BAD_PARENT: return "bad parent array";
     case HINES_ERR_BAD_BRANCHES: return "bad branch layout";
-    case HINES_ERR_TOO_WIDE: return "level too wide";
     case HINES_ERR_NCELLS: return "cell count mismatch";
     case HINES_ERR_OPTION: return "bad option";
     case HINES_ERR_OOM: return "out of memory";

@@ -1674,6 +1674,23 @@ __global__ void k_adjoint_rhs(int64_t n, const int32_t* __restrict__ parent, con
   mu[i] = m;
 }
 
+// Row test of strict diagonal dominance with a positive diagonal (paper §1):
+// d_i > |u_i| (non-root) + sum over children k of |u_k|, children in ascending
+// order.  A failing row lowers *bad to its index (NaN rows fail).
+__global__ void k_check_sdd(int64_t n, const int32_t* __restrict__ parent, const int32_t* __restrict__ ch_off,
+                            const int32_t* __restrict__ ch, const double* __restrict__ d,
+                            const double* __restrict__ u, unsigned long long* bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = parent[i] >= 0 ? fabs(u[i]) : 0.0;
+  for (int32_t k = ch_off[i]; k < ch_off[i + 1]; ++k) s += fabs(u[ch[k]]);
+  if (!(d[i] > s)) atomicMin(bad, (unsigned long long)i);
+}
+
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
 // out[cell] = v[first compartment of cell]
 __global__ void k_gather_roots(int32_t ncells, const int64_t* __restrict__ cell_off, const double* __restrict__ v,
                                double* __restrict__ out) {

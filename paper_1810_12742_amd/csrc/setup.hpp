@@ -16,7 +16,6 @@ enum Status : int32_t {
   ERR_BAD_OFFSETS = 2,
   ERR_BAD_PARENT = 3,
   ERR_BAD_BRANCHES = 4,
-  ERR_TOO_WIDE = 5,
   ERR_NCELLS = 6,
   ERR_OPTION = 7,
   ERR_OOM = 8,

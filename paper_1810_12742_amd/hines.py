@@ -20,7 +20,7 @@ TABLES = {
     "flow_groups": 8, "flow_masks": 9, "flow_pos": 10, "flow_aux": 11,
     "cell_waves": 12, "cell_lanes": 13, "cell_pos": 14, "cell_flags": 15, "cell_mbsrc": 16,
 }
-STATUS = {0: "OK", 1: "NULL", 2: "BAD_OFFSETS", 3: "BAD_PARENT", 4: "BAD_BRANCHES", 5: "TOO_WIDE",
+STATUS = {0: "OK", 1: "NULL", 2: "BAD_OFFSETS", 3: "BAD_PARENT", 4: "BAD_BRANCHES",
           6: "NCELLS", 7: "OPTION", 8: "OOM", 9: "HIP", 10: "TOO_BIG", 11: "NOT_SDD", 12: "STATE"}
 
 
@@ -85,12 +85,14 @@ def load():
     lib.hines_gather_roots.argtypes = [P, P, P, P]
     lib.hines_adjoint_rhs.argtypes = [P, P, P, P, P, P]
     lib.hines_adjoint_accumulate.argtypes = [P, P, P, P, P, P, P, P]
+    lib.hines_check_matrix.argtypes = [P, P, P, ctypes.POINTER(I64), P]
     for name in ("hines_setup", "hines_solve", "hines_solve_mixed", "hines_solve_stored32", "hines_timestep_assembled",
                  "hines_plan_info_get",
                  "hines_get_table",
                  "hines_destroy",
                  "hines_timestep", "hines_timeloop_create", "hines_timeloop_launch", "hines_timeloop_destroy",
-                 "hines_assemble", "hines_gather_roots", "hines_adjoint_rhs", "hines_adjoint_accumulate"):
+                 "hines_assemble", "hines_gather_roots", "hines_adjoint_rhs", "hines_adjoint_accumulate",
+                 "hines_check_matrix"):
         getattr(lib, name).restype = I32
     _lib = lib
     return lib
@@ -261,6 +263,20 @@ class Plan:
             float(noise_sigma), int(noise_seed) & 0xFFFFFFFF, int(first_step) & 0xFFFFFFFF, int(nsteps),
             self.ncells, ctypes.byref(h)))
         return TimeLoop(h, self, keep)
+
+    def check_matrix(self, diag, upper, stream=None):
+        """Strict diagonal dominance with a positive diagonal (``hines_check_matrix``).
+        Returns -1 when every row passes, else the smallest failing user index."""
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        bad = ctypes.c_int64(-1)
+        status = load().hines_check_matrix(self._h, _dev(diag, self.n, torch.float64, "diag"),
+                                           _dev(upper, self.n, torch.float64, "upper"), ctypes.byref(bad),
+                                           ctypes.c_void_p(st.cuda_stream))
+        if status == 11:
+            return int(bad.value)
+        _check(status)
+        return -1
 
     # ---- element-wise kernels of the adjoint ----------------------------------
     def assemble(self, a, c, diag=None, upper=None, stream=None):

@@ -216,6 +216,12 @@ def test_mixed_precision_refinement(torch_dev, dt):
     u32 = s.upper.astype(np.float32)
     xs = oracle.solve(f, d32.astype(np.float64), u32.astype(np.float64), s.rhs)
     oracle_its = oracle.refine(f, d32, u32, s.rhs, sweeps=3)
+    # sweep 0 is an FP32 elimination of fl32(rhs): the oracle's FP32 solve of
+    # the same system (plain order, IEEE division) is the reference.  Two FP32
+    # eliminations of one system differ by rounding only, which is of the size
+    # of either one's distance from the FP64 solution; a dropped or misplaced
+    # term is orders of magnitude larger.
+    e_o32 = cell_rel_err(f, oracle_its[0], xs)
     errs = []
     for opts in (dict(), dict(level_sync=1), dict(split_branches=1, max_group_unknowns=1024)):
         p = Plan(f.parent, f.cell_offsets, f.branch_offsets, **opts)
@@ -226,7 +232,11 @@ def test_mixed_precision_refinement(torch_dev, dt):
         for sweeps in range(4):
             x = p.solve_mixed(D, U, B, sweeps=sweeps).cpu().numpy()
             errs.append(cell_rel_err(f, x, xs))
+            if sweeps == 0:
+                e32 = cell_rel_err(f, x, oracle_its[0])
+                assert e32 <= 4.0 * e_o32 + 1e-7, (opts, e32, e_o32)
         assert errs[0] > 1e-10  # FP32 alone is far from FP64
+        assert 0.25 * e_o32 <= errs[0] <= 4.0 * e_o32, (opts, errs[0], e_o32)
         assert errs[-1] <= 1e-11, (opts, errs)
         assert errs[1] < errs[0]
         # the oracle's own refinement converges the same way

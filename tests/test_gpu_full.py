@@ -1,0 +1,122 @@
+"""GPU parity at the sizes of the measured configurations.
+
+* Config 3 (batching + time loop): 1,000 implicit-Euler steps captured in one
+  graph, on a subset of 64 cells from each size class (50, 500, 5,000 and
+  20,000 compartments), against the oracle's time loop over the same 1,000
+  steps (paper §1: one solve of the discrete system per step).  The oracle
+  takes about a second per 100 steps at this size, so the subset is 64 cells
+  per class, not the full 200,000.
+* Config 5 (differentiation): the full 16,384 cells x 1,000 compartments over
+  100 steps with checkpoints every 10; central differences (h = 1e-6) on 32
+  parameters drawn with seed 5 from the edge conductances, capacitive terms
+  and injected currents, against the adjoint gradient.  Each difference is
+  taken on the owning cell's loss term, which is the only one the parameter
+  changes (cells are independent).
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def cell_rel_err(f, x, xo):
+    err = np.maximum.reduceat(np.abs(x - xo), f.cell_offsets[:-1])
+    scale = np.maximum.reduceat(np.abs(xo), f.cell_offsets[:-1])
+    return float(np.max(err / np.maximum(scale, 1e-300)))
+
+
+def c3_class_subset(per_class: int):
+    """The first `per_class` cells of every size class of the config-3 recipe."""
+    ncells = 1
+    while True:
+        ncells *= 2
+        sizes = configs.c3_sizes(ncells)
+        if min(int(np.sum(sizes == s)) for s in configs.C3_SIZES) >= per_class:
+            break
+    s = configs.c3(ncells)
+    sizes = np.diff(s.forest.cell_offsets)
+    pick = np.sort(np.concatenate([np.flatnonzero(sizes == z)[:per_class] for z in configs.C3_SIZES]))
+    f = s.forest.subset(pick)
+    idx = np.concatenate([np.arange(s.forest.cell_offsets[c], s.forest.cell_offsets[c + 1]) for c in pick])
+    return f, s.diag[idx], s.upper[idx], s.c[idx]
+
+
+def test_c3_thousand_captured_steps_per_size_class():
+    import torch
+    from paper_1810_12742_amd import Plan
+    dev = torch.device("cuda")
+    f, diag, upper, c = c3_class_subset(64)
+    steps = 1000
+    print(f"c3 subset: {f.ncells} cells, {f.n} unknowns, {steps} steps", flush=True)
+    t0 = time.perf_counter()
+    Vo = oracle.timeloop(f, diag, upper, c, steps, noise_seed=3, noise_sigma=0.1)
+    print(f"oracle {time.perf_counter() - t0:.1f} s", flush=True)
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets, cell_lanes=True)
+    d = torch.from_numpy(diag).to(dev)
+    u = torch.from_numpy(upper).to(dev)
+    cc = torch.from_numpy(c).to(dev)
+    V = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    loop = p.timeloop(d, u, cc, V, steps, noise_sigma=0.1, noise_seed=3, first_step=0)
+    loop.launch()
+    torch.cuda.synchronize()
+    err = cell_rel_err(f, V.cpu().numpy(), Vo)
+    print(f"1000-step error {err:.2e}", flush=True)
+    assert err <= 1e-12
+    loop.close()
+    p.close()
+
+
+def test_c5_central_differences_full_configuration():
+    import torch
+    from paper_1810_12742_amd import Plan
+    from paper_1810_12742_amd.adjoint import soma_traces
+    dev = torch.device("cuda")
+    s = configs.c5()
+    f = s.forest
+    steps, every = s.meta["steps"], s.meta["checkpoint_every"]
+    print(f"c5: {f.ncells} cells, {f.n} unknowns, {steps} steps", flush=True)
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets)
+    target = torch.from_numpy(s.meta["target"]).to(dev)
+    base = {"a": torch.from_numpy(s.a).to(dev), "c": torch.from_numpy(s.c).to(dev),
+            "I": torch.from_numpy(s.meta["I"]).to(dev)}
+    params = {k: v.clone().requires_grad_(True) for k, v in base.items()}
+    tr = soma_traces(p, params["a"], params["c"], params["I"], steps, every)
+    ((tr - target) ** 2).sum().backward()
+    grads = {k: v.grad.cpu().numpy() for k, v in params.items()}
+    # 32 parameters drawn uniformly from {a_e (non-root)} U {c_i} U {I_i}
+    nonroot = np.flatnonzero(f.parent >= 0)
+    pool = len(nonroot) + 2 * f.n
+    rng = np.random.default_rng(5)
+    draws = rng.choice(pool, size=32, replace=False)
+    cell_of = np.searchsorted(f.cell_offsets, np.arange(f.n), side="right") - 1
+    h = 1e-6
+    worst = 0.0
+    with torch.no_grad():
+        for q in draws:
+            if q < len(nonroot):
+                kind, i = "a", int(nonroot[q])
+            elif q < len(nonroot) + f.n:
+                kind, i = "c", int(q - len(nonroot))
+            else:
+                kind, i = "I", int(q - len(nonroot) - f.n)
+            cell = int(cell_of[i])
+            vals = []
+            for sgn in (1.0, -1.0):
+                pp = {k: v.clone() for k, v in base.items()}
+                pp[kind][i] += sgn * h
+                t = soma_traces(p, pp["a"], pp["c"], pp["I"], steps, every)
+                vals.append(float(((t[:, cell] - target[cell]) ** 2).sum().item()))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            g = float(grads[kind][i])
+            # round-off of a cell's loss term (about 1e2) over 2h bounds the
+            # difference quotient's absolute error near 1e-7
+            tol = 1e-5 * abs(g) + 5e-7
+            worst = max(worst, abs(fd - g) / max(tol, 1e-300))
+            assert abs(fd - g) <= tol, (kind, i, fd, g)
+    print(f"32 central differences: worst |fd - g| / tol = {worst:.3f}", flush=True)
+    p.close()

@@ -221,3 +221,42 @@ def test_error_paths(torch_dev):
     e = torch.zeros(0, dtype=torch.float64, device=dev)
     pe.solve(e, e, e, out=e)
     torch.cuda.synchronize()
+
+
+def test_check_matrix_through_the_c_abi(torch_dev):
+    """hines_check_matrix (paper §1: SDD with a positive diagonal): the
+    generated cable matrices pass; a row made non-dominant, a negative
+    diagonal and a NaN are reported at their index, the smallest first."""
+    import ctypes
+    torch, dev = torch_dev
+    from paper_1810_12742_amd import Plan
+    from paper_1810_12742_amd.hines import load
+    s = configs.c2(64)
+    f = s.forest
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets)
+    lib = load()
+    P = ctypes.c_void_p
+    d = torch.from_numpy(s.diag).to(dev)
+    u = torch.from_numpy(s.upper).to(dev)
+    bad = ctypes.c_int64(7)
+    assert lib.hines_check_matrix(p._h, P(d.data_ptr()), P(u.data_ptr()), ctypes.byref(bad), None) == 0
+    assert bad.value == -1
+    # the row sum of |off-diagonals| of row i, computed on the host
+    par = f.parent
+    rowsum = np.abs(np.where(par >= 0, s.upper, 0.0))
+    np.add.at(rowsum, par[par >= 0], np.abs(s.upper[par >= 0]))
+    i_dom, i_neg, i_nan = 5000, 777, 20000
+    d2 = s.diag.copy()
+    d2[i_dom] = 0.999 * rowsum[i_dom]  # positive, but below the off-diagonal sum
+    d2[i_nan] = np.nan
+    dd = torch.from_numpy(d2).to(dev)
+    assert lib.hines_check_matrix(p._h, P(dd.data_ptr()), P(u.data_ptr()), ctypes.byref(bad), None) == 11
+    assert bad.value == i_dom
+    d2[i_neg] = -1.0
+    dd = torch.from_numpy(d2).to(dev)
+    assert p.check_matrix(dd, u) == i_neg
+    # a root's upper entry is ignored, whatever it holds
+    u2 = s.upper.copy()
+    u2[f.cell_offsets[:-1]] = 1e300
+    assert p.check_matrix(d, torch.from_numpy(u2).to(dev)) == -1
+    p.close()

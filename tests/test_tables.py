@@ -299,3 +299,87 @@ def test_setup_time_is_linear():
         Plan(f.parent, f.cell_offsets, f.branch_offsets, host_only=True, split_branches=1).close()
         times.append((time.perf_counter() - t0) / f.n)
     assert times[1] < 2.5 * times[0]
+
+
+def _forest_from_cells(cells):
+    """Concatenate per-cell (parent list, branch starts) pairs into a Forest."""
+    par, off, bo = [], [0], []
+    for p, starts in cells:
+        o = off[-1]
+        par.extend(v + o if v >= 0 else -1 for v in p)
+        bo.extend(s + o for s in starts)
+        off.append(o + len(p))
+    bo.append(off[-1])
+    return Forest(np.array(par, dtype=np.int32), np.array(off, dtype=np.int64), np.array(bo, dtype=np.int64))
+
+
+def _chain(parent_of_first, start, length):
+    """Parents of a run of `length` compartments starting at `start`."""
+    return [parent_of_first] + list(range(start, start + length - 1))
+
+
+def test_split_rule_below_level_zero_hand_derived():
+    """S5 worked by hand on two cells (section 6: the average is taken over the
+    branches of one level of all cells, after the levels above were cut).
+
+    Cell A: root branch of 2 (0-1), children of 6 (2-7) and 2 (8-9).
+    Cell B: root branch of 4 (10-13), one child of 4 (14-17).
+    Level 0: S = 6, m = 2, average 3: B's root (4 > 3) keeps 3; its tail
+      (compartment 13) moves to level 1 and adopts B's child (now level 2).
+    Level 1: A's 6, A's 2, B's tail 1: S = 9, m = 3, average 3: A's 6 keeps
+      2-4, its tail 5-7 moves to level 2.
+    Level 2: A's tail 3, B's child 4: S = 7, m = 2, floor 3: B's child keeps
+      14-16, its tail 17 moves to level 3.
+    Level 3: B's tail alone (1 = average): unchanged."""
+    a = _chain(-1, 0, 2) + _chain(1, 2, 6) + _chain(1, 8, 2)
+    b = _chain(-1, 0, 4) + _chain(3, 4, 4)
+    f = _forest_from_cells([(a, [0, 2, 8]), (b, [0, 4])])
+    t = py_tables(f, split_branches=1)
+    br = t["branches"]
+    got = sorted((int(r[0]), int(r[1]), int(r[2]), int(r[4])) for r in br)  # cell, level, first, len
+    want = sorted([
+        (0, 0, 0, 2), (0, 1, 2, 3), (0, 1, 8, 2), (0, 2, 5, 3),
+        (1, 0, 10, 3), (1, 1, 13, 1), (1, 2, 14, 3), (1, 3, 17, 1),
+    ])
+    assert got == want
+    # parents: each tail hangs under its kept piece, adopted children under the tail
+    by_first = {int(r[2]): k for k, r in enumerate(br)}
+    assert br[by_first[5], 5] == by_first[2]
+    assert br[by_first[13], 5] == by_first[10]
+    assert br[by_first[14], 5] == by_first[13]
+    assert br[by_first[17], 5] == by_first[14]
+    assert_same(lib_tables(f, split_branches=1), t)
+
+
+def _star_cell(nkids):
+    """A root compartment with nkids single-compartment child branches."""
+    return ([-1] + [0] * nkids, list(range(nkids + 1)))
+
+
+def test_packing_is_greedy_by_level_width():
+    """S7 (section 4): a cell joins the open group whenever every level's
+    branch count stays within the group width; only a cell that does not fit
+    opens a new group.  Level-1 widths 40, 30, 20, 14, 50 with T = 64:
+    {40}, {30, 20, 14} (64 fits exactly), {50}."""
+    f = _forest_from_cells([_star_cell(k) for k in (40, 30, 20, 14, 50)])
+    t = py_tables(f, branch_offsets=None, group_width=64, max_group_unknowns=0)
+    assert list(t["group_offsets"]) == [0, 1, 4, 5]
+    assert list(t["group_cells"]) == [0, 1, 2, 3, 4]
+    assert_same(lib_tables(f, branch_offsets=None, group_width=64, max_group_unknowns=0), t)
+
+
+def test_packing_is_greedy_by_compartment_cap():
+    """S7 with a compartment cap of 10: sizes 4, 4, 4, 2, 7, 3 pack as
+    {4, 4}, {4, 2}, {7, 3}; a cell that fits (the 3 after the 7) joins the
+    open group instead of a later or a new one."""
+    sizes = [4, 4, 4, 2, 7, 3]
+    f = _forest_from_cells([(_chain(-1, 0, s), [0]) for s in sizes])
+    t = py_tables(f, max_group_unknowns=10)
+    assert list(t["group_offsets"]) == [0, 2, 4, 6]
+    assert_same(lib_tables(f, max_group_unknowns=10), t)
+    # descending sizes (cell_order 1) visit 7, 4, 4, 4, 3, 2: the open group
+    # takes each cell that fits, giving {7}, {4, 4}, {4, 3, 2}
+    t1 = py_tables(f, max_group_unknowns=10, cell_order=1)
+    assert list(t1["group_cells"]) == [4, 0, 1, 2, 5, 3]
+    assert list(t1["group_offsets"]) == [0, 1, 3, 6]
+    assert_same(lib_tables(f, max_group_unknowns=10, cell_order=1), t1)
