@@ -98,13 +98,20 @@ def cell_rel_err(f, x, xo):
     return float(np.max(e / np.maximum(s, 1e-300)))
 
 
-def cpu_baseline(system, budget_s: float = 12.0):
-    """The FP64 oracle on the host cores: repeated full solves of the same
-    workload until about ``budget_s`` seconds of wall time have passed."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(system, threads: int, budget_s: float):
     import oracle
-    oracle.build(force=False)
     f = system.forest
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     reps = 0
     t0 = time.perf_counter()
     while True:
@@ -113,8 +120,63 @@ def cpu_baseline(system, budget_s: float = 12.0):
         el = time.perf_counter() - t0
         if el >= budget_s:
             break
-    return {"value": f.n * reps / el, "unit": "unknowns/s", "cores": threads, "kind": "oracle",
-            "sample": f"full workload ({f.n} unknowns), {reps} solves, {el:.1f} s, OpenMP over cells"}
+    return f.n * reps / el, reps, el
+
+
+def cpu_baseline(system, budget_s: float = 10.0):
+    """The FP64 oracle on the host: repeated full solves of the same workload
+    until about ``budget_s`` seconds of wall time have passed, with every host
+    thread (OpenMP over cells) and with one thread."""
+    import oracle
+    oracle.build(force=False)
+    f = system.forest
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    v, reps, el = _oracle_rate(system, threads, budget_s)
+    v1, reps1, el1 = _oracle_rate(system, 1, budget_s)
+    return {"value": v, "unit": "unknowns/s", "cores": threads, "kind": "oracle",
+            "sample": f"full workload ({f.n} unknowns), {reps} solves, {el:.1f} s, OpenMP over cells",
+            "cpu_model": _cpu_model(),
+            "single_thread": {"value": v1, "unit": "unknowns/s", "cores": 1,
+                              "sample": f"full workload, {reps1} solves, {el1:.1f} s"}}
+
+
+def run_c1(torch, dev, reps: int = 20):
+    """Config 1: 4,096 full binary trees of 75 compartments, one solve, in
+    the small-workload regime (the whole system fits the on-chip caches).
+    Each solve is timed alone after a 1 GiB device write that evicts the
+    caches; reported per plan kind, median over reps."""
+    from workloads import configs
+    from paper_1810_12742_amd import Plan
+    import oracle
+    s = configs.c1()
+    f = s.forest
+    d, u, b = (torch.from_numpy(a).to(dev) for a in (s.diag, s.upper, s.rhs))
+    x = torch.empty_like(b)
+    flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    xo = oracle.solve(f, s.diag, s.upper, s.rhs)
+    out = {"workload": "c1: 4,096 full binary trees, 15 branches x 5 compartments, seed 0, one solve",
+           "unknowns": f.n, "cache_flush_bytes": flush.numel() * 8}
+    for name, opts in (("resident", dict(resident=1)), ("flow", dict(C2_FLOW_OPTIONS)),
+                       ("cell_lanes", dict(cell_lanes=1))):
+        p = Plan(f.parent, f.cell_offsets, f.branch_offsets, **opts)
+        times = []
+        for k in range(reps + 2):
+            flush.fill_(float(k))
+            torch.cuda.synchronize()
+            e0, e1 = _events(torch)
+            e0.record(stream)
+            p.solve(d, u, b, out=x, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if k >= 2:
+                times.append(e0.elapsed_time(e1) * 1e3)
+        us = float(np.median(times))
+        out[name] = {"us_per_solve": us, "unknowns_per_s": f.n / (us * 1e-6),
+                     "max_rel_err_vs_oracle": cell_rel_err(f, x.cpu().numpy(), xo)}
+        p.close()
+    del flush
+    return out
 
 
 def fp32_refine(torch, dev, plan, s, fp64_ms, reps, check):
@@ -168,8 +230,9 @@ def run_c2(args, torch, dev):
 
     s = configs.c2()
     f = s.forest
+    opts = json.loads(args.options) if args.options else dict(C2_OPTIONS)
     t0 = time.perf_counter()
-    plan = Plan(f.parent, f.cell_offsets, f.branch_offsets, **C2_OPTIONS)
+    plan = Plan(f.parent, f.cell_offsets, f.branch_offsets, **opts)
     setup_s = time.perf_counter() - t0
     info = plan.info
     d = torch.from_numpy(s.diag).to(dev)
@@ -214,8 +277,9 @@ def run_c2(args, torch, dev):
             "workload": "c2: 65,536 random dendritic cells, 16-256 branches, geometric(12) branch "
                         "lengths, dt=0.025, one FP64 solve per step",
             "ncells": f.ncells, "unknowns": n, "groups": info["ngroups"], "launches_per_step": launches,
-            "kernel": {3: "cell lanes", 1: "flow", 2: "bitwise"}.get(info["kernel"], "level-synchronous"),
-            "options": C2_OPTIONS, "setup_s": round(setup_s, 3),
+            "kernel": {4: "LDS-resident", 3: "cell lanes", 1: "flow", 2: "bitwise"}.get(info["kernel"],
+                                                                                         "level-synchronous"),
+            "options": opts, "setup_s": round(setup_s, 3),
         },
         "roofline": {
             "bound": "hbm",
@@ -224,7 +288,7 @@ def run_c2(args, torch, dev):
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": _traffic(launches),
-            "kernel": {3: "k_solve_cells", 1: "k_solve_flow"}.get(info["kernel"], "k_solve_level"),
+            "kernel": {4: "k_solve_res", 3: "k_solve_cells", 1: "k_solve_flow"}.get(info["kernel"], "k_solve_level"),
             "bytes_per_launch": bytes_per_solve / launches,
             "avg_launch_us": ms * 1e3 / launches,
         },
@@ -233,9 +297,11 @@ def run_c2(args, torch, dev):
     if not args.no_forms:
         del d, u
         out["fp32_refine"] = fp32_refine(torch, dev, plan, s, ms, max(3, args.steps // 2), not args.no_check)
+    plan.close()
+    if not args.no_forms:
+        out["c1"] = run_c1(torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s)
-    plan.close()
     return out
 
 
@@ -496,7 +562,7 @@ def main(argv=None):
     ap.add_argument("--workload", choices=("c2", "c3", "c5", "scaling", "branching"), default="c2")
     ap.add_argument("--cells", type=int, default=0, help="c3/c5: number of cells (default: the full workload)")
     ap.add_argument("--graph-steps", type=int, default=100, help="c3: time steps per captured graph")
-    ap.add_argument("--options", default="", help="c3/c5: plan options as JSON (c3: instead of the autotuner's pick)")
+    ap.add_argument("--options", default="", help="plan options as JSON (c3: instead of the autotuner's pick)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="c2: skip the FP32+refinement measurement")

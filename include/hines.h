@@ -82,7 +82,16 @@ typedef struct hines_options {
                                  bitwise 0, cells of at most 65535 compartments and a stack need
                                  of at most 12 (HINES_ERR_TOO_BIG otherwise).  hines_solve_mixed
                                  keeps using the groups.  0 (default): groups (§3-§4)        */
-  int32_t reserved[6];        /* must be 0 */
+  int32_t resident;           /* 1: hines_solve runs the LDS-resident kernel: consecutive whole
+                                 cells form a group of up to 1400 compartments (a larger cell is
+                                 a group of its own); one wave stages the group's d, u, b and
+                                 parent slots into LDS once, eliminates every compartment after
+                                 its children (§2) along root-ward paths scheduled at setup, one
+                                 path per lane at a time (§3-§4), and stores x.  Needs bitwise 0,
+                                 cell_lanes 0 and every cell's image within LDS (up to about 6,000
+                                 compartments; HINES_ERR_TOO_BIG otherwise).  The other calls
+                                 keep using the groups.                                      */
+  int32_t reserved[5];        /* must be 0 */
 } hines_options;
 
 /* Plan summary. */
@@ -93,9 +102,10 @@ typedef struct hines_plan_info {
   int64_t device_table_bytes; /* device memory held by the plan */
   int64_t max_group_lds_bytes;
   int32_t kernel;             /* 0 level-synchronous, 1 flow (static step schedule), 2 bitwise,
-                                 3 cell lanes                                                 */
+                                 3 cell lanes, 4 LDS-resident                                 */
   int32_t max_makespan;       /* flow plans: longest schedule, in chunk steps; cell-lane plans:
-                                 chunks per sweep of the longest wave                        */
+                                 chunks per sweep of the longest wave; resident plans: steps
+                                 per sweep of the longest group                              */
   int64_t workspace_groups;   /* groups too large for LDS, solved from a global workspace */
 } hines_plan_info;
 
@@ -135,9 +145,21 @@ enum {
                                         64 root of a cut-off subtree (its contribution leaves
                                         through mailbox c), 128 parent of such a root (takes
                                         the next mailbox of the lane's source list)           */
-  HINES_TABLE_CELL_MBSRC = 16        /* [nwaves*64] per lane: the mailbox (source lane) of each
+  HINES_TABLE_CELL_MBSRC = 16,       /* [nwaves*64] per lane: the mailbox (source lane) of each
                                         take, 6 bits each, in backward order in bits 0-31 and
                                         in forward order in bits 32-63; 0 without takes       */
+  /* LDS-resident plans (hines_plan_info.kernel == 4).  Group image: slot s holds user index
+     lo + s; slot nslot is a zero entry.                                                     */
+  HINES_TABLE_RES_GROUPS = 17,       /* [ngroups*10] lo, blob (16-byte units), nslot, staged
+                                        slots, slot of the first compartment, compartments,
+                                        steps per sweep, blob units, cells, path records      */
+  HINES_TABLE_RES_PAR = 18,          /* [n] parent slot of each compartment in its group image
+                                        (nslot for a cell root)                              */
+  HINES_TABLE_RES_BLOB = 19          /* [blob bytes / 2] the group blobs as 16-bit words: 65
+                                        record offsets (one per lane, then the total; 72
+                                        words), the root slots padded to 8 words, the path
+                                        records (bottom slot, first step, length, 1 if the
+                                        top's contribution goes to its parent's entry)       */
 };
 
 /* Fill *opt with the defaults: no re-rooting, no splitting, group_width 64,
@@ -263,6 +285,30 @@ hines_status hines_adjoint_rhs(hines_plan* plan, const double* c, const double* 
                                double* mu, void* stream);
 hines_status hines_adjoint_accumulate(hines_plan* plan, const double* lam, const double* v, const double* v_prev,
                                       double* grad_a, double* grad_c, double* grad_i, void* stream);
+
+/* The solver layout of a cell-lane plan (paper §7, Fig 7.1: the solver works
+ * on a solver-specific data format; permutation kernels move data into it and
+ * the solution out of it).  A compartment's slot is its step in the walk of
+ * its lane: per (wave, chunk of 16 steps, pair of steps, lane) one 16-byte
+ * unit of two doubles, so a wave instruction of the solve touches one
+ * contiguous KiB.  Slots beyond a lane's walk (padding) hold a copy of the
+ * cell's first compartment.
+ *   hines_layout_size: *slots = doubles of one array in the layout (the
+ *     padded step count of all waves times 64).
+ *   hines_to_layout:   dst[slots] <- src[n] (user numbering), any array.
+ *   hines_from_layout: dst[n] <- src[slots]; padding slots are not read.
+ *   hines_solve_layout: A x = rhs with diag, upper, rhs and x all in the
+ *     layout (device arrays of `slots` doubles); upper of a cell root and of
+ *     padding is ignored.  x may alias rhs, not diag or upper.  Bytes moved:
+ *     d, u, b read and x written once, plus a 16-byte round trip per slot
+ *     through the plan's scratch (the factors between the two sweeps).
+ * HINES_ERR_STATE on a plan without cell lanes.  src and dst must not alias.
+ * Asynchronous on stream. */
+hines_status hines_layout_size(const hines_plan* plan, int64_t* slots);
+hines_status hines_to_layout(const hines_plan* plan, const double* src, double* dst, void* stream);
+hines_status hines_from_layout(const hines_plan* plan, const double* src, double* dst, void* stream);
+hines_status hines_solve_layout(const hines_plan* plan, const double* diag_l, const double* upper_l,
+                                const double* rhs_l, double* x_l, int32_t ncells, void* stream);
 
 /* Check that (diag, upper) is a matrix the solver is defined for (paper §1:
  * A is symmetric, which the storage of one coupling per edge guarantees, and

@@ -32,7 +32,7 @@ def _run(cmd, verbose):
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
-    for src in ("setup.cpp", "cells.cpp"):
+    for src in ("setup.cpp", "cells.cpp", "resident.cpp"):
         o = os.path.join(BUILD, src.replace(".cpp", ".o"))
         _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", o], verbose)
         objs.append(o)

@@ -68,6 +68,8 @@ hines_status ok() {
 // matter; each class is one launch, so there are few of them.
 constexpr int kBuckets[] = {4096, 8192, 12288, 16384, 20480, 23296, 27136, 32768, 40960, 54528, 81920, 163840};
 constexpr int kGlobalT = 256;  // workgroup of groups whose image lives in the workspace
+// LDS classes of the resident kernel: 160 KiB / k for k = 8 .. 1 waves per CU
+constexpr int kResBuckets[] = {20480, 23296, 27136, 32768, 40960, 54528, 81920, 163840};
 
 inline LdsLayout layout_of(const KGroup& g) {
   return LdsLayout{g.ws_off >= 0 ? 0 : g.nunk, (g.nbr + 1) & ~1, g.nlev};
@@ -88,6 +90,8 @@ struct hines_plan {
   };
   std::vector<Bucket> buckets;
   std::vector<Bucket> mixed_buckets;  // FP32+refinement kernel (its own LDS layout)
+  std::vector<Bucket> res_buckets;    // LDS-resident kernel, by LDS class
+  std::vector<int32_t> res_list;      // resident group ids in launch order
   bool mixed_ok = false;              // every group fits the mixed layout in LDS
   int64_t max_lds = 0;
   // user-numbering tables of the element-wise kernels, uploaded on first use
@@ -144,8 +148,21 @@ void launch_bucket(const hines_plan* p, const hines_plan::Bucket& bk, const RhsS
   }
 }
 
+hipError_t launch_resident(const hines_plan* p, const double* d, const double* u, const double* b, double* x,
+                           hipStream_t s) {
+  for (const auto& bk : p->res_buckets) {
+    DevTables t = p->t;
+    t.rlist = p->t.rlist + bk.first;
+    hipLaunchKernelGGL(hdev::k_solve_res, dim3((unsigned)bk.count), dim3(64), bk.lds_bytes, s, t, d, u, b, x);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_solve(const hines_plan* p, const RhsSpec& rs, const double* d, const double* u, double* x,
                         hipStream_t s) {
+  if (p->host.res.built && rs.mode == hdev::kRhsGiven) return launch_resident(p, d, u, rs.rhs, x, s);
   if (p->host.cl.built) {
     const dim3 grid((unsigned)p->host.cl.nwaves);
     if (rs.mode == hdev::kRhsGiven)
@@ -565,10 +582,12 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
     opt = *opt_in;
   else
     hines_default_options(&opt);
-  for (int k = 0; k < 6; ++k)
+  for (int k = 0; k < 5; ++k)
     if (opt.reserved[k] != 0) return set_err(HINES_ERR_OPTION, "reserved option fields must be 0");
   if (opt.cell_lanes && opt.bitwise)
     return set_err(HINES_ERR_OPTION, "cell_lanes needs the fast arithmetic form (bitwise 0)");
+  if (opt.resident && (opt.bitwise || opt.cell_lanes))
+    return set_err(HINES_ERR_OPTION, "resident needs bitwise 0 and cell_lanes 0");
   hines::Options o;
   o.rebalance_root = opt.rebalance_root != 0;
   o.split_branches = opt.split_branches != 0;
@@ -580,6 +599,7 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   o.bitwise = opt.bitwise != 0;
   o.scheduler = opt.level_sync ? 0 : 1;
   o.cell_lanes = opt.cell_lanes != 0;
+  o.resident = opt.resident != 0;
   if (o.cell_lanes) o.scheduler = 0;  // the groups serve hines_solve_mixed only
   hines_plan* p = new (std::nothrow) hines_plan();
   if (!p) return set_err(HINES_ERR_OOM, "host allocation failed");
@@ -595,6 +615,14 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
     if (s != hines::OK) {
       delete p;
       return set_err((hines_status)s, "cell lanes: %s", why.c_str());
+    }
+  }
+  if (o.resident) {
+    s = hines::build_resident(parent, n, cell_offsets, ncells, p->host.res, why);
+    if (s == hines::OK && !hines::check_resident(p->host.res, parent, n, why)) s = hines::ERR_STATE;
+    if (s != hines::OK) {
+      delete p;
+      return set_err((hines_status)s, "resident: %s", why.c_str());
     }
   }
   bool capacity = false;
@@ -662,6 +690,26 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
         glist.insert(glist.end(), m.begin(), m.end());
       }
   }
+  // resident groups by LDS class, longest schedules first within a class
+  if (P.res.built) {
+    const int nbk2 = (int)(sizeof kResBuckets / sizeof kResBuckets[0]);
+    std::vector<std::vector<int32_t>> rm(nbk2);
+    for (int64_t g = 0; g < (int64_t)P.res.groups.size(); ++g) {
+      const int32_t bytes = P.res.groups[g].lds_bytes;
+      int k = 0;
+      while (k < nbk2 - 1 && kResBuckets[k] < bytes) ++k;
+      rm[k].push_back((int32_t)g);
+    }
+    for (int k = nbk2 - 1; k >= 0; --k) {
+      auto& m = rm[k];
+      if (m.empty()) continue;
+      std::stable_sort(m.begin(), m.end(), [&](int32_t a, int32_t b) {
+        return P.res.groups[a].makespan > P.res.groups[b].makespan;
+      });
+      p->res_buckets.push_back({kResBuckets[k], (int32_t)p->res_list.size(), (int32_t)m.size(), 0, 0});
+      p->res_list.insert(p->res_list.end(), m.begin(), m.end());
+    }
+  }
   if (o.host_only) {
     *out = p;
     return ok();
@@ -686,11 +734,19 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   const int64_t sz_cp = al((int64_t)CL.pos.size() * sizeof(uint16_t));
   const int64_t sz_cf = al((int64_t)CL.flags.size());
   const int64_t sz_cm = al((int64_t)CL.mbsrc.size() * sizeof(uint64_t));
+  const hines::ResPlan& RP = P.res;
+  const int64_t sz_rg = al((int64_t)RP.groups.size() * sizeof(hines::KResGroup));
+  const int64_t sz_rl = al((int64_t)p->res_list.size() * sizeof(int32_t));
+  const int64_t sz_rp = al((int64_t)RP.par.size() * sizeof(uint16_t));
+  const int64_t sz_rb = al((int64_t)RP.blob.size());
   const int64_t total = sz_br + sz_grp + sz_seg + sz_cell + sz_gl + sz_ws + sz_fl + sz_fm + sz_fp + sz_fa + sz_cw +
-                        sz_cb + sz_cp + sz_cf + sz_cm + 256;
+                        sz_cb + sz_cp + sz_cf + sz_cm + sz_rg + sz_rl + sz_rp + sz_rb + 256;
   const int64_t scr_bytes = CL.nchunks * hines::kCellChunk * 64 * 16;
   hipError_t e = hipGetDevice(&p->device);
   if (e == hipSuccess) e = allow_lds(o.group_width);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)hdev::k_solve_res, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)hines::kLdsLimitBytes);
   if (e != hipSuccess) {
     delete p;
     return set_err(HINES_ERR_HIP, "device setup: %s", hipGetErrorString(e));
@@ -762,6 +818,18 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   p->t.cmsrc = (const uint64_t*)(base + off);
   if (e == hipSuccess) e = up(CL.mbsrc.data(), (int64_t)CL.mbsrc.size() * sizeof(uint64_t), off);
   off += sz_cm;
+  p->t.rgrp = (const hines::KResGroup*)(base + off);
+  if (e == hipSuccess) e = up(RP.groups.data(), (int64_t)RP.groups.size() * sizeof(hines::KResGroup), off);
+  off += sz_rg;
+  p->t.rlist = (const int32_t*)(base + off);
+  if (e == hipSuccess) e = up(p->res_list.data(), (int64_t)p->res_list.size() * sizeof(int32_t), off);
+  off += sz_rl;
+  p->t.rpar = (const uint16_t*)(base + off);
+  if (e == hipSuccess) e = up(RP.par.data(), (int64_t)RP.par.size() * sizeof(uint16_t), off);
+  off += sz_rp;
+  p->t.rblob = (const uint8_t*)(base + off);
+  if (e == hipSuccess) e = up(RP.blob.data(), (int64_t)RP.blob.size(), off);
+  off += sz_rb;
   p->t.cscr = (double*)p->scr_mem;
   p->t.cslots = CL.nchunks * hines::kCellChunk * 64;
   if (e != hipSuccess) {
@@ -1059,6 +1127,56 @@ hines_status hines_adjoint_accumulate(hines_plan* p, const double* lam, const do
   return launched();
 }
 
+hines_status hines_layout_size(const hines_plan* p, int64_t* slots) {
+  if (!p || !slots) return set_err(HINES_ERR_NULL, "NULL argument");
+  *slots = 0;
+  if (!p->host.cl.built) return set_err(HINES_ERR_STATE, "the solver layout needs a cell-lane plan");
+  *slots = p->host.cl.nchunks * hines::kCellChunk * 64;
+  return ok();
+}
+
+static hines_status layout_call(const hines_plan* p, const void* a, const void* b) {
+  hines_status st = check_call(p, p ? (int32_t)p->host.ncells : 0);
+  if (st != HINES_OK) return st;
+  if (!p->host.cl.built) return set_err(HINES_ERR_STATE, "the solver layout needs a cell-lane plan");
+  if (p->host.n > 0 && (!a || !b)) return set_err(HINES_ERR_NULL, "a device array is NULL");
+  if (p->host.n > 0 && a == b) return set_err(HINES_ERR_STATE, "src and dst must not alias");
+  return HINES_OK;
+}
+
+hines_status hines_to_layout(const hines_plan* p, const double* src, double* dst, void* stream) {
+  hines_status st = layout_call(p, src, dst);
+  if (st != HINES_OK) return st;
+  if (p->host.n == 0) return ok();
+  hipLaunchKernelGGL(hdev::k_cells_to_walk, dim3((unsigned)p->host.cl.nwaves), dim3(64), 0, (hipStream_t)stream,
+                     p->t, src, dst);
+  return launched();
+}
+
+hines_status hines_from_layout(const hines_plan* p, const double* src, double* dst, void* stream) {
+  hines_status st = layout_call(p, src, dst);
+  if (st != HINES_OK) return st;
+  if (p->host.n == 0) return ok();
+  hipLaunchKernelGGL(hdev::k_cells_from_walk, dim3((unsigned)p->host.cl.nwaves), dim3(64), 0, (hipStream_t)stream,
+                     p->t, src, dst);
+  return launched();
+}
+
+hines_status hines_solve_layout(const hines_plan* p, const double* diag_l, const double* upper_l,
+                                const double* rhs_l, double* x_l, int32_t ncells, void* stream) {
+  hines_status st = check_call(p, ncells);
+  if (st != HINES_OK) return st;
+  if (!p->host.cl.built) return set_err(HINES_ERR_STATE, "hines_solve_layout needs a cell-lane plan");
+  if (p->host.n == 0) return ok();
+  if (!diag_l || !upper_l || !rhs_l || !x_l) return set_err(HINES_ERR_NULL, "a device array is NULL");
+  if ((const void*)x_l == (const void*)diag_l || (const void*)x_l == (const void*)upper_l)
+    return set_err(HINES_ERR_STATE, "x must not alias diag or upper");
+  hdev::WalkSolve L{diag_l, upper_l, rhs_l, x_l, p->t.cscr};
+  hipLaunchKernelGGL(hdev::k_solve_walk, dim3((unsigned)p->host.cl.nwaves), dim3(64), 0, (hipStream_t)stream, p->t,
+                     L);
+  return launched();
+}
+
 hines_status hines_check_matrix(hines_plan* p, const double* diag, const double* upper, int64_t* first_bad,
                                 void* stream) {
   if (first_bad) *first_bad = -1;
@@ -1099,8 +1217,9 @@ hines_status hines_plan_info_get(const hines_plan* p, hines_plan_info* info) {
   info->nclasses = nb;
   info->device_table_bytes = p->dev_bytes;
   info->max_group_lds_bytes = p->max_lds;
-  info->kernel = p->host.cl.built ? 3 : (p->host.flow ? 1 : (p->host.opt.bitwise ? 2 : 0));
+  info->kernel = p->host.res.built ? 4 : p->host.cl.built ? 3 : (p->host.flow ? 1 : (p->host.opt.bitwise ? 2 : 0));
   if (p->host.cl.built) info->nclasses = 1;
+  if (p->host.res.built) info->nclasses = (int32_t)p->res_buckets.size();
   int32_t mk = 0;
   int64_t ng_ws = 0;
   for (const auto& G : p->host.kgroup) {
@@ -1109,6 +1228,10 @@ hines_status hines_plan_info_get(const hines_plan* p, hines_plan_info* info) {
   }
   if (p->host.cl.built)
     for (const auto& W : p->host.cl.waves) mk = std::max(mk, W.nchunk);
+  if (p->host.res.built) {
+    mk = 0;
+    for (const auto& G : p->host.res.groups) mk = std::max(mk, G.makespan);
+  }
   info->max_makespan = mk;
   info->workspace_groups = ng_ws;
   return ok();

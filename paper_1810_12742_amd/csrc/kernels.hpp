@@ -39,6 +39,10 @@ struct DevTables {
   const uint64_t* cmsrc;          // cell-lane kernel: mailbox source lists per lane
   double* cscr;                   // cell-lane kernel: (f, y) per step and lane
   int64_t cslots;                 // cell-lane kernel: steps x lanes of all waves (walk-layout array length)
+  const hines::KResGroup* rgrp;   // resident kernel: per group
+  const int32_t* rlist;           // resident kernel: group ids of one launch
+  const uint16_t* rpar;           // resident kernel: parent slot of every compartment (n + 2)
+  const uint8_t* rblob;           // resident kernel: per-group lane offsets, roots and path records
 };
 
 // Right-hand side of a solve: given (kRhsGiven), c v + i (kRhsCV; i may be
@@ -1219,6 +1223,211 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
 }
 
 // ---------------------------------------------------------------------------
+// LDS-resident solve: one wave per group of whole cells.  The group's d, u, b
+// and parent slots are staged into LDS once by global->LDS DMA, in the user
+// numbering (slot s = user index lo + s); the sweeps touch only LDS; the
+// solution leaves in coalesced 16-byte stores.
+//
+// Backward sweep (paper §2: every compartment after its children).  Lane l
+// runs its path records in step order: a path is eliminated from its bottom
+// (a leaf) to its top in consecutive steps, each step j -> parent(j), so the
+// contribution (u f, f b') to the next compartment stays in registers; at the
+// top it is added into the parent's LDS entry (d_p -= u f, b_p -= f b') unless
+// the top is a cell root.  The setup ends every such path at least one step
+// before its parent is eliminated, and every LDS read of a step's operands is
+// issued after all additions of the steps before it (the wave executes its
+// LDS operations in order), so each compartment is eliminated once all its
+// children have contributed.  A step stores f = u / d' over d, y = b' / d'
+// over b and, over u, the slot the lane eliminated before it on this path.
+//
+// Forward sweep: the steps in reverse.  A path runs from its top (x of the
+// parent read from LDS, written at an earlier step, zero for a root) down the
+// stored links: x_j = y_j - f_j x_parent, written over y.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) u32x2 lds_u2;
+
+struct ResRec {
+  int slot, t0, tend, aux;
+};
+// record k of the lane (records kb .. ke - 1), or an idle record (never
+// active, reads the zero slot)
+__device__ __forceinline__ ResRec res_rec(const lds_u2* recs, int k, int kb, int ke, int zero, int F) {
+  ResRec r{zero, F + 1, F + 1, zero};
+  if (k >= kb && k < ke) {
+    const u32x2 w = recs[k];
+    r.slot = (int)(w.x & 0xffffu);
+    r.t0 = (int)(w.x >> 16);
+    r.tend = r.t0 + (int)(w.y & 0xffffu);
+    r.aux = (int)(w.y >> 16);
+  }
+  return r;
+}
+
+__global__ __launch_bounds__(64) void k_solve_res(DevTables tb, const double* __restrict__ d,
+                                                  const double* __restrict__ u, const double* __restrict__ b,
+                                                  double* __restrict__ x) {
+  extern __shared__ __attribute__((aligned(16))) double res_raw[];
+  const hines::KResGroup G = tb.rgrp[tb.rlist[blockIdx.x]];
+  const int lane = threadIdx.x;
+  const int S = G.nslot + 2;  // slots nslot (zero entry) and nslot + 1 (spare)
+  const int zero = G.nslot;
+  const int F = G.makespan;
+  char* base = (char*)res_raw;
+  const int oU = 8 * S, oB = 16 * S, oP = 24 * S, oBlob = oP + ((2 * G.nslot + 15) & ~15);
+  // ---- staging ----
+  const int nu = G.ndma >> 1;
+  dma16<64>(d + G.lo, base, nu, lane);
+  dma16<64>(u + G.lo, base + oU, nu, lane);
+  dma16<64>(b + G.lo, base + oB, nu, lane);
+  dma4<64>(tb.rpar + G.lo, base + oP, G.nslot >> 1, lane);
+  dma16<64>(tb.rblob + 16 * G.blob, base + oBlob, G.blob_units, lane);
+  lds_f64* D = (lds_f64*)base;
+  lds_f64* U = (lds_f64*)(base + oU);
+  lds_f64* B = (lds_f64*)(base + oB);
+  const lds_u16* PAR = (const lds_u16*)(base + oP);
+  double tail_d = 0.0, tail_u = 0.0, tail_b = 0.0;
+  const bool tail = (G.ndma & 1) && lane == 0;
+  if (tail) {
+    tail_d = d[G.lo + G.ndma - 1];
+    tail_u = u[G.lo + G.ndma - 1];
+    tail_b = b[G.lo + G.ndma - 1];
+  }
+  __builtin_amdgcn_s_waitcnt(0);  // every DMA of this wave has landed
+  if (tail) {
+    D[G.ndma - 1] = tail_d;
+    U[G.ndma - 1] = tail_u;
+    B[G.ndma - 1] = tail_b;
+  }
+  if (lane < 2) {  // the zero entry (and the spare): eliminates to nothing
+    D[zero + lane] = 1.0;
+    U[zero + lane] = 0.0;
+    B[zero + lane] = 0.0;
+  }
+  const lds_u16* ltab = (const lds_u16*)(base + oBlob);
+  const lds_u16* roots = ltab + hines::kResLaneTab / 2;
+  for (int r = lane; r < G.nroot; r += 64) U[roots[r]] = 0.0;  // a root has no coupling
+  lds_u2* recs = (lds_u2*)(base + oBlob + hines::kResLaneTab + ((2 * G.nroot + 15) & ~15));
+  const int kb = ltab[lane], ke = ltab[lane + 1];
+
+  // ---- backward sweep ----
+  {
+    int ri = kb;
+    ResRec c = res_rec(recs, ri, kb, ke, zero, F), nx = res_rec(recs, ri + 1, kb, ke, zero, F);
+    int j = c.slot, prev = zero;
+    double d1 = D[j], u1 = U[j], b1 = B[j];
+    int p1 = PAR[j];
+    double d2 = D[nx.slot], u2 = U[nx.slot], b2 = B[nx.slot];
+    int p2 = PAR[nx.slot];
+    double cd = 0.0, cb = 0.0;
+    for (int t = 0; t < F; ++t) {
+      const bool act = t >= c.t0 && t < c.tend;
+      const bool top = act && t == c.tend - 1;
+      if (act) {
+        const double dd = d1 - cd, bb = b1 - cb;
+        const double r = rcp_nr(dd);
+        const double f = u1 * r;
+        D[j] = f;
+        B[j] = bb * r;
+        *(lds_u16*)(U + j) = (uint16_t)prev;
+        cd = u1 * f;
+        cb = f * bb;
+      }
+      if (top && c.aux) {  // the path's contribution to the parent of its top
+        lds_add(D + p1, -cd);
+        lds_add(B + p1, -cb);
+      }
+      __asm__ volatile("" ::: "memory");  // the additions precede every read below
+      if (act) {
+        if (top) {
+          recs[ri] = u32x2{(unsigned)j | ((unsigned)c.t0 << 16), (unsigned)(c.tend - c.t0) | ((unsigned)p1 << 16)};
+          cd = 0.0;
+          cb = 0.0;
+          prev = zero;
+          ri += 1;
+          c = nx;
+          j = c.slot;
+          d1 = d2;
+          u1 = u2;
+          b1 = b2;
+          p1 = p2;
+          nx = res_rec(recs, ri + 1, kb, ke, zero, F);
+          d2 = D[nx.slot];  // a path's bottom is a leaf: nothing adds into it
+          u2 = U[nx.slot];
+          b2 = B[nx.slot];
+          p2 = PAR[nx.slot];
+        } else {
+          prev = j;
+          j = p1;
+          d1 = D[j];
+          u1 = U[j];
+          b1 = B[j];
+          p1 = PAR[j];
+        }
+      }
+    }
+  }
+  __asm__ volatile("" ::: "memory");
+
+  // ---- forward sweep: steps in reverse, records in reverse ----
+  {
+    int ri = ke - 1;
+    // after the backward sweep a record holds (top slot, t0, len, parent slot of the top)
+    ResRec c = res_rec(recs, ri, kb, ke, zero, F), nx = res_rec(recs, ri - 1, kb, ke, zero, F);
+    int j = c.slot;
+    double f1 = D[j], y1 = B[j];
+    int l1 = *(const lds_u16*)(U + j);
+    double f2 = D[nx.slot], y2 = B[nx.slot];
+    int l2 = *(const lds_u16*)(U + nx.slot);
+    double xp = 0.0;
+    for (int t = F - 1; t >= 0; --t) {
+      const bool act = t >= c.t0 && t < c.tend;
+      if (act) {
+        if (t == c.tend - 1) xp = B[c.aux];  // x of the top's parent (0 for a root)
+        const double xv = __builtin_fma(-f1, xp, y1);
+        B[j] = xv;
+        xp = xv;
+      }
+      __asm__ volatile("" ::: "memory");
+      if (act) {
+        if (t == c.t0) {  // the path's bottom: next record
+          ri -= 1;
+          c = nx;
+          j = c.slot;
+          f1 = f2;
+          y1 = y2;
+          l1 = l2;
+          nx = res_rec(recs, ri - 1, kb, ke, zero, F);
+          f2 = D[nx.slot];  // a top's f and y are not written before its own step
+          y2 = B[nx.slot];
+          l2 = *(const lds_u16*)(U + nx.slot);
+        } else {
+          j = l1;
+          f1 = D[j];
+          y1 = B[j];
+          l1 = *(const lds_u16*)(U + j);
+        }
+      }
+    }
+  }
+  __asm__ volatile("" ::: "memory");
+
+  // ---- store slots [first, first + count) ----
+  const int s0 = G.first, s1 = G.first + G.count;
+  double* xo = x + G.lo;
+  for (int k = lane; 2 * k < s1; k += 64) {
+    const int a = 2 * k;
+    if (a >= s0 && a + 1 < s1) {
+      *(double2_t*)(xo + a) = *(const lds_d2*)(B + a);
+    } else {
+      if (a >= s0 && a < s1) xo[a] = B[a];
+      if (a + 1 >= s0 && a + 1 < s1) xo[a + 1] = B[a + 1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Time loop with the factors kept (cell-lane plans).  The matrix of a time
 // loop does not change between steps, so the elimination of A (paper §2: the
 // pivots d' and f = u / d') is done once per loop launch and each step only
@@ -1457,6 +1666,173 @@ __global__ __launch_bounds__(64) void k_cells_step(DevTables tb, CellLoop L) {
     if (k < 1) break;
     if (k >= 2) step_load_f<RHS>(A, L, W, flv, k - 2, lane);
     step_forward<RHS>(B, L, W, k - 1, lane, stk, mb, xc, xt, m, msf);
+    if (k < 2) break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Solve in the walk layout (cell-lane plans; paper §7, Fig 7.1: the solver
+// works on its own data format, permutation kernels move data into and out
+// of it).  d, u, b and x sit in the walk layout of k_cells_to_walk, so every
+// access of the sweeps is one coalesced 16-byte unit per lane (a KiB per wave
+// instruction) and no gather passes through LDS.  The elimination is the
+// cell-lane one (cell_backward's flags, stack and mailboxes); the backward
+// sweep stores f = u / d' in the plan's scratch and y = b' / d' in x, the
+// forward sweep overwrites y with x.  Roots and padding have no coupling.
+// ---------------------------------------------------------------------------
+struct WalkSolve {
+  const double* d;
+  const double* u;
+  const double* b;
+  double* x;
+  double* f;  // f per walk slot (the plan's scratch)
+};
+
+struct WalkChunk {
+  double2_t d[CK / 2], u[CK / 2], b[CK / 2];
+  cflag_t fl;
+};
+
+__device__ __forceinline__ void walk_load_b(WalkChunk& C, const WalkSolve& L, const cflag_t* flv, int64_t chunk,
+                                            int k, int lane) {
+  C.fl = flag_ld(flv + 64 * k);
+#pragma unroll
+  for (int q = 0; q < CK / 2; ++q) {
+    const int64_t o = walk_pair(chunk, q, lane);
+    C.d[q] = ((const double2_t*)L.d)[o];
+    C.u[q] = ((const double2_t*)L.u)[o];
+    C.b[q] = ((const double2_t*)L.b)[o];
+  }
+}
+
+__device__ __forceinline__ void walk_load_f(WalkChunk& C, const WalkSolve& L, const cflag_t* flv, int64_t chunk,
+                                            int k, int lane) {
+  C.fl = flag_ld(flv + 64 * k);
+#pragma unroll
+  for (int q = 0; q < CK / 2; ++q) {
+    const int64_t o = walk_pair(chunk, q, lane);
+    C.d[q] = ((const double2_t*)L.f)[o];  // f
+    C.b[q] = ((const double2_t*)L.x)[o];  // y
+  }
+}
+
+__device__ __forceinline__ void walk_backward(const WalkChunk& C, const WalkSolve& L, int64_t chunk, int lane,
+                                              lds_d2* stk, lds_d2* mb, double& cd, double& cb, double& td,
+                                              double& tb, int& m, unsigned& msrc) {
+  double fv[CK], yv[CK];
+#pragma unroll
+  for (int e = 0; e < CK; ++e) {
+    const unsigned fe = cell_byte(C.fl, e);
+    double dd = pair_at(C.d, e), bb = pair_at(C.b, e);
+    const double uu = (fe & (hines::CF_ROOT | hines::CF_PAD)) ? 0.0 : pair_at(C.u, e);
+    const double kc = (fe & hines::CF_TIP) ? 0.0 : 1.0;
+    dd = __builtin_fma(-kc, cd, dd);
+    bb = __builtin_fma(-kc, cb, bb);
+    if (fe & hines::CF_MBIN) {
+      const double2_t mv = mb[msrc & 63u];
+      msrc >>= 6;
+      dd = dd - mv.x;
+      bb = bb - mv.y;
+    }
+    if (fe & hines::CF_POP) {
+      dd = dd - td;
+      bb = bb - tb;
+      m -= 1;
+      const double2_t t = stk[64 * m];
+      td = t.x;
+      tb = t.y;
+    }
+    const double rr = rcp_nr(dd);
+    fv[e] = uu * rr;
+    yv[e] = bb * rr;
+    cd = uu * fv[e];
+    cb = fv[e] * bb;
+    if (fe & hines::CF_PUSH) {
+      stk[64 * m] = double2_t{td, tb};
+      m += 1;
+      td = cd;
+      tb = cb;
+    }
+    if (fe & hines::CF_MERGE) {
+      td = td + cd;
+      tb = tb + cb;
+    }
+    if (fe & hines::CF_MBOUT) mb[lane] = double2_t{cd, cb};
+  }
+#pragma unroll
+  for (int q = 0; q < CK / 2; ++q) {
+    const int64_t o = walk_pair(chunk, q, lane);
+    ((double2_t*)L.f)[o] = double2_t{fv[2 * q], fv[2 * q + 1]};
+    ((double2_t*)L.x)[o] = double2_t{yv[2 * q], yv[2 * q + 1]};
+  }
+}
+
+__device__ __forceinline__ void walk_forward(const WalkChunk& C, const WalkSolve& L, int64_t chunk, int lane,
+                                             lds_f64* stx, lds_d2* mb, double& xc, double& xt, int& m,
+                                             unsigned& msrc) {
+  double x[CK];
+#pragma unroll
+  for (int e = CK - 1; e >= 0; --e) {
+    const unsigned fe = cell_byte(C.fl, e);
+    double xp = (fe & (hines::CF_PUSH | hines::CF_MERGE)) ? xt : xc;
+    if (fe & hines::CF_MBOUT) xp = mb[lane].x;  // x of the parent, posted by the receiving lane
+    if (fe & hines::CF_PUSH) {
+      m -= 1;
+      xt = stx[64 * m];
+    }
+    const double xv = __builtin_fma(-pair_at(C.d, e), xp, pair_at(C.b, e));
+    if (fe & hines::CF_POP) {
+      stx[64 * m] = xt;
+      m += 1;
+      xt = xv;
+    }
+    if (fe & hines::CF_MBIN) {
+      mb[msrc & 63u].x = xv;
+      msrc >>= 6;
+    }
+    xc = xv;
+    x[e] = xv;
+  }
+#pragma unroll
+  for (int q = 0; q < CK / 2; ++q)
+    ((double2_t*)L.x)[walk_pair(chunk, q, lane)] = double2_t{x[2 * q], x[2 * q + 1]};
+}
+
+__global__ __launch_bounds__(64) void k_solve_walk(DevTables tb, WalkSolve L) {
+  __shared__ __attribute__((aligned(16))) double2_t wraw[hines::kCellStack * 64 + 64];
+  lds_d2* stk = (lds_d2*)wraw + threadIdx.x;  // slot s at stk[64 s]
+  lds_d2* mb = (lds_d2*)wraw + hines::kCellStack * 64;
+  const int lane = threadIdx.x;
+  const hines::KCellWave W = tb.cwave[blockIdx.x];
+  const int nk = W.nchunk;
+  const cflag_t* flv = (const cflag_t*)(tb.cflag + W.chunk_off * hines::kCellChunkElems) + lane;
+  WalkChunk A, B;
+  const uint64_t ms = tb.cmsrc[(int64_t)blockIdx.x * 64 + lane];
+  unsigned msb = (unsigned)ms, msf = (unsigned)(ms >> 32);
+  double cd = 0.0, cb = 0.0, td = 0.0, tb_ = 0.0;
+  int m = 0;
+  walk_load_b(A, L, flv, W.chunk_off, 0, lane);
+  for (int k = 0;; k += 2) {
+    if (k + 1 < nk) walk_load_b(B, L, flv, W.chunk_off + k + 1, k + 1, lane);
+    walk_backward(A, L, W.chunk_off + k, lane, stk, mb, cd, cb, td, tb_, m, msb);
+    if (k + 1 >= nk) break;
+    if (k + 2 < nk) walk_load_b(A, L, flv, W.chunk_off + k + 2, k + 2, lane);
+    walk_backward(B, L, W.chunk_off + k + 1, lane, stk, mb, cd, cb, td, tb_, m, msb);
+    if (k + 2 >= nk) break;
+  }
+  // the forward sweep reads back this wave's own stores
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  lds_f64* stx = (lds_f64*)wraw + threadIdx.x;  // slot s at stx[64 s]
+  double xc = 0.0, xt = 0.0;
+  m = 0;
+  walk_load_f(A, L, flv, W.chunk_off + nk - 1, nk - 1, lane);
+  for (int k = nk - 1;; k -= 2) {
+    if (k >= 1) walk_load_f(B, L, flv, W.chunk_off + k - 1, k - 1, lane);
+    walk_forward(A, L, W.chunk_off + k, lane, stx, mb, xc, xt, m, msf);
+    if (k < 1) break;
+    if (k >= 2) walk_load_f(A, L, flv, W.chunk_off + k - 2, k - 2, lane);
+    walk_forward(B, L, W.chunk_off + k - 1, lane, stx, mb, xc, xt, m, msf);
     if (k < 2) break;
   }
 }

@@ -946,6 +946,47 @@ int64_t export_table(const HostPlan& p, int32_t id, int64_t* out, int64_t capaci
     case T_CELL_POS: return put(p.cl.pos);
     case T_CELL_FLAGS: return put(p.cl.flags);
     case T_CELL_MBSRC: return put(p.cl.mbsrc);
+    case T_RES_GROUPS: {
+      const int64_t cnt = 10 * (int64_t)p.res.groups.size();
+      if (out) {
+        if (capacity < cnt) return -1;
+        for (int64_t g = 0; g < cnt / 10; ++g) {
+          const KResGroup& G = p.res.groups[g];
+          int64_t* r = out + 10 * g;
+          r[0] = G.lo;
+          r[1] = G.blob;
+          r[2] = G.nslot;
+          r[3] = G.ndma;
+          r[4] = G.first;
+          r[5] = G.count;
+          r[6] = G.makespan;
+          r[7] = G.blob_units;
+          r[8] = G.nroot;
+          r[9] = G.npath;
+        }
+      }
+      return cnt;
+    }
+    case T_RES_PAR: {
+      const int64_t cnt = p.res.built ? p.n : 0;
+      if (out) {
+        if (capacity < cnt) return -1;
+        for (int64_t i = 0; i < cnt; ++i) out[i] = p.res.par[i];
+      }
+      return cnt;
+    }
+    case T_RES_BLOB: {
+      const int64_t cnt = (int64_t)p.res.blob.size() / 2;
+      if (out) {
+        if (capacity < cnt) return -1;
+        for (int64_t k = 0; k < cnt; ++k) {
+          uint16_t v;
+          std::memcpy(&v, p.res.blob.data() + 2 * k, 2);
+          out[k] = v;
+        }
+      }
+      return cnt;
+    }
     default: return -1;
   }
 }

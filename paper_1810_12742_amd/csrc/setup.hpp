@@ -37,6 +37,7 @@ struct Options {
   int32_t scheduler = 1;           // 1: static heavy-path lane schedule when every branch ascends;
                                    // 0: level-synchronous sweeps (paper §3)
   int32_t cell_lanes = 0;          // 1: one lane per cell (streaming kernel) for hines_solve / timestep
+  int32_t resident = 0;            // 1: LDS-resident path-walk kernel for hines_solve
 };
 
 // Static chunk schedule (flow kernel): one lane eliminates kFlowChunk
@@ -92,7 +93,10 @@ enum TableId : int32_t {
   T_CELL_POS = 14,        // int64[nchunks*kCellChunkElems]: [chunk][staging lane][slot] relative position
   T_CELL_FLAGS = 15,      // int64[nchunks*kCellChunkElems]: [chunk][cell lane][element] flags
   T_CELL_MBSRC = 16,      // int64[nwaves*64]: mailbox source lanes (6 bits each), backward | forward << 32
-  T_NUM = 17,
+  T_RES_GROUPS = 17,      // int64[ngroups*10]: lo, blob, nslot, ndma, first, count, makespan, blob_units, nroot, npath
+  T_RES_PAR = 18,         // int64[n]: parent slot of each compartment in its group image
+  T_RES_BLOB = 19,        // int64[blob bytes / 2]: the blobs as uint16 words
+  T_NUM = 20,
 };
 
 // Cell-lane kernel (one lane per cell, or per half of a long cell).  Each cell is processed in a depth-
@@ -158,6 +162,69 @@ struct CellLanes {
 // than kCellStack stack entries.
 Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_offsets, int64_t ncells,
                         CellLanes& out, std::string& err);
+
+// LDS-resident solve (one wave per group of whole cells).  A group's d, u, b
+// (8 bytes each) and the parent slot of every compartment (2 bytes) are staged
+// into LDS once, in the user numbering: slot s holds user index lo + s.  Each
+// lane walks root-ward paths of the tree (paper §2: children before parents):
+// a path starts at a leaf and follows parents up to the top, a compartment
+// that is either a cell root or not the "heavy" child of its parent (the child
+// whose subtree finishes last).  A path's contribution to the parent of its top
+// is added into the parent's LDS entry at its last step, at least one step
+// before the parent is eliminated; inside a path the contribution stays in
+// registers.  The steps are fixed at setup (an as-late-as-possible list
+// schedule over the wave's 64 lanes), so every lane knows from its records when
+// it is busy; the forward sweep runs the steps in reverse.
+struct KResGroup {
+  int64_t lo;          // user index of LDS slot 0 (even)
+  int64_t blob;        // first 16-byte unit of the group's blob
+  int32_t nslot;       // slots of the image (even); slot nslot is the zero entry
+  int32_t ndma;        // slots staged from the user arrays: min(nslot, n - lo)
+  int32_t first;       // slot of the group's first compartment (0 or 1)
+  int32_t count;       // compartments of the group
+  int32_t makespan;    // steps per sweep
+  int32_t blob_units;  // 16-byte units of the blob
+  int32_t nroot;       // cells of the group
+  int32_t lds_bytes;   // LDS image
+  int32_t npath;       // paths (records)
+  int32_t pad;
+};
+static_assert(sizeof(KResGroup) == 56, "layout");
+// Path record: bottom slot (a leaf; replaced by the top slot during the
+// backward sweep), first step, length, flags (bit 0: the contribution of the
+// top goes to its parent's LDS entry; replaced by the top's parent slot during
+// the backward sweep).
+struct KResRec {
+  uint16_t slot, t0, len, aux;
+};
+static_assert(sizeof(KResRec) == 8, "layout");
+// Blob of a group, in 16-byte units: the 65 record offsets of the lanes (uint16,
+// kResLaneTab bytes), the root slots of its cells (uint16, padded to 16 bytes),
+// then the records, lane by lane in step order.
+constexpr int32_t kResLaneTab = 144;
+constexpr int32_t kResMaxSlots = 16000;  // image slots addressable by the 16-bit records
+constexpr int64_t res_lds_bytes(int64_t nslot, int64_t blob_units) {
+  return 24 * (nslot + 2) + ((2 * nslot + 15) & ~(int64_t)15) + 16 * blob_units;
+}
+// Target of the packing: consecutive cells share a group while it holds at
+// most this many compartments (a larger cell is a group of its own).
+constexpr int32_t kResPackSlots = 1400;
+
+struct ResPlan {
+  bool built = false;
+  std::vector<KResGroup> groups;
+  std::vector<uint16_t> par;   // [n + 2] parent slot in the group image (roots: the zero slot)
+  std::vector<uint8_t> blob;   // group blobs, 16-byte aligned
+  int64_t max_lds = 0;
+};
+
+// Build the LDS-resident tables; parent / cell_offsets must already be valid.
+// ERR_TOO_BIG if a cell's image does not fit kLdsLimitBytes.
+Status build_resident(const int32_t* parent, int64_t n, const int64_t* cell_offsets, int64_t ncells,
+                      ResPlan& out, std::string& err);
+// Replay of the resident tables: every record, slot and parent slot inside its
+// group image, every compartment eliminated once, after all its children.
+bool check_resident(const ResPlan& R, const int32_t* parent, int64_t n, std::string& why);
 
 // Per-branch record of the LDS-staged solve kernel, in (group, level, lane)
 // order; 16 bytes so that one DMA lane moves one record.  All indices are
@@ -267,6 +334,7 @@ struct HostPlan {
   std::vector<int16_t> faux;      // [pushes]: parent position
   int64_t ws_doubles = 0;         // global workspace for groups that exceed LDS
   CellLanes cl;                   // cell-lane kernel tables (opt.cell_lanes)
+  ResPlan res;                    // LDS-resident kernel tables (opt.resident)
 };
 
 Status build_plan(const int32_t* parent, int64_t n, const int64_t* branch_offsets, int64_t nbranches,

@@ -19,6 +19,7 @@ TABLES = {
     "group_seg_offsets": 5, "seg_offsets": 6, "lanes": 7,
     "flow_groups": 8, "flow_masks": 9, "flow_pos": 10, "flow_aux": 11,
     "cell_waves": 12, "cell_lanes": 13, "cell_pos": 14, "cell_flags": 15, "cell_mbsrc": 16,
+    "res_groups": 17, "res_par": 18, "res_blob": 19,
 }
 STATUS = {0: "OK", 1: "NULL", 2: "BAD_OFFSETS", 3: "BAD_PARENT", 4: "BAD_BRANCHES",
           6: "NCELLS", 7: "OPTION", 8: "OOM", 9: "HIP", 10: "TOO_BIG", 11: "NOT_SDD", 12: "STATE"}
@@ -37,7 +38,7 @@ class _Options(ctypes.Structure):
                 ("max_group_unknowns", ctypes.c_int32), ("host_only", ctypes.c_int32),
                 ("keep_tables", ctypes.c_int32), ("bitwise", ctypes.c_int32),
                 ("level_sync", ctypes.c_int32), ("cell_lanes", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("resident", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class _Info(ctypes.Structure):
@@ -86,13 +87,18 @@ def load():
     lib.hines_adjoint_rhs.argtypes = [P, P, P, P, P, P]
     lib.hines_adjoint_accumulate.argtypes = [P, P, P, P, P, P, P, P]
     lib.hines_check_matrix.argtypes = [P, P, P, ctypes.POINTER(I64), P]
+    lib.hines_layout_size.argtypes = [P, ctypes.POINTER(I64)]
+    lib.hines_to_layout.argtypes = [P, P, P, P]
+    lib.hines_from_layout.argtypes = [P, P, P, P]
+    lib.hines_solve_layout.argtypes = [P, P, P, P, P, I32, P]
     for name in ("hines_setup", "hines_solve", "hines_solve_mixed", "hines_solve_stored32", "hines_timestep_assembled",
                  "hines_plan_info_get",
                  "hines_get_table",
                  "hines_destroy",
                  "hines_timestep", "hines_timeloop_create", "hines_timeloop_launch", "hines_timeloop_destroy",
                  "hines_assemble", "hines_gather_roots", "hines_adjoint_rhs", "hines_adjoint_accumulate",
-                 "hines_check_matrix"):
+                 "hines_check_matrix", "hines_layout_size", "hines_to_layout", "hines_from_layout",
+                 "hines_solve_layout"):
         getattr(lib, name).restype = I32
     _lib = lib
     return lib
@@ -121,7 +127,8 @@ class Plan:
 
     def __init__(self, parent, cell_offsets, branch_offsets=None, *, rebalance_root=False,
                  split_branches=False, group_width=64, cell_order=0, max_group_unknowns=None,
-                 host_only=False, keep_tables=True, bitwise=False, level_sync=False, cell_lanes=False):
+                 host_only=False, keep_tables=True, bitwise=False, level_sync=False, cell_lanes=False,
+                 resident=False):
         lib = load()
         opt = _Options()
         lib.hines_default_options(ctypes.byref(opt))
@@ -136,6 +143,7 @@ class Plan:
         opt.bitwise = int(bool(bitwise))
         opt.level_sync = int(bool(level_sync))
         opt.cell_lanes = int(bool(cell_lanes))
+        opt.resident = int(bool(resident))
         self._par = _host(parent, np.int32)
         self._coff = _host(cell_offsets, np.int64)
         bo = None if branch_offsets is None else _host(branch_offsets, np.int64)
@@ -176,7 +184,11 @@ class Plan:
         out = np.empty(cnt.value, dtype=np.int64)
         _check(lib.hines_get_table(self._h, which, ctypes.c_void_p(out.ctypes.data), out.shape[0],
                                    ctypes.byref(cnt)))
-        return out.reshape(-1, 8) if name == "branches" else out
+        if name == "branches":
+            return out.reshape(-1, 8)
+        if name == "res_groups":
+            return out.reshape(-1, 10)
+        return out
 
     def tables(self) -> dict:
         return {k: self.table(k) for k in TABLES}
@@ -263,6 +275,43 @@ class Plan:
             float(noise_sigma), int(noise_seed) & 0xFFFFFFFF, int(first_step) & 0xFFFFFFFF, int(nsteps),
             self.ncells, ctypes.byref(h)))
         return TimeLoop(h, self, keep)
+
+    # ---- solver layout of a cell-lane plan (paper §7: permutation kernels) ----
+    @property
+    def layout_size(self) -> int:
+        n = ctypes.c_int64()
+        _check(load().hines_layout_size(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def to_layout(self, src, dst=None, stream=None):
+        import torch
+        m = self.layout_size
+        dst = torch.empty(m, dtype=torch.float64, device=src.device) if dst is None else dst
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(load().hines_to_layout(self._h, _dev(src, self.n, torch.float64, "src"),
+                                      _dev(dst, m, torch.float64, "dst"), ctypes.c_void_p(st.cuda_stream)))
+        return dst
+
+    def from_layout(self, src, dst=None, stream=None):
+        import torch
+        m = self.layout_size
+        dst = torch.empty(self.n, dtype=torch.float64, device=src.device) if dst is None else dst
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(load().hines_from_layout(self._h, _dev(src, m, torch.float64, "src"),
+                                        _dev(dst, self.n, torch.float64, "dst"), ctypes.c_void_p(st.cuda_stream)))
+        return dst
+
+    def solve_layout(self, diag_l, upper_l, rhs_l, out=None, stream=None):
+        """A x = rhs with every array in the solver layout (``hines_solve_layout``)."""
+        import torch
+        m = self.layout_size
+        out = torch.empty_like(rhs_l) if out is None else out
+        st = stream if stream is not None else torch.cuda.current_stream()
+        f64 = torch.float64
+        _check(load().hines_solve_layout(self._h, _dev(diag_l, m, f64, "diag_l"), _dev(upper_l, m, f64, "upper_l"),
+                                         _dev(rhs_l, m, f64, "rhs_l"), _dev(out, m, f64, "out"), self.ncells,
+                                         ctypes.c_void_p(st.cuda_stream)))
+        return out
 
     def check_matrix(self, diag, upper, stream=None):
         """Strict diagonal dominance with a positive diagonal (``hines_check_matrix``).

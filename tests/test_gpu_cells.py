@@ -269,3 +269,42 @@ def test_assembled_step(torch_dev, which):
     with pytest.raises(HinesError):
         q.timestep_assembled(G, U, C, GE, V, V)
     q.close()
+
+
+def test_layout_resident_solve_through_the_c_abi():
+    """hines_to_layout / hines_solve_layout / hines_from_layout on cell-lane
+    plans (whole cells, cells cut over two to four lanes, padding): the same
+    elimination as hines_solve on the same plan, bit for bit, and within 1e-12
+    of the oracle; x may alias rhs in the layout."""
+    import ctypes
+    import torch
+    from paper_1810_12742_amd import Plan
+    from paper_1810_12742_amd.hines import load
+    dev = torch.device("cuda")
+    lib = load()
+    P = ctypes.c_void_p
+    for s in (configs.c2(3000), configs.c3(300), configs.random_system(200, seed=5)):
+        f = s.forest
+        print(f"layout solve: {f.ncells} cells, {f.n} unknowns", flush=True)
+        rhs = s.rhs if np.any(s.rhs) else np.random.default_rng(1).standard_normal(f.n)
+        xo = oracle.solve(f, s.diag, s.upper, rhs)
+        p = Plan(f.parent, f.cell_offsets, f.branch_offsets, cell_lanes=True)
+        d, u, b = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (s.diag, s.upper, rhs))
+        m = ctypes.c_int64()
+        assert lib.hines_layout_size(p._h, ctypes.byref(m)) == 0 and m.value == p.layout_size >= f.n
+        dl, ul, bl = p.to_layout(d), p.to_layout(u), p.to_layout(b)
+        xl = torch.empty_like(bl)
+        st = lib.hines_solve_layout(p._h, P(dl.data_ptr()), P(ul.data_ptr()), P(bl.data_ptr()), P(xl.data_ptr()),
+                                    f.ncells, None)
+        assert st == 0
+        x = p.from_layout(xl).cpu().numpy()
+        assert cell_rel_err(f, x, xo) <= 1e-12
+        xs = p.solve(d, u, b).cpu().numpy()
+        assert np.array_equal(x, xs)
+        p.solve_layout(dl, ul, bl, out=bl)  # in place
+        assert np.array_equal(p.from_layout(bl).cpu().numpy(), x)
+        assert lib.hines_solve_layout(p._h, P(dl.data_ptr()), P(ul.data_ptr()), P(bl.data_ptr()),
+                                      P(dl.data_ptr()), f.ncells, None) == 12
+        p.close()
+    q = Plan(f.parent, f.cell_offsets, f.branch_offsets)
+    assert lib.hines_layout_size(q._h, ctypes.byref(m)) == 12  # not a cell-lane plan

@@ -260,3 +260,35 @@ def test_check_matrix_through_the_c_abi(torch_dev):
     u2[f.cell_offsets[:-1]] = 1e300
     assert p.check_matrix(d, torch.from_numpy(u2).to(dev)) == -1
     p.close()
+
+
+def test_resident_kernel_parity(torch_dev):
+    """The LDS-resident kernel (plan option resident) on C2 slices, packed
+    small cells with odd group offsets, one-compartment cells, an unbranched
+    cable and a near-LDS-limit cell; x aliasing rhs; run-to-run equality."""
+    from paper_1810_12742_amd import Plan
+    cases = [configs.c2(2048), configs.random_system(500, seed=31), configs.c1(1000)]
+    # one cell of 5,500 compartments (the image fills most of LDS) plus singletons
+    n = 5500
+    par = np.concatenate([np.arange(-1, n - 1), [-1, -1, -1]]).astype(np.int32)
+    f = Forest(par, np.array([0, n, n + 1, n + 2, n + 3], dtype=np.int64),
+               np.array([0, n, n + 1, n + 2, n + 3], dtype=np.int64))
+    from workloads import cable_values
+    cases.append(cable_values(f, np.random.default_rng(6), a_kind="cable", dt=0.025))
+    for s in cases:
+        f = s.forest
+        print(f"resident: {f.ncells} cells, {f.n} unknowns", flush=True)
+        xo = oracle.solve(f, s.diag, s.upper, s.rhs)
+        assert Plan(f.parent, f.cell_offsets, f.branch_offsets, resident=True).info["kernel"] == 4
+        x1 = gpu_solve(torch_dev, s, resident=True)
+        assert cell_rel_err(f, x1, xo) <= TOL
+        x2 = gpu_solve(torch_dev, s, alias=True, resident=True)
+        assert np.array_equal(x1, x2)
+
+
+def test_resident_full_c2(torch_dev):
+    """The full 65,536-cell C2 workload on the resident kernel."""
+    s = configs.c2()
+    xo = oracle.solve(s.forest, s.diag, s.upper, s.rhs)
+    x = gpu_solve(torch_dev, s, resident=True)
+    assert cell_rel_err(s.forest, x, xo) <= TOL
