@@ -76,22 +76,30 @@ typedef struct hines_options {
   int32_t cell_lanes;         /* 1: hines_solve and hines_timestep run one lane per cell, the
                                  one-thread-per-matrix solver of §3 and §7 (§2's elimination in a
                                  depth-first order of each cell, 64 lanes of similar length per
-                                 wave; a cell longer than 0.8 times the mean cell is cut into
-                                 pieces on two to four lanes of one wave; elimination factors kept in a
+                                 wave; a cell longer than 80% of the mean cell (cell_cut_percent)
+                                 is cut into pieces on two to four lanes of one wave (at most
+                                 cell_max_cuts + 1); elimination factors kept in a
                                  device scratch of 16 bytes per step owned by the plan).  Needs
                                  bitwise 0, cells of at most 65535 compartments and a stack need
                                  of at most 12 (HINES_ERR_TOO_BIG otherwise).  hines_solve_mixed
                                  keeps using the groups.  0 (default): groups (§3-§4)        */
   int32_t resident;           /* 1: hines_solve runs the LDS-resident kernel: consecutive whole
                                  cells form a group of up to 1400 compartments (a larger cell is
-                                 a group of its own); one wave stages the group's d, u, b and
+                                 a group of its own; see res_pack); one wave stages the group's d, u, b and
                                  parent slots into LDS once, eliminates every compartment after
                                  its children (§2) along root-ward paths scheduled at setup, one
                                  path per lane at a time (§3-§4), and stores x.  Needs bitwise 0,
                                  cell_lanes 0 and every cell's image within LDS (up to about 6,000
                                  compartments; HINES_ERR_TOO_BIG otherwise).  The other calls
                                  keep using the groups.                                      */
-  int32_t reserved[5];        /* must be 0 */
+  /* Tuning of the cell-lane and resident tables (0 selects the default): */
+  int32_t cell_cut_percent;   /* cell lanes: cells longer than this percentage of the mean cell
+                                 are cut into pieces on several lanes (default 80)           */
+  int32_t cell_max_cuts;      /* cell lanes: at most this many cut-off subtrees per cell, 1..3
+                                 (default 3)                                                 */
+  int32_t res_pack;           /* resident: consecutive cells share a group while it holds at
+                                 most this many compartments, 1..16000 (default 1400)       */
+  int32_t reserved[2];        /* must be 0 */
 } hines_options;
 
 /* Plan summary. */

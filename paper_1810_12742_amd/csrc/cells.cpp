@@ -140,7 +140,7 @@ struct LaneWork {
 }  // namespace
 
 Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_offsets, int64_t ncells,
-                        CellLanes& out, std::string& err) {
+                        CellLanes& out, std::string& err, int32_t cut_percent, int32_t max_cuts) {
   out = CellLanes{};
   auto size_of = [&](int64_t c) { return cell_offsets[c + 1] - cell_offsets[c]; };
   for (int64_t c = 0; c < ncells; ++c) {
@@ -150,10 +150,15 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
       return ERR_TOO_BIG;
     }
   }
-  // cells longer than 0.8 times the mean are cut (when the pieces fit): shorter
-  // lanes and more waves than wave slots, so that short waves fill in behind long ones
+  if (cut_percent < 1 || max_cuts < 1 || max_cuts > kCellMaxCuts) {
+    err = "cell cut options out of range";
+    return ERR_OPTION;
+  }
+  // cells longer than cut_percent of the mean (80% by default) are cut (when
+  // the pieces fit): shorter lanes and more waves than wave slots, so that
+  // short waves fill in behind long ones
   const double mean = ncells ? (double)n / (double)ncells : 0.0;
-  const int64_t split_above = std::max<int64_t>(4 * kCellChunk, (int64_t)(0.8 * mean));
+  const int64_t split_above = std::max<int64_t>(4 * kCellChunk, (int64_t)(0.01 * cut_percent * mean));
   // cutting a lane below the steps every wave slot of the device walks anyway
   // only adds padding: 1,024 slots (256 compute units, 4 SIMDs, one wave each
   // at this kernel's register use), 64 lanes, about 15% padding
@@ -208,7 +213,7 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
     out.clear();
     int64_t rest = m;
     for (auto& cs : cand) {
-      if (rest <= t || (int)out.size() >= kCellMaxCuts) break;
+      if (rest <= t || (int)out.size() >= max_cuts) break;
       out.push_back(cs.second);
       rest -= cs.first;
     }
@@ -249,7 +254,7 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
           path.push_back(h);
           onpath[h] = 1;
         }
-        int64_t tl = std::max<int64_t>((m + kCellMaxCuts) / (kCellMaxCuts + 1), target_floor), th = span;
+        int64_t tl = std::max<int64_t>((m + max_cuts) / (max_cuts + 1), target_floor), th = span;
         if (tl < th && heavy_cut(m, th - 1, pick)) {
           while (tl < th) {  // smallest feasible target
             const int64_t mid = (tl + th) / 2;

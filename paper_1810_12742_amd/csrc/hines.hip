@@ -582,8 +582,11 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
     opt = *opt_in;
   else
     hines_default_options(&opt);
-  for (int k = 0; k < 5; ++k)
+  for (int k = 0; k < 2; ++k)
     if (opt.reserved[k] != 0) return set_err(HINES_ERR_OPTION, "reserved option fields must be 0");
+  if (opt.cell_cut_percent < 0 || opt.cell_max_cuts < 0 || opt.cell_max_cuts > hines::kCellMaxCuts ||
+      opt.res_pack < 0 || opt.res_pack > hines::kResMaxSlots)
+    return set_err(HINES_ERR_OPTION, "tuning option out of range");
   if (opt.cell_lanes && opt.bitwise)
     return set_err(HINES_ERR_OPTION, "cell_lanes needs the fast arithmetic form (bitwise 0)");
   if (opt.resident && (opt.bitwise || opt.cell_lanes))
@@ -600,6 +603,9 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   o.scheduler = opt.level_sync ? 0 : 1;
   o.cell_lanes = opt.cell_lanes != 0;
   o.resident = opt.resident != 0;
+  if (opt.cell_cut_percent > 0) o.cell_cut_percent = opt.cell_cut_percent;
+  if (opt.cell_max_cuts > 0) o.cell_max_cuts = opt.cell_max_cuts;
+  if (opt.res_pack > 0) o.res_pack = opt.res_pack;
   if (o.cell_lanes) o.scheduler = 0;  // the groups serve hines_solve_mixed only
   hines_plan* p = new (std::nothrow) hines_plan();
   if (!p) return set_err(HINES_ERR_OOM, "host allocation failed");
@@ -610,7 +616,7 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
     return set_err((hines_status)s, "%s", why.c_str());
   }
   if (o.cell_lanes) {
-    s = hines::build_cell_lanes(parent, n, cell_offsets, ncells, p->host.cl, why);
+    s = hines::build_cell_lanes(parent, n, cell_offsets, ncells, p->host.cl, why, o.cell_cut_percent, o.cell_max_cuts);
     if (s == hines::OK && !check_cell_tables(p->host, cell_offsets, why)) s = hines::ERR_STATE;
     if (s != hines::OK) {
       delete p;
@@ -618,7 +624,7 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
     }
   }
   if (o.resident) {
-    s = hines::build_resident(parent, n, cell_offsets, ncells, p->host.res, why);
+    s = hines::build_resident(parent, n, cell_offsets, ncells, p->host.res, why, o.res_pack);
     if (s == hines::OK && !hines::check_resident(p->host.res, parent, n, why)) s = hines::ERR_STATE;
     if (s != hines::OK) {
       delete p;

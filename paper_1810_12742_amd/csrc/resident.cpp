@@ -86,8 +86,12 @@ bool schedule_group(int32_t m, const std::vector<int32_t>& lpar, const std::vect
 }  // namespace
 
 Status build_resident(const int32_t* parent, int64_t n, const int64_t* cell_offsets, int64_t ncells,
-                      ResPlan& out, std::string& err) {
+                      ResPlan& out, std::string& err, int32_t pack) {
   out = ResPlan{};
+  if (pack < 1 || pack > kResMaxSlots) {
+    err = "resident pack size out of range";
+    return ERR_OPTION;
+  }
   out.par.assign((size_t)n + 2, 0);
   // groups of consecutive cells
   std::vector<int64_t> gc;  // first cell of each group, then ncells
@@ -95,7 +99,7 @@ Status build_resident(const int32_t* parent, int64_t n, const int64_t* cell_offs
     gc.push_back(c);
     int64_t slots = cell_offsets[c + 1] - cell_offsets[c];
     int64_t c1 = c + 1;
-    while (c1 < ncells && slots + (cell_offsets[c1 + 1] - cell_offsets[c1]) <= kResPackSlots) {
+    while (c1 < ncells && slots + (cell_offsets[c1 + 1] - cell_offsets[c1]) <= pack) {
       slots += cell_offsets[c1 + 1] - cell_offsets[c1];
       ++c1;
     }

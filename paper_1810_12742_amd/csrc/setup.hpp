@@ -38,6 +38,9 @@ struct Options {
                                    // 0: level-synchronous sweeps (paper §3)
   int32_t cell_lanes = 0;          // 1: one lane per cell (streaming kernel) for hines_solve / timestep
   int32_t resident = 0;            // 1: LDS-resident path-walk kernel for hines_solve
+  int32_t cell_cut_percent = 80;   // cell lanes: cut cells longer than this percentage of the mean
+  int32_t cell_max_cuts = 3;       // cell lanes: cut-off subtrees per cell
+  int32_t res_pack = 1400;         // resident: compartments per group of consecutive cells
 };
 
 // Static chunk schedule (flow kernel): one lane eliminates kFlowChunk
@@ -160,8 +163,11 @@ struct CellLanes {
 // Build the cell-lane tables.  parent / cell_offsets must already be valid.
 // ERR_TOO_BIG if a cell has more than kCellMaxSize compartments or needs more
 // than kCellStack stack entries.
+// cut_percent: cells longer than this percentage of the mean cell are cut
+// (80 by default); max_cuts: cut-off subtrees per cell, 1 .. kCellMaxCuts.
 Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_offsets, int64_t ncells,
-                        CellLanes& out, std::string& err);
+                        CellLanes& out, std::string& err, int32_t cut_percent = 80,
+                        int32_t max_cuts = kCellMaxCuts);
 
 // LDS-resident solve (one wave per group of whole cells).  A group's d, u, b
 // (8 bytes each) and the parent slot of every compartment (2 bytes) are staged
@@ -220,8 +226,10 @@ struct ResPlan {
 
 // Build the LDS-resident tables; parent / cell_offsets must already be valid.
 // ERR_TOO_BIG if a cell's image does not fit kLdsLimitBytes.
+// pack: consecutive cells share a group while it holds at most this many
+// compartments (kResPackSlots by default).
 Status build_resident(const int32_t* parent, int64_t n, const int64_t* cell_offsets, int64_t ncells,
-                      ResPlan& out, std::string& err);
+                      ResPlan& out, std::string& err, int32_t pack = kResPackSlots);
 // Replay of the resident tables: every record, slot and parent slot inside its
 // group image, every compartment eliminated once, after all its children.
 bool check_resident(const ResPlan& R, const int32_t* parent, int64_t n, std::string& why);

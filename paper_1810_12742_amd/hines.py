@@ -38,7 +38,9 @@ class _Options(ctypes.Structure):
                 ("max_group_unknowns", ctypes.c_int32), ("host_only", ctypes.c_int32),
                 ("keep_tables", ctypes.c_int32), ("bitwise", ctypes.c_int32),
                 ("level_sync", ctypes.c_int32), ("cell_lanes", ctypes.c_int32),
-                ("resident", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("resident", ctypes.c_int32), ("cell_cut_percent", ctypes.c_int32),
+                ("cell_max_cuts", ctypes.c_int32), ("res_pack", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class _Info(ctypes.Structure):
@@ -128,7 +130,7 @@ class Plan:
     def __init__(self, parent, cell_offsets, branch_offsets=None, *, rebalance_root=False,
                  split_branches=False, group_width=64, cell_order=0, max_group_unknowns=None,
                  host_only=False, keep_tables=True, bitwise=False, level_sync=False, cell_lanes=False,
-                 resident=False):
+                 resident=False, cell_cut_percent=0, cell_max_cuts=0, res_pack=0):
         lib = load()
         opt = _Options()
         lib.hines_default_options(ctypes.byref(opt))
@@ -144,6 +146,9 @@ class Plan:
         opt.level_sync = int(bool(level_sync))
         opt.cell_lanes = int(bool(cell_lanes))
         opt.resident = int(bool(resident))
+        opt.cell_cut_percent = int(cell_cut_percent)
+        opt.cell_max_cuts = int(cell_max_cuts)
+        opt.res_pack = int(res_pack)
         self._par = _host(parent, np.int32)
         self._coff = _host(cell_offsets, np.int64)
         bo = None if branch_offsets is None else _host(branch_offsets, np.int64)

@@ -226,3 +226,41 @@ def test_large_cell_refused():
     with pytest.raises(HinesError) as ei:
         Plan(par[:10], np.array([0, 10]), None, host_only=True, resident=True, cell_lanes=True)
     assert ei.value.code == "OPTION"
+
+
+def test_pack_option_sets_group_sizes():
+    s = configs.random_system(80, seed=2)
+    f = s.forest
+    t1, _ = plan_tables(f, res_pack=1)
+    assert (t1["res_groups"][:, 8] == 1).all()          # one cell per group
+    t2, _ = plan_tables(f, res_pack=600)
+    g = t2["res_groups"]
+    multi = g[:, 8] > 1
+    assert multi.any() and (g[multi, 5] <= 600).all()
+    x = replay(t2, f.n, s.diag, s.upper, s.rhs)
+    assert cell_rel_err(f, x, oracle.solve(f, s.diag, s.upper, s.rhs)) <= TOL
+
+
+def _lanes_per_cell(f, **o):
+    from paper_1810_12742_amd import Plan
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets, host_only=True, cell_lanes=True, **o)
+    lc = p.table("cell_lanes")
+    p.close()
+    return np.bincount(lc[lc >= 0], minlength=f.ncells)
+
+
+def test_cell_cut_options():
+    """cell_max_cuts bounds the lanes of a cut cell.  On a network with more
+    cells than half the device's lanes (40,000: 39,990 cables of 10 and ten of
+    2,000 compartments) only the threshold decides: the long cables are cut by
+    default and stay whole when the threshold is far above them."""
+    f = configs.c2(3000).forest
+    assert _lanes_per_cell(f).max() >= 3
+    assert _lanes_per_cell(f, cell_max_cuts=1).max() <= 2
+    sizes = np.array([10] * 39990 + [2000] * 10)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    par = np.arange(-1, off[-1] - 1, dtype=np.int64)
+    par[off[:-1]] = -1
+    g = Forest(par.astype(np.int32), off, off.copy())
+    assert _lanes_per_cell(g)[-10:].min() >= 2
+    assert _lanes_per_cell(g, cell_cut_percent=100000).max() == 1
