@@ -60,7 +60,10 @@ typedef enum hines_status {
 /* Setup options (paper §4-§6).  Obtain defaults from hines_default_options. */
 typedef struct hines_options {
   int32_t rebalance_root;     /* §6: re-root each cell at its tree centre (0/1)            */
-  int32_t split_branches;     /* §6: split branches longer than their level's average (0/1) */
+  int32_t split_branches;     /* §6: split branches longer than their level's average: 0 no,
+                                 1 the average over all cells, 2 the average over the cells of
+                                 one group of an intermediate packing (the per-block averages
+                                 of the outlook, §8)                                         */
   int32_t group_width;        /* §3-§4: lanes per group; multiple of 64 in [64, 1024]      */
   int32_t cell_order;         /* §4 greedy packing order: 0 input order, 1 size descending  */
   int32_t max_group_unknowns; /* cap on compartments packed into one group; 0 = automatic   */
@@ -99,7 +102,11 @@ typedef struct hines_options {
                                  (default 3)                                                 */
   int32_t res_pack;           /* resident: consecutive cells share a group while it holds at
                                  most this many compartments, 1..16000 (default 1400)       */
-  int32_t reserved[2];        /* must be 0 */
+  int32_t level_balance;      /* 1: §8 outlook: a cell that overflows a level of the open group
+                                 may move subtrees one level down (the smallest first) until
+                                 every level fits; the level of a branch is then its step in the
+                                 level-synchronous sweeps, deeper than its parent's            */
+  int32_t reserved[1];        /* must be 0 */
 } hines_options;
 
 /* Plan summary. */

@@ -31,11 +31,27 @@ S5 split (option)  [§6 "split long branches", §5].  For level l = 0, 1, ...
    branches; each branch with len*m > S keeps its first floor(S/m)
    compartments, the rest becomes its only child one level down and adopts
    its children.  The numbering of S4 is then recomputed.
+S5' per-group averages (split option 2)  [§8, the outlook: an intermediate
+   packing gives local heuristics such as per-block averages].  The cells are
+   first packed by S7 on the unsplit trees; then S5 runs inside each of these
+   groups, with S and m taken over that group's level-l branches only; the
+   final packing (S7) runs on the split trees.
 S6 levels: root branch 0, child = parent + 1.
 S7 packing  [§4].  Cells in input order (or by size, descending, stable); a
    cell joins the open group iff every level's branch count stays <= the
    group width T and, when a cap is set, the group's compartment count stays
    <= the cap; otherwise a new group opens.
+S7' level balancing (option)  [§8, the outlook: let subtrees move one level
+   down when that evens out the level widths of a block].  A cell that meets
+   the cap but overflows some level of the open group is given a trial: while
+   some level l overflows (the smallest such l), one of the cell's branches
+   on level l (l > 0) moves down one level together with its whole subtree:
+   the branch with the fewest branches in its subtree, then the smallest
+   breadth-first rank.  If no level overflows after at most 4 x (branches of
+   the cell) moves, the cell joins with the moved levels; otherwise it opens a
+   new group with its own levels.  A branch's level then is its step in the
+   level-synchronous sweeps (always deeper than its parent's), and S8 and the
+   exported tables use it.
 S8 lane order  [§4, Fig 4.1].  Inside (group, level): branches by descending
    length, ties by (cell, breadth-first rank in the cell).
 
@@ -147,14 +163,57 @@ class _Branch:
         return self.node(self.len - 1)
 
 
+def _greedy_groups(cells, sizes, counts_of, T, cap):
+    """S7 greedy packing by level counts (no level balancing)."""
+    groups, cur, cur_cnt, cur_u = [], [], {}, 0
+    for c in cells:
+        fits = True
+        if cur:
+            for lvl, k in counts_of(c).items():
+                if cur_cnt.get(lvl, 0) + k > T:
+                    fits = False
+            if cap and cur_u + sizes[c] > cap:
+                fits = False
+        if not fits:
+            groups.append(cur)
+            cur, cur_cnt, cur_u = [], {}, 0
+        cur.append(c)
+        for lvl, k in counts_of(c).items():
+            cur_cnt[lvl] = cur_cnt.get(lvl, 0) + k
+        cur_u += sizes[c]
+    if cur:
+        groups.append(cur)
+    return groups
+
+
+def _split_levels(level_list):
+    """S5 on the branches reachable from level_list (the top level)."""
+    while level_list:
+        S = sum(b.len for b in level_list)
+        m = len(level_list)
+        nxt = []
+        for b in level_list:
+            if b.len * m > S:
+                k = S // m
+                t = _Branch(b.cell, b.node(k), b.dir, b.len - k, b)
+                t.children = b.children
+                for ch in t.children:
+                    ch.parent = t
+                b.children = [t]
+                b.len = k
+            nxt.extend(b.children)
+        level_list = nxt
+
+
 def build(parent, cell_offsets, branch_offsets=None, *, rebalance_root=0, split_branches=0,
-          group_width=64, cell_order=0, max_group_unknowns=0):
+          group_width=64, cell_order=0, max_group_unknowns=0, level_balance=0):
     parent = [int(v) for v in np.asarray(parent)]
     cell_offsets = [int(v) for v in np.asarray(cell_offsets)]
     bo = None if branch_offsets is None else [int(v) for v in np.asarray(branch_offsets)]
     if group_width < 1 or group_width > 1024 or group_width % 64:
         raise SetupError("OPTION", "group_width must be a multiple of 64 in [64, 1024]")
-    if cell_order not in (0, 1) or max_group_unknowns < 0:
+    if cell_order not in (0, 1) or max_group_unknowns < 0 or split_branches not in (0, 1, 2) \
+            or level_balance not in (0, 1):
         raise SetupError("OPTION", "bad option")
     user_starts = _validate(parent, cell_offsets, bo)
     if rebalance_root:
@@ -219,24 +278,27 @@ def build(parent, cell_offsets, branch_offsets=None, *, rebalance_root=0, split_
     for rb in root_branches:
         _sort_children(rb)
 
+    sizes = [cell_offsets[c + 1] - cell_offsets[c] for c in range(ncells)]
+    if cell_order == 1:
+        cells = sorted(range(ncells), key=lambda c: (-sizes[c], c))
+    else:
+        cells = list(range(ncells))
+
     # ---- S5: split, level by level over all cells ----
-    if split_branches:
-        level_list = list(root_branches)
-        while level_list:
-            S = sum(b.len for b in level_list)
-            m = len(level_list)
-            nxt = []
-            for b in level_list:
-                if b.len * m > S:
-                    k = S // m
-                    t = _Branch(b.cell, b.node(k), b.dir, b.len - k, b)
-                    t.children = b.children
-                    for ch in t.children:
-                        ch.parent = t
-                    b.children = [t]
-                    b.len = k
-                nxt.extend(b.children)
-            level_list = nxt
+    if split_branches == 1:
+        _split_levels(list(root_branches))
+    # ---- S5': split inside the groups of an intermediate packing ----
+    if split_branches == 2:
+        def natural_counts(c):
+            cnt, lvl = {}, [root_branches[c]]
+            depth = 0
+            while lvl:
+                cnt[depth] = len(lvl)
+                lvl = [ch for b in lvl for ch in b.children]
+                depth += 1
+            return cnt
+        for grp in _greedy_groups(cells, sizes, natural_counts, group_width, max_group_unknowns):
+            _split_levels([root_branches[c] for c in grp])
 
     # ---- S4/S6: breadth-first numbering and levels ----
     all_branches = []
@@ -276,20 +338,54 @@ def build(parent, cell_offsets, branch_offsets=None, *, rebalance_root=0, split_
             else:
                 raise AssertionError("branch step is not a tree edge")
 
-    # ---- S7: packing ----
+    # ---- S7: packing (S7': with level balancing) ----
     T = group_width
     cap = max_group_unknowns
-    cell_counts = []
-    for c in range(ncells):
-        cell_counts.append({})
+    by_cell = {}
     for b in all_branches:
-        cc = cell_counts[b.cell]
-        cc[b.level] = cc.get(b.level, 0) + 1
-    sizes = [cell_offsets[c + 1] - cell_offsets[c] for c in range(ncells)]
-    if cell_order == 1:
-        cells = sorted(range(ncells), key=lambda c: (-sizes[c], c))
-    else:
-        cells = list(range(ncells))
+        by_cell.setdefault(b.cell, []).append(b)
+
+    def counts(c, lv=None):
+        cnt = {}
+        for b in by_cell[c]:
+            l_ = b.level if lv is None else lv[b.gid]
+            cnt[l_] = cnt.get(l_, 0) + 1
+        return cnt
+
+    def subtree(b):
+        out, stack = [], [b]
+        while stack:
+            x = stack.pop()
+            out.append(x)
+            stack.extend(x.children)
+        return out
+
+    subtree_size = {}
+
+    def balance(c, cur_cnt):
+        """S7' trial for cell c against the open group's level counts; the
+        moved levels (gid -> level) or None."""
+        lv = {b.gid: b.level for b in by_cell[c]}
+        for b in by_cell[c]:
+            if b.gid not in subtree_size:
+                subtree_size[b.gid] = len(subtree(b))
+        moves, limit = 0, 4 * len(by_cell[c])
+        cnt = counts(c, lv)
+        while True:
+            over = [l_ for l_ in sorted(cnt) if cnt[l_] > 0 and cur_cnt.get(l_, 0) + cnt[l_] > T]
+            if not over:
+                return lv
+            l_ = over[0]
+            if l_ == 0 or moves >= limit:
+                return None
+            cand = [b for b in by_cell[c] if lv[b.gid] == l_]
+            b = min(cand, key=lambda x: (subtree_size[x.gid], x.rank))
+            for x in subtree(b):
+                cnt[lv[x.gid]] -= 1
+                lv[x.gid] += 1
+                cnt[lv[x.gid]] = cnt.get(lv[x.gid], 0) + 1
+            moves += 1
+
     groups = []
     cur = []
     cur_cnt = {}
@@ -297,16 +393,25 @@ def build(parent, cell_offsets, branch_offsets=None, *, rebalance_root=0, split_
     for c in cells:
         fits = True
         if cur:
-            for lvl, k in cell_counts[c].items():
+            for lvl, k in counts(c).items():
                 if cur_cnt.get(lvl, 0) + k > T:
                     fits = False
             if cap and cur_u + sizes[c] > cap:
                 fits = False
+                cap_fail = True
+            else:
+                cap_fail = False
+            if not fits and level_balance and not cap_fail:
+                lv = balance(c, cur_cnt)
+                if lv is not None:
+                    for b in by_cell[c]:
+                        b.level = lv[b.gid]
+                    fits = True
         if not fits:
             groups.append(cur)
             cur, cur_cnt, cur_u = [], {}, 0
         cur.append(c)
-        for lvl, k in cell_counts[c].items():
+        for lvl, k in counts(c).items():
             cur_cnt[lvl] = cur_cnt.get(lvl, 0) + k
         cur_u += sizes[c]
     if cur:
@@ -317,9 +422,6 @@ def build(parent, cell_offsets, branch_offsets=None, *, rebalance_root=0, split_
             group_of_cell[c] = g
 
     # ---- S8: lane order ----
-    by_cell = {}
-    for b in all_branches:
-        by_cell.setdefault(b.cell, []).append(b)
     group_seg_offsets = [0]
     seg_offsets = [0]
     lanes = []

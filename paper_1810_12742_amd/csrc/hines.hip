@@ -582,8 +582,7 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
     opt = *opt_in;
   else
     hines_default_options(&opt);
-  for (int k = 0; k < 2; ++k)
-    if (opt.reserved[k] != 0) return set_err(HINES_ERR_OPTION, "reserved option fields must be 0");
+  if (opt.reserved[0] != 0) return set_err(HINES_ERR_OPTION, "reserved option fields must be 0");
   if (opt.cell_cut_percent < 0 || opt.cell_max_cuts < 0 || opt.cell_max_cuts > hines::kCellMaxCuts ||
       opt.res_pack < 0 || opt.res_pack > hines::kResMaxSlots)
     return set_err(HINES_ERR_OPTION, "tuning option out of range");
@@ -593,7 +592,8 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
     return set_err(HINES_ERR_OPTION, "resident needs bitwise 0 and cell_lanes 0");
   hines::Options o;
   o.rebalance_root = opt.rebalance_root != 0;
-  o.split_branches = opt.split_branches != 0;
+  o.split_branches = opt.split_branches;
+  o.level_balance = opt.level_balance;
   o.group_width = opt.group_width;
   o.cell_order = opt.cell_order;
   o.max_group_unknowns = opt.max_group_unknowns;

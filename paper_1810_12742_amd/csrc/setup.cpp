@@ -211,6 +211,8 @@ struct Builder {
     if (opt.group_width < 64 || opt.group_width > 1024 || opt.group_width % 64)
       return fail(ERR_OPTION, "group_width must be a multiple of 64 in [64, 1024]");
     if (opt.cell_order != 0 && opt.cell_order != 1) return fail(ERR_OPTION, "cell_order must be 0 or 1");
+    if (opt.split_branches < 0 || opt.split_branches > 2) return fail(ERR_OPTION, "split_branches must be 0, 1 or 2");
+    if (opt.level_balance != 0 && opt.level_balance != 1) return fail(ERR_OPTION, "level_balance must be 0 or 1");
     if (opt.max_group_unknowns < 0) return fail(ERR_OPTION, "max_group_unknowns < 0");
     if (coff[0] != 0 || coff[ncells] != n) return fail(ERR_BAD_OFFSETS, "cell_offsets must run from 0 to n");
     for (int64_t c = 0; c < ncells; ++c)
@@ -398,9 +400,19 @@ struct Builder {
     }
     std::vector<int32_t>().swap(br);
 
-    // ---- split (level by level over all cells) ----
-    if (opt.split_branches) {
-      std::vector<int32_t> cur(root_br.begin(), root_br.end()), nxt;
+    // packing order of the cells (§4)
+    std::vector<int64_t> cells(ncells);
+    std::iota(cells.begin(), cells.end(), 0);
+    if (opt.cell_order == 1)
+      std::stable_sort(cells.begin(), cells.end(),
+                       [&](int64_t a, int64_t b) { return coff[a + 1] - coff[a] > coff[b + 1] - coff[b]; });
+    const int32_t T = opt.group_width;
+    const int64_t cap = opt.max_group_unknowns;
+
+    // ---- split (level by level over all cells, or inside the groups of an
+    // intermediate packing of the unsplit trees: the outlook of §8) ----
+    auto split_from = [&](std::vector<int32_t> cur) {
+      std::vector<int32_t> nxt;
       while (!cur.empty()) {
         int64_t S = 0;
         for (int32_t b : cur) S += blen[b];
@@ -430,6 +442,45 @@ struct Builder {
         }
         cur.swap(nxt);
       }
+    };
+    if (opt.split_branches == 1) split_from(std::vector<int32_t>(root_br.begin(), root_br.end()));
+    if (opt.split_branches == 2) {
+      // intermediate packing (S7 without level balancing) on the natural levels
+      std::vector<int32_t> gc, lvl, nxtl, roots;
+      int64_t gU = 0;
+      auto natural = [&](int64_t c, std::vector<int32_t>& cnt) {
+        cnt.clear();
+        lvl.assign(1, root_br[c]);
+        while (!lvl.empty()) {
+          cnt.push_back((int32_t)lvl.size());
+          nxtl.clear();
+          for (int32_t b : lvl)
+            for (int32_t e = bcl_lo[b]; e < bcl_hi[b]; ++e) nxtl.push_back(clist[e]);
+          lvl.swap(nxtl);
+        }
+      };
+      std::vector<int32_t> cc;
+      for (int64_t c : cells) {
+        natural(c, cc);
+        const int64_t sz = coff[c + 1] - coff[c];
+        bool fits = true;
+        if (!roots.empty()) {
+          for (size_t l = 0; l < cc.size() && fits; ++l)
+            if ((l < gc.size() ? gc[l] : 0) + cc[l] > T) fits = false;
+          if (cap && gU + sz > cap) fits = false;
+        }
+        if (!fits) {
+          split_from(roots);
+          roots.clear();
+          gc.clear();
+          gU = 0;
+        }
+        roots.push_back(root_br[c]);
+        if (gc.size() < cc.size()) gc.resize(cc.size(), 0);
+        for (size_t l = 0; l < cc.size(); ++l) gc[l] += cc[l];
+        gU += sz;
+      }
+      if (!roots.empty()) split_from(roots);
     }
     const int64_t nb = (int64_t)bfirst.size();
     P.nbranches = nb;
@@ -486,8 +537,6 @@ struct Builder {
     for (auto* v : {&bfirst, &bdir, &blen, &bparent, &bcell, &gorder, &gid_of, &root_br})
       std::vector<int32_t>().swap(*v);
     int32_t maxlev = -1;
-    for (int64_t k = 0; k < nb; ++k) maxlev = std::max(maxlev, glevel[k]);
-    P.max_level = maxlev;
 
     // ---- node numbering and coupling sources ----
     std::vector<int32_t> node_plan(n), u_src(n);
@@ -518,67 +567,103 @@ struct Builder {
       }
     }
 
-    // ---- packing (§4) ----
-    std::vector<int64_t> cnt_off(ncells + 1, 0);
-    for (int64_t c = 0; c < ncells; ++c) {
-      int64_t hi = cell_br_lo[c + 1];
-      int32_t nl = glevel[hi - 1] + 1;  // breadth first: last branch is deepest
-      cnt_off[c + 1] = cnt_off[c] + nl;
-    }
-    std::vector<int32_t> lvl_lo(cnt_off[ncells] + ncells, 0);  // per cell: nl+1 prefix
-    // lvl_lo[cnt_off[c] + c + l] = first gid of level l in cell c
-    for (int64_t c = 0; c < ncells; ++c) {
-      int64_t base = cnt_off[c] + c;
-      int32_t nl = (int32_t)(cnt_off[c + 1] - cnt_off[c]);
-      int64_t k = cell_br_lo[c];
-      for (int32_t l = 0; l <= nl; ++l) {
-        while (k < cell_br_lo[c + 1] && glevel[k] < l) ++k;
-        lvl_lo[base + l] = (int32_t)(k - cell_br_lo[c]);
+    // ---- packing (§4; with level balancing, the outlook of §8) ----
+    // slev: the level of each branch in the level-synchronous sweeps; the
+    // breadth-first depth unless packing moved its subtree down
+    std::vector<int32_t> slev(glevel.begin(), glevel.end());
+    std::vector<int32_t> subn(nb, 1);  // branches in each branch's subtree
+    for (int64_t k = nb - 1; k >= 0; --k)
+      for (int32_t j = 0; j < gnchild[k]; ++j) subn[k] += subn[gfchild[k] + j];
+    std::vector<int32_t> gcnt, ccnt, trial, stk;
+    auto cell_counts = [&](int64_t c, const int32_t* lv, std::vector<int32_t>& cnt) {
+      cnt.clear();
+      for (int64_t k = cell_br_lo[c]; k < cell_br_lo[c + 1]; ++k) {
+        const int32_t l = lv[k - cell_br_lo[c]];
+        if ((int32_t)cnt.size() <= l) cnt.resize(l + 1, 0);
+        ++cnt[l];
       }
-    }
-    auto cell_level_count = [&](int64_t c, int32_t l) -> int32_t {
-      int64_t base = cnt_off[c] + c;
-      int32_t nl = (int32_t)(cnt_off[c + 1] - cnt_off[c]);
-      if (l >= nl) return 0;
-      return lvl_lo[base + l + 1] - lvl_lo[base + l];
     };
-    std::vector<int64_t> cells(ncells);
-    std::iota(cells.begin(), cells.end(), 0);
-    if (opt.cell_order == 1)
-      std::stable_sort(cells.begin(), cells.end(),
-                       [&](int64_t a, int64_t b) { return coff[a + 1] - coff[a] > coff[b + 1] - coff[b]; });
-    const int32_t T = opt.group_width;
-    const int64_t cap = opt.max_group_unknowns;
-    std::vector<int32_t> gcnt(maxlev + 2, 0);
+    // the smallest level on which the cell has branches and overflows the
+    // open group, or -1
+    auto overflow = [&](const std::vector<int32_t>& cnt) {
+      for (size_t l = 0; l < cnt.size(); ++l)
+        if (cnt[l] > 0 && (l < gcnt.size() ? gcnt[l] : 0) + cnt[l] > T) return (int32_t)l;
+      return (int32_t)-1;
+    };
     P.group_offsets.assign(1, 0);
     P.group_cells.clear();
     P.group_cells.reserve(ncells);
     {
-      int32_t gnl = 0;
       int64_t gU = 0;
       for (int64_t c : cells) {
-        int32_t nl = (int32_t)(cnt_off[c + 1] - cnt_off[c]);
-        int64_t sz = coff[c + 1] - coff[c];
+        const int64_t kb = cell_br_lo[c], nbc = cell_br_lo[c + 1] - kb;
+        const int64_t sz = coff[c + 1] - coff[c];
         bool open = (int64_t)P.group_cells.size() > P.group_offsets.back();
+        cell_counts(c, slev.data() + kb, ccnt);
         bool fits = true;
         if (open) {
-          for (int32_t l = 0; l < nl && fits; ++l)
-            if (gcnt[l] + cell_level_count(c, l) > T) fits = false;
-          if (cap && gU + sz > cap) fits = false;
+          const bool cap_ok = !(cap && gU + sz > cap);
+          fits = cap_ok && overflow(ccnt) < 0;
+          if (!fits && cap_ok && opt.level_balance) {
+            trial.assign(slev.begin() + kb, slev.begin() + kb + nbc);
+            int64_t moves = 0;
+            for (;;) {
+              cell_counts(c, trial.data(), ccnt);
+              const int32_t l = overflow(ccnt);
+              if (l < 0) {
+                fits = true;
+                break;
+              }
+              if (l == 0 || moves >= 4 * nbc) break;
+              int64_t pick = -1;  // fewest branches in the subtree, then the smallest rank
+              for (int64_t r = 0; r < nbc; ++r)
+                if (trial[r] == l && (pick < 0 || subn[kb + r] < subn[kb + pick])) pick = r;
+              stk.assign(1, (int32_t)(kb + pick));
+              while (!stk.empty()) {
+                const int32_t x = stk.back();
+                stk.pop_back();
+                ++trial[x - kb];
+                for (int32_t j = 0; j < gnchild[x]; ++j) stk.push_back(gfchild[x] + j);
+              }
+              ++moves;
+            }
+            if (fits) std::copy(trial.begin(), trial.end(), slev.begin() + kb);
+            else cell_counts(c, slev.data() + kb, ccnt);
+          }
         }
         if (open && !fits) {
           P.group_offsets.push_back((int64_t)P.group_cells.size());
-          std::fill(gcnt.begin(), gcnt.begin() + gnl, 0);
-          gnl = 0;
+          gcnt.clear();
           gU = 0;
         }
         P.group_cells.push_back(c);
-        for (int32_t l = 0; l < nl; ++l) gcnt[l] += cell_level_count(c, l);
-        gnl = std::max(gnl, nl);
+        if (gcnt.size() < ccnt.size()) gcnt.resize(ccnt.size(), 0);
+        for (size_t l = 0; l < ccnt.size(); ++l) gcnt[l] += ccnt[l];
         gU += sz;
       }
       if ((int64_t)P.group_cells.size() > P.group_offsets.back())
         P.group_offsets.push_back((int64_t)P.group_cells.size());
+    }
+    std::copy(slev.begin(), slev.end(), glevel.begin());
+    for (int64_t k = 0; k < nb; ++k) maxlev = std::max(maxlev, glevel[k]);
+    P.max_level = maxlev;
+    // per cell: its branches ordered by level (stable in breadth-first order)
+    // and the first entry of each level
+    std::vector<int64_t> cnt_off(ncells + 1, 0);
+    std::vector<int32_t> by_lev(nb);
+    for (int64_t c = 0; c < ncells; ++c) {
+      int32_t nl = 0;
+      for (int64_t k = cell_br_lo[c]; k < cell_br_lo[c + 1]; ++k) nl = std::max(nl, glevel[k] + 1);
+      cnt_off[c + 1] = cnt_off[c] + nl;
+    }
+    std::vector<int32_t> lvl_lo(cnt_off[ncells] + ncells, 0);  // lvl_lo[cnt_off[c] + c + l]: first entry of level l
+    for (int64_t c = 0; c < ncells; ++c) {
+      const int64_t base = cnt_off[c] + c, kb = cell_br_lo[c];
+      const int32_t nl = (int32_t)(cnt_off[c + 1] - cnt_off[c]);
+      for (int64_t k = kb; k < cell_br_lo[c + 1]; ++k) ++lvl_lo[base + glevel[k] + 1];
+      for (int32_t l = 0; l < nl; ++l) lvl_lo[base + l + 1] += lvl_lo[base + l];
+      std::vector<int32_t> fillp(lvl_lo.begin() + base, lvl_lo.begin() + base + nl);
+      for (int64_t k = kb; k < cell_br_lo[c + 1]; ++k) by_lev[kb + fillp[glevel[k]]++] = (int32_t)k;
     }
     const int64_t ng = (int64_t)P.group_offsets.size() - 1;
     P.ngroups = ng;
@@ -643,7 +728,7 @@ struct Builder {
           int32_t nl = (int32_t)(cnt_off[c + 1] - cnt_off[c]);
           if (l >= nl) continue;
           int64_t base = cnt_off[c] + c;
-          for (int32_t r = lvl_lo[base + l]; r < lvl_lo[base + l + 1]; ++r) seg.push_back((int32_t)(cell_br_lo[c] + r));
+          for (int32_t r = lvl_lo[base + l]; r < lvl_lo[base + l + 1]; ++r) seg.push_back(by_lev[cell_br_lo[c] + r]);
         }
         std::sort(seg.begin(), seg.end(), [&](int32_t a, int32_t b) {
           if (glen[a] != glen[b]) return glen[a] > glen[b];

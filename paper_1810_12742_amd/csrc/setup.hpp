@@ -27,7 +27,10 @@ enum Status : int32_t {
 
 struct Options {
   int32_t rebalance_root = 0;      // §6: re-root each cell at its tree centre
-  int32_t split_branches = 0;      // §6: per-level split of longer-than-average branches
+  int32_t split_branches = 0;      // §6: per-level split of longer-than-average branches (1: level
+                                   // averages over all cells; 2: over the groups of an
+                                   // intermediate packing, the outlook of §8)
+  int32_t level_balance = 0;       // §8 outlook: packing may move subtrees one level down
   int32_t group_width = 64;        // §4: lanes per group (multiple of 64, <= 1024)
   int32_t cell_order = 0;          // §4 packing order: 0 input, 1 size descending
   int32_t max_group_unknowns = 0;  // packing cap on compartments per group (0: none)

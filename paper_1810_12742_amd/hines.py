@@ -40,7 +40,7 @@ class _Options(ctypes.Structure):
                 ("level_sync", ctypes.c_int32), ("cell_lanes", ctypes.c_int32),
                 ("resident", ctypes.c_int32), ("cell_cut_percent", ctypes.c_int32),
                 ("cell_max_cuts", ctypes.c_int32), ("res_pack", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("level_balance", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class _Info(ctypes.Structure):
@@ -130,12 +130,12 @@ class Plan:
     def __init__(self, parent, cell_offsets, branch_offsets=None, *, rebalance_root=False,
                  split_branches=False, group_width=64, cell_order=0, max_group_unknowns=None,
                  host_only=False, keep_tables=True, bitwise=False, level_sync=False, cell_lanes=False,
-                 resident=False, cell_cut_percent=0, cell_max_cuts=0, res_pack=0):
+                 resident=False, cell_cut_percent=0, cell_max_cuts=0, res_pack=0, level_balance=False):
         lib = load()
         opt = _Options()
         lib.hines_default_options(ctypes.byref(opt))
         opt.rebalance_root = int(bool(rebalance_root))
-        opt.split_branches = int(bool(split_branches))
+        opt.split_branches = int(split_branches)
         opt.group_width = int(group_width)
         opt.cell_order = int(cell_order)
         if max_group_unknowns is not None:
@@ -149,6 +149,7 @@ class Plan:
         opt.cell_cut_percent = int(cell_cut_percent)
         opt.cell_max_cuts = int(cell_max_cuts)
         opt.res_pack = int(res_pack)
+        opt.level_balance = int(bool(level_balance))
         self._par = _host(parent, np.int32)
         self._coff = _host(cell_offsets, np.int64)
         bo = None if branch_offsets is None else _host(branch_offsets, np.int64)

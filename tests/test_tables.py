@@ -20,6 +20,10 @@ OPTION_SETS = [
     dict(cell_order=1, max_group_unknowns=900),
     dict(group_width=128, max_group_unknowns=0),
     dict(rebalance_root=1, split_branches=1, cell_order=1, group_width=256, max_group_unknowns=3000),
+    dict(split_branches=2),
+    dict(level_balance=1, max_group_unknowns=0),
+    dict(split_branches=2, level_balance=1, cell_order=1, max_group_unknowns=6000),
+    dict(rebalance_root=1, split_branches=2, level_balance=1, group_width=128, max_group_unknowns=0),
 ]
 
 
@@ -99,7 +103,7 @@ def test_breadth_first_inputs_keep_identity_numbering(name):
     assert (br[:, 3] == 1).all()
 
 
-def _check_invariants(f, t, T):
+def _check_invariants(f, t, T, balanced=False):
     n = f.n
     node_plan = t["node_plan"]
     br = t["branches"]
@@ -114,7 +118,10 @@ def _check_invariants(f, t, T):
         nodes = first + d * np.arange(ln)
         seen[nodes] += 1
         if pb >= 0:
-            assert br[pb, 1] == lvl - 1 and br[pb, 0] == cell
+            # a child runs at a deeper level than its parent; one deeper unless
+            # level balancing moved its subtree
+            assert br[pb, 0] == cell
+            assert br[pb, 1] < lvl if balanced else br[pb, 1] == lvl - 1
         else:
             assert lvl == 0
     assert (seen == 1).all()
@@ -150,7 +157,7 @@ def test_table_invariants(opts):
     f = configs.random_system(120, seed=8).forest
     o = dict(opts)
     T = o.get("group_width", 64)
-    _check_invariants(f, py_tables(f, **o), T)
+    _check_invariants(f, py_tables(f, **o), T, balanced=bool(o.get("level_balance")))
 
 
 def _eccentricity(adj, v):
@@ -383,3 +390,53 @@ def test_packing_is_greedy_by_compartment_cap():
     assert list(t1["group_cells"]) == [4, 0, 1, 2, 5, 3]
     assert list(t1["group_offsets"]) == [0, 1, 3, 6]
     assert_same(lib_tables(f, max_group_unknowns=10, cell_order=1), t1)
+
+
+def test_split_per_group_averages_hand_derived():
+    """S5' (the outlook, §8: per-block averages from an intermediate packing).
+    The cells of the S5 example (A: 2 + {6, 2}; B: 4 + 4) packed with a cap of
+    10 compartments form two groups, {A} and {B}.  Inside {A}: level 0 holds A's
+    root alone (average 2, nothing to cut); level 1 holds 6 and 2 (S = 8, m = 2,
+    average 4): the 6 keeps 4 (2-5), its tail 6-7 moves to level 2.  Inside {B}
+    every level holds one branch: nothing is cut.  (The averages over all
+    cells cut B's root instead.)"""
+    a = _chain(-1, 0, 2) + _chain(1, 2, 6) + _chain(1, 8, 2)
+    b = _chain(-1, 0, 4) + _chain(3, 4, 4)
+    f = _forest_from_cells([(a, [0, 2, 8]), (b, [0, 4])])
+    t = py_tables(f, split_branches=2, max_group_unknowns=10)
+    got = sorted((int(r[0]), int(r[1]), int(r[2]), int(r[4])) for r in t["branches"])
+    want = sorted([(0, 0, 0, 2), (0, 1, 2, 4), (0, 1, 8, 2), (0, 2, 6, 2), (1, 0, 10, 4), (1, 1, 14, 4)])
+    assert got == want
+    assert list(t["group_offsets"]) == [0, 1, 2]
+    assert_same(lib_tables(f, split_branches=2, max_group_unknowns=10), t)
+    # with one group (no cap) the per-group and the global averages agree
+    assert_same(py_tables(f, split_branches=2, max_group_unknowns=0), py_tables(f, split_branches=1, max_group_unknowns=0))
+
+
+def test_level_balance_moves_smallest_subtrees_down():
+    """S7' (the outlook, §8: subtrees may move one level down to even out the
+    level widths of a block).  The open group holds P, a root with 50 leaf
+    branches on level 1.  Q is a root with 20 children on level 1, the first
+    ten with one child each (level 2), the last ten leaves.  With T = 64, Q
+    overflows level 1 by 6: the six leaf children of smallest breadth-first
+    rank (Q's branches 11-16) move to level 2 and Q joins P's group
+    (64 branches on level 1, 16 on level 2).  Without balancing Q opens a
+    second group."""
+    p_cell = _star_cell(50)
+    q_par = [-1] + [0] * 20 + list(range(1, 11))
+    q_cell = (q_par, list(range(31)))
+    f = _forest_from_cells([p_cell, q_cell])
+    t0 = py_tables(f, branch_offsets=None, group_width=64, max_group_unknowns=0)
+    assert list(t0["group_offsets"]) == [0, 1, 2]
+    t = py_tables(f, branch_offsets=None, group_width=64, max_group_unknowns=0, level_balance=1)
+    assert list(t["group_offsets"]) == [0, 2]
+    br = t["branches"]
+    q = br[br[:, 0] == 1]
+    moved = sorted(int(r[7]) for r in q if r[1] == 2 and f.parent[int(r[2])] == 51)  # children of Q's root on level 2
+    assert moved == list(range(11, 17))
+    assert np.bincount(br[:, 1]).tolist() == [2, 64, 16]
+    # every branch stays deeper than its parent; lanes of a level run by length
+    for r in br:
+        if r[5] >= 0:
+            assert r[1] > br[r[5], 1]
+    assert_same(lib_tables(f, branch_offsets=None, group_width=64, max_group_unknowns=0, level_balance=1), t)
