@@ -1084,7 +1084,9 @@ __device__ __forceinline__ void cell_forward(const cflag_t& f, const CellPos& P,
       m -= 1;
       xt = stx[64 * m];
     }
-    const double xv = __builtin_fma(-fy[e].x, xp, fy[e].y);
+    // a padding step's factors were never stored: its value must not reach
+    // the next step (a cell root multiplies it by f = 0)
+    const double xv = (fe & hines::CF_PAD) ? 0.0 : __builtin_fma(-fy[e].x, xp, fy[e].y);
     if (fe & hines::CF_POP) {
       stx[64 * m] = xt;
       m += 1;
