@@ -554,13 +554,67 @@ def run_branching(args, torch, dev):
     }
 
 
+OUTLOOK_OPTIONS = (
+    ("split_global", dict(split_branches=1)),
+    ("split_per_group", dict(split_branches=2)),
+    ("no_split_level_balance", dict(level_balance=1)),
+    ("split_per_group_level_balance", dict(split_branches=2, level_balance=1)),
+    ("no_split", dict()),
+)
+
+
+def run_outlook(args, torch, dev):
+    """The outlook of the paper (section 8) on the level-synchronous kernel it
+    concerns: branch splitting with the average over all cells against the
+    average over each group of an intermediate packing, and packing with and
+    without moving subtrees one level down.  Groups of up to 4,096
+    compartments and 64 lanes, so that level widths, not the compartment cap,
+    limit the packing.  Default: the first 16,384 cells of the headline
+    workload (``--cells``)."""
+    from workloads import configs
+    from paper_1810_12742_amd import Plan
+    import oracle
+
+    nc = args.cells or 16384
+    s = configs.c2()
+    f = s.forest.subset(np.arange(nc)) if nc < s.forest.ncells else s.forest
+    n = f.n
+    d, u, b = (torch.from_numpy(np.ascontiguousarray(a[:n])).to(dev) for a in (s.diag, s.upper, s.rhs))
+    x = torch.empty_like(b)
+    stream = torch.cuda.current_stream()
+    xo = None if args.no_check else oracle.solve(f, s.diag[:n], s.upper[:n], s.rhs[:n])
+    rows = []
+    for name, extra in OUTLOOK_OPTIONS:
+        opts = dict(level_sync=1, max_group_unknowns=4096, group_width=64, **extra)
+        p = Plan(f.parent, f.cell_offsets, f.branch_offsets, **opts)
+        info = p.info
+        ms = _time(torch, lambda: p.solve(d, u, b, out=x, stream=stream), args.steps, args.warmup, stream)
+        row = {"variant": name, "options": opts, "ms": ms, "groups": info["ngroups"],
+               "levels": info["max_level"] + 1, "branches": info["nbranches"], "launches": info["nclasses"]}
+        if xo is not None:
+            row["max_rel_err_vs_oracle"] = cell_rel_err(f, x.cpu().numpy(), xo)
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+        p.close()
+    best = min(rows, key=lambda r: r["ms"])
+    return {
+        "metric": METRIC, "value": n / (best["ms"] * 1e-3), "unit": "unknowns/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": best["ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"outlook: first {nc} cells of c2 on the level-synchronous kernel, groups of up to "
+                               "4,096 compartments and 64 lanes; value is the fastest variant",
+                   "unknowns": n},
+        "rows": rows,
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("c2", "c3", "c5", "scaling", "branching"), default="c2")
-    ap.add_argument("--cells", type=int, default=0, help="c3/c5: number of cells (default: the full workload)")
+    ap.add_argument("--workload", choices=("c2", "c3", "c5", "scaling", "branching", "outlook"), default="c2")
+    ap.add_argument("--cells", type=int, default=0, help="c3/c5/outlook: number of cells (default: the full workload)")
     ap.add_argument("--graph-steps", type=int, default=100, help="c3: time steps per captured graph")
     ap.add_argument("--options", default="", help="plan options as JSON (c3: instead of the autotuner's pick)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -579,7 +633,7 @@ def main(argv=None):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     run = {"c2": run_c2, "c3": run_c3, "c5": run_c5, "scaling": run_scaling,
-           "branching": run_branching}[args.workload]
+           "branching": run_branching, "outlook": run_outlook}[args.workload]
     print(json.dumps(run(args, torch, dev)), flush=True)
     return 0
 

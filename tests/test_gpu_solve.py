@@ -62,6 +62,10 @@ OPTS = [
     dict(group_width=256, max_group_unknowns=5000, split_branches=1),
     dict(level_sync=1),
     dict(level_sync=1, split_branches=1, max_group_unknowns=3000),
+    # the outlook (§8): per-group split averages, subtrees moved down a level
+    dict(level_sync=1, split_branches=2, max_group_unknowns=4096),
+    dict(level_sync=1, level_balance=1, max_group_unknowns=4096),
+    dict(split_branches=2, level_balance=1, max_group_unknowns=4096),
 ]
 
 
