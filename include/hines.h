@@ -88,13 +88,14 @@ typedef struct hines_options {
                                  keeps using the groups.  0 (default): groups (§3-§4)        */
   int32_t resident;           /* 1: hines_solve runs the LDS-resident kernel: consecutive whole
                                  cells form a group of up to 1400 compartments (a larger cell is
-                                 a group of its own; see res_pack); one wave stages the group's d, u, b and
-                                 parent slots into LDS once, eliminates every compartment after
-                                 its children (§2) along root-ward paths scheduled at setup, one
-                                 path per lane at a time (§3-§4), and stores x.  Needs bitwise 0,
-                                 cell_lanes 0 and every cell's image within LDS (up to about 6,000
-                                 compartments; HINES_ERR_TOO_BIG otherwise).  The other calls
-                                 keep using the groups.                                      */
+                                 a group of its own; see res_pack); one wave stages the group's
+                                 d, u, b into LDS once, eliminates every compartment after its
+                                 children (§2) along root-ward paths that setup cuts into chunks
+                                 of 8 steps and schedules on the wave's 64 lanes (§3-§4), and
+                                 stores x.  Needs bitwise 0, cell_lanes 0 and every cell's
+                                 image within LDS (up to about 6,100 compartments;
+                                 HINES_ERR_TOO_BIG otherwise).  The other calls keep using the
+                                 groups.                                                     */
   /* Tuning of the cell-lane and resident tables (0 selects the default): */
   int32_t cell_cut_percent;   /* cell lanes: cells longer than this percentage of the mean cell
                                  are cut into pieces on several lanes (default 80)           */
@@ -164,17 +165,22 @@ enum {
                                         take, 6 bits each, in backward order in bits 0-31 and
                                         in forward order in bits 32-63; 0 without takes       */
   /* LDS-resident plans (hines_plan_info.kernel == 4).  Group image: slot s holds user index
-     lo + s; slot nslot is a zero entry.                                                     */
-  HINES_TABLE_RES_GROUPS = 17,       /* [ngroups*10] lo, blob (16-byte units), nslot, staged
+     lo + s; slot nslot is a zero entry (d = 1, u = 0, b = 0).                                */
+  HINES_TABLE_RES_GROUPS = 17,       /* [ngroups*15] lo, blob (16-byte units), nslot, staged
                                         slots, slot of the first compartment, compartments,
-                                        steps per sweep, blob units, cells, path records      */
-  HINES_TABLE_RES_PAR = 18,          /* [n] parent slot of each compartment in its group image
-                                        (nslot for a cell root)                              */
-  HINES_TABLE_RES_BLOB = 19          /* [blob bytes / 2] the group blobs as 16-bit words: 65
-                                        record offsets (one per lane, then the total; 72
-                                        words), the root slots padded to 8 words, the path
-                                        records (bottom slot, first step, length, 1 if the
-                                        top's contribution goes to its parent's entry)       */
+                                        chunks per sweep, blob units, cells, path records,
+                                        slot-list entries, byte offsets of the records and of
+                                        the slot lists in the blob, LDS class, steps per chunk */
+  /* 18 is not used */
+  HINES_TABLE_RES_BLOB = 19          /* [blob bytes / 2] the group blobs as 16-bit words: per lane
+                                        its first record and its first slot-list entry (65 + 65
+                                        words, 136 in all), the root slots padded to 8 words,
+                                        the path records (first chunk, chunks, byte offset of
+                                        the top's parent entry or 0xffff for a cell root, 0),
+                                        each lane's records enclosed by idle records (65535, 0,
+                                        0xffff, 0), then per lane one entry per active chunk:
+                                        the byte offsets (slot * 8) of its steps, the path's
+                                        bottom first (padding steps point at the zero entry) */
 };
 
 /* Fill *opt with the defaults: no re-rooting, no splitting, group_width 64,

@@ -68,8 +68,6 @@ hines_status ok() {
 // matter; each class is one launch, so there are few of them.
 constexpr int kBuckets[] = {4096, 8192, 12288, 16384, 20480, 23296, 27136, 32768, 40960, 54528, 81920, 163840};
 constexpr int kGlobalT = 256;  // workgroup of groups whose image lives in the workspace
-// LDS classes of the resident kernel: 160 KiB / k for k = 8 .. 1 waves per CU
-constexpr int kResBuckets[] = {20480, 23296, 27136, 32768, 40960, 54528, 81920, 163840};
 
 inline LdsLayout layout_of(const KGroup& g) {
   return LdsLayout{g.ws_off >= 0 ? 0 : g.nunk, (g.nbr + 1) & ~1, g.nlev};
@@ -148,12 +146,42 @@ void launch_bucket(const hines_plan* p, const hines_plan::Bucket& bk, const RhsS
   }
 }
 
+// one instantiation of the resident kernel per LDS class (plane stride S)
+template <int C>
+void launch_res_class(const DevTables& t, int32_t count, const double* d, const double* u, const double* b, double* x,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(hdev::k_solve_res<hines::kResClassStride[C]>, dim3((unsigned)count), dim3(64),
+                     hines::kResClassBytes[C], s, t, d, u, b, x);
+}
+
+template <int C = 0>
+hipError_t res_class_attr() {
+  if constexpr (C < hines::kResClasses) {
+    hipError_t e = hipFuncSetAttribute((const void*)hdev::k_solve_res<hines::kResClassStride[C]>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, hines::kResClassBytes[C]);
+    return e == hipSuccess ? res_class_attr<C + 1>() : e;
+  } else {
+    return hipSuccess;
+  }
+}
+
+template <int C = 0>
+void launch_res(int32_t cls, const DevTables& t, int32_t count, const double* d, const double* u, const double* b,
+                double* x, hipStream_t s) {
+  if constexpr (C < hines::kResClasses) {
+    if (cls == C)
+      launch_res_class<C>(t, count, d, u, b, x, s);
+    else
+      launch_res<C + 1>(cls, t, count, d, u, b, x, s);
+  }
+}
+
 hipError_t launch_resident(const hines_plan* p, const double* d, const double* u, const double* b, double* x,
                            hipStream_t s) {
   for (const auto& bk : p->res_buckets) {
     DevTables t = p->t;
     t.rlist = p->t.rlist + bk.first;
-    hipLaunchKernelGGL(hdev::k_solve_res, dim3((unsigned)bk.count), dim3(64), bk.lds_bytes, s, t, d, u, b, x);
+    launch_res(bk.level, t, bk.count, d, u, b, x, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -698,21 +726,16 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   }
   // resident groups by LDS class, longest schedules first within a class
   if (P.res.built) {
-    const int nbk2 = (int)(sizeof kResBuckets / sizeof kResBuckets[0]);
-    std::vector<std::vector<int32_t>> rm(nbk2);
-    for (int64_t g = 0; g < (int64_t)P.res.groups.size(); ++g) {
-      const int32_t bytes = P.res.groups[g].lds_bytes;
-      int k = 0;
-      while (k < nbk2 - 1 && kResBuckets[k] < bytes) ++k;
-      rm[k].push_back((int32_t)g);
-    }
-    for (int k = nbk2 - 1; k >= 0; --k) {
+    std::vector<std::vector<int32_t>> rm(hines::kResClasses);
+    for (int64_t g = 0; g < (int64_t)P.res.groups.size(); ++g) rm[P.res.groups[g].cls].push_back((int32_t)g);
+    for (int k = 0; k < hines::kResClasses; ++k) {
       auto& m = rm[k];
       if (m.empty()) continue;
       std::stable_sort(m.begin(), m.end(), [&](int32_t a, int32_t b) {
-        return P.res.groups[a].makespan > P.res.groups[b].makespan;
+        return P.res.groups[a].nchunk > P.res.groups[b].nchunk;
       });
-      p->res_buckets.push_back({kResBuckets[k], (int32_t)p->res_list.size(), (int32_t)m.size(), 0, 0});
+      // Bucket.level carries the LDS class of a resident launch
+      p->res_buckets.push_back({hines::kResClassBytes[k], (int32_t)p->res_list.size(), (int32_t)m.size(), 0, k});
       p->res_list.insert(p->res_list.end(), m.begin(), m.end());
     }
   }
@@ -743,16 +766,13 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   const hines::ResPlan& RP = P.res;
   const int64_t sz_rg = al((int64_t)RP.groups.size() * sizeof(hines::KResGroup));
   const int64_t sz_rl = al((int64_t)p->res_list.size() * sizeof(int32_t));
-  const int64_t sz_rp = al((int64_t)RP.par.size() * sizeof(uint16_t));
   const int64_t sz_rb = al((int64_t)RP.blob.size());
   const int64_t total = sz_br + sz_grp + sz_seg + sz_cell + sz_gl + sz_ws + sz_fl + sz_fm + sz_fp + sz_fa + sz_cw +
-                        sz_cb + sz_cp + sz_cf + sz_cm + sz_rg + sz_rl + sz_rp + sz_rb + 256;
+                        sz_cb + sz_cp + sz_cf + sz_cm + sz_rg + sz_rl + sz_rb + 256;
   const int64_t scr_bytes = CL.nchunks * hines::kCellChunk * 64 * 16;
   hipError_t e = hipGetDevice(&p->device);
   if (e == hipSuccess) e = allow_lds(o.group_width);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)hdev::k_solve_res, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)hines::kLdsLimitBytes);
+  if (e == hipSuccess) e = res_class_attr();
   if (e != hipSuccess) {
     delete p;
     return set_err(HINES_ERR_HIP, "device setup: %s", hipGetErrorString(e));
@@ -830,9 +850,6 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   p->t.rlist = (const int32_t*)(base + off);
   if (e == hipSuccess) e = up(p->res_list.data(), (int64_t)p->res_list.size() * sizeof(int32_t), off);
   off += sz_rl;
-  p->t.rpar = (const uint16_t*)(base + off);
-  if (e == hipSuccess) e = up(RP.par.data(), (int64_t)RP.par.size() * sizeof(uint16_t), off);
-  off += sz_rp;
   p->t.rblob = (const uint8_t*)(base + off);
   if (e == hipSuccess) e = up(RP.blob.data(), (int64_t)RP.blob.size(), off);
   off += sz_rb;
@@ -1236,7 +1253,7 @@ hines_status hines_plan_info_get(const hines_plan* p, hines_plan_info* info) {
     for (const auto& W : p->host.cl.waves) mk = std::max(mk, W.nchunk);
   if (p->host.res.built) {
     mk = 0;
-    for (const auto& G : p->host.res.groups) mk = std::max(mk, G.makespan);
+    for (const auto& G : p->host.res.groups) mk = std::max(mk, G.nchunk * hines::kResK);
   }
   info->max_makespan = mk;
   info->workspace_groups = ng_ws;

@@ -41,7 +41,6 @@ struct DevTables {
   int64_t cslots;                 // cell-lane kernel: steps x lanes of all waves (walk-layout array length)
   const hines::KResGroup* rgrp;   // resident kernel: per group
   const int32_t* rlist;           // resident kernel: group ids of one launch
-  const uint16_t* rpar;           // resident kernel: parent slot of every compartment (n + 2)
   const uint8_t* rblob;           // resident kernel: per-group lane offsets, roots and path records
 };
 
@@ -940,6 +939,8 @@ static_assert(CK == 8 || CK == 16, "chunk of 8 or 16 steps");
 typedef double double2_t __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) double2_t lds_d2;
 typedef __attribute__((address_space(3))) char lds_char;
+// LDS double at an absolute byte address
+__device__ __forceinline__ lds_f64* lds_at(int a) { return (lds_f64*)(uintptr_t)(unsigned)a; }
 typedef unsigned int cflag_t __attribute__((ext_vector_type(CK / 4)));  // CK flag bytes of one lane
 
 // The CK 16-bit positions of one lane's gather slots.
@@ -1226,69 +1227,160 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
 
 // ---------------------------------------------------------------------------
 // LDS-resident solve: one wave per group of whole cells.  The group's d, u, b
-// and parent slots are staged into LDS once by global->LDS DMA, in the user
-// numbering (slot s = user index lo + s); the sweeps touch only LDS; the
-// solution leaves in coalesced 16-byte stores.
+// are staged into LDS once by global->LDS DMA, as three planes of S slots in
+// the user numbering (slot s = user index lo + s); the sweeps touch only LDS;
+// the solution leaves in coalesced 16-byte stores.
 //
-// Backward sweep (paper §2: every compartment after its children).  Lane l
-// runs its path records in step order: a path is eliminated from its bottom
-// (a leaf) to its top in consecutive steps, each step j -> parent(j), so the
-// contribution (u f, f b') to the next compartment stays in registers; at the
-// top it is added into the parent's LDS entry (d_p -= u f, b_p -= f b') unless
-// the top is a cell root.  The setup ends every such path at least one step
-// before its parent is eliminated, and every LDS read of a step's operands is
-// issued after all additions of the steps before it (the wave executes its
-// LDS operations in order), so each compartment is eliminated once all its
-// children have contributed.  A step stores f = u / d' over d, y = b' / d'
-// over b and, over u, the slot the lane eliminated before it on this path.
+// Backward sweep (paper §2: every compartment after its children).  Each lane
+// runs its path records in chunk order, kResK steps per chunk: a path is
+// eliminated from its bottom (a leaf, after any padding steps on the zero
+// entry) to its top in consecutive steps, so the contribution (u f, u y) to
+// the next compartment stays in registers; at the end of its last chunk it is
+// added into the parent's LDS entry (d_p -= u f, b_p -= u y) unless the top is
+// a cell root.  A lane reads the operands of its next active chunk while the
+// current one runs; setup ends every light path two chunks before the chunk
+// that eliminates its parent, so each compartment is read after all its
+// children have contributed (the wave executes its LDS operations in order).
+// A step stores f = u / d' over u and y = b' / d' over b.
 //
-// Forward sweep: the steps in reverse.  A path runs from its top (x of the
-// parent read from LDS, written at an earlier step, zero for a root) down the
-// stored links: x_j = y_j - f_j x_parent, written over y.
+// Forward sweep: the chunks in reverse.  A path runs from its top (x of the
+// parent read from LDS, written at least two chunks earlier; zero for a root)
+// down to its bottom: x_j = y_j - f_j x_parent, written over y.  Lanes with no
+// path in a chunk are masked off for the whole chunk.
 // ---------------------------------------------------------------------------
 typedef __attribute__((address_space(3))) uint16_t lds_u16;
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) u32x2 lds_u2;
 
 struct ResRec {
-  int slot, t0, tend, aux;
+  int c0, cend, par;
 };
-// record k of the lane (records kb .. ke - 1), or an idle record (never
-// active, reads the zero slot)
-__device__ __forceinline__ ResRec res_rec(const lds_u2* recs, int k, int kb, int ke, int zero, int F) {
-  ResRec r{zero, F + 1, F + 1, zero};
-  if (k >= kb && k < ke) {
-    const u32x2 w = recs[k];
-    r.slot = (int)(w.x & 0xffffu);
-    r.t0 = (int)(w.x >> 16);
-    r.tend = r.t0 + (int)(w.y & 0xffffu);
-    r.aux = (int)(w.y >> 16);
-  }
+// a record word as loaded; decoded only where it is used, so the LDS read of a
+// lane's next record is not waited for at once.  Every lane's records are
+// enclosed by idle sentinels (first chunk 65535, no chunks): reading one
+// record past either end needs no bounds test.
+__device__ __forceinline__ ResRec res_decode(u32x2 w) {
+  ResRec r;
+  r.c0 = (int)(w.x & 0xffffu);
+  r.cend = r.c0 + (int)(w.x >> 16);
+  r.par = (int)(w.y & 0xffffu);
   return r;
 }
+// keep the decoded fields computed here (not sunk past a later load of the word)
+__device__ __forceinline__ void res_pin(ResRec& r) { __asm__ volatile("" : "+v"(r.c0), "+v"(r.cend), "+v"(r.par)); }
 
+// s_waitcnt lgkmcnt(0) with the vector-memory and export counters left free
+constexpr int kWaitLgkm0 = 0xc07f;
+
+// slot-list entry: the byte offsets (uint16) of a chunk's kResK steps
+template <int KK>
+struct ResEntOf;
+template <>
+struct ResEntOf<4> {
+  typedef u32x2 type;
+};
+template <>
+struct ResEntOf<8> {
+  typedef u32x4 type;
+};
+typedef ResEntOf<hines::kResK>::type res_ent;
+typedef __attribute__((address_space(3))) res_ent lds_ent;
+static_assert(sizeof(res_ent) == hines::kResEntBytes, "slot-list entry");
+
+__device__ __forceinline__ int res_a(res_ent a, int k) {
+  const unsigned w = a[k >> 1];
+  return (int)((k & 1) ? (w >> 16) : (w & 0xffffu));
+}
+
+// (d, u) of a step in one register pair: the two plane reads merge into one
+// ds_read2st64 whose destination is the pair
+template <int S>
+__device__ __forceinline__ void res_load_bwd(const lds_char* base, const int (&o4)[hines::kResK],
+                                             double2_t (&odu)[hines::kResK], double (&ob)[hines::kResK]) {
+#pragma unroll
+  for (int k = 0; k < hines::kResK; ++k) {
+    const int o = o4[k];
+    double2_t v;
+    v.x = *lds_at(o);
+    v.y = *lds_at(8 * S + o);
+    odu[k] = v;
+    ob[k] = *lds_at(16 * S + o);
+  }
+}
+
+// (f, y) of a step
+template <int S>
+__device__ __forceinline__ void res_load_fwd(const lds_char* base, const int (&o4)[hines::kResK],
+                                             double2_t (&ofy)[hines::kResK]) {
+#pragma unroll
+  for (int k = 0; k < hines::kResK; ++k) {
+    const int o = o4[k];
+    double2_t v;
+    v.x = *lds_at(8 * S + o);
+    v.y = *lds_at(16 * S + o);
+    ofy[k] = v;
+  }
+}
+
+// one backward chunk: eliminate kResK steps, then store f and y (each value in
+// a register of its own, so no store holds up the next step's arithmetic)
+template <int S>
+__device__ __forceinline__ void res_elim(lds_char* base, const int (&o4)[hines::kResK], const double2_t (&odu)[hines::kResK],
+                                         const double (&ob)[hines::kResK], double& ncd, double& ncb) {
+  double fv[hines::kResK], yv[hines::kResK];
+#pragma unroll
+  for (int k = 0; k < hines::kResK; ++k) {
+    const double uk = odu[k].y;
+    const double dd = odu[k].x + ncd;
+    const double bb = ob[k] + ncb;
+    const double r = rcp_nr(dd);
+    fv[k] = uk * r;
+    yv[k] = bb * r;
+    ncd = -(uk * fv[k]);
+    ncb = -(uk * yv[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < hines::kResK; ++k) {
+    *lds_at(8 * S + o4[k]) = fv[k];
+    *lds_at(16 * S + o4[k]) = yv[k];
+  }
+}
+
+template <int S>
+__device__ __forceinline__ void res_subst(lds_char* base, const int (&o4)[hines::kResK], const double2_t (&ofy)[hines::kResK],
+                                          double& xp) {
+  double xv[hines::kResK];
+#pragma unroll
+  for (int k = hines::kResK - 1; k >= 0; --k) {
+    xv[k] = __builtin_fma(-ofy[k].x, xp, ofy[k].y);
+    xp = xv[k];
+  }
+#pragma unroll
+  for (int k = hines::kResK - 1; k >= 0; --k) *lds_at(16 * S + o4[k]) = xv[k];
+}
+
+template <int S>
 __global__ __launch_bounds__(64) void k_solve_res(DevTables tb, const double* __restrict__ d,
                                                   const double* __restrict__ u, const double* __restrict__ b,
                                                   double* __restrict__ x) {
+  constexpr int K = hines::kResK;
   extern __shared__ __attribute__((aligned(16))) double res_raw[];
   const hines::KResGroup G = tb.rgrp[tb.rlist[blockIdx.x]];
   const int lane = threadIdx.x;
-  const int S = G.nslot + 2;  // slots nslot (zero entry) and nslot + 1 (spare)
-  const int zero = G.nslot;
-  const int F = G.makespan;
-  char* base = (char*)res_raw;
-  const int oU = 8 * S, oB = 16 * S, oP = 24 * S, oBlob = oP + ((2 * G.nslot + 15) & ~15);
-  // ---- staging ----
-  const int nu = G.ndma >> 1;
-  dma16<64>(d + G.lo, base, nu, lane);
-  dma16<64>(u + G.lo, base + oU, nu, lane);
-  dma16<64>(b + G.lo, base + oB, nu, lane);
-  dma4<64>(tb.rpar + G.lo, base + oP, G.nslot >> 1, lane);
-  dma16<64>(tb.rblob + 16 * G.blob, base + oBlob, G.blob_units, lane);
+  // the group's image starts at LDS address 0 (the kernel declares no other
+  // LDS): list entries and record fields are absolute LDS byte addresses
+  lds_char* base = (lds_char*)res_raw;
+  constexpr int oU = 8 * S, oB = 16 * S, oBlob = 24 * S;
   lds_f64* D = (lds_f64*)base;
   lds_f64* U = (lds_f64*)(base + oU);
   lds_f64* B = (lds_f64*)(base + oB);
-  const lds_u16* PAR = (const lds_u16*)(base + oP);
+  // ---- staging ----
+  const int nu = G.ndma >> 1;
+  char* gbase = (char*)res_raw;  // generic pointer for the DMA helper
+  dma16<64>(d + G.lo, gbase, nu, lane);
+  dma16<64>(u + G.lo, gbase + oU, nu, lane);
+  dma16<64>(b + G.lo, gbase + oB, nu, lane);
+  dma16<64>(tb.rblob + 16 * G.blob, gbase + oBlob, G.blob_units, lane);
   double tail_d = 0.0, tail_u = 0.0, tail_b = 0.0;
   const bool tail = (G.ndma & 1) && lane == 0;
   if (tail) {
@@ -1297,120 +1389,131 @@ __global__ __launch_bounds__(64) void k_solve_res(DevTables tb, const double* __
     tail_b = b[G.lo + G.ndma - 1];
   }
   __builtin_amdgcn_s_waitcnt(0);  // every DMA of this wave has landed
+  const int zero = G.nslot;
   if (tail) {
     D[G.ndma - 1] = tail_d;
     U[G.ndma - 1] = tail_u;
     B[G.ndma - 1] = tail_b;
   }
-  if (lane < 2) {  // the zero entry (and the spare): eliminates to nothing
-    D[zero + lane] = 1.0;
-    U[zero + lane] = 0.0;
-    B[zero + lane] = 0.0;
+  if (lane == 0) {  // the zero entry: eliminates to nothing
+    D[zero] = 1.0;
+    U[zero] = 0.0;
+    B[zero] = 0.0;
   }
   const lds_u16* ltab = (const lds_u16*)(base + oBlob);
   const lds_u16* roots = ltab + hines::kResLaneTab / 2;
   for (int r = lane; r < G.nroot; r += 64) U[roots[r]] = 0.0;  // a root has no coupling
-  lds_u2* recs = (lds_u2*)(base + oBlob + hines::kResLaneTab + ((2 * G.nroot + 15) & ~15));
-  const int kb = ltab[lane], ke = ltab[lane + 1];
+  const lds_u2* recs = (const lds_u2*)(base + oBlob + G.rec_off);
+  const lds_ent* lists = (const lds_ent*)(base + oBlob + G.list_off);
+  const int kb = ltab[lane], ke = ltab[lane + 1] - 1;  // records [kb, ke), sentinels at kb - 1 and ke
+  const int lb = ltab[65 + lane], le = ltab[65 + lane + 1];
+  const int NC = G.nchunk;
+  __asm__ volatile("" ::: "memory");
 
   // ---- backward sweep ----
   {
     int ri = kb;
-    ResRec c = res_rec(recs, ri, kb, ke, zero, F), nx = res_rec(recs, ri + 1, kb, ke, zero, F);
-    int j = c.slot, prev = zero;
-    double d1 = D[j], u1 = U[j], b1 = B[j];
-    int p1 = PAR[j];
-    double d2 = D[nx.slot], u2 = U[nx.slot], b2 = B[nx.slot];
-    int p2 = PAR[nx.slot];
-    double cd = 0.0, cb = 0.0;
-    for (int t = 0; t < F; ++t) {
-      const bool act = t >= c.t0 && t < c.tend;
-      const bool top = act && t == c.tend - 1;
-      if (act) {
-        const double dd = d1 - cd, bb = b1 - cb;
-        const double r = rcp_nr(dd);
-        const double f = u1 * r;
-        D[j] = f;
-        B[j] = bb * r;
-        *(lds_u16*)(U + j) = (uint16_t)prev;
-        cd = u1 * f;
-        cb = f * bb;
+    ResRec R = res_decode(recs[ri]);
+    u32x2 Rn = recs[ri + 1];  // the next record, raw
+    res_ent ahead = lists[lb];  // the list region holds one spare entry past the last
+    int li = lb + 1;
+    double2_t du0[K] = {}, du1[K] = {};
+    double b0[K] = {}, b1[K] = {};
+    int a0[K] = {}, a1[K] = {};  // byte offsets of the chunk's steps
+    double ncd = 0.0, ncb = 0.0;
+    // operands of chunk c1 for the lanes active in it (the next list entry)
+    auto pre = [&](int c1, int (&anx)[K], double2_t (&dun)[K], double (&bn)[K]) {
+      const bool act1 = c1 < R.cend ? c1 >= R.c0 : c1 >= (int)(Rn.x & 0xffffu);
+      if (act1 && c1 < NC) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) anx[k] = res_a(ahead, k);
+        res_load_bwd<S>(base, anx, dun, bn);
+        __builtin_amdgcn_sched_barrier(0);
+        ahead = lists[li];
+        li += 1;
       }
-      if (top && c.aux) {  // the path's contribution to the parent of its top
-        lds_add(D + p1, -cd);
-        lds_add(B + p1, -cb);
-      }
-      __asm__ volatile("" ::: "memory");  // the additions precede every read below
-      if (act) {
-        if (top) {
-          recs[ri] = u32x2{(unsigned)j | ((unsigned)c.t0 << 16), (unsigned)(c.tend - c.t0) | ((unsigned)p1 << 16)};
-          cd = 0.0;
-          cb = 0.0;
-          prev = zero;
+    };
+    // one chunk: prefetch the next chunk's operands, eliminate, push
+    auto chunk = [&](int c, int (&acur)[K], double2_t (&duc)[K], double (&bc)[K], int (&anx)[K], double2_t (&dun)[K],
+                     double (&bn)[K]) {
+      // the operands of chunk c (read during the chunk before) have landed;
+      // waiting here, where every lane passes, spares the masked blocks below
+      // a wait of their own
+      __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+      pre(c + 1, anx, dun, bn);
+      __asm__ volatile("" ::: "memory");
+      if (c >= R.c0 && c < R.cend) {
+        res_elim<S>(base, acur, duc, bc, ncd, ncb);
+        if (c == R.cend - 1) {  // the path's top
+          if (R.par != hines::kResNoParent) {
+            lds_add(lds_at(R.par), ncd);
+            lds_add(lds_at(oB + R.par), ncb);
+          }
+          ncd = 0.0;
+          ncb = 0.0;
           ri += 1;
-          c = nx;
-          j = c.slot;
-          d1 = d2;
-          u1 = u2;
-          b1 = b2;
-          p1 = p2;
-          nx = res_rec(recs, ri + 1, kb, ke, zero, F);
-          d2 = D[nx.slot];  // a path's bottom is a leaf: nothing adds into it
-          u2 = U[nx.slot];
-          b2 = B[nx.slot];
-          p2 = PAR[nx.slot];
-        } else {
-          prev = j;
-          j = p1;
-          d1 = D[j];
-          u1 = U[j];
-          b1 = B[j];
-          p1 = PAR[j];
+          R = res_decode(Rn);
+          res_pin(R);
+          Rn = recs[ri + 1];
         }
       }
+      __asm__ volatile("" ::: "memory");
+    };
+    pre(0, a0, du0, b0);
+    for (int c = 0; c < NC; c += 2) {
+      chunk(c, a0, du0, b0, a1, du1, b1);
+      if (c + 1 < NC) chunk(c + 1, a1, du1, b1, a0, du0, b0);
     }
   }
   __asm__ volatile("" ::: "memory");
 
-  // ---- forward sweep: steps in reverse, records in reverse ----
+  // ---- forward sweep: chunks in reverse, records in reverse ----
   {
     int ri = ke - 1;
-    // after the backward sweep a record holds (top slot, t0, len, parent slot of the top)
-    ResRec c = res_rec(recs, ri, kb, ke, zero, F), nx = res_rec(recs, ri - 1, kb, ke, zero, F);
-    int j = c.slot;
-    double f1 = D[j], y1 = B[j];
-    int l1 = *(const lds_u16*)(U + j);
-    double f2 = D[nx.slot], y2 = B[nx.slot];
-    int l2 = *(const lds_u16*)(U + nx.slot);
+    ResRec R = res_decode(recs[ri]);
+    u32x2 Rp = recs[ri - 1];  // the previous record, raw
+    res_ent ahead = lists[le > lb ? le - 1 : lb];
+    int li = le - 2;
+    double2_t fy0[K] = {}, fy1[K] = {};
+    double xq0 = 0.0, xq1 = 0.0;  // x of the parent of a top chunk's top
+    int a0[K] = {}, a1[K] = {};
     double xp = 0.0;
-    for (int t = F - 1; t >= 0; --t) {
-      const bool act = t >= c.t0 && t < c.tend;
-      if (act) {
-        if (t == c.tend - 1) xp = B[c.aux];  // x of the top's parent (0 for a root)
-        const double xv = __builtin_fma(-f1, xp, y1);
-        B[j] = xv;
-        xp = xv;
+    // operands of chunk c1 (and x of its top's parent) for the lanes active in it
+    auto pre = [&](int c1, int (&anx)[K], double2_t (&fyn)[K], double& xqn) {
+      const bool inR = c1 >= R.c0;
+      const ResRec Q = inR ? R : res_decode(Rp);
+      if (c1 >= Q.c0 && c1 < Q.cend && c1 >= 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) anx[k] = res_a(ahead, k);
+        res_load_fwd<S>(base, anx, fyn);
+        const int pq = Q.par != hines::kResNoParent && c1 == Q.cend - 1 ? Q.par : 8 * zero;
+        xqn = *lds_at(oB + pq);
+        __builtin_amdgcn_sched_barrier(0);
+        ahead = lists[li < lb ? lb : li];
+        li -= 1;
       }
+    };
+    auto chunk = [&](int c, int (&acur)[K], double2_t (&fyc)[K], double& xqc, int (&anx)[K], double2_t (&fyn)[K],
+                     double& xqn) {
+      __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+      pre(c - 1, anx, fyn, xqn);
       __asm__ volatile("" ::: "memory");
-      if (act) {
-        if (t == c.t0) {  // the path's bottom: next record
+      if (c >= R.c0 && c < R.cend) {
+        if (c == R.cend - 1) xp = xqc;
+        res_subst<S>(base, acur, fyc, xp);
+        if (c == R.c0) {  // the path's bottom: previous record
           ri -= 1;
-          c = nx;
-          j = c.slot;
-          f1 = f2;
-          y1 = y2;
-          l1 = l2;
-          nx = res_rec(recs, ri - 1, kb, ke, zero, F);
-          f2 = D[nx.slot];  // a top's f and y are not written before its own step
-          y2 = B[nx.slot];
-          l2 = *(const lds_u16*)(U + nx.slot);
-        } else {
-          j = l1;
-          f1 = D[j];
-          y1 = B[j];
-          l1 = *(const lds_u16*)(U + j);
+          R = res_decode(Rp);
+          res_pin(R);
+          Rp = recs[ri - 1];
         }
       }
+      __asm__ volatile("" ::: "memory");
+    };
+    pre(NC - 1, a0, fy0, xq0);
+    for (int c = NC - 1; c >= 0; c -= 2) {
+      chunk(c, a0, fy0, xq0, a1, fy1, xq1);
+      if (c - 1 >= 0) chunk(c - 1, a1, fy1, xq1, a0, fy0, xq0);
     }
   }
   __asm__ volatile("" ::: "memory");
@@ -1428,7 +1531,6 @@ __global__ __launch_bounds__(64) void k_solve_res(DevTables tb, const double* __
     }
   }
 }
-
 // ---------------------------------------------------------------------------
 // Time loop with the factors kept (cell-lane plans).  The matrix of a time
 // loop does not change between steps, so the elimination of A (paper §2: the

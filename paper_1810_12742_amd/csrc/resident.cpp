@@ -6,13 +6,15 @@
 // "light" child) the path follows the heavy child down to a leaf, the heavy
 // child of a compartment being the one whose subtree finishes last when every
 // compartment runs as soon as its children are done.  A lane eliminates a
-// path bottom-up in consecutive steps, so inside a path the contribution to
-// the parent stays in registers; a light child's path adds its contribution
-// into the parent's LDS entry at its last step.  Paths are placed as late as
-// possible: the root paths end at the last step, and every other path must end
-// at least one step before the step that eliminates its top's parent (§3's
-// level-by-level order is replaced by these per-compartment deadlines).  A
-// path goes on the lane whose earliest placed path starts latest.
+// path bottom-up in consecutive steps, kResK steps per chunk, so inside a path
+// the contribution to the parent stays in registers; a light child's path adds
+// its contribution into the parent's LDS entry at the end of its last chunk.
+// Paths are placed as late as possible, in whole chunks: the root paths end in
+// the last chunk, and every other path must end at least two chunks before
+// the chunk that eliminates its top's parent (the kernel reads a chunk's
+// operands while the chunk before it runs; §3's level-by-level order is
+// replaced by these per-compartment deadlines).  A path goes on the lane whose
+// earliest placed path starts latest.
 #include <algorithm>
 #include <cstring>
 #include <string>
@@ -28,31 +30,34 @@ struct PathInfo {
 };
 
 struct Ready {
-  int32_t deadline, len, top;
+  int32_t deadline, nch, top;  // chunks
 };
 // max deadline first, then the longer path, then the smaller top
 inline bool ready_less(const Ready& a, const Ready& b) {
   if (a.deadline != b.deadline) return a.deadline < b.deadline;
-  if (a.len != b.len) return a.len < b.len;
+  if (a.nch != b.nch) return a.nch < b.nch;
   return a.top > b.top;
 }
 
 struct Placed {
-  int32_t lane, start, len, bottom, top;
+  int32_t lane, c0, nch, top;
 };
 
-// Schedule the compartments [0, m) of one group (local numbering, parent
-// lpar[i] < i or -1) on 64 lanes within F steps.  Returns false if some path
-// does not fit.
+inline int32_t nchunks(int32_t len) { return (len + kResK - 1) / kResK; }
+
+// Schedule the paths of one group (local numbering, parent lpar[i] < i or -1)
+// on 64 lanes within NC chunks.  chunk_of[i] receives the chunk that
+// eliminates compartment i.  Returns false if some path does not fit.
 bool schedule_group(int32_t m, const std::vector<int32_t>& lpar, const std::vector<int32_t>& ch_off,
                     const std::vector<int32_t>& ch, const std::vector<int32_t>& heavy,
-                    const std::vector<PathInfo>& path_of_top, int32_t F, std::vector<Placed>& placed) {
+                    const std::vector<PathInfo>& path_of_top, int32_t NC, std::vector<Placed>& placed,
+                    std::vector<int32_t>& chunk_of) {
   placed.clear();
   int32_t frontier[kSchedLanes];
-  for (int l = 0; l < kSchedLanes; ++l) frontier[l] = F;
+  for (int l = 0; l < kSchedLanes; ++l) frontier[l] = NC;
   std::vector<Ready> heap;
   for (int32_t i = 0; i < m; ++i)
-    if (lpar[i] < 0) heap.push_back({F - 1, path_of_top[i].len, i});
+    if (lpar[i] < 0) heap.push_back({NC - 1, nchunks(path_of_top[i].len), i});
   std::make_heap(heap.begin(), heap.end(), ready_less);
   while (!heap.empty()) {
     std::pop_heap(heap.begin(), heap.end(), ready_less);
@@ -62,25 +67,35 @@ bool schedule_group(int32_t m, const std::vector<int32_t>& lpar, const std::vect
     for (int l = 1; l < kSchedLanes; ++l)
       if (frontier[l] > frontier[best]) best = l;
     const int32_t end = std::min(r.deadline, frontier[best] - 1);
-    const int32_t start = end - r.len + 1;
-    if (start < 0) return false;
-    frontier[best] = start;
+    const int32_t c0 = end - r.nch + 1;
+    if (c0 < 0) return false;
+    frontier[best] = c0;
+    placed.push_back({best, c0, r.nch, r.top});
     const PathInfo& P = path_of_top[r.top];
-    placed.push_back({best, start, r.len, P.bottom, r.top});
-    // light children of every compartment of the path: their paths must end
-    // one step before the compartment's step
+    const int32_t pad = r.nch * kResK - P.len;
+    // step q of the path (0 = its bottom) runs in chunk c0 + (pad + q) / kResK;
+    // light children of each of its compartments must end two chunks earlier
     int32_t j = P.bottom;
-    for (int32_t k = 0; k < r.len; ++k) {
+    for (int32_t q = 0; q < P.len; ++q) {
+      const int32_t cj = c0 + (pad + q) / kResK;
+      chunk_of[j] = cj;
       for (int32_t e = ch_off[j]; e < ch_off[j + 1]; ++e) {
         const int32_t c = ch[e];
         if (c == heavy[j]) continue;
-        heap.push_back({start + k - 1, path_of_top[c].len, c});
+        heap.push_back({cj - 2, nchunks(path_of_top[c].len), c});
         std::push_heap(heap.begin(), heap.end(), ready_less);
       }
       j = lpar[j];
     }
   }
   return true;
+}
+
+// Smallest LDS class (most groups per CU) that holds the image.
+int32_t res_class(int32_t nslot, int64_t blob_units) {
+  for (int32_t k = kResClasses - 1; k >= 0; --k)
+    if (nslot + 1 <= kResClassStride[k] && res_lds_bytes(k, blob_units) <= kResClassBytes[k]) return k;
+  return -1;
 }
 
 }  // namespace
@@ -92,7 +107,6 @@ Status build_resident(const int32_t* parent, int64_t n, const int64_t* cell_offs
     err = "resident pack size out of range";
     return ERR_OPTION;
   }
-  out.par.assign((size_t)n + 2, 0);
   // groups of consecutive cells
   std::vector<int64_t> gc;  // first cell of each group, then ncells
   for (int64_t c = 0; c < ncells;) {
@@ -107,24 +121,25 @@ Status build_resident(const int32_t* parent, int64_t n, const int64_t* cell_offs
   }
   gc.push_back(ncells);
   const int64_t ng = (int64_t)gc.size() - 1;
-  std::vector<int32_t> lpar, ch_off, ch, fin, heavy, fill;
+  std::vector<int32_t> lpar, ch_off, ch, fin, heavy, fill, chunk_of;
   std::vector<PathInfo> path_of_top;
   std::vector<Placed> placed;
-  std::vector<int32_t> lane_count(kSchedLanes + 1);
+  std::vector<int32_t> lane_rec(kSchedLanes + 1), lane_list(kSchedLanes + 1);
   for (int64_t g = 0; g < ng; ++g) {
     const int64_t u0 = cell_offsets[gc[g]], u1 = cell_offsets[gc[g + 1]];
-    const int32_t m = (int32_t)(u1 - u0);
+    const int64_t m64 = u1 - u0;
     KResGroup G{};
     G.lo = u0 & ~(int64_t)1;
     G.first = (int32_t)(u0 - G.lo);
+    if (m64 + G.first + 2 > kResMaxSlots) {
+      err = "a cell of " + std::to_string(m64) + " compartments exceeds the resident kernel's LDS image";
+      return ERR_TOO_BIG;
+    }
+    const int32_t m = (int32_t)m64;
     G.count = m;
     G.nslot = (G.first + m + 1) & ~1;
     G.ndma = (int32_t)std::min<int64_t>(G.nslot, n - G.lo);
     G.nroot = (int32_t)(gc[g + 1] - gc[g]);
-    if (G.nslot > kResMaxSlots) {
-      err = "a cell of " + std::to_string(m) + " compartments exceeds the resident kernel's LDS image";
-      return ERR_TOO_BIG;
-    }
     // local tree: children (ascending), finishing steps, heavy children
     lpar.assign(m, -1);
     ch_off.assign(m + 1, 0);
@@ -148,7 +163,7 @@ Status build_resident(const int32_t* parent, int64_t n, const int64_t* cell_offs
       fin[i] = h < 0 ? 0 : fin[h] + 1;
     }
     path_of_top.assign(m, PathInfo{-1, 0});
-    int32_t F = 1;
+    int32_t NC = 1;
     for (int32_t i = 0; i < m; ++i) {
       if (lpar[i] >= 0 && heavy[lpar[i]] == i) continue;
       int32_t b = i, len = 1;
@@ -157,51 +172,92 @@ Status build_resident(const int32_t* parent, int64_t n, const int64_t* cell_offs
         ++len;
       }
       path_of_top[i] = {b, len};
-      if (lpar[i] < 0) F = std::max(F, fin[i] + 1);
+      if (lpar[i] < 0) NC = std::max(NC, nchunks(len));
     }
-    while (!schedule_group(m, lpar, ch_off, ch, heavy, path_of_top, F, placed)) F += std::max(1, F / 32);
-    if (F > 65535) {
-      err = "resident schedule longer than 65535 steps";
+    chunk_of.assign(m, -1);
+    while (!schedule_group(m, lpar, ch_off, ch, heavy, path_of_top, NC, placed, chunk_of))
+      NC += std::max(1, NC / 32);
+    if (NC > 65535) {
+      err = "resident schedule longer than 65535 chunks";
       return ERR_TOO_BIG;
     }
-    G.makespan = F;
+    G.nchunk = NC;
     G.npath = (int32_t)placed.size();
-    // records lane by lane in step order
+    const int32_t nrec = G.npath + kSchedLanes + 1;  // records and sentinels
+    // records lane by lane in chunk order; list entries in the same order
     std::stable_sort(placed.begin(), placed.end(), [](const Placed& a, const Placed& b) {
-      return a.lane != b.lane ? a.lane < b.lane : a.start < b.start;
+      return a.lane != b.lane ? a.lane < b.lane : a.c0 < b.c0;
     });
-    std::fill(lane_count.begin(), lane_count.end(), 0);
-    for (const Placed& p : placed) ++lane_count[p.lane + 1];
-    for (int l = 0; l < kSchedLanes; ++l) lane_count[l + 1] += lane_count[l];
+    std::fill(lane_rec.begin(), lane_rec.end(), 0);
+    std::fill(lane_list.begin(), lane_list.end(), 0);
+    for (const Placed& p : placed) {
+      ++lane_rec[p.lane + 1];
+      lane_list[p.lane + 1] += p.nch;
+    }
+    // records: an idle sentinel before every lane's records and after the
+    // last lane's, so a lane reads its next (or previous) record ahead of
+    // use without a bounds test
+    lane_rec[0] = 1;
+    for (int l = 0; l < kSchedLanes; ++l) {
+      lane_rec[l + 1] += lane_rec[l] + 1;
+      lane_list[l + 1] += lane_list[l];
+    }
+    G.nlist = lane_list[kSchedLanes];
+    if (nrec > 65535 || G.nlist > 65535) {
+      err = "resident group with too many paths";
+      return ERR_TOO_BIG;
+    }
     const int64_t root_bytes = (2 * (int64_t)G.nroot + 15) & ~(int64_t)15;
-    const int64_t rec_bytes = (8 * (int64_t)G.npath + 15) & ~(int64_t)15;
-    const int64_t bytes = kResLaneTab + root_bytes + rec_bytes;
+    const int64_t rec_bytes = (8 * (int64_t)nrec + 15) & ~(int64_t)15;
+    // one spare entry past the last: a lane reads its next entry ahead of use
+    const int64_t list_bytes = (kResEntBytes * ((int64_t)G.nlist + 1) + 15) & ~(int64_t)15;
+    G.rec_off = kResLaneTab + (int32_t)root_bytes;
+    G.list_off = G.rec_off + (int32_t)rec_bytes;
+    const int64_t bytes = G.list_off + list_bytes;
     G.blob_units = (int32_t)(bytes / 16);
+    G.cls = res_class(G.nslot, G.blob_units);
+    if (G.cls < 0) {
+      err = "a group of " + std::to_string(m) + " compartments exceeds LDS in the resident kernel";
+      return ERR_TOO_BIG;
+    }
     G.blob = (int64_t)out.blob.size() / 16;
     const size_t b0 = out.blob.size();
     out.blob.resize(b0 + bytes, 0);
     uint8_t* bp = out.blob.data() + b0;
     auto put16 = [&](int64_t off, uint16_t v) { std::memcpy(bp + off, &v, 2); };
-    for (int l = 0; l <= kSchedLanes; ++l) put16(2 * l, (uint16_t)lane_count[l]);
+    for (int l = 0; l <= kSchedLanes; ++l) {
+      put16(2 * l, (uint16_t)lane_rec[l]);
+      put16(2 * (kSchedLanes + 1) + 2 * l, (uint16_t)lane_list[l]);
+    }
     for (int32_t c = 0; c < G.nroot; ++c)
       put16(kResLaneTab + 2 * c, (uint16_t)(cell_offsets[gc[g] + c] - G.lo));
+    const uint16_t zero_off = (uint16_t)(8 * G.nslot);
+    const KResRec idle{0xffff, 0, (uint16_t)kResNoParent, 0};
+    for (int l = 0; l <= kSchedLanes; ++l) std::memcpy(bp + G.rec_off + 8 * (lane_rec[l] - 1), &idle, 8);
+    int64_t le = 0;
     for (int32_t k = 0; k < G.npath; ++k) {
       const Placed& p = placed[k];
+      const PathInfo& P = path_of_top[p.top];
       KResRec r;
-      r.slot = (uint16_t)(p.bottom + G.first);
-      r.t0 = (uint16_t)p.start;
-      r.len = (uint16_t)p.len;
-      r.aux = lpar[p.top] >= 0 ? 1 : 0;
-      std::memcpy(bp + kResLaneTab + root_bytes + 8 * k, &r, 8);
+      r.c0 = (uint16_t)p.c0;
+      r.nch = (uint16_t)p.nch;
+      r.par = lpar[p.top] >= 0 ? (uint16_t)(8 * (lpar[p.top] + G.first)) : (uint16_t)kResNoParent;
+      r.spare = 0;
+      std::memcpy(bp + G.rec_off + 8 * ((int64_t)k + p.lane + 1), &r, 8);  // k records and lane + 1 sentinels before
+      // slot lists: the path's steps from its bottom up, padding first
+      const int32_t pad = p.nch * kResK - P.len;
+      int32_t j = P.bottom;
+      for (int32_t s = 0; s < p.nch * kResK; ++s) {
+        uint16_t v = zero_off;
+        if (s >= pad) {
+          v = (uint16_t)(8 * (j + G.first));
+          j = lpar[j];
+        }
+        put16(G.list_off + kResEntBytes * le + 2 * (s % kResK), v);
+        if (s % kResK == kResK - 1) ++le;
+      }
     }
-    for (int32_t i = 0; i < m; ++i)
-      out.par[u0 + i] = (uint16_t)(lpar[i] < 0 ? G.nslot : lpar[i] + G.first);
-    G.lds_bytes = (int32_t)res_lds_bytes(G.nslot, G.blob_units);
-    if (G.lds_bytes > kLdsLimitBytes) {
-      err = "a group of " + std::to_string(m) + " compartments exceeds LDS in the resident kernel";
-      return ERR_TOO_BIG;
-    }
-    out.max_lds = std::max<int64_t>(out.max_lds, G.lds_bytes);
+    out.max_lds = std::max<int64_t>(out.max_lds, res_lds_bytes(G.cls, G.blob_units));
     out.groups.push_back(G);
   }
   out.built = true;
@@ -209,16 +265,16 @@ Status build_resident(const int32_t* parent, int64_t n, const int64_t* cell_offs
 }
 
 bool check_resident(const ResPlan& R, const int32_t* parent, int64_t n, std::string& why) {
-  std::vector<int32_t> step, lane_of;
-  std::vector<uint8_t> leaf;
+  std::vector<int32_t> chunk, sub, top_end;
   for (size_t g = 0; g < R.groups.size(); ++g) {
     const KResGroup& G = R.groups[g];
     const std::string gs = "resident group " + std::to_string(g);
     if (G.lo < 0 || (G.lo & 1) || G.first < 0 || G.first > 1 || G.count < 1 || G.nslot < G.first + G.count ||
-        (G.nslot & 1) || G.nslot > kResMaxSlots || G.ndma < G.first + G.count || G.ndma > G.nslot ||
-        G.lo + G.ndma > n || G.makespan < 1 || G.makespan > 65535 || G.blob < 0 ||
-        16 * (G.blob + G.blob_units) > (int64_t)R.blob.size() || G.lds_bytes > kLdsLimitBytes ||
-        G.lds_bytes != res_lds_bytes(G.nslot, G.blob_units)) {
+        (G.nslot & 1) || G.nslot + 2 > kResMaxSlots || G.ndma < G.first + G.count || G.ndma > G.nslot ||
+        G.lo + G.ndma > n || G.nchunk < 1 || G.nchunk > 65535 || G.blob < 0 || G.cls < 0 || G.cls >= kResClasses ||
+        G.nslot + 1 > kResClassStride[G.cls] || res_lds_bytes(G.cls, G.blob_units) > kResClassBytes[G.cls] ||
+        16 * (G.blob + G.blob_units) > (int64_t)R.blob.size() || G.rec_off < kResLaneTab ||
+        (G.rec_off & 7) || (G.list_off & 7)) {
       why = gs + ": record out of range";
       return false;
     }
@@ -228,31 +284,17 @@ bool check_resident(const ResPlan& R, const int32_t* parent, int64_t n, std::str
       std::memcpy(&v, bp + off, 2);
       return (int32_t)v;
     };
-    const int64_t root_bytes = (2 * (int64_t)G.nroot + 15) & ~(int64_t)15;
-    if (kResLaneTab + root_bytes + 8 * (int64_t)G.npath > 16 * (int64_t)G.blob_units || get16(0) != 0 ||
-        get16(2 * kSchedLanes) != G.npath) {
-      why = gs + ": blob size";
+    const int32_t nrec = G.npath + kSchedLanes + 1;
+    if (get16(0) != 1 || get16(2 * kSchedLanes) != nrec || get16(2 * (kSchedLanes + 1)) != 0 ||
+        get16(2 * (kSchedLanes + 1) + 2 * kSchedLanes) != G.nlist || G.list_off < G.rec_off + 8 * nrec ||
+        G.list_off + kResEntBytes * ((int64_t)G.nlist + 1) > 16 * (int64_t)G.blob_units) {
+      why = gs + ": lane table";
       return false;
     }
     const int32_t s0 = G.first, s1 = G.first + G.count;
-    step.assign(G.nslot, -1);
-    leaf.assign(G.nslot, 1);
-    for (int32_t s = s0; s < s1; ++s) {
-      const int64_t i = G.lo + s;
-      const int32_t ps = R.par[i];
-      if (parent[i] < 0) {
-        if (ps != G.nslot) {
-          why = gs + ": root parent slot";
-          return false;
-        }
-      } else {
-        if (ps != parent[i] - G.lo || ps < s0 || ps >= s) {
-          why = gs + ": parent slot";
-          return false;
-        }
-        leaf[ps] = 0;
-      }
-    }
+    chunk.assign(G.nslot, -1);
+    sub.assign(G.nslot, -1);
+    top_end.assign(G.nslot, -1);  // for a path top: the chunk of its contribution
     for (int32_t c = 0; c < G.nroot; ++c) {
       const int32_t r = get16(kResLaneTab + 2 * c);
       if (r < s0 || r >= s1 || parent[G.lo + r] >= 0) {
@@ -260,51 +302,98 @@ bool check_resident(const ResPlan& R, const int32_t* parent, int64_t n, std::str
         return false;
       }
     }
+    auto sentinel = [&](int32_t k) {
+      KResRec r;
+      std::memcpy(&r, bp + G.rec_off + 8 * (int64_t)k, 8);
+      return r.c0 == 0xffff && r.nch == 0 && r.par == kResNoParent;
+    };
     for (int l = 0; l < kSchedLanes; ++l) {
-      const int32_t a = get16(2 * l), b = get16(2 * l + 2);
-      if (a > b || b > G.npath) {
+      // records [a, b); sentinels at a - 1 and b
+      const int32_t a = get16(2 * l), b = get16(2 * l + 2) - 1;
+      const int32_t la = get16(2 * (kSchedLanes + 1) + 2 * l), lb = get16(2 * (kSchedLanes + 1) + 2 * l + 2);
+      if (a < 1 || a > b || b >= nrec || la > lb || lb > G.nlist || !sentinel(a - 1) || !sentinel(b)) {
         why = gs + ": lane offsets";
         return false;
       }
-      int32_t busy_until = 0;
+      int32_t busy_until = 0, le = la;
       for (int32_t k = a; k < b; ++k) {
         KResRec r;
-        std::memcpy(&r, bp + kResLaneTab + root_bytes + 8 * k, 8);
-        if (r.len < 1 || r.t0 < busy_until || (int32_t)r.t0 + r.len > G.makespan || r.slot < s0 || r.slot >= s1 ||
-            !leaf[r.slot] || r.aux > 1) {
+        std::memcpy(&r, bp + G.rec_off + 8 * k, 8);
+        if (r.nch < 1 || r.c0 < busy_until || (int32_t)r.c0 + r.nch > G.nchunk || le + r.nch > lb) {
           why = gs + ": path record";
           return false;
         }
-        busy_until = r.t0 + r.len;
-        int32_t j = r.slot;
-        for (int32_t q = 0; q < r.len; ++q) {
-          if (j < s0 || j >= s1 || step[j] >= 0) {
+        busy_until = r.c0 + r.nch;
+        // walk the path's list: padding (the zero entry) first, then a chain
+        // of parents up to the top
+        int32_t prev = -1;
+        bool started = false;
+        for (int32_t s = 0; s < r.nch * kResK; ++s) {
+          const int32_t v = get16(G.list_off + kResEntBytes * (le + s / kResK) + 2 * (s % kResK));
+          if (v & 7) {
+            why = gs + ": list entry alignment";
+            return false;
+          }
+          const int32_t slot = v / 8;
+          if (slot == G.nslot) {
+            if (started) {
+              why = gs + ": padding above a path's bottom";
+              return false;
+            }
+            continue;
+          }
+          if (slot < s0 || slot >= s1 || chunk[slot] >= 0) {
             why = gs + ": path walk";
             return false;
           }
-          step[j] = r.t0 + q;
-          const int32_t pj = R.par[G.lo + j];
-          if (q + 1 < r.len) {
-            if (pj == G.nslot) {
-              why = gs + ": path runs past a root";
+          if (started) {
+            const int32_t ps = parent[G.lo + prev] < 0 ? -1 : (int32_t)(parent[G.lo + prev] - G.lo);
+            if (ps != slot) {
+              why = gs + ": path does not follow parents";
               return false;
             }
-            j = pj;
-          } else if ((r.aux == 1) != (pj != G.nslot)) {
-            why = gs + ": push flag";
-            return false;
           }
+          started = true;
+          chunk[slot] = r.c0 + s / kResK;
+          sub[slot] = s % kResK;
+          prev = slot;
         }
+        if (!started || sub[prev] != kResK - 1 || chunk[prev] != busy_until - 1) {
+          why = gs + ": a path top is not the last step of its last chunk";
+          return false;
+        }
+        const int32_t pp = parent[G.lo + prev];
+        const int32_t want = pp < 0 ? kResNoParent : 8 * (int32_t)(pp - G.lo);
+        if (r.par != want) {
+          why = gs + ": push target";
+          return false;
+        }
+        top_end[prev] = busy_until - 1;
+        le += r.nch;
+      }
+      if (le != lb) {
+        why = gs + ": list entries of lane " + std::to_string(l);
+        return false;
       }
     }
     for (int32_t s = s0; s < s1; ++s) {
-      if (step[s] < 0) {
+      if (chunk[s] < 0) {
         why = gs + ": compartment not scheduled";
         return false;
       }
-      const int32_t ps = R.par[G.lo + s];
-      if (ps != G.nslot && step[ps] <= step[s]) {
-        why = gs + ": a parent is eliminated before its child";
+      const int64_t p = parent[G.lo + s];
+      if (p < 0) continue;
+      const int32_t ps = (int32_t)(p - G.lo);
+      if (top_end[s] >= 0) {
+        // a light path's top: its contribution lands two chunks before the
+        // chunk that eliminates the parent (and the parent's x is written two
+        // chunks before the forward sweep reads it)
+        if (chunk[ps] < top_end[s] + 2) {
+          why = gs + ": a light path ends too late for its parent";
+          return false;
+        }
+      } else if (!(chunk[ps] * kResK + sub[ps] == chunk[s] * kResK + sub[s] + 1)) {
+        why = gs + ": a path's next step is not its parent";
         return false;
       }
     }

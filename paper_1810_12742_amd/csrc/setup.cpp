@@ -1032,31 +1032,29 @@ int64_t export_table(const HostPlan& p, int32_t id, int64_t* out, int64_t capaci
     case T_CELL_FLAGS: return put(p.cl.flags);
     case T_CELL_MBSRC: return put(p.cl.mbsrc);
     case T_RES_GROUPS: {
-      const int64_t cnt = 10 * (int64_t)p.res.groups.size();
+      constexpr int64_t kF = 15;
+      const int64_t cnt = kF * (int64_t)p.res.groups.size();
       if (out) {
         if (capacity < cnt) return -1;
-        for (int64_t g = 0; g < cnt / 10; ++g) {
+        for (int64_t g = 0; g < cnt / kF; ++g) {
           const KResGroup& G = p.res.groups[g];
-          int64_t* r = out + 10 * g;
+          int64_t* r = out + kF * g;
           r[0] = G.lo;
           r[1] = G.blob;
           r[2] = G.nslot;
           r[3] = G.ndma;
           r[4] = G.first;
           r[5] = G.count;
-          r[6] = G.makespan;
+          r[6] = G.nchunk;
           r[7] = G.blob_units;
           r[8] = G.nroot;
           r[9] = G.npath;
+          r[10] = G.nlist;
+          r[11] = G.rec_off;
+          r[12] = G.list_off;
+          r[13] = G.cls;
+          r[14] = kResK;
         }
-      }
-      return cnt;
-    }
-    case T_RES_PAR: {
-      const int64_t cnt = p.res.built ? p.n : 0;
-      if (out) {
-        if (capacity < cnt) return -1;
-        for (int64_t i = 0; i < cnt; ++i) out[i] = p.res.par[i];
       }
       return cnt;
     }

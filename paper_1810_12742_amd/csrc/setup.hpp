@@ -99,8 +99,8 @@ enum TableId : int32_t {
   T_CELL_POS = 14,        // int64[nchunks*kCellChunkElems]: [chunk][staging lane][slot] relative position
   T_CELL_FLAGS = 15,      // int64[nchunks*kCellChunkElems]: [chunk][cell lane][element] flags
   T_CELL_MBSRC = 16,      // int64[nwaves*64]: mailbox source lanes (6 bits each), backward | forward << 32
-  T_RES_GROUPS = 17,      // int64[ngroups*10]: lo, blob, nslot, ndma, first, count, makespan, blob_units, nroot, npath
-  T_RES_PAR = 18,         // int64[n]: parent slot of each compartment in its group image
+  T_RES_GROUPS = 17,      // int64[ngroups*15]: lo, blob, nslot, ndma, first, count, nchunk, blob_units, nroot,
+                          // npath, nlist, rec_off, list_off, cls, steps per chunk
   T_RES_BLOB = 19,        // int64[blob bytes / 2]: the blobs as uint16 words
   T_NUM = 20,
 };
@@ -173,47 +173,61 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
                         int32_t max_cuts = kCellMaxCuts);
 
 // LDS-resident solve (one wave per group of whole cells).  A group's d, u, b
-// (8 bytes each) and the parent slot of every compartment (2 bytes) are staged
-// into LDS once, in the user numbering: slot s holds user index lo + s.  Each
-// lane walks root-ward paths of the tree (paper §2: children before parents):
-// a path starts at a leaf and follows parents up to the top, a compartment
-// that is either a cell root or not the "heavy" child of its parent (the child
-// whose subtree finishes last).  A path's contribution to the parent of its top
-// is added into the parent's LDS entry at its last step, at least one step
-// before the parent is eliminated; inside a path the contribution stays in
-// registers.  The steps are fixed at setup (an as-late-as-possible list
-// schedule over the wave's 64 lanes), so every lane knows from its records when
-// it is busy; the forward sweep runs the steps in reverse.
+// are staged into LDS once, as three planes in the user numbering (slot s
+// holds user index lo + s; the planes are `stride` slots apart, a per-class
+// constant that is a multiple of 64).  Each lane walks root-ward paths of the
+// tree (paper §2: children before parents): a path starts at a leaf and
+// follows parents up to its top, a compartment that is either a cell root or
+// not the "heavy" child of its parent (the child whose subtree finishes last).
+// A path is cut into chunks of kResK steps, padded at its bottom with steps on
+// the zero entry (d = 1, u = 0, b = 0), so its top is the last step of its last
+// chunk.  Inside a path the contribution to the next compartment stays in
+// registers; a light path adds its top's contribution into its parent's LDS
+// entry at the end of its last chunk, at least two chunks before the chunk
+// that eliminates the parent (a lane reads a chunk's operands one chunk
+// ahead).  The chunks are fixed at setup (an as-late-as-possible list schedule
+// over the wave's 64 lanes); the forward sweep runs them in reverse.
+constexpr int32_t kResK = 8;             // steps per chunk
+constexpr int32_t kResEntBytes = 2 * kResK;  // slot-list entry: the byte offsets (uint16) of a chunk's steps
+constexpr int32_t kResLaneTab = 272;     // 65 record offsets + 65 list offsets (uint16), padded
+constexpr int32_t kResMaxSlots = 8000;   // image slots: 16-bit list entries hold slot * 8
+constexpr int32_t kResNoParent = 0xffff; // record field: the top is a cell root
+constexpr int32_t kResClasses = 10;
+// LDS classes: class k holds floor(160 KiB / waves) bytes for waves = 1, 2, 3,
+// 4, 5, 6, 7, 8, 10, 16 groups per CU; planes `stride` slots apart.
+constexpr int32_t kResClassBytes[kResClasses] = {163840, 81920, 54528, 40960, 32768, 27136, 23296, 20480, 16384, 10240};
+constexpr int32_t kResClassStride[kResClasses] = {6144, 3008, 1984, 1472, 1152, 960, 832, 704, 576, 320};
 struct KResGroup {
-  int64_t lo;          // user index of LDS slot 0 (even)
+  int64_t lo;          // user index of slot 0 (even)
   int64_t blob;        // first 16-byte unit of the group's blob
   int32_t nslot;       // slots of the image (even); slot nslot is the zero entry
   int32_t ndma;        // slots staged from the user arrays: min(nslot, n - lo)
   int32_t first;       // slot of the group's first compartment (0 or 1)
   int32_t count;       // compartments of the group
-  int32_t makespan;    // steps per sweep
+  int32_t nchunk;      // chunks per sweep
   int32_t blob_units;  // 16-byte units of the blob
   int32_t nroot;       // cells of the group
-  int32_t lds_bytes;   // LDS image
-  int32_t npath;       // paths (records)
-  int32_t pad;
+  int32_t npath;       // path records
+  int32_t nlist;       // slot-list entries (one per active chunk of a lane)
+  int32_t rec_off;     // byte offset of the records in the blob
+  int32_t list_off;    // byte offset of the slot lists in the blob
+  int32_t cls;         // LDS class (index into kResClassBytes / kResClassStride)
 };
-static_assert(sizeof(KResGroup) == 56, "layout");
-// Path record: bottom slot (a leaf; replaced by the top slot during the
-// backward sweep), first step, length, flags (bit 0: the contribution of the
-// top goes to its parent's LDS entry; replaced by the top's parent slot during
-// the backward sweep).
+static_assert(sizeof(KResGroup) == 64, "layout");
+// Path record: first chunk, chunks, byte offset (slot * 8) of the top's parent
+// entry or kResNoParent, spare.
 struct KResRec {
-  uint16_t slot, t0, len, aux;
+  uint16_t c0, nch, par, spare;
 };
 static_assert(sizeof(KResRec) == 8, "layout");
-// Blob of a group, in 16-byte units: the 65 record offsets of the lanes (uint16,
-// kResLaneTab bytes), the root slots of its cells (uint16, padded to 16 bytes),
-// then the records, lane by lane in step order.
-constexpr int32_t kResLaneTab = 144;
-constexpr int32_t kResMaxSlots = 16000;  // image slots addressable by the 16-bit records
-constexpr int64_t res_lds_bytes(int64_t nslot, int64_t blob_units) {
-  return 24 * (nslot + 2) + ((2 * nslot + 15) & ~(int64_t)15) + 16 * blob_units;
+// Blob of a group, in 16-byte units: per lane the first record and the first
+// slot-list entry (65 + 65 uint16, kResLaneTab bytes), the root slots of its
+// cells (uint16, padded to 16 bytes), the records lane by lane in chunk order,
+// then the slot lists: per lane, one kResEntBytes entry per active chunk, in
+// chunk order, holding the byte offsets (slot * 8) of the chunk's kResK steps from
+// the bottom of the path upward.
+constexpr int64_t res_lds_bytes(int32_t cls, int64_t blob_units) {
+  return 24 * (int64_t)kResClassStride[cls] + 16 * blob_units;
 }
 // Target of the packing: consecutive cells share a group while it holds at
 // most this many compartments (a larger cell is a group of its own).
@@ -222,19 +236,19 @@ constexpr int32_t kResPackSlots = 1400;
 struct ResPlan {
   bool built = false;
   std::vector<KResGroup> groups;
-  std::vector<uint16_t> par;   // [n + 2] parent slot in the group image (roots: the zero slot)
   std::vector<uint8_t> blob;   // group blobs, 16-byte aligned
   int64_t max_lds = 0;
 };
 
 // Build the LDS-resident tables; parent / cell_offsets must already be valid.
-// ERR_TOO_BIG if a cell's image does not fit kLdsLimitBytes.
+// ERR_TOO_BIG if a cell's image does not fit the largest LDS class.
 // pack: consecutive cells share a group while it holds at most this many
 // compartments (kResPackSlots by default).
 Status build_resident(const int32_t* parent, int64_t n, const int64_t* cell_offsets, int64_t ncells,
                       ResPlan& out, std::string& err, int32_t pack = kResPackSlots);
-// Replay of the resident tables: every record, slot and parent slot inside its
-// group image, every compartment eliminated once, after all its children.
+// Replay of the resident tables: every record, list entry and slot inside its
+// group image, every compartment eliminated once, after all its children, and
+// every light path's contribution added two chunks before its parent's chunk.
 bool check_resident(const ResPlan& R, const int32_t* parent, int64_t n, std::string& why);
 
 // Per-branch record of the LDS-staged solve kernel, in (group, level, lane)

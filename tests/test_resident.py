@@ -1,16 +1,20 @@
 """Tables of the LDS-resident solve, checked on the CPU.
 
 The replay below executes the kernel's per-lane program on the exported
-tables, step by step in lockstep over the wave's 64 lanes, with the kernel's
+tables, chunk by chunk in lockstep over the wave's 64 lanes, with the kernel's
 timing of every LDS read and write:
-  * a path's bottom operands are read when its record becomes the lane's next
-    one; every other compartment's operands are read at the end of the step
-    before it, after the contributions added in that step;
-  * a step's contribution additions happen after all eliminations of the step;
-  * the forward sweep reads x of a path top's parent at the top's step.
+  * backward sweep: at the start of chunk c a lane active in chunk c + 1 reads
+    that chunk's operands (d, u, b at its four list entries); then every lane
+    active in chunk c eliminates its four steps from the operands it read a
+    chunk earlier, storing f over u and y over b; then lanes whose path tops
+    in chunk c add their contribution into the parent's entry;
+  * forward sweep: at the start of chunk c a lane active in chunk c - 1 reads
+    (f, y) of that chunk and, if its path tops there, x of the top's parent;
+    then every lane active in chunk c substitutes its four steps downward.
 Its result is compared with the FP64 oracle (paper §2, Listing 2).  A
 schedule that eliminated a compartment before one of its children had added
-its contribution would read a stale entry and fail the comparison.
+its contribution, or read a parent's x before it was written, would read a
+stale entry and fail the comparison.
 """
 import numpy as np
 import pytest
@@ -20,7 +24,13 @@ from workloads import Forest, cable_values, configs, full_binary_forest
 
 TOL = 1e-12
 LANES = 64
-LANE_TAB_WORDS = 72  # 144 bytes
+LANE_TAB_WORDS = 136   # 272 bytes: 65 record offsets, 65 list offsets
+NO_PARENT = 0xFFFF
+# LDS classes: bytes per group (160 KiB / groups per CU) and plane stride in slots
+CLASS_BYTES = (163840, 81920, 54528, 40960, 32768, 27136, 23296, 20480, 16384, 10240)
+STRIDES = (6144, 3008, 1984, 1472, 1152, 960, 832, 704, 576, 320)
+GROUP_FIELDS = ("lo", "blob", "nslot", "ndma", "first", "count", "nchunk", "blob_units", "nroot", "npath",
+                "nlist", "rec_off", "list_off", "cls", "k")
 
 
 def cell_rel_err(f, x, xo):
@@ -32,134 +42,130 @@ def cell_rel_err(f, x, xo):
 def plan_tables(f, **opts):
     from paper_1810_12742_amd import Plan
     p = Plan(f.parent, f.cell_offsets, f.branch_offsets, host_only=True, resident=True, **opts)
-    t = {k: p.table(k) for k in ("res_groups", "res_par", "res_blob")}
+    t = {k: p.table(k) for k in ("res_groups", "res_blob")}
+    t["res_groups"] = t["res_groups"].reshape(-1, len(GROUP_FIELDS))
     info = p.info
     p.close()
     return t, info
 
 
-def rcp_fast(d):
-    return 1.0 / d
+def group_view(t, g):
+    G = dict(zip(GROUP_FIELDS, (int(v) for v in g)))
+    words = t["res_blob"][8 * G["blob"]:8 * (G["blob"] + G["blob_units"])]
+    G["rec_first"] = words[:LANES + 1]
+    G["list_first"] = words[LANES + 1:2 * LANES + 2]
+    G["roots"] = words[LANE_TAB_WORDS:LANE_TAB_WORDS + G["nroot"]]
+    r0 = G["rec_off"] // 2
+    nrec = G["npath"] + LANES + 1
+    G["recs"] = words[r0:r0 + 4 * nrec].reshape(-1, 4)      # c0, nch, parent byte offset, spare
+    l0 = G["list_off"] // 2
+    K = G["k"]
+    G["lists"] = words[l0:l0 + K * G["nlist"]].reshape(-1, K)  # byte offsets of a chunk's steps
+    return G
 
 
 def replay(t, n, diag, upper, rhs):
-    groups, par, blob = t["res_groups"], t["res_par"], t["res_blob"]
     x = np.full(n, np.nan)
-    parx = np.concatenate([par, np.zeros(2, dtype=np.int64)])
-    for g in groups:
-        lo, bu0, nslot, ndma, first, count, F, bun, nroot, npath = (int(v) for v in g)
-        S = nslot + 2
+    for g in t["res_groups"]:
+        G = group_view(t, g)
+        lo, nslot, ndma, first, count, NC, K = (G[k] for k in ("lo", "nslot", "ndma", "first", "count", "nchunk", "k"))
         zero = nslot
-        D = np.zeros(S)
-        U = np.zeros(S)
-        B = np.zeros(S)
+        D = np.zeros(nslot + 1)
+        U = np.zeros(nslot + 1)
+        B = np.zeros(nslot + 1)
         D[:ndma] = diag[lo:lo + ndma]
         U[:ndma] = upper[lo:lo + ndma]
         B[:ndma] = rhs[lo:lo + ndma]
-        PAR = parx[lo:lo + nslot].copy()
-        D[zero:] = 1.0
-        U[zero:] = 0.0
-        B[zero:] = 0.0
-        words = blob[8 * bu0:8 * (bu0 + bun)]
-        ltab = words[:LANES + 1]
-        roots = words[LANE_TAB_WORDS:LANE_TAB_WORDS + nroot]
-        U[roots] = 0.0
-        rb = LANE_TAB_WORDS + 8 * ((2 * nroot + 15) // 16)
-        recs = words[rb:rb + 4 * npath].reshape(-1, 4).copy()  # slot, t0, len, aux
-        LINK = np.full(S, zero)
+        D[zero], U[zero], B[zero] = 1.0, 0.0, 0.0
+        U[G["roots"]] = 0.0
+        recs, lists = G["recs"], G["lists"]
+        lanes = []
+        for l in range(LANES):
+            kb, ke = int(G["rec_first"][l]), int(G["rec_first"][l + 1]) - 1
+            lb, le = int(G["list_first"][l]), int(G["list_first"][l + 1])
+            assert tuple(recs[kb - 1][:3]) == (0xFFFF, 0, NO_PARENT) and tuple(recs[ke][:3]) == (0xFFFF, 0, NO_PARENT)
+            paths = [(int(r[0]), int(r[0]) + int(r[1]), int(r[2])) for r in recs[kb:ke]]
+            ents = lists[lb:le] // 8
+            assert len(ents) == sum(p[1] - p[0] for p in paths)
+            chunk_ent = {}
+            e = 0
+            for c0, c1, _ in paths:
+                for c in range(c0, c1):
+                    chunk_ent[c] = ents[e]
+                    e += 1
+            lanes.append((paths, chunk_ent))
 
-        def rec(k, kb, ke):
-            if kb <= k < ke:
-                s_, t0, ln, aux = (int(v) for v in recs[k])
-                return [s_, t0, t0 + ln, aux]
-            return [zero, F + 1, F + 1, zero]
+        def path_at(paths, c):
+            for p in paths:
+                if p[0] <= c < p[1]:
+                    return p
+            return None
 
         # ---- backward ----
-        st = []
-        for l in range(LANES):
-            kb, ke = int(ltab[l]), int(ltab[l + 1])
-            c, nx = rec(kb, kb, ke), rec(kb + 1, kb, ke)
-            st.append(dict(kb=kb, ke=ke, ri=kb, c=c, nx=nx, j=c[0], prev=zero,
-                           op1=(D[c[0]], U[c[0]], B[c[0]], PAR[c[0]] if c[0] < nslot else 0),
-                           op2=(D[nx[0]], U[nx[0]], B[nx[0]], PAR[nx[0]] if nx[0] < nslot else 0),
-                           cd=0.0, cb=0.0))
-        for tt in range(F):
+        ops = [dict() for _ in range(LANES)]
+        for l, (paths, ce) in enumerate(lanes):
+            if 0 in ce:
+                a = ce[0]
+                ops[l][0] = (D[a].copy(), U[a].copy(), B[a].copy())
+        carry = [(0.0, 0.0)] * LANES
+        for c in range(NC):
+            for l, (paths, ce) in enumerate(lanes):     # reads of chunk c + 1
+                if c + 1 < NC and (c + 1) in ce:
+                    a = ce[c + 1]
+                    ops[l][c + 1] = (D[a].copy(), U[a].copy(), B[a].copy())
             pushes = []
-            acts = []
-            for l, s in enumerate(st):
-                c = s["c"]
-                act = c[1] <= tt < c[2]
-                if not act:
+            for l, (paths, ce) in enumerate(lanes):     # eliminations of chunk c
+                p = path_at(paths, c)
+                if p is None:
                     continue
-                d1, u1, b1, p1 = s["op1"]
-                dd, bb = d1 - s["cd"], b1 - s["cb"]
-                r = rcp_fast(dd)
-                f_ = u1 * r
-                j = s["j"]
-                D[j] = f_
-                B[j] = bb * r
-                LINK[j] = s["prev"]
-                s["cd"], s["cb"] = u1 * f_, f_ * bb
-                top = tt == c[2] - 1
-                if top and c[3]:
-                    pushes.append((p1, s["cd"], s["cb"]))
-                acts.append((l, top))
-            for p1, cd, cb in pushes:
-                D[p1] -= cd
-                B[p1] -= cb
-            for l, top in acts:
-                s = st[l]
-                if top:
-                    j, c = s["j"], s["c"]
-                    recs[s["ri"]] = (j, c[1], c[2] - c[1], s["op1"][3])
-                    s["cd"] = s["cb"] = 0.0
-                    s["prev"] = zero
-                    s["ri"] += 1
-                    s["c"] = s["nx"]
-                    s["j"] = s["c"][0]
-                    s["op1"] = s["op2"]
-                    s["nx"] = rec(s["ri"] + 1, s["kb"], s["ke"])
-                    q = s["nx"][0]
-                    s["op2"] = (D[q], U[q], B[q], PAR[q] if q < nslot else 0)
-                else:
-                    s["prev"] = s["j"]
-                    j = s["op1"][3]
-                    s["j"] = j
-                    s["op1"] = (D[j], U[j], B[j], PAR[j] if j < nslot else 0)
+                a = ce[c]
+                d4, u4, b4 = ops[l].pop(c)
+                ncd, ncb = carry[l]
+                for k in range(K):
+                    dd = d4[k] + ncd
+                    bb = b4[k] + ncb
+                    f_ = u4[k] / dd
+                    y_ = bb / dd
+                    ncd, ncb = -(u4[k] * f_), -(u4[k] * y_)
+                    U[a[k]] = f_
+                    B[a[k]] = y_
+                carry[l] = (ncd, ncb)
+                if c == p[1] - 1:
+                    if p[2] != NO_PARENT:
+                        pushes.append((p[2] // 8, ncd, ncb))
+                    carry[l] = (0.0, 0.0)
+            for q, ncd, ncb in pushes:                  # contributions of chunk c
+                D[q] += ncd
+                B[q] += ncb
         # ---- forward ----
-        st = []
-        for l in range(LANES):
-            kb, ke = int(ltab[l]), int(ltab[l + 1])
-            c, nx = rec(ke - 1, kb, ke), rec(ke - 2, kb, ke)
-            st.append(dict(kb=kb, ke=ke, ri=ke - 1, c=c, nx=nx, j=c[0], xp=0.0,
-                           op1=(D[c[0]], B[c[0]], LINK[c[0]]), op2=(D[nx[0]], B[nx[0]], LINK[nx[0]])))
-        for tt in range(F - 1, -1, -1):
-            acts = []
-            for l, s in enumerate(st):
-                c = s["c"]
-                if not (c[1] <= tt < c[2]):
+        fops = [dict() for _ in range(LANES)]
+
+        def fread(l, c):
+            paths, ce = lanes[l]
+            p = path_at(paths, c)
+            a = ce[c]
+            q = p[2] // 8 if (c == p[1] - 1 and p[2] != NO_PARENT) else zero
+            fops[l][c] = (U[a].copy(), B[a].copy(), B[q])
+
+        for l, (paths, ce) in enumerate(lanes):
+            if NC - 1 in ce:
+                fread(l, NC - 1)
+        xp = [0.0] * LANES
+        for c in range(NC - 1, -1, -1):
+            for l, (paths, ce) in enumerate(lanes):     # reads of chunk c - 1
+                if c >= 1 and (c - 1) in ce:
+                    fread(l, c - 1)
+            for l, (paths, ce) in enumerate(lanes):
+                p = path_at(paths, c)
+                if p is None:
                     continue
-                if tt == c[2] - 1:
-                    s["xp"] = B[c[3]]
-                f1, y1, _ = s["op1"]
-                xv = y1 - f1 * s["xp"]
-                B[s["j"]] = xv
-                s["xp"] = xv
-                acts.append(l)
-            for l in acts:
-                s = st[l]
-                if tt == s["c"][1]:
-                    s["ri"] -= 1
-                    s["c"] = s["nx"]
-                    s["j"] = s["c"][0]
-                    s["op1"] = s["op2"]
-                    s["nx"] = rec(s["ri"] - 1, s["kb"], s["ke"])
-                    q = s["nx"][0]
-                    s["op2"] = (D[q], B[q], LINK[q])
-                else:
-                    j = s["op1"][2]
-                    s["j"] = j
-                    s["op1"] = (D[j], B[j], LINK[j])
+                a = ce[c]
+                f4, y4, xq = fops[l].pop(c)
+                if c == p[1] - 1:
+                    xp[l] = xq
+                for k in range(K - 1, -1, -1):
+                    xp[l] = y4[k] - f4[k] * xp[l]
+                    B[a[k]] = xp[l]
         x[lo + first:lo + first + count] = B[first:first + count]
     return x
 
@@ -181,6 +187,7 @@ def test_replay_c2_slice():
     # every compartment once: the groups tile the cells in order
     assert g[:, 5].sum() == s.forest.n
     assert np.all(g[:, 0] % 2 == 0)
+    assert np.all(g[:, 2] + 1 <= np.array(STRIDES)[g[:, 13]])
 
 
 def test_replay_small_cells_packed_and_odd_offsets():
@@ -203,17 +210,35 @@ def test_replay_full_binary_and_single_compartments():
 
 def test_critical_path_makespan_on_c2_cells():
     """With 64 lanes and cells of about ten-fold parallelism the schedule of a
-    single-cell group needs no more steps than its longest root-to-leaf path."""
-    s = configs.c2(16)
+    single-cell group is as long as its longest root-to-leaf path in whole
+    chunks, plus at most a few chunks of the two-chunk margins that light
+    paths keep before their parents."""
+    s = configs.c2(48)
     f = s.forest
     t, _ = plan_tables(f)
     depth = np.zeros(f.n, dtype=np.int64)
     for i in range(f.n):
         depth[i] = 1 if f.parent[i] < 0 else depth[f.parent[i]] + 1
+    excess = []
     for g in t["res_groups"]:
-        lo, first, count, F, nroot = int(g[0]), int(g[4]), int(g[5]), int(g[6]), int(g[8])
+        lo, first, count, NC, nroot, K = int(g[0]), int(g[4]), int(g[5]), int(g[6]), int(g[8]), int(g[14])
         if nroot == 1:
-            assert F == depth[lo + first:lo + first + count].max()
+            lb = -(-int(depth[lo + first:lo + first + count].max()) // K)
+            assert lb <= NC <= lb + 6
+            excess.append(NC - lb)
+    assert np.mean(excess) < 1.5
+
+
+def test_lds_class_is_the_smallest_that_fits():
+    s = configs.c2(64)
+    t, _ = plan_tables(s.forest)
+    for g in t["res_groups"]:
+        nslot, bu, cls = int(g[2]), int(g[7]), int(g[13])
+
+        def fits(k):
+            return nslot + 1 <= STRIDES[k] and 24 * STRIDES[k] + 16 * bu <= CLASS_BYTES[k]
+        assert fits(cls)
+        assert not any(fits(k) for k in range(cls + 1, len(STRIDES)))
 
 
 def test_large_cell_refused():
