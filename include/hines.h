@@ -212,6 +212,22 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
 hines_status hines_solve(const hines_plan* plan, const double* diag, const double* upper,
                          const double* rhs, double* x, int32_t ncells, void* stream);
 
+/* hines_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same cell-lane kernel and results as hines_solve, with its per-step factors
+ * (16 bytes per walk slot) kept in a file-scope device array of 256 MiB
+ * (kStaticScratchBytes) instead of the plan's own scratch.  The call launches
+ * one kernel and allocates or frees nothing.  Each device holds one such array
+ * from the first hines_setup on it until the process ends; every call on that
+ * device uses it, so calls that overlap on one device (several streams, or
+ * host threads) race and must be serialised by the caller.  The kernel writes
+ * every scratch slot it reads within the same call, so nothing needs clearing.
+ *   Cell-lane plans only (HINES_ERR_STATE otherwise).  HINES_ERR_TOO_BIG if the
+ *   plan's factors exceed the array (about 14 million compartments of C2-like
+ *   cells).  Arguments as hines_solve; x may alias rhs.  Async on stream. */
+hines_status hines_solve_noalloc(const hines_plan* plan, const double* diag, const double* upper,
+                                 const double* rhs, double* x, int32_t ncells, void* stream);
+
 /* FP32 storage, FP64 elimination (cell-lane plans only).  The matrix is the
  * FP32 one (diag32, upper32: device float arrays, user numbering); the kernel
  * widens each entry exactly on load and runs §2's elimination in FP64, so one

@@ -28,6 +28,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -35,6 +36,15 @@
 #include "../../include/hines.h"
 #include "kernels.hpp"
 #include "setup.hpp"
+
+// Scratch of hines_solve_noalloc: the (f, y) factors of the cell-lane solve,
+// 16 bytes per walk slot, in a file-scope device array instead of the plan's
+// allocation.  Each device holds its own copy for the life of the process.  In
+// host code the name `scratch` is not a device address: its address on a
+// device comes from hipGetSymbolAddress (static_scratch_init), taken once per
+// device with the device current, and only that address is passed to kernels.
+constexpr int64_t kStaticScratchBytes = (int64_t)256 << 20;
+static __device__ __align__(256) double scratch[kStaticScratchBytes / 8];
 
 using hdev::DevTables;
 using hdev::RhsSpec;
@@ -60,6 +70,27 @@ hines_status set_err(hines_status s, const char* fmt, ...) {
 hines_status ok() {
   g_last_error.clear();
   return HINES_OK;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch`, per device
+
+// Resolve `scratch` on device dev (the current device), once per device.
+hipError_t static_scratch_init(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) g_scratch_ptr[dev] = ptr;
+  return e;
+}
+
+void* static_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[dev];
 }
 
 // LDS footprint classes (bytes); a launch reserves its class's size per
@@ -771,6 +802,7 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
                         sz_cb + sz_cp + sz_cf + sz_cm + sz_rg + sz_rl + sz_rb + 256;
   const int64_t scr_bytes = CL.nchunks * hines::kCellChunk * 64 * 16;
   hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) e = static_scratch_init(p->device);
   if (e == hipSuccess) e = allow_lds(o.group_width);
   if (e == hipSuccess) e = res_class_attr();
   if (e != hipSuccess) {
@@ -886,6 +918,33 @@ hines_status hines_solve(const hines_plan* p, const double* diag, const double* 
   rs.rhs = rhs;
   rs.mode = hdev::kRhsGiven;
   return run_solve(p, rs, diag, upper, x, stream);
+}
+
+hines_status hines_solve_noalloc(const hines_plan* p, const double* diag, const double* upper, const double* rhs,
+                                 double* x, int32_t ncells, void* stream) {
+  hines_status st = check_call(p, ncells);
+  if (st != HINES_OK) return st;
+  if (!p->host.cl.built) return set_err(HINES_ERR_STATE, "hines_solve_noalloc needs a cell-lane plan");
+  if (p->host.n == 0) return ok();
+  if (!diag || !upper || !rhs || !x) return set_err(HINES_ERR_NULL, "a device array is NULL");
+  if ((const void*)x == (const void*)diag || (const void*)x == (const void*)upper)
+    return set_err(HINES_ERR_STATE, "x must not alias diag or upper");
+  const int64_t need = p->t.cslots * 16;
+  if (need > kStaticScratchBytes)
+    return set_err(HINES_ERR_TOO_BIG, "the plan's factors need %lld bytes; the static scratch holds %lld",
+                   (long long)need, (long long)kStaticScratchBytes);
+  void* ptr = static_scratch(p->device);
+  if (!ptr) return set_err(HINES_ERR_STATE, "the static scratch of device %d is not resolved", p->device);
+  DevTables t = p->t;
+  t.cscr = (double*)ptr;
+  RhsSpec rs{};
+  rs.rhs = rhs;
+  rs.mode = hdev::kRhsGiven;
+  hipLaunchKernelGGL(hdev::k_solve_cells<hdev::kFlowGiven>, dim3((unsigned)p->host.cl.nwaves), dim3(64), 0,
+                     (hipStream_t)stream, t, rs, diag, upper, x);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_err(HINES_ERR_HIP, "launch: %s", hipGetErrorString(e));
+  return ok();
 }
 
 hines_status hines_solve_mixed(const hines_plan* p, const float* diag32, const float* upper32, const double* rhs,
