@@ -39,8 +39,6 @@ if ROOT not in sys.path:
 METRIC = "Hines unknowns solved/s and % HBM roofline, plain FP64 vs batched/FP32+refine"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UNKNOWN = 32  # read diag, upper, rhs; write x (FP64)
-# Launch configuration of the timed solve (setup options of the plan).
-C2_OPTIONS = dict(cell_lanes=1)
 # The fine-grained (flow kernel) plan used for comparisons.
 C2_FLOW_OPTIONS = dict(max_group_unknowns=1536, split_branches=0, cell_order=0, group_width=64)
 CALIB_BYTES = 512 << 20  # bytes read (and written) by one calibration copy
@@ -230,16 +228,25 @@ def run_c2(args, torch, dev):
 
     s = configs.c2()
     f = s.forest
-    opts = json.loads(args.options) if args.options else dict(C2_OPTIONS)
-    t0 = time.perf_counter()
-    plan = Plan(f.parent, f.cell_offsets, f.branch_offsets, **opts)
-    setup_s = time.perf_counter() - t0
-    info = plan.info
     d = torch.from_numpy(s.diag).to(dev)
     u = torch.from_numpy(s.upper).to(dev)
     b = torch.from_numpy(s.rhs).to(dev)
     x = torch.empty_like(b)
     stream = torch.cuda.current_stream()
+    tried = []
+    if args.options:
+        opts = json.loads(args.options)
+    else:
+        # the autotuner's pick among the whole-cell kernels and their knobs,
+        # from the shipped cache when this device and workload have been tuned
+        from paper_1810_12742_amd.autotune import CELL_CANDIDATES, autotune
+        opts, tried = autotune(f.parent, f.cell_offsets, f.branch_offsets,
+                               lambda p: p.solve(d, u, b, out=x, stream=stream), candidates=CELL_CANDIDATES,
+                               reps=5, cache_path=args.tune_cache)
+    t0 = time.perf_counter()
+    plan = Plan(f.parent, f.cell_offsets, f.branch_offsets, **opts)
+    setup_s = time.perf_counter() - t0
+    info = plan.info
     ms = _time(torch, lambda: plan.solve(d, u, b, out=x, stream=stream), args.steps, args.warmup, stream)
 
     if args.copy_calibration:
@@ -280,6 +287,7 @@ def run_c2(args, torch, dev):
             "kernel": {4: "LDS-resident", 3: "cell lanes", 1: "flow", 2: "bitwise"}.get(info["kernel"],
                                                                                          "level-synchronous"),
             "options": opts, "setup_s": round(setup_s, 3),
+            "autotune_ms": [[o, round(t, 4)] for o, t in tried],
         },
         "roofline": {
             "bound": "hbm",
@@ -327,7 +335,7 @@ def run_c3(args, torch, dev):
         cands = [dict(max_group_unknowns=3000), dict(cell_lanes=1)]
         best, tried = autotune(f.parent, f.cell_offsets, f.branch_offsets,
                                lambda p: p.timestep(d, u, c, vs, vs, noise_sigma=0.1, noise_seed=3),
-                               candidates=cands, reps=2, cache_path=None)
+                               candidates=cands, reps=2, cache_path=args.tune_cache)
         del vs
     t0 = time.perf_counter()
     plan = Plan(f.parent, f.cell_offsets, f.branch_offsets, **best)
@@ -616,7 +624,9 @@ def main(argv=None):
     ap.add_argument("--workload", choices=("c2", "c3", "c5", "scaling", "branching", "outlook"), default="c2")
     ap.add_argument("--cells", type=int, default=0, help="c3/c5/outlook: number of cells (default: the full workload)")
     ap.add_argument("--graph-steps", type=int, default=100, help="c3: time steps per captured graph")
-    ap.add_argument("--options", default="", help="plan options as JSON (c3: instead of the autotuner's pick)")
+    ap.add_argument("--options", default="", help="plan options as JSON (c2, c3: instead of the autotuner's pick)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="c2, c3: autotuner cache file (default: the picks shipped with the package)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="c2: skip the FP32+refinement measurement")
@@ -624,6 +634,9 @@ def main(argv=None):
                     help="after the timed region, run a plain device copy of 512 MiB (read and write) three "
                          "times, the reference kernel for scaling HBM byte counters")
     args = ap.parse_args(argv)
+    if args.tune_cache is None:
+        from paper_1810_12742_amd.autotune import SHIPPED_CACHE
+        args.tune_cache = SHIPPED_CACHE
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the per-cell solve has no cross-GPU step and the path is "
               f"built for a single MI355X (asked for --gpus {args.gpus})", file=sys.stderr)

@@ -28,7 +28,19 @@ DEFAULT_CANDIDATES = [
     for ls in (0, 1)
 ] + [dict(cell_lanes=1)]
 
+# Candidates for large networks of whole-cell kernels: the one-lane-per-cell
+# kernel with its cut threshold (percent of the mean cell) and the number of
+# lanes a long cell may be cut into, and the LDS-resident kernel with its
+# packing target (compartments per group).
+CELL_CANDIDATES = [
+    dict(cell_lanes=1, cell_cut_percent=cp, cell_max_cuts=mc) for cp in (60, 80, 110) for mc in (1, 3)
+] + [dict(resident=1, res_pack=rp) for rp in (1400, 3000)]
+
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "hines_mi355x_autotune.json")
+# Picks measured on one MI355X for the benchmark workloads, shipped with the
+# package so that a run on a fresh device reuses them (same key: morphology,
+# device name, candidate list).
+SHIPPED_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
 
 def _key(parent, cell_offsets, branch_offsets, device_name, candidates) -> str:
@@ -53,6 +65,20 @@ def _time(plan, run, reps, torch):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def cached_pick(parent, cell_offsets, branch_offsets, *, candidates=None, cache_path=CACHE):
+    """The cached best option set for this morphology, device and candidate
+    list, or None when it has not been tuned."""
+    import torch
+    cands = candidates or DEFAULT_CANDIDATES
+    dev_name = torch.cuda.get_device_name(torch.cuda.current_device())
+    key = _key(parent, cell_offsets, branch_offsets, dev_name, cands)
+    try:
+        with open(cache_path) as fh:
+            return json.load(fh).get(key, {}).get("best")
+    except (OSError, ValueError):
+        return None
 
 
 def autotune(parent, cell_offsets, branch_offsets, run, *, candidates=None, reps=5, cache_path=CACHE,

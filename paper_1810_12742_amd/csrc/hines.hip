@@ -120,6 +120,22 @@ struct hines_plan {
   std::vector<Bucket> buckets;
   std::vector<Bucket> mixed_buckets;  // FP32+refinement kernel (its own LDS layout)
   std::vector<Bucket> res_buckets;    // LDS-resident kernel, by LDS class
+  // LDS classes launch concurrently: bucket i runs on res_lane[i] (0: the
+  // caller's stream, k > 0: res_streams[k - 1]), forked from and joined back
+  // into the caller's stream with events, so groups of different classes
+  // share CUs and no class waits for the tail of another
+  static constexpr int kResStreams = 3;
+  hipStream_t res_streams[kResStreams] = {};
+  hipEvent_t res_fork = nullptr;
+  hipEvent_t res_join[kResStreams] = {};
+  std::vector<int32_t> res_lane;
+  ~hines_plan() {
+    for (int k = 0; k < kResStreams; ++k) {
+      if (res_streams[k]) (void)hipStreamDestroy(res_streams[k]);
+      if (res_join[k]) (void)hipEventDestroy(res_join[k]);
+    }
+    if (res_fork) (void)hipEventDestroy(res_fork);
+  }
   std::vector<int32_t> res_list;      // resident group ids in launch order
   bool mixed_ok = false;              // every group fits the mixed layout in LDS
   int64_t max_lds = 0;
@@ -209,14 +225,33 @@ void launch_res(int32_t cls, const DevTables& t, int32_t count, const double* d,
 
 hipError_t launch_resident(const hines_plan* p, const double* d, const double* u, const double* b, double* x,
                            hipStream_t s) {
-  for (const auto& bk : p->res_buckets) {
-    DevTables t = p->t;
-    t.rlist = p->t.rlist + bk.first;
-    launch_res(bk.level, t, bk.count, d, u, b, x, s);
-    hipError_t e = hipGetLastError();
+  bool used[hines_plan::kResStreams] = {};
+  for (size_t i = 0; i < p->res_buckets.size(); ++i)
+    if (p->res_lane[i] > 0) used[p->res_lane[i] - 1] = true;
+  hipError_t e = hipSuccess;
+  bool fork = false;
+  for (int k = 0; k < hines_plan::kResStreams; ++k) fork = fork || used[k];
+  if (fork) {
+    e = hipEventRecord(p->res_fork, s);
+    for (int k = 0; k < hines_plan::kResStreams && e == hipSuccess; ++k)
+      if (used[k]) e = hipStreamWaitEvent(p->res_streams[k], p->res_fork, 0);
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  for (size_t i = 0; i < p->res_buckets.size(); ++i) {
+    const auto& bk = p->res_buckets[i];
+    DevTables t = p->t;
+    t.rlist = p->t.rlist + bk.first;
+    const hipStream_t si = p->res_lane[i] > 0 ? p->res_streams[p->res_lane[i] - 1] : s;
+    launch_res(bk.level, t, bk.count, d, u, b, x, si);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  for (int k = 0; k < hines_plan::kResStreams && e == hipSuccess; ++k)
+    if (used[k]) {
+      e = hipEventRecord(p->res_join[k], p->res_streams[k]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, p->res_join[k], 0);
+    }
+  return e;
 }
 
 hipError_t launch_solve(const hines_plan* p, const RhsSpec& rs, const double* d, const double* u, double* x,
@@ -769,6 +804,26 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
       p->res_buckets.push_back({hines::kResClassBytes[k], (int32_t)p->res_list.size(), (int32_t)m.size(), 0, k});
       p->res_list.insert(p->res_list.end(), m.begin(), m.end());
     }
+    // streams of the class launches: the largest estimated work (chunks of
+    // its groups over the groups a CU holds) first, each on the least loaded
+    std::vector<double> work(p->res_buckets.size(), 0.0);
+    for (size_t i = 0; i < p->res_buckets.size(); ++i) {
+      const auto& bk = p->res_buckets[i];
+      for (int32_t j = bk.first; j < bk.first + bk.count; ++j) work[i] += P.res.groups[p->res_list[j]].nchunk;
+      work[i] /= (double)(hines::kLdsLimitBytes / bk.lds_bytes);
+    }
+    std::vector<size_t> order(work.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return work[a] > work[b]; });
+    double load[hines_plan::kResStreams + 1] = {};
+    p->res_lane.assign(p->res_buckets.size(), 0);
+    for (size_t i : order) {
+      int best = 0;
+      for (int k = 1; k <= hines_plan::kResStreams; ++k)
+        if (load[k] < load[best]) best = k;
+      p->res_lane[i] = best;
+      load[best] += work[i];
+    }
   }
   if (o.host_only) {
     *out = p;
@@ -805,6 +860,13 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   if (e == hipSuccess) e = static_scratch_init(p->device);
   if (e == hipSuccess) e = allow_lds(o.group_width);
   if (e == hipSuccess) e = res_class_attr();
+  if (e == hipSuccess && P.res.built) {
+    for (int k = 0; k < hines_plan::kResStreams && e == hipSuccess; ++k) {
+      e = hipStreamCreateWithFlags(&p->res_streams[k], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&p->res_join[k], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->res_fork, hipEventDisableTiming);
+  }
   if (e != hipSuccess) {
     delete p;
     return set_err(HINES_ERR_HIP, "device setup: %s", hipGetErrorString(e));

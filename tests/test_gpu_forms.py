@@ -267,3 +267,30 @@ def test_autotune_picks_a_measured_candidate(torch_dev, tmp_path):
     best2, _ = autotune(f.parent, f.cell_offsets, f.branch_offsets, lambda p: 1 / 0, candidates=cands,
                         cache_path=cache)
     assert best2 == best  # served from the cache, nothing re-timed
+
+
+def test_autotune_over_whole_cell_kernel_knobs(torch_dev, tmp_path):
+    """The candidates the C2 bench tunes over (cut threshold and lanes per cell
+    of the one-lane-per-cell kernel, packing of the LDS-resident kernel): each
+    builds, solves to the oracle's tolerance, and the pick is the fastest."""
+    torch, dev = torch_dev
+    from paper_1810_12742_amd import Plan
+    from paper_1810_12742_amd.autotune import CELL_CANDIDATES, autotune, cached_pick
+    s = configs.c2(1024)
+    f = s.forest
+    d, u, b = (torch.from_numpy(a).to(dev) for a in (s.diag, s.upper, s.rhs))
+    x = torch.empty_like(b)
+    cache = str(tmp_path / "tune.json")
+    best, res = autotune(f.parent, f.cell_offsets, f.branch_offsets, lambda p: p.solve(d, u, b, out=x),
+                         candidates=CELL_CANDIDATES, reps=2, cache_path=cache)
+    assert len(res) == len(CELL_CANDIDATES)
+    assert min(res, key=lambda r: r[1])[0] == best
+    assert cached_pick(f.parent, f.cell_offsets, f.branch_offsets, candidates=CELL_CANDIDATES,
+                       cache_path=cache) == best
+    xo = oracle.solve(f, s.diag, s.upper, s.rhs)
+    for opts in CELL_CANDIDATES:
+        p = Plan(f.parent, f.cell_offsets, f.branch_offsets, **opts)
+        p.solve(d, u, b, out=x)
+        torch.cuda.synchronize()
+        assert cell_rel_err(f, x.cpu().numpy(), xo) <= 1e-12, opts
+        p.close()

@@ -95,12 +95,19 @@ def test_c2_slice_all_options(torch_dev, opts):
 
 
 def test_c2_full_bench_configuration(torch_dev):
-    """The full 65,536-cell workload in the launch configuration the bench times."""
-    import bench
+    """The full 65,536-cell workload in the launch configuration the bench
+    times: the autotuner's shipped pick for this device, or, when this device
+    has not been tuned, every candidate the bench would time."""
+    from paper_1810_12742_amd.autotune import CELL_CANDIDATES, SHIPPED_CACHE, cached_pick
     s = configs.c2()
-    xo = oracle.solve(s.forest, s.diag, s.upper, s.rhs)
-    x = gpu_solve(torch_dev, s, **bench.C2_OPTIONS)
-    assert cell_rel_err(s.forest, x, xo) <= TOL
+    f = s.forest
+    xo = oracle.solve(f, s.diag, s.upper, s.rhs)
+    pick = cached_pick(f.parent, f.cell_offsets, f.branch_offsets, candidates=CELL_CANDIDATES,
+                       cache_path=SHIPPED_CACHE)
+    for opts in ([pick] if pick else CELL_CANDIDATES):
+        print(f"c2 full: {opts}", flush=True)
+        x = gpu_solve(torch_dev, s, **opts)
+        assert cell_rel_err(f, x, xo) <= TOL
 
 
 def test_rhs_alias_and_determinism(torch_dev):
