@@ -92,7 +92,10 @@ typedef struct hines_options {
                                  d, u, b into LDS once, eliminates every compartment after its
                                  children (§2) along root-ward paths that setup cuts into chunks
                                  of 8 steps and schedules on the wave's 64 lanes (§3-§4), and
-                                 stores x.  Needs bitwise 0, cell_lanes 0 and every cell's
+                                 stores x.  With rebalance_root each cell is eliminated from
+                                 its tree centre (§6), the couplings on the path from the old
+                                 root moved at staging; x is still written in the user
+                                 numbering.  Needs bitwise 0, cell_lanes 0 and every cell's
                                  image within LDS (up to about 6,100 compartments;
                                  HINES_ERR_TOO_BIG otherwise).  The other calls keep using the
                                  groups.                                                     */
@@ -166,15 +169,18 @@ enum {
                                         in forward order in bits 32-63; 0 without takes       */
   /* LDS-resident plans (hines_plan_info.kernel == 4).  Group image: slot s holds user index
      lo + s; slot nslot is a zero entry (d = 1, u = 0, b = 0).                                */
-  HINES_TABLE_RES_GROUPS = 17,       /* [ngroups*15] lo, blob (16-byte units), nslot, staged
+  HINES_TABLE_RES_GROUPS = 17,       /* [ngroups*16] lo, blob (16-byte units), nslot, staged
                                         slots, slot of the first compartment, compartments,
                                         chunks per sweep, blob units, cells, path records,
                                         slot-list entries, byte offsets of the records and of
-                                        the slot lists in the blob, LDS class, steps per chunk */
+                                        the slot lists in the blob, LDS class, steps per chunk,
+                                        re-rooting pairs                                      */
   /* 18 is not used */
   HINES_TABLE_RES_BLOB = 19          /* [blob bytes / 2] the group blobs as 16-bit words: per lane
                                         its first record and its first slot-list entry (65 + 65
                                         words, 136 in all), the root slots padded to 8 words,
+                                        the re-rooting pairs (slot, slot whose staged u becomes
+                                        its coupling) padded to 8 words,
                                         the path records (first chunk, chunks, byte offset of
                                         the top's parent entry or 0xffff for a cell root, 0),
                                         each lane's records enclosed by idle records (65535, 0,

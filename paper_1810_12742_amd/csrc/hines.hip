@@ -718,7 +718,7 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
     }
   }
   if (o.resident) {
-    s = hines::build_resident(parent, n, cell_offsets, ncells, p->host.res, why, o.res_pack);
+    s = hines::build_resident(parent, n, cell_offsets, ncells, p->host.res, why, o.res_pack, o.rebalance_root);
     if (s == hines::OK && !hines::check_resident(p->host.res, parent, n, why)) s = hines::ERR_STATE;
     if (s != hines::OK) {
       delete p;

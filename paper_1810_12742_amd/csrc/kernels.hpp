@@ -1336,7 +1336,9 @@ __device__ __forceinline__ void res_elim(lds_char* base, const int (&o4)[hines::
     const double r = rcp_nr(dd);
     fv[k] = uk * r;
     yv[k] = bb * r;
-    ncd = -(uk * fv[k]);
+    // u^2 / d' with u^2 formed off the chain of dependent steps (u is read a
+    // chunk ahead): the next pivot waits on one product less
+    ncd = -((uk * uk) * r);
     ncb = -(uk * yv[k]);
   }
 #pragma unroll
@@ -1402,6 +1404,23 @@ __global__ __launch_bounds__(64) void k_solve_res(DevTables tb, const double* __
   }
   const lds_u16* ltab = (const lds_u16*)(base + oBlob);
   const lds_u16* roots = ltab + hines::kResLaneTab / 2;
+  // cells re-rooted at their centre: on the path from the old root to the new
+  // one every compartment takes as coupling to its new parent the u staged at
+  // that parent (its old child); a batch reads all its sources before it
+  // writes, and a later batch reads no slot an earlier one wrote
+  const lds_u16* flips = roots + ((2 * G.nroot + 15) & ~15) / 2;
+  for (int q0 = 0; q0 < G.nflip; q0 += 64) {
+    const int q = q0 + lane;
+    int dst = zero;
+    double v = 0.0;
+    if (q < G.nflip) {
+      dst = flips[2 * q];
+      v = U[flips[2 * q + 1]];
+    }
+    __asm__ volatile("" ::: "memory");
+    if (q < G.nflip) U[dst] = v;
+    __asm__ volatile("" ::: "memory");
+  }
   for (int r = lane; r < G.nroot; r += 64) U[roots[r]] = 0.0;  // a root has no coupling
   const lds_u2* recs = (const lds_u2*)(base + oBlob + G.rec_off);
   const lds_ent* lists = (const lds_ent*)(base + oBlob + G.list_off);

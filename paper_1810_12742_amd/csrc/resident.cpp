@@ -91,6 +91,40 @@ bool schedule_group(int32_t m, const std::vector<int32_t>& lpar, const std::vect
   return true;
 }
 
+// Re-rooting at the tree centre (paper §6): the compartment of least
+// eccentricity (largest hop distance to another compartment), the smaller
+// index on ties.  lp: parents of one cell in local numbering (lp[0] = -1,
+// lp[i] < i).  Fills path with the old root, its child toward the centre, ...,
+// the centre (a single entry when the root is the centre).
+void center_path(const int32_t* lp, int32_t m, std::vector<int32_t>& h, std::vector<int32_t>& up,
+                 std::vector<int32_t>& b1, std::vector<int32_t>& b2, std::vector<int32_t>& path) {
+  h.assign(m, 0);
+  for (int32_t i = m - 1; i >= 1; --i) h[lp[i]] = std::max(h[lp[i]], h[i] + 1);
+  b1.assign(m, -1);  // the two tallest children subtrees (height + 1) of each node
+  b2.assign(m, -1);
+  for (int32_t i = m - 1; i >= 1; --i) {
+    const int32_t p = lp[i], v = h[i] + 1;
+    if (v > b1[p]) {
+      b2[p] = b1[p];
+      b1[p] = v;
+    } else if (v > b2[p]) {
+      b2[p] = v;
+    }
+  }
+  up.assign(m, 0);  // longest path that leaves i through its parent
+  for (int32_t i = 1; i < m; ++i) {
+    const int32_t p = lp[i];
+    const int32_t other = b1[p] == h[i] + 1 ? b2[p] : b1[p];
+    up[i] = std::max(up[p], std::max(other, 0)) + 1;
+  }
+  int32_t z = 0;
+  for (int32_t i = 1; i < m; ++i)
+    if (std::max(h[i], up[i]) < std::max(h[z], up[z])) z = i;
+  path.clear();
+  for (int32_t v = z; v >= 0; v = lp[v]) path.push_back(v);
+  std::reverse(path.begin(), path.end());
+}
+
 // Smallest LDS class (most groups per CU) that holds the image.
 int32_t res_class(int32_t nslot, int64_t blob_units) {
   for (int32_t k = kResClasses - 1; k >= 0; --k)
@@ -101,33 +135,22 @@ int32_t res_class(int32_t nslot, int64_t blob_units) {
 }  // namespace
 
 Status build_resident(const int32_t* parent, int64_t n, const int64_t* cell_offsets, int64_t ncells,
-                      ResPlan& out, std::string& err, int32_t pack) {
+                      ResPlan& out, std::string& err, int32_t pack, bool reroot) {
   out = ResPlan{};
   if (pack < 1 || pack > kResMaxSlots) {
     err = "resident pack size out of range";
     return ERR_OPTION;
   }
-  // groups of consecutive cells
-  std::vector<int64_t> gc;  // first cell of each group, then ncells
-  for (int64_t c = 0; c < ncells;) {
-    gc.push_back(c);
-    int64_t slots = cell_offsets[c + 1] - cell_offsets[c];
-    int64_t c1 = c + 1;
-    while (c1 < ncells && slots + (cell_offsets[c1 + 1] - cell_offsets[c1]) <= pack) {
-      slots += cell_offsets[c1 + 1] - cell_offsets[c1];
-      ++c1;
-    }
-    c = c1;
-  }
-  gc.push_back(ncells);
-  const int64_t ng = (int64_t)gc.size() - 1;
-  std::vector<int32_t> lpar, ch_off, ch, fin, heavy, fill, chunk_of;
+  std::vector<int32_t> lpar, ch_off, ch, fin, heavy, fill, chunk_of, topo, roots, lp1, hh, uu, b1, b2, path;
+  std::vector<std::pair<int32_t, int32_t>> flips;
   std::vector<PathInfo> path_of_top;
   std::vector<Placed> placed;
   std::vector<int32_t> lane_rec(kSchedLanes + 1), lane_list(kSchedLanes + 1);
-  for (int64_t g = 0; g < ng; ++g) {
-    const int64_t u0 = cell_offsets[gc[g]], u1 = cell_offsets[gc[g + 1]];
-    const int64_t m64 = u1 - u0;
+  // One group: cells [ca, cb), re-rooted when rr.  Appends the group and its
+  // blob on success; ERR_TOO_BIG (nothing appended) when the image does not
+  // fit the largest LDS class.
+  auto build_group = [&](int64_t ca, int64_t cb, bool rr) -> Status {
+    const int64_t u0 = cell_offsets[ca], u1 = cell_offsets[cb];    const int64_t m64 = u1 - u0;
     KResGroup G{};
     G.lo = u0 & ~(int64_t)1;
     G.first = (int32_t)(u0 - G.lo);
@@ -139,23 +162,57 @@ Status build_resident(const int32_t* parent, int64_t n, const int64_t* cell_offs
     G.count = m;
     G.nslot = (G.first + m + 1) & ~1;
     G.ndma = (int32_t)std::min<int64_t>(G.nslot, n - G.lo);
-    G.nroot = (int32_t)(gc[g + 1] - gc[g]);
-    // local tree: children (ascending), finishing steps, heavy children
+    G.nroot = (int32_t)(cb - ca);
+    // local tree (re-rooted at each cell's centre on request): children
+    // (ascending), finishing steps, heavy children
     lpar.assign(m, -1);
-    ch_off.assign(m + 1, 0);
     for (int32_t i = 0; i < m; ++i) {
       const int32_t p = parent[u0 + i];
       lpar[i] = p < 0 ? -1 : (int32_t)(p - u0);
-      if (p >= 0) ++ch_off[lpar[i] + 1];
     }
+    flips.clear();  // (slot whose coupling changes, slot it comes from)
+    roots.clear();
+    for (int64_t c = ca; c < cb; ++c) {
+      const int32_t c0 = (int32_t)(cell_offsets[c] - u0), cm = (int32_t)(cell_offsets[c + 1] - cell_offsets[c]);
+      int32_t z = c0;
+      if (rr && cm > 2) {
+        lp1.resize(cm);
+        for (int32_t i = 0; i < cm; ++i) lp1[i] = i == 0 ? -1 : lpar[c0 + i] - c0;
+        center_path(lp1.data(), cm, hh, uu, b1, b2, path);
+        // the edges on the path from the old root to the centre turn round:
+        // a_i's parent becomes a_(i+1), whose stored coupling (u of the old
+        // child) is the coupling of that edge
+        for (size_t k = 0; k + 1 < path.size(); ++k) {
+          lpar[c0 + path[k]] = c0 + path[k + 1];
+          flips.push_back({c0 + path[k] + G.first, c0 + path[k + 1] + G.first});
+        }
+        z = c0 + path.back();
+        lpar[z] = -1;
+      }
+      roots.push_back(z + G.first);
+    }
+    ch_off.assign(m + 1, 0);
+    for (int32_t i = 0; i < m; ++i)
+      if (lpar[i] >= 0) ++ch_off[lpar[i] + 1];
     for (int32_t i = 0; i < m; ++i) ch_off[i + 1] += ch_off[i];
     ch.assign(std::max(ch_off[m], 1), 0);
     fill.assign(ch_off.begin(), ch_off.end() - 1);
     for (int32_t i = 0; i < m; ++i)
       if (lpar[i] >= 0) ch[fill[lpar[i]]++] = i;
+    // breadth-first order from the roots; children are finished before
+    // their parents when it is taken backwards
+    topo.clear();
+    for (int32_t r : roots) topo.push_back(r - G.first);
+    for (size_t k = 0; k < topo.size(); ++k)
+      for (int32_t e = ch_off[topo[k]]; e < ch_off[topo[k] + 1]; ++e) topo.push_back(ch[e]);
+    if ((int32_t)topo.size() != m) {
+      err = "resident: the cells of a group do not form a forest";
+      return ERR_STATE;
+    }
     fin.assign(m, 0);
     heavy.assign(m, -1);
-    for (int32_t i = m - 1; i >= 0; --i) {
+    for (int32_t k = m - 1; k >= 0; --k) {
+      const int32_t i = topo[k];
       int32_t h = -1;
       for (int32_t e = ch_off[i]; e < ch_off[i + 1]; ++e)
         if (h < 0 || fin[ch[e]] > fin[h]) h = ch[e];  // last to finish; the smallest index on ties
@@ -208,10 +265,12 @@ Status build_resident(const int32_t* parent, int64_t n, const int64_t* cell_offs
       return ERR_TOO_BIG;
     }
     const int64_t root_bytes = (2 * (int64_t)G.nroot + 15) & ~(int64_t)15;
+    G.nflip = (int32_t)flips.size();
+    const int64_t flip_bytes = (4 * (int64_t)G.nflip + 15) & ~(int64_t)15;
     const int64_t rec_bytes = (8 * (int64_t)nrec + 15) & ~(int64_t)15;
     // one spare entry past the last: a lane reads its next entry ahead of use
     const int64_t list_bytes = (kResEntBytes * ((int64_t)G.nlist + 1) + 15) & ~(int64_t)15;
-    G.rec_off = kResLaneTab + (int32_t)root_bytes;
+    G.rec_off = kResLaneTab + (int32_t)(root_bytes + flip_bytes);
     G.list_off = G.rec_off + (int32_t)rec_bytes;
     const int64_t bytes = G.list_off + list_bytes;
     G.blob_units = (int32_t)(bytes / 16);
@@ -229,8 +288,11 @@ Status build_resident(const int32_t* parent, int64_t n, const int64_t* cell_offs
       put16(2 * l, (uint16_t)lane_rec[l]);
       put16(2 * (kSchedLanes + 1) + 2 * l, (uint16_t)lane_list[l]);
     }
-    for (int32_t c = 0; c < G.nroot; ++c)
-      put16(kResLaneTab + 2 * c, (uint16_t)(cell_offsets[gc[g] + c] - G.lo));
+    for (int32_t c = 0; c < G.nroot; ++c) put16(kResLaneTab + 2 * c, (uint16_t)roots[c]);
+    for (int32_t k = 0; k < G.nflip; ++k) {
+      put16(kResLaneTab + root_bytes + 4 * k, (uint16_t)flips[k].first);
+      put16(kResLaneTab + root_bytes + 4 * k + 2, (uint16_t)flips[k].second);
+    }
     const uint16_t zero_off = (uint16_t)(8 * G.nslot);
     const KResRec idle{0xffff, 0, (uint16_t)kResNoParent, 0};
     for (int l = 0; l <= kSchedLanes; ++l) std::memcpy(bp + G.rec_off + 8 * (lane_rec[l] - 1), &idle, 8);
@@ -259,13 +321,40 @@ Status build_resident(const int32_t* parent, int64_t n, const int64_t* cell_offs
     }
     out.max_lds = std::max<int64_t>(out.max_lds, res_lds_bytes(G.cls, G.blob_units));
     out.groups.push_back(G);
+    return OK;
+  };
+  // groups of consecutive cells of at most `pack` compartments (a larger
+  // cell alone); a group whose image does not fit LDS is built again with
+  // half its cells, and a single cell that does not fit re-rooted is built
+  // from its own root
+  for (int64_t c = 0; c < ncells;) {
+    int64_t slots = cell_offsets[c + 1] - cell_offsets[c];
+    int64_t c1 = c + 1;
+    while (c1 < ncells && slots + (cell_offsets[c1 + 1] - cell_offsets[c1]) <= pack) {
+      slots += cell_offsets[c1 + 1] - cell_offsets[c1];
+      ++c1;
+    }
+    bool rr = reroot;
+    for (;;) {
+      const Status st = build_group(c, c1, rr);
+      if (st == OK) break;
+      if (st != ERR_TOO_BIG) return st;
+      if (c1 - c > 1) {
+        c1 = c + (c1 - c) / 2;
+      } else if (rr) {
+        rr = false;
+      } else {
+        return st;
+      }
+    }
+    c = c1;
   }
   out.built = true;
   return OK;
 }
 
 bool check_resident(const ResPlan& R, const int32_t* parent, int64_t n, std::string& why) {
-  std::vector<int32_t> chunk, sub, top_end;
+  std::vector<int32_t> chunk, sub, top_end, np, cell_of;
   for (size_t g = 0; g < R.groups.size(); ++g) {
     const KResGroup& G = R.groups[g];
     const std::string gs = "resident group " + std::to_string(g);
@@ -295,10 +384,51 @@ bool check_resident(const ResPlan& R, const int32_t* parent, int64_t n, std::str
     chunk.assign(G.nslot, -1);
     sub.assign(G.nslot, -1);
     top_end.assign(G.nslot, -1);  // for a path top: the chunk of its contribution
+    // the (re-rooted) parent slot of every compartment: the user parents with
+    // the pairs of the blob turned round and the listed roots cut off
+    np.assign(G.nslot, -1);
+    cell_of.assign(G.nslot, -1);
+    int32_t ncell = -1;
+    for (int32_t s = s0; s < s1; ++s) {
+      const int64_t p = parent[G.lo + s];
+      if (p < 0) ++ncell;
+      cell_of[s] = ncell;
+      np[s] = p < 0 ? -1 : (int32_t)(p - G.lo);
+    }
+    const int64_t root_bytes = (2 * (int64_t)G.nroot + 15) & ~(int64_t)15;
+    if (G.nflip < 0 || G.rec_off < kResLaneTab + root_bytes + 4 * (int64_t)G.nflip || ncell + 1 != G.nroot) {
+      why = gs + ": root and re-rooting lists";
+      return false;
+    }
+    for (int32_t k = 0; k < G.nflip; ++k) {
+      const int32_t dst = get16(kResLaneTab + root_bytes + 4 * k), src = get16(kResLaneTab + root_bytes + 4 * k + 2);
+      // src must be dst's child in the user tree: its coupling is the edge's
+      if (dst < s0 || dst >= s1 || src < s0 || src >= s1 || parent[G.lo + src] != G.lo + dst) {
+        why = gs + ": re-rooting pair";
+        return false;
+      }
+      np[dst] = src;
+    }
     for (int32_t c = 0; c < G.nroot; ++c) {
       const int32_t r = get16(kResLaneTab + 2 * c);
-      if (r < s0 || r >= s1 || parent[G.lo + r] >= 0) {
+      if (r < s0 || r >= s1 || cell_of[r] != c) {
         why = gs + ": root list";
+        return false;
+      }
+      np[r] = -1;
+    }
+    for (int32_t s = s0; s < s1; ++s) {  // every compartment reaches its cell's root
+      int32_t v = s, hops = 0;
+      while (np[v] >= 0 && hops <= G.count) {
+        if (cell_of[np[v]] != cell_of[s]) {
+          why = gs + ": re-rooted parent outside the cell";
+          return false;
+        }
+        v = np[v];
+        ++hops;
+      }
+      if (np[v] >= 0) {
+        why = gs + ": re-rooted parents form a cycle";
         return false;
       }
     }
@@ -347,8 +477,7 @@ bool check_resident(const ResPlan& R, const int32_t* parent, int64_t n, std::str
             return false;
           }
           if (started) {
-            const int32_t ps = parent[G.lo + prev] < 0 ? -1 : (int32_t)(parent[G.lo + prev] - G.lo);
-            if (ps != slot) {
+            if (np[prev] != slot) {
               why = gs + ": path does not follow parents";
               return false;
             }
@@ -362,8 +491,7 @@ bool check_resident(const ResPlan& R, const int32_t* parent, int64_t n, std::str
           why = gs + ": a path top is not the last step of its last chunk";
           return false;
         }
-        const int32_t pp = parent[G.lo + prev];
-        const int32_t want = pp < 0 ? kResNoParent : 8 * (int32_t)(pp - G.lo);
+        const int32_t want = np[prev] < 0 ? kResNoParent : 8 * np[prev];
         if (r.par != want) {
           why = gs + ": push target";
           return false;
@@ -381,9 +509,8 @@ bool check_resident(const ResPlan& R, const int32_t* parent, int64_t n, std::str
         why = gs + ": compartment not scheduled";
         return false;
       }
-      const int64_t p = parent[G.lo + s];
-      if (p < 0) continue;
-      const int32_t ps = (int32_t)(p - G.lo);
+      if (np[s] < 0) continue;
+      const int32_t ps = np[s];
       if (top_end[s] >= 0) {
         // a light path's top: its contribution lands two chunks before the
         // chunk that eliminates the parent (and the parent's x is written two

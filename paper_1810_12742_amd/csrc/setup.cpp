@@ -1032,7 +1032,7 @@ int64_t export_table(const HostPlan& p, int32_t id, int64_t* out, int64_t capaci
     case T_CELL_FLAGS: return put(p.cl.flags);
     case T_CELL_MBSRC: return put(p.cl.mbsrc);
     case T_RES_GROUPS: {
-      constexpr int64_t kF = 15;
+      constexpr int64_t kF = 16;
       const int64_t cnt = kF * (int64_t)p.res.groups.size();
       if (out) {
         if (capacity < cnt) return -1;
@@ -1054,6 +1054,7 @@ int64_t export_table(const HostPlan& p, int32_t id, int64_t* out, int64_t capaci
           r[12] = G.list_off;
           r[13] = G.cls;
           r[14] = kResK;
+          r[15] = G.nflip;
         }
       }
       return cnt;

@@ -99,8 +99,8 @@ enum TableId : int32_t {
   T_CELL_POS = 14,        // int64[nchunks*kCellChunkElems]: [chunk][staging lane][slot] relative position
   T_CELL_FLAGS = 15,      // int64[nchunks*kCellChunkElems]: [chunk][cell lane][element] flags
   T_CELL_MBSRC = 16,      // int64[nwaves*64]: mailbox source lanes (6 bits each), backward | forward << 32
-  T_RES_GROUPS = 17,      // int64[ngroups*15]: lo, blob, nslot, ndma, first, count, nchunk, blob_units, nroot,
-                          // npath, nlist, rec_off, list_off, cls, steps per chunk
+  T_RES_GROUPS = 17,      // int64[ngroups*16]: lo, blob, nslot, ndma, first, count, nchunk, blob_units, nroot,
+                          // npath, nlist, rec_off, list_off, cls, steps per chunk, nflip
   T_RES_BLOB = 19,        // int64[blob bytes / 2]: the blobs as uint16 words
   T_NUM = 20,
 };
@@ -212,8 +212,10 @@ struct KResGroup {
   int32_t rec_off;     // byte offset of the records in the blob
   int32_t list_off;    // byte offset of the slot lists in the blob
   int32_t cls;         // LDS class (index into kResClassBytes / kResClassStride)
+  int32_t nflip;       // couplings that move when the cells are re-rooted (pairs in the blob)
+  int32_t pad;
 };
-static_assert(sizeof(KResGroup) == 64, "layout");
+static_assert(sizeof(KResGroup) == 72, "layout");
 // Path record: first chunk, chunks, byte offset (slot * 8) of the top's parent
 // entry or kResNoParent, spare.
 struct KResRec {
@@ -222,7 +224,9 @@ struct KResRec {
 static_assert(sizeof(KResRec) == 8, "layout");
 // Blob of a group, in 16-byte units: per lane the first record and the first
 // slot-list entry (65 + 65 uint16, kResLaneTab bytes), the root slots of its
-// cells (uint16, padded to 16 bytes), the records lane by lane in chunk order,
+// cells (uint16, padded to 16 bytes), the re-rooting pairs (uint16 slot whose
+// coupling to its new parent is the u staged at the second uint16 slot; padded
+// to 16 bytes), the records lane by lane in chunk order,
 // then the slot lists: per lane, one kResEntBytes entry per active chunk, in
 // chunk order, holding the byte offsets (slot * 8) of the chunk's kResK steps from
 // the bottom of the path upward.
@@ -245,7 +249,7 @@ struct ResPlan {
 // pack: consecutive cells share a group while it holds at most this many
 // compartments (kResPackSlots by default).
 Status build_resident(const int32_t* parent, int64_t n, const int64_t* cell_offsets, int64_t ncells,
-                      ResPlan& out, std::string& err, int32_t pack = kResPackSlots);
+                      ResPlan& out, std::string& err, int32_t pack = kResPackSlots, bool reroot = false);
 // Replay of the resident tables: every record, list entry and slot inside its
 // group image, every compartment eliminated once, after all its children, and
 // every light path's contribution added two chunks before its parent's chunk.

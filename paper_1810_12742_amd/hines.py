@@ -193,7 +193,7 @@ class Plan:
         if name == "branches":
             return out.reshape(-1, 8)
         if name == "res_groups":
-            return out.reshape(-1, 15)
+            return out.reshape(-1, 16)
         return out
 
     def tables(self) -> dict:

@@ -288,18 +288,23 @@ def test_resident_kernel_parity(torch_dev):
     cases.append(cable_values(f, np.random.default_rng(6), a_kind="cable", dt=0.025))
     for s in cases:
         f = s.forest
-        print(f"resident: {f.ncells} cells, {f.n} unknowns", flush=True)
         xo = oracle.solve(f, s.diag, s.upper, s.rhs)
         assert Plan(f.parent, f.cell_offsets, f.branch_offsets, resident=True).info["kernel"] == 4
-        x1 = gpu_solve(torch_dev, s, resident=True)
-        assert cell_rel_err(f, x1, xo) <= TOL
-        x2 = gpu_solve(torch_dev, s, alias=True, resident=True)
-        assert np.array_equal(x1, x2)
+        # re-rooted at the tree centres (paper §6), and packed into larger groups
+        for opts in (dict(), dict(rebalance_root=1), dict(rebalance_root=1, res_pack=3000)):
+            print(f"resident {opts}: {f.ncells} cells, {f.n} unknowns", flush=True)
+            x1 = gpu_solve(torch_dev, s, resident=True, **opts)
+            assert cell_rel_err(f, x1, xo) <= TOL
+            x2 = gpu_solve(torch_dev, s, alias=True, resident=True, **opts)
+            assert np.array_equal(x1, x2)
 
 
 def test_resident_full_c2(torch_dev):
-    """The full 65,536-cell C2 workload on the resident kernel."""
+    """The full 65,536-cell C2 workload on the resident kernel, with the soma
+    as root and re-rooted at the tree centres."""
     s = configs.c2()
     xo = oracle.solve(s.forest, s.diag, s.upper, s.rhs)
-    x = gpu_solve(torch_dev, s, resident=True)
-    assert cell_rel_err(s.forest, x, xo) <= TOL
+    for opts in (dict(), dict(rebalance_root=1, res_pack=3000)):
+        print(f"resident full c2 {opts}", flush=True)
+        x = gpu_solve(torch_dev, s, resident=True, **opts)
+        assert cell_rel_err(s.forest, x, xo) <= TOL

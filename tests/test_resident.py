@@ -30,7 +30,7 @@ NO_PARENT = 0xFFFF
 CLASS_BYTES = (163840, 81920, 54528, 40960, 32768, 27136, 23296, 20480, 16384, 10240)
 STRIDES = (6144, 3008, 1984, 1472, 1152, 960, 832, 704, 576, 320)
 GROUP_FIELDS = ("lo", "blob", "nslot", "ndma", "first", "count", "nchunk", "blob_units", "nroot", "npath",
-                "nlist", "rec_off", "list_off", "cls", "k")
+                "nlist", "rec_off", "list_off", "cls", "k", "nflip")
 
 
 def cell_rel_err(f, x, xo):
@@ -55,6 +55,8 @@ def group_view(t, g):
     G["rec_first"] = words[:LANES + 1]
     G["list_first"] = words[LANES + 1:2 * LANES + 2]
     G["roots"] = words[LANE_TAB_WORDS:LANE_TAB_WORDS + G["nroot"]]
+    f0 = LANE_TAB_WORDS + 8 * ((2 * G["nroot"] + 15) // 16)
+    G["flips"] = words[f0:f0 + 2 * G["nflip"]].reshape(-1, 2)  # slot, slot whose u it takes
     r0 = G["rec_off"] // 2
     nrec = G["npath"] + LANES + 1
     G["recs"] = words[r0:r0 + 4 * nrec].reshape(-1, 4)      # c0, nch, parent byte offset, spare
@@ -77,6 +79,8 @@ def replay(t, n, diag, upper, rhs):
         U[:ndma] = upper[lo:lo + ndma]
         B[:ndma] = rhs[lo:lo + ndma]
         D[zero], U[zero], B[zero] = 1.0, 0.0, 0.0
+        for dst, src in G["flips"]:   # re-rooted cells: couplings move along the old root's path
+            U[dst] = U[src]
         U[G["roots"]] = 0.0
         recs, lists = G["recs"], G["lists"]
         lanes = []
@@ -188,6 +192,69 @@ def test_replay_c2_slice():
     assert g[:, 5].sum() == s.forest.n
     assert np.all(g[:, 0] % 2 == 0)
     assert np.all(g[:, 2] + 1 <= np.array(STRIDES)[g[:, 13]])
+
+
+def _eccentricities(par):
+    """Hop eccentricity of every node of one tree (parents par, par[0] = -1), by
+    a breadth-first search from each node."""
+    m = len(par)
+    adj = [[] for _ in range(m)]
+    for i in range(1, m):
+        adj[i].append(par[i])
+        adj[par[i]].append(i)
+    ecc = np.zeros(m, dtype=np.int64)
+    for s0 in range(m):
+        dist = np.full(m, -1)
+        dist[s0] = 0
+        q = [s0]
+        for v in q:
+            for w in adj[v]:
+                if dist[w] < 0:
+                    dist[w] = dist[v] + 1
+                    q.append(w)
+        ecc[s0] = dist.max()
+    return ecc
+
+
+def test_replay_rerooted_cells():
+    """Cells re-rooted at their centre (paper §6): the replay with the moved
+    couplings solves to the oracle's tolerance, each new root is the
+    compartment of least eccentricity (the smaller index on ties, found here by
+    brute force), and the schedules get shorter than with the soma as root."""
+    for s, opts in ((configs.c2(24), {}), (configs.random_system(60, seed=23), dict(res_pack=600))):
+        f = s.forest
+        t = _check(f, s, rebalance_root=True, **opts)
+        t0, _ = plan_tables(f, **opts)
+        assert t["res_groups"][:, 6].sum() < t0["res_groups"][:, 6].sum()
+        assert t["res_groups"][:, 15].sum() > 0
+        roots = []
+        for g in t["res_groups"]:
+            G = group_view(t, g)
+            roots.extend(int(G["lo"]) + int(r) for r in G["roots"])
+        for c in range(min(f.ncells, 12)):
+            lo, hi = int(f.cell_offsets[c]), int(f.cell_offsets[c + 1])
+            par = f.parent[lo:hi].astype(np.int64) - lo
+            par[0] = -1
+            ecc = _eccentricities(par)
+            want = lo + int(np.flatnonzero(ecc == ecc.min())[0]) if hi - lo > 2 else lo
+            assert roots[c] == want
+
+
+def test_groups_that_do_not_fit_are_split_or_kept_at_their_root():
+    """A packed group whose tables overflow LDS (many small re-rooted cells)
+    is built again with fewer cells; a near-limit cable that would not fit
+    re-rooted keeps its own root.  Both still replay to the oracle."""
+    s = configs.random_system(500, seed=31)
+    t = _check(s.forest, s, rebalance_root=True, res_pack=3000)
+    assert t["res_groups"][:, 5].sum() == s.forest.n
+    n = 5500
+    par = np.concatenate([np.arange(-1, n - 1), [-1, -1, -1]]).astype(np.int32)
+    off = np.array([0, n, n + 1, n + 2, n + 3], dtype=np.int64)
+    f = Forest(par, off, off.copy())
+    sc = cable_values(f, np.random.default_rng(6), a_kind="cable", dt=0.025)
+    t = _check(f, sc, rebalance_root=True)
+    g = t["res_groups"]
+    assert g[0, 5] == n and g[0, 15] == 0   # the cable alone, from its soma
 
 
 def test_replay_small_cells_packed_and_odd_offsets():
