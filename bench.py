@@ -352,6 +352,7 @@ def run_c3(args, torch, dev):
     ncells = args.cells or configs.C3_CELLS
     s = configs.c3(ncells)
     f = s.forest
+    print(f"c3: {f.ncells} cells, {f.n} unknowns generated", file=sys.stderr, flush=True)
     d, u, c = (torch.from_numpy(a).to(dev) for a in (s.diag, s.upper, s.c))
     if args.options:
         best, tried = json.loads(args.options), []
@@ -360,10 +361,11 @@ def run_c3(args, torch, dev):
         # the serial walk of its longest lanes on a small draw and by throughput
         # on the full one, while the group plans scale with the cell count
         vs = torch.zeros(f.n, dtype=torch.float64, device=dev)
-        cands = [dict(max_group_unknowns=3000), dict(cell_lanes=1)]
+        cands = [dict(max_group_unknowns=3000)] + [dict(cell_lanes=1, cell_cut_percent=cp, cell_max_cuts=mc)
+                                                    for cp in (60, 80, 110) for mc in (1, 3)]
         best, tried = autotune(f.parent, f.cell_offsets, f.branch_offsets,
                                lambda p: p.timestep(d, u, c, vs, vs, noise_sigma=0.1, noise_seed=3),
-                               candidates=cands, reps=2, cache_path=args.tune_cache)
+                               candidates=cands, reps=2, cache_path=args.tune_cache, verbose=True)
         del vs
     t0 = time.perf_counter()
     plan = Plan(f.parent, f.cell_offsets, f.branch_offsets, **best)

@@ -17,6 +17,7 @@ from __future__ import annotations
 import hashlib
 import json
 import os
+import sys
 
 import numpy as np
 
@@ -116,7 +117,7 @@ def autotune(parent, cell_offsets, branch_offsets, run, *, candidates=None, reps
         plan.close()
         results.append((opts, ms))
         if verbose:
-            print(f"autotune {opts}: {ms:.4f} ms", flush=True)
+            print(f"autotune {opts}: {ms:.4f} ms", file=sys.stderr, flush=True)
     if not results:
         raise RuntimeError("no candidate option set could be built")
     best = min(results, key=lambda r: r[1])[0]
