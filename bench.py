@@ -7,7 +7,10 @@ dt = 0.025, one right-hand side; seed 1.  Inputs are resident in HBM before
 the timed region.  A step is one hines_solve over all cells: every matrix
 entry is read from HBM once and the solution written once (32 algorithmic
 bytes per compartment).  The same line carries the FP32-storage + FP64
-refinement form on the same cells at dt in {0.001, 0.025, 1.0}.
+refinement form on the same cells at dt in {0.001, 0.025, 1.0}, the
+layout-resident solve, the small single-solve case (4,096 cells of 75
+compartments), the oracle timed on the host's cores, and (key ``c3``, unless
+``--no-c3``) the batched time loop below with the autotuner's cached pick.
 
 Other workloads (``--workload``): ``c3`` the batched implicit-Euler time loop
 (200,000 cells of 50/500/5,000/20,000 compartments, noise current, K steps per
@@ -660,6 +663,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="c2: skip the FP32+refinement measurement")
+    ap.add_argument("--no-c3", action="store_true", help="c2: skip the time-loop (C3) summary on the same line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run a plain device copy of 512 MiB (read and write) three "
                          "times, the reference kernel for scaling HBM byte counters")
@@ -677,8 +681,28 @@ def main(argv=None):
     torch.cuda.set_device(dev)
     run = {"c2": run_c2, "c3": run_c3, "c5": run_c5, "scaling": run_scaling,
            "branching": run_branching, "outlook": run_outlook}[args.workload]
-    print(json.dumps(run(args, torch, dev)), flush=True)
+    out = run(args, torch, dev)
+    if args.workload == "c2" and not args.no_c3:
+        out["c3"] = c3_summary(args, torch, dev)
+    print(json.dumps(out), flush=True)
     return 0
+
+
+def c3_summary(args, torch, dev):
+    """The batched time loop (200,000 cells, 100 steps per captured graph) beside
+    the C2 line: the autotuner's cached pick, 3 timed graph launches."""
+    a = argparse.Namespace(**vars(args))
+    a.steps, a.warmup, a.graph_steps, a.options, a.cells = 3, 1, 100, "", 0
+    try:
+        r = run_c3(a, torch, dev)
+    except Exception as e:  # the C2 line stands on its own
+        return {"error": f"{type(e).__name__}: {e}"}
+    K = r["config"]["graph_steps"]
+    return {"metric": r["metric"], "value": r["value"], "unit": r["unit"], "graph_steps": K,
+            "ms_per_graph_launch": r["ms_per_step"], "ms_per_time_step": r["ms_per_step"] / K,
+            "launches": r["steps"], "roofline": r["roofline"], "options": r["config"]["options"],
+            "workload": r["config"]["workload"], "setup_s": r["config"]["setup_s"],
+            "charge_conservation_max_rel_err_step0": r["charge_conservation_max_rel_err_step0"]}
 
 
 if __name__ == "__main__":

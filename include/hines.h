@@ -175,7 +175,9 @@ enum {
                                         slot-list entries, byte offsets of the records and of
                                         the slot lists in the blob, LDS class, steps per chunk,
                                         re-rooting pairs                                      */
-  /* 18 is not used */
+  HINES_TABLE_CELL_RANGE = 18,      /* [nwaves*64] per lane: the steps q0 .. q1 - 1 of its walk
+                                        (bits 0-31: q0, bits 32-63: q1); every other step of
+                                        the lane is padding; 0 for empty lanes                */
   HINES_TABLE_RES_BLOB = 19          /* [blob bytes / 2] the group blobs as 16-bit words: per lane
                                         its first record and its first slot-list entry (65 + 65
                                         words, 136 in all), the root slots padded to 8 words,

@@ -368,8 +368,19 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
         slot = 0;
       }
       WavePlan& P = plans.back();
-      // lane of piece i: pairs split across the halves, larger groups consecutive
-      auto lane_of = [&](int i) { return nl == 2 ? (i == 0 ? slot + 32 : slot) : slot * nl + i; };
+      // lane of piece i: piece-major, so that lanes of similar length are
+      // adjacent and their padding fills whole memory lines of the walk
+      // layout.  Pieces: the rest P in the first block, the cut-off subtrees
+      // ranked by length (longest first) in the next ones; pairs split across
+      // the halves (P in the upper one).
+      int blk[kCellMaxCuts + 1] = {0, 1, 2, 3};
+      if (nl >= 3) {
+        int ord[kCellMaxCuts];
+        for (int i = 1; i < nl; ++i) ord[i - 1] = i;
+        std::stable_sort(ord, ord + nl - 1, [&](int a, int b) { return g.lanes[a].back.size() > g.lanes[b].back.size(); });
+        for (int r = 0; r + 1 < nl; ++r) blk[ord[r]] = r + 1;
+      }
+      auto lane_of = [&](int i) { return nl == 2 ? (i == 0 ? slot + 32 : slot) : blk[i] * per + slot; };
       uint64_t bw = 0, fw = 0;
       for (int i = 1; i < nl; ++i) {
         bw |= (uint64_t)lane_of(i) << (6 * (i - 1));
@@ -388,6 +399,7 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
   out.lane_cell.assign(nw * 64, -1);
   out.base.assign(nw * 64, 0);
   out.mbsrc.assign(nw * 64, 0);
+  out.range.assign(nw * 64, 0);
   int64_t chunks = 0;
   for (int64_t w = 0; w < nw; ++w) {
     const int32_t nk = (int32_t)((plans[w].span + kCellChunk - 1) / kCellChunk);
@@ -410,6 +422,7 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
       out.base[w * 64 + c] = cell_offsets[L->cell];
       const int64_t len = (int64_t)L->back.size();
       const int64_t q0 = L->pad_after ? 0 : span - len;
+      out.range[w * 64 + c] = (uint64_t)q0 | ((uint64_t)(q0 + len) << 32);
       for (int64_t t = 0; t < len; ++t) {
         const int64_t q = q0 + t;
         const int64_t k = q / kCellChunk;

@@ -476,6 +476,10 @@ bool check_kernel_tables(const hines::HostPlan& P, std::string& why, bool& capac
 // leaves its buffers whatever the tables hold.
 bool check_cell_tables(const hines::HostPlan& P, const int64_t* cell_offsets, std::string& why) {
   const hines::CellLanes& C = P.cl;
+  if ((int64_t)C.range.size() != 64 * C.nwaves || (int64_t)C.mbsrc.size() != 64 * C.nwaves) {
+    why = "per-lane tables of the wrong size";
+    return false;
+  }
   for (int64_t w = 0; w < C.nwaves; ++w) {
     const hines::KCellWave& W = C.waves[w];
     if (W.chunk_off < 0 || W.nchunk < 0 || W.chunk_off + W.nchunk > C.nchunks || W.ncell < 1 || W.ncell > 64) {
@@ -496,6 +500,14 @@ bool check_cell_tables(const hines::HostPlan& P, const int64_t* cell_offsets, st
         why = "empty lane with a base";
         return false;
       }
+      // the steps outside the lane's range are its padding, and only those
+      // (the step kernel reads the zero block in their place)
+      const uint64_t rg = C.range[w * 64 + c];
+      const int64_t q0 = (int64_t)(rg & 0xffffffffu), q1 = (int64_t)(rg >> 32);
+      if (q0 > q1 || q1 > (int64_t)W.nchunk * hines::kCellChunk || (cell < 0 && rg != 0)) {
+        why = "wave " + std::to_string(w) + " lane " + std::to_string(c) + " step range out of bounds";
+        return false;
+      }
       // stack entries per sweep (the top in registers, the rest in slots 1..)
       int m = 0;
       bool ok_b = true;
@@ -506,6 +518,11 @@ bool check_cell_tables(const hines::HostPlan& P, const int64_t* cell_offsets, st
           const uint16_t ps = C.pos[hines::cell_pos_index(g, c, e)];
           if ((ps == hines::kCellPadPos) != ((f & hines::CF_PAD) != 0) || (ps != hines::kCellPadPos && ps >= size)) {
             why = "wave " + std::to_string(w) + " position out of range";
+            return false;
+          }
+          const int64_t q = k * hines::kCellChunk + e;
+          if (((f & hines::CF_PAD) != 0) == (q >= q0 && q < q1)) {
+            why = "wave " + std::to_string(w) + " lane " + std::to_string(c) + " padding outside its step range";
             return false;
           }
           if (f & hines::CF_POP) ok_b = m-- >= 1;
@@ -849,12 +866,14 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   const int64_t sz_cp = al((int64_t)CL.pos.size() * sizeof(uint16_t));
   const int64_t sz_cf = al((int64_t)CL.flags.size());
   const int64_t sz_cm = al((int64_t)CL.mbsrc.size() * sizeof(uint64_t));
+  const int64_t sz_cr = al((int64_t)CL.range.size() * sizeof(uint64_t));
+  const int64_t sz_cz = CL.built ? al(64 * 16) : 0;  // the step kernel's zero block
   const hines::ResPlan& RP = P.res;
   const int64_t sz_rg = al((int64_t)RP.groups.size() * sizeof(hines::KResGroup));
   const int64_t sz_rl = al((int64_t)p->res_list.size() * sizeof(int32_t));
   const int64_t sz_rb = al((int64_t)RP.blob.size());
   const int64_t total = sz_br + sz_grp + sz_seg + sz_cell + sz_gl + sz_ws + sz_fl + sz_fm + sz_fp + sz_fa + sz_cw +
-                        sz_cb + sz_cp + sz_cf + sz_cm + sz_rg + sz_rl + sz_rb + 256;
+                        sz_cb + sz_cp + sz_cf + sz_cm + sz_cr + sz_cz + sz_rg + sz_rl + sz_rb + 256;
   const int64_t scr_bytes = CL.nchunks * hines::kCellChunk * 64 * 16;
   hipError_t e = hipGetDevice(&p->device);
   if (e == hipSuccess) e = static_scratch_init(p->device);
@@ -938,6 +957,15 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   p->t.cmsrc = (const uint64_t*)(base + off);
   if (e == hipSuccess) e = up(CL.mbsrc.data(), (int64_t)CL.mbsrc.size() * sizeof(uint64_t), off);
   off += sz_cm;
+  p->t.crange = (const uint64_t*)(base + off);
+  if (e == hipSuccess) e = up(CL.range.data(), (int64_t)CL.range.size() * sizeof(uint64_t), off);
+  off += sz_cr;
+  p->t.czero = sz_cz ? (double*)(base + off) : nullptr;
+  if (e == hipSuccess && sz_cz) {
+    static const double zeros[128] = {};
+    e = up(zeros, sizeof(zeros), off);
+  }
+  off += sz_cz;
   p->t.rgrp = (const hines::KResGroup*)(base + off);
   if (e == hipSuccess) e = up(RP.groups.data(), (int64_t)RP.groups.size() * sizeof(hines::KResGroup), off);
   off += sz_rg;

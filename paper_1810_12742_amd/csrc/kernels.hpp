@@ -37,6 +37,9 @@ struct DevTables {
   const uint16_t* cpos;           // cell-lane kernel: positions, staging order
   const uint8_t* cflag;           // cell-lane kernel: flags, cell-lane order
   const uint64_t* cmsrc;          // cell-lane kernel: mailbox source lists per lane
+  const uint64_t* crange;         // cell-lane kernel: per lane the steps [q0, q1) that are not padding
+  double* czero;                  // cell-lane kernel: 1 KiB of zeros (64 lanes x 16 bytes), the stand-in
+                                  // for walk-layout pairs of padding steps (only zeros are stored to it)
   double* cscr;                   // cell-lane kernel: (f, y) per step and lane
   int64_t cslots;                 // cell-lane kernel: steps x lanes of all waves (walk-layout array length)
   const hines::KResGroup* rgrp;   // resident kernel: per group
@@ -1654,39 +1657,68 @@ struct StepChunk {
   CellPos p;  // kFlowNoise: positions of the lane's steps
 };
 
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt not waited for).  Issued once after
+// the per-lane lists are loaded at the step kernel's start: the loop then
+// updates them with plain ALU operations, and the compiler no longer counts
+// them as loads that may still be in flight (which made it wait for every
+// load in flight, the next chunk's included, at each mailbox take).
+constexpr int kWaitVm0 = 0x0f70;
+__device__ __forceinline__ void lists_settled() { __builtin_amdgcn_s_waitcnt(kWaitVm0); }
+
+// Pair q of chunk k (steps k CK + 2q and the next) holds a step of the lane's
+// walk [lo, hi).  A pair of padding steps reads and writes the lane's 16
+// bytes of the zero block instead of its walk slot: its operands are zeros
+// (the carry and the stack skip padding, and products of zeros and finite
+// values are zeros, so only zeros are written back), and a memory line of
+// such pairs is never fetched from HBM.  The choice is an address select,
+// not a branch, so that the loads of the next chunk stay in flight while
+// this one is swept.
+__device__ __forceinline__ bool pair_real(int k, int q, int lo, int hi) {
+  const int t = k * CK + 2 * q;
+  return t + 2 > lo && t < hi;
+}
+__device__ __forceinline__ const double2_t* pair_src(const double* a, int64_t o, bool real, const double2_t* zp) {
+  return real ? (const double2_t*)a + o : zp;
+}
+
 template <int RHS>
 __device__ __forceinline__ void step_load_b(StepChunk<RHS>& C, const CellLoop& L, const hines::KCellWave& W,
-                                            const cflag_t* flv, int k, int lane) {
+                                            const cflag_t* flv, int k, int lane, int lo, int hi,
+                                            const double2_t* zp) {
   C.fl = flag_ld(flv + 64 * k);
   if constexpr (RHS == kFlowNoise)
     C.p = pos_ld((const u32x4*)(L.lp + (W.chunk_off + k) * hines::kCellChunkElems) + (CK / 8) * lane);
 #pragma unroll
   for (int q = 0; q < CK / 2; ++q) {
     const int64_t o = walk_pair(W.chunk_off + k, q, lane);
-    C.f[q] = ((const double2_t*)L.f)[o];
-    C.r[q] = ((const double2_t*)L.r)[o];
-    C.c[q] = ((const double2_t*)L.c)[o];
-    if constexpr (RHS == kFlowCVI) C.i[q] = ((const double2_t*)L.ci)[o];
-    C.v[q] = ((const double2_t*)L.v)[o];
+    const bool real = pair_real(k, q, lo, hi);
+    C.f[q] = *pair_src(L.f, o, real, zp);
+    C.r[q] = *pair_src(L.r, o, real, zp);
+    C.c[q] = *pair_src(L.c, o, real, zp);
+    if constexpr (RHS == kFlowCVI) C.i[q] = *pair_src(L.ci, o, real, zp);
+    C.v[q] = *pair_src(L.v, o, real, zp);
   }
 }
 
 template <int RHS>
 __device__ __forceinline__ void step_load_f(StepChunk<RHS>& C, const CellLoop& L, const hines::KCellWave& W,
-                                            const cflag_t* flv, int k, int lane) {
+                                            const cflag_t* flv, int k, int lane, int lo, int hi,
+                                            const double2_t* zp) {
   C.fl = flag_ld(flv + 64 * k);
 #pragma unroll
   for (int q = 0; q < CK / 2; ++q) {
     const int64_t o = walk_pair(W.chunk_off + k, q, lane);
-    C.f[q] = ((const double2_t*)L.f)[o];
-    C.v[q] = ((const double2_t*)L.v)[o];  // y from the backward sweep
+    const bool real = pair_real(k, q, lo, hi);
+    C.f[q] = *pair_src(L.f, o, real, zp);
+    C.v[q] = *pair_src(L.v, o, real, zp);  // y from the backward sweep
   }
 }
 
 template <int RHS>
 __device__ __forceinline__ void step_backward(const StepChunk<RHS>& C, const CellLoop& L, const hines::KCellWave& W,
-                                              int k, int lane, int64_t base, lds_f64* stk, lds_f64* mb, double& cb,
-                                              double& tb, int& m, unsigned& msrc) {
+                                              int k, int lane, int lo, int hi, double2_t* zp, int64_t base,
+                                              lds_f64* stk, lds_f64* mb, double& cb, double& tb, int& m,
+                                              unsigned& msrc) {
   double y[CK];
 #pragma unroll
   for (int e = 0; e < CK; ++e) {
@@ -1717,14 +1749,17 @@ __device__ __forceinline__ void step_backward(const StepChunk<RHS>& C, const Cel
     }
     if (fe & hines::CF_MERGE) tb = tb + cb;
     if (fe & hines::CF_MBOUT) mb[lane] = cb;
-    if (e & 1) ((double2_t*)L.v)[walk_pair(W.chunk_off + k, e >> 1, lane)] = double2_t{y[e - 1], y[e]};
+    if (e & 1) {
+      const bool real = pair_real(k, e >> 1, lo, hi);
+      *(real ? (double2_t*)L.v + walk_pair(W.chunk_off + k, e >> 1, lane) : zp) = double2_t{y[e - 1], y[e]};
+    }
   }
 }
 
 template <int RHS>
 __device__ __forceinline__ void step_forward(const StepChunk<RHS>& C, const CellLoop& L, const hines::KCellWave& W,
-                                             int k, int lane, lds_f64* stk, lds_f64* mb, double& xc, double& xt,
-                                             int& m, unsigned& msrc) {
+                                             int k, int lane, int lo, int hi, double2_t* zp, lds_f64* stk,
+                                             lds_f64* mb, double& xc, double& xt, int& m, unsigned& msrc) {
   double x[CK];
 #pragma unroll
   for (int e = CK - 1; e >= 0; --e) {
@@ -1747,7 +1782,10 @@ __device__ __forceinline__ void step_forward(const StepChunk<RHS>& C, const Cell
     }
     xc = xv;
     x[e] = xv;
-    if (!(e & 1)) ((double2_t*)L.v)[walk_pair(W.chunk_off + k, e >> 1, lane)] = double2_t{x[e], x[e + 1]};
+    if (!(e & 1)) {
+      const bool real = pair_real(k, e >> 1, lo, hi);
+      *(real ? (double2_t*)L.v + walk_pair(W.chunk_off + k, e >> 1, lane) : zp) = double2_t{x[e], x[e + 1]};
+    }
   }
 }
 
@@ -1765,16 +1803,23 @@ __global__ __launch_bounds__(64) void k_cells_step(DevTables tb, CellLoop L) {
   StepChunk<RHS> A, B;
   const uint64_t ms = tb.cmsrc[(int64_t)blockIdx.x * 64 + lane];
   unsigned msb = (unsigned)ms, msf = (unsigned)(ms >> 32);
+  const uint64_t rg = tb.crange[(int64_t)blockIdx.x * 64 + lane];
+  const int lo = (int)(unsigned)rg, hi = (int)(unsigned)(rg >> 32);
+  double2_t* zp = (double2_t*)tb.czero + lane;
+  lists_settled();
   // backward: y = (b - contributions) / d', in place of V
   double cb = 0.0, tb_ = 0.0;
   int m = 0;
-  step_load_b<RHS>(A, L, W, flv, 0, lane);
+  // the next chunk is loaded unconditionally (past the end, the last chunk
+  // again, unused): loads under a branch would make the compiler wait for
+  // every load in flight where the branches join
+  step_load_b<RHS>(A, L, W, flv, 0, lane, lo, hi, zp);
   for (int k = 0;; k += 2) {
-    if (k + 1 < nk) step_load_b<RHS>(B, L, W, flv, k + 1, lane);
-    step_backward<RHS>(A, L, W, k, lane, base, stk, mb, cb, tb_, m, msb);
+    step_load_b<RHS>(B, L, W, flv, min(k + 1, nk - 1), lane, lo, hi, zp);
+    step_backward<RHS>(A, L, W, k, lane, lo, hi, zp, base, stk, mb, cb, tb_, m, msb);
     if (k + 1 >= nk) break;
-    if (k + 2 < nk) step_load_b<RHS>(A, L, W, flv, k + 2, lane);
-    step_backward<RHS>(B, L, W, k + 1, lane, base, stk, mb, cb, tb_, m, msb);
+    step_load_b<RHS>(A, L, W, flv, min(k + 2, nk - 1), lane, lo, hi, zp);
+    step_backward<RHS>(B, L, W, k + 1, lane, lo, hi, zp, base, stk, mb, cb, tb_, m, msb);
     if (k + 2 >= nk) break;
   }
   // the forward sweep reads back this wave's own stores
@@ -1782,13 +1827,13 @@ __global__ __launch_bounds__(64) void k_cells_step(DevTables tb, CellLoop L) {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   double xc = 0.0, xt = 0.0;
   m = 0;
-  step_load_f<RHS>(A, L, W, flv, nk - 1, lane);
+  step_load_f<RHS>(A, L, W, flv, nk - 1, lane, lo, hi, zp);
   for (int k = nk - 1;; k -= 2) {
-    if (k >= 1) step_load_f<RHS>(B, L, W, flv, k - 1, lane);
-    step_forward<RHS>(A, L, W, k, lane, stk, mb, xc, xt, m, msf);
+    step_load_f<RHS>(B, L, W, flv, max(k - 1, 0), lane, lo, hi, zp);
+    step_forward<RHS>(A, L, W, k, lane, lo, hi, zp, stk, mb, xc, xt, m, msf);
     if (k < 1) break;
-    if (k >= 2) step_load_f<RHS>(A, L, W, flv, k - 2, lane);
-    step_forward<RHS>(B, L, W, k - 1, lane, stk, mb, xc, xt, m, msf);
+    step_load_f<RHS>(A, L, W, flv, max(k - 2, 0), lane, lo, hi, zp);
+    step_forward<RHS>(B, L, W, k - 1, lane, lo, hi, zp, stk, mb, xc, xt, m, msf);
     if (k < 2) break;
   }
 }

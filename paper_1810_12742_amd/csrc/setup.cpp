@@ -1031,6 +1031,7 @@ int64_t export_table(const HostPlan& p, int32_t id, int64_t* out, int64_t capaci
     case T_CELL_POS: return put(p.cl.pos);
     case T_CELL_FLAGS: return put(p.cl.flags);
     case T_CELL_MBSRC: return put(p.cl.mbsrc);
+    case T_CELL_RANGE: return put(p.cl.range);
     case T_RES_GROUPS: {
       constexpr int64_t kF = 16;
       const int64_t cnt = kF * (int64_t)p.res.groups.size();

@@ -101,6 +101,7 @@ enum TableId : int32_t {
   T_CELL_MBSRC = 16,      // int64[nwaves*64]: mailbox source lanes (6 bits each), backward | forward << 32
   T_RES_GROUPS = 17,      // int64[ngroups*16]: lo, blob, nslot, ndma, first, count, nchunk, blob_units, nroot,
                           // npath, nlist, rec_off, list_off, cls, steps per chunk, nflip
+  T_CELL_RANGE = 18,      // int64[nwaves*64]: first step of the lane's walk | end step << 32 (padding outside)
   T_RES_BLOB = 19,        // int64[blob bytes / 2]: the blobs as uint16 words
   T_NUM = 20,
 };
@@ -161,6 +162,8 @@ struct CellLanes {
   std::vector<uint64_t> mbsrc;      // [nwaves*64] mailbox source lanes in the order the lane's
                                     // backward sweep takes them (6 bits each), and in the order
                                     // of its forward sweep << 32; 0 for lanes without takes
+  std::vector<uint64_t> range;      // [nwaves*64] steps [q0, q1) of the lane's walk: q0 | q1 << 32;
+                                    // every other step of the lane is padding (0 for empty lanes)
 };
 
 // Build the cell-lane tables.  parent / cell_offsets must already be valid.

@@ -19,7 +19,7 @@ TABLES = {
     "group_seg_offsets": 5, "seg_offsets": 6, "lanes": 7,
     "flow_groups": 8, "flow_masks": 9, "flow_pos": 10, "flow_aux": 11,
     "cell_waves": 12, "cell_lanes": 13, "cell_pos": 14, "cell_flags": 15, "cell_mbsrc": 16,
-    "res_groups": 17, "res_blob": 19,
+    "cell_range": 18, "res_groups": 17, "res_blob": 19,
 }
 STATUS = {0: "OK", 1: "NULL", 2: "BAD_OFFSETS", 3: "BAD_PARENT", 4: "BAD_BRANCHES",
           6: "NCELLS", 7: "OPTION", 8: "OOM", 9: "HIP", 10: "TOO_BIG", 11: "NOT_SDD", 12: "STATE"}

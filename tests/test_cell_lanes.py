@@ -50,6 +50,7 @@ def replay(plan, f, diag, upper, rhs):
     pos = plan.table("cell_pos").reshape(-1, 64, K)     # [chunk][j][r]
     flags = plan.table("cell_flags").reshape(-1, 64, K)  # [chunk][c][e]
     mbsrc = plan.table("cell_mbsrc").reshape(-1, 64).astype(np.uint64)
+    rng_ = plan.table("cell_range").reshape(-1, 64).astype(np.uint64)
     co = f.cell_offsets
     x = np.full(f.n, np.nan)
     seen_b = np.zeros(f.n, dtype=np.int64)
@@ -61,6 +62,12 @@ def replay(plan, f, diag, upper, rhs):
         cells = lane_cell[w]
         assert 1 <= ncell <= 64 and np.any(cells >= 0)
         base = np.where(cells >= 0, co[np.maximum(cells, 0)], 0)
+        # each lane's real steps are one run [q0, q1); the rest is padding
+        q0 = (rng_[w] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+        q1 = (rng_[w] >> np.uint64(32)).astype(np.int64)
+        steps = np.arange(nk * K)
+        lane_pad = (flags[off:off + nk].transpose(1, 0, 2).reshape(64, -1) & PAD) != 0
+        assert np.array_equal(lane_pad, (steps[None, :] < q0[:, None]) | (steps[None, :] >= q1[:, None]))
         mb = np.zeros((64, 2))
         msb = (mbsrc[w] & np.uint64(0xFFFFFFFF)).astype(np.int64)  # next take in the low 6 bits
         msf = (mbsrc[w] >> np.uint64(32)).astype(np.int64)

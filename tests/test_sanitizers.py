@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1810_12742_amd", "csrc")
 TABLES = ["node_plan", "branches", "u_src", "group_offsets", "group_cells", "group_seg_offsets", "seg_offsets",
           "lanes", "flow_groups", "flow_masks", "flow_pos", "flow_aux", "cell_waves", "cell_lanes", "cell_pos",
-          "cell_flags", "cell_mbsrc", "res_groups", None, "res_blob"]  # table id 18 is not used
+          "cell_flags", "cell_mbsrc", "res_groups", "cell_range", "res_blob"]
 
 
 @pytest.fixture(scope="module")
