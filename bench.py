@@ -76,6 +76,18 @@ def _traffic(n_launches_per_solve: int, path: str = TRAFFIC_FILE):
     return t.get("bytes_per_launch")
 
 
+def copy_calibration(torch, dev):
+    """A plain device copy of CALIB_BYTES (read and write), three times: the
+    reference kernel whose counter readings scale the HBM byte counters."""
+    src = torch.empty(CALIB_BYTES // 8, dtype=torch.float64, device=dev).uniform_()
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
@@ -279,13 +291,7 @@ def run_c2(args, torch, dev):
     ms = _time(torch, lambda: plan.solve(d, u, b, out=x, stream=stream), args.steps, args.warmup, stream)
 
     if args.copy_calibration:
-        src = torch.empty(CALIB_BYTES // 8, dtype=torch.float64, device=dev).uniform_()
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration(torch, dev)
 
     err = None
     if not args.no_check:
@@ -390,6 +396,8 @@ def run_c3(args, torch, dev):
     loop = plan.timeloop(d, u, c, V, K, first_step=1, noise_sigma=0.1, noise_seed=3)
     stream = torch.cuda.current_stream()
     ms = _time(torch, loop.launch, args.steps, args.warmup, stream)
+    if args.copy_calibration:
+        copy_calibration(torch, dev)
     assembled = None
     if plan.info["kernel"] == 3:
         # a step whose diagonal changes (linearised current g (V - E)): the
@@ -665,8 +673,8 @@ def main(argv=None):
     ap.add_argument("--no-forms", action="store_true", help="c2: skip the FP32+refinement measurement")
     ap.add_argument("--no-c3", action="store_true", help="c2: skip the time-loop (C3) summary on the same line")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="after the timed region, run a plain device copy of 512 MiB (read and write) three "
-                         "times, the reference kernel for scaling HBM byte counters")
+                    help="c2, c3: after the timed region, run a plain device copy of 512 MiB (read and write) "
+                         "three times, the reference kernel for scaling HBM byte counters")
     args = ap.parse_args(argv)
     if args.tune_cache is None:
         from paper_1810_12742_amd.autotune import SHIPPED_CACHE
