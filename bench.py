@@ -49,6 +49,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hines_solve_c2.json")
 TRAFFIC_FILE_C3 = os.path.join(ROOT, "profiles", "traffic_k_cells_step_c3.json")
 KERNEL_SRC_DIR = os.path.join(ROOT, "paper_1810_12742_amd", "csrc")
 C4_DTS = (0.001, 0.025, 1.0)
+# the time loop's plans: the group plan and the cell-lane cut knobs
+C3_CANDIDATES = [dict(max_group_unknowns=3000)] + [dict(cell_lanes=1, cell_cut_percent=cp, cell_max_cuts=mc)
+                                                   for cp in (60, 80, 110) for mc in (1, 3)]
 
 
 def _kernel_sha() -> str:
@@ -370,8 +373,7 @@ def run_c3(args, torch, dev):
         # the serial walk of its longest lanes on a small draw and by throughput
         # on the full one, while the group plans scale with the cell count
         vs = torch.zeros(f.n, dtype=torch.float64, device=dev)
-        cands = [dict(max_group_unknowns=3000)] + [dict(cell_lanes=1, cell_cut_percent=cp, cell_max_cuts=mc)
-                                                    for cp in (60, 80, 110) for mc in (1, 3)]
+        cands = C3_CANDIDATES
         best, tried = autotune(f.parent, f.cell_offsets, f.branch_offsets,
                                lambda p: p.timestep(d, u, c, vs, vs, noise_sigma=0.1, noise_seed=3),
                                candidates=cands, reps=2, cache_path=args.tune_cache, verbose=True)

@@ -134,14 +134,18 @@ def noise(seed: int, step: int, idx, scale: float):
 
 
 def timeloop(forest, diag, upper, c, steps: int, *, V0=None, I_const=None, noise_seed=None,
-             noise_sigma=0.0, first_step: int = 0, keep_all: bool = False, nthreads: int = 0):
+             noise_sigma=0.0, first_step: int = 0, keep_all: bool = False, nthreads: int = 0,
+             index=None):
     """Implicit-Euler steps V^{k+1} = A^-1 (c V^k + I^k) (paper §1, the discrete
     system with I evaluated at the old step).  I^k is ``I_const`` if given,
-    else ``noise_sigma * Z(noise_seed, k, i)``.  Returns V^steps (and the list
+    else ``noise_sigma * Z(noise_seed, k, i)`` with i the compartment's user
+    index: ``index[j]`` for compartment j when given (cells taken out of a
+    larger network keep their draws), else j.  Returns V^steps (and the list
     of all states when ``keep_all``)."""
     n = forest.n
     V = np.zeros(n) if V0 is None else np.array(V0, dtype=np.float64, copy=True)
-    idx = np.arange(n, dtype=np.int64)
+    idx = np.arange(n, dtype=np.int64) if index is None else np.ascontiguousarray(index, dtype=np.int64)
+    assert idx.shape == (n,)
     hist = [V.copy()] if keep_all else None
     for k in range(first_step, first_step + steps):
         if I_const is not None:

@@ -5,7 +5,9 @@
   20,000 compartments), against the oracle's time loop over the same 1,000
   steps (paper §1: one solve of the discrete system per step).  The oracle
   takes about a second per 100 steps at this size, so the subset is 64 cells
-  per class, not the full 200,000.
+  per class, not the full 200,000.  The full 200,000 cells run once more in
+  the bench's plan over 3 steps, and 128 of them are checked against the
+  oracle.
 * Config 5 (differentiation): the full 16,384 cells x 1,000 compartments over
   100 steps with checkpoints every 10; central differences (h = 1e-6) on 32
   parameters drawn with seed 5 from the edge conductances, capacitive terms
@@ -69,6 +71,50 @@ def test_c3_thousand_captured_steps_per_size_class():
     assert err <= 1e-12
     loop.close()
     p.close()
+
+
+def test_c3_full_configuration_sampled_cells():
+    """The full config-3 network (200,000 cells, 6.3e8 compartments) in the
+    launch configuration the bench times: the autotuner's shipped pick for it
+    and the kept-factor loop captured in one graph, here over 3 noise steps.
+    32 cells of every size class, spread over the network, are compared with
+    the oracle's time loop on those cells alone (cells are independent), the
+    draws keyed by the cells' user indices in the full network."""
+    import torch
+    import bench
+    from paper_1810_12742_amd import Plan
+    from paper_1810_12742_amd.autotune import SHIPPED_CACHE, cached_pick
+    dev = torch.device("cuda")
+    t0 = time.perf_counter()
+    s = configs.c3(configs.C3_CELLS)
+    f = s.forest
+    print(f"c3 full: {f.ncells} cells, {f.n} unknowns, generated in {time.perf_counter() - t0:.0f} s", flush=True)
+    opts = cached_pick(f.parent, f.cell_offsets, f.branch_offsets, candidates=bench.C3_CANDIDATES,
+                       cache_path=SHIPPED_CACHE)
+    print(f"plan options {opts}", flush=True)
+    assert opts is not None and opts.get("cell_lanes")
+    plan = Plan(f.parent, f.cell_offsets, f.branch_offsets, **opts)
+    d, u, c = (torch.from_numpy(a).to(dev) for a in (s.diag, s.upper, s.c))
+    V = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    steps = 3
+    loop = plan.timeloop(d, u, c, V, steps, first_step=0, noise_sigma=0.1, noise_seed=3)
+    loop.launch()
+    torch.cuda.synchronize()
+    sizes = np.diff(f.cell_offsets)
+    pick = []
+    for z in configs.C3_SIZES:
+        cls = np.flatnonzero(sizes == z)
+        pick.append(cls[np.linspace(0, cls.size - 1, 32).astype(np.int64)])
+    pick = np.unique(np.concatenate(pick))
+    idx = np.concatenate([np.arange(f.cell_offsets[q], f.cell_offsets[q + 1]) for q in pick])
+    got = V[torch.from_numpy(idx).to(dev)].cpu().numpy()
+    loop.close()
+    plan.close()
+    sub = f.subset(pick)
+    Vo = oracle.timeloop(sub, s.diag[idx], s.upper[idx], s.c[idx], steps, noise_seed=3, noise_sigma=0.1, index=idx)
+    err = cell_rel_err(sub, got, Vo)
+    print(f"{pick.size} sampled cells, {idx.size} unknowns: error {err:.2e}", flush=True)
+    assert err <= 1e-12
 
 
 def test_c5_central_differences_full_configuration():

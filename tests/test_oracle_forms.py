@@ -55,6 +55,26 @@ def test_timeloop_charge_conservation():
         V = Vn
 
 
+def test_timeloop_cells_out_of_a_network_keep_their_draws():
+    """Cells do not couple: the oracle's time loop over a few cells taken out
+    of a network, with the draws keyed by their user indices in it, gives the
+    full loop's values on those cells exactly; with the identity index it is
+    the plain loop."""
+    s = configs.c3(40)
+    f = s.forest
+    full = oracle.timeloop(f, s.diag, s.upper, s.c, 3, noise_seed=3, noise_sigma=0.1)
+    same = oracle.timeloop(f, s.diag, s.upper, s.c, 3, noise_seed=3, noise_sigma=0.1, index=np.arange(f.n))
+    assert np.array_equal(full, same)
+    pick = np.array([1, 5, 17, 30])
+    idx = np.concatenate([np.arange(f.cell_offsets[q], f.cell_offsets[q + 1]) for q in pick])
+    part = oracle.timeloop(f.subset(pick), s.diag[idx], s.upper[idx], s.c[idx], 3, noise_seed=3,
+                           noise_sigma=0.1, index=idx)
+    assert np.array_equal(part, full[idx])
+    # the draws are keyed: without the index the subset's values differ
+    plain = oracle.timeloop(f.subset(pick), s.diag[idx], s.upper[idx], s.c[idx], 3, noise_seed=3,
+                            noise_sigma=0.1)
+    assert not np.array_equal(plain, full[idx])
+
 @pytest.mark.parametrize("dt", [0.001, 0.025, 1.0])
 def test_refinement_reaches_fp64_solution(dt):
     s = configs.c4(dts=(dt,), ncells=256)[dt]
