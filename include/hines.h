@@ -206,7 +206,10 @@ void hines_default_options(hines_options* opt);
  *     rebalance_root is set.
  *   opt: NULL for defaults.
  * Host arrays are only read during the call.  The plan's device tables are
- * allocated on the current device.  On error *out is set to NULL. */
+ * allocated on the current device.  On error *out is set to NULL.
+ * The per-cell tables of cell-lane plans are built by host threads, as many
+ * as the environment variable HINES_SETUP_THREADS says, else one per host
+ * core (at most 16); the tables do not depend on the count. */
 hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch_offsets,
                          int64_t nbranches, const int64_t* cell_offsets, int32_t ncells,
                          const hines_options* opt, hines_plan** out);

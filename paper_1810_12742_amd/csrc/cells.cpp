@@ -26,7 +26,10 @@
 // compartments at every step from the root), up to kCellMaxCuts subtrees.
 
 #include <algorithm>
+#include <atomic>
+#include <cstdlib>
 #include <numeric>
+#include <thread>
 
 #include "setup.hpp"
 
@@ -170,174 +173,221 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
   const int64_t heavy_above = underfull ? cut_above : 2 * split_above;
   const int64_t target_floor = underfull ? cut_above : std::max(split_above, slot_steps);
 
-  CellTree T;
-  std::vector<int32_t> forced, need, pre, seen, st, depth, path, pick;
-  std::vector<uint8_t> fl, excl, onpath;
   // a group: the lanes of one cell, lanes[0] whole or P, then the S_i in the
   // order P's backward walk takes their contributions
   struct Group {
     int64_t span = 0;
     std::vector<LaneWork> lanes;
   };
-  std::vector<Group> groups;
+  std::vector<Group> groups(ncells);
   auto to_back = [](const std::vector<int32_t>& pre_, const std::vector<uint8_t>& fl_, LaneWork& w) {
     w.back.assign(pre_.rbegin(), pre_.rend());
     w.bfl.resize(w.back.size());
     for (size_t i = 0; i < w.back.size(); ++i) w.bfl[i] = fl_[w.back[i]];
   };
-  // span of cutting off the subtrees `vs` (receivers on one root path): P
-  // ends with the root and has receiver r at step span - 1 - depth(r)
-  auto cut_span = [&](int32_t m, const std::vector<int32_t>& vs, int32_t lo) {
-    int64_t rest = m, sp = 0;
-    for (int32_t v : vs) {
-      rest -= T.size[v];
-      sp = std::max<int64_t>(sp, (int64_t)T.size[v] + depth[parent[lo + v] - lo] + 1);
-    }
-    return std::max(rest, sp);
+  // the cells are planned independently, by several threads over blocks of
+  // cells; each result lands at its cell's index, so the tables do not
+  // depend on the thread count
+  struct RangeResult {
+    int32_t max_need = 0;
+    int64_t bad = -1;  // first cell whose walk needs too deep a stack
+    std::string err;
   };
-  // cut along the heavy path: for a target span t, per receiver the largest
-  // off-path child that fits, largest first, until the rest fits
-  auto heavy_cut = [&](int32_t m, int64_t t, std::vector<int32_t>& out) {
-    std::vector<std::pair<int32_t, int32_t>> cand;  // (size, child)
-    for (size_t i = 0; i + 1 < path.size(); ++i) {
-      const int32_t a = path[i];
-      int32_t best = -1;
-      for (int32_t k = T.ch_off[a]; k < T.ch_off[a + 1]; ++k) {
-        const int32_t c = T.ch[k];
-        if (onpath[c] || (int64_t)T.size[c] + depth[a] + 1 > t) continue;
-        if (best < 0 || T.size[c] > T.size[best]) best = c;
+  auto run_range = [&](int64_t c0, int64_t c1, RangeResult& R) {
+    CellTree T;
+    std::vector<int32_t> forced, need, pre, seen, st, depth, path, pick;
+    std::vector<uint8_t> fl, excl, onpath;
+    // span of cutting off the subtrees `vs` (receivers on one root path): P
+    // ends with the root and has receiver r at step span - 1 - depth(r)
+    auto cut_span = [&](int32_t m, const std::vector<int32_t>& vs, int32_t lo) {
+      int64_t rest = m, sp = 0;
+      for (int32_t v : vs) {
+        rest -= T.size[v];
+        sp = std::max<int64_t>(sp, (int64_t)T.size[v] + depth[parent[lo + v] - lo] + 1);
       }
-      if (best >= 0) cand.push_back({T.size[best], best});
-    }
-    std::sort(cand.begin(), cand.end(), [](auto x, auto y) { return x.first > y.first || (x.first == y.first && x.second < y.second); });
-    out.clear();
-    int64_t rest = m;
-    for (auto& cs : cand) {
-      if (rest <= t || (int)out.size() >= max_cuts) break;
-      out.push_back(cs.second);
-      rest -= cs.first;
-    }
-    return rest <= t;
-  };
-  for (int64_t c = 0; c < ncells; ++c) {
-    const int64_t lo = cell_offsets[c];
-    const int32_t m = (int32_t)size_of(c);
-    cell_tree(parent, lo, m, T);
-    forced.assign(m, -1);
-    need.assign(m, 0);
-    excl.assign(m, 0);
-    bool done = false;
-    if (m > cut_above) {
-      depth.assign(m, 0);
-      for (int32_t i = 1; i < m; ++i) depth[i] = depth[parent[lo + i] - lo] + 1;
-      // one cut: the subtree closest to m / 2 from below (at least a quarter)
-      // candidate cuts, preferred first: (subtree roots, span)
-      std::vector<std::pair<std::vector<int32_t>, int64_t>> cands;
-      int32_t v = -1;
-      for (int32_t i = 1; i < m; ++i)
-        if (2 * T.size[i] <= m && (v < 0 || T.size[i] > T.size[v])) v = i;
-      int64_t span = m;
-      if (v > 0 && 4 * T.size[v] >= m) {
-        cands.push_back({{v}, cut_span(m, {v}, (int32_t)lo)});
-        span = cands.back().second;
-      }
-      if (span > heavy_above) {  // still much longer than the average (or a slot's share): the heavy path
-        path.assign(1, 0);
-        onpath.assign(m, 0);
-        onpath[0] = 1;
-        for (;;) {
-          const int32_t a = path.back();
-          int32_t h = -1;
-          for (int32_t k = T.ch_off[a]; k < T.ch_off[a + 1]; ++k)
-            if (h < 0 || T.size[T.ch[k]] > T.size[h]) h = T.ch[k];
-          if (h < 0) break;
-          path.push_back(h);
-          onpath[h] = 1;
+      return std::max(rest, sp);
+    };
+    // cut along the heavy path: for a target span t, per receiver the largest
+    // off-path child that fits, largest first, until the rest fits
+    auto heavy_cut = [&](int32_t m, int64_t t, std::vector<int32_t>& out) {
+      std::vector<std::pair<int32_t, int32_t>> cand;  // (size, child)
+      for (size_t i = 0; i + 1 < path.size(); ++i) {
+        const int32_t a = path[i];
+        int32_t best = -1;
+        for (int32_t k = T.ch_off[a]; k < T.ch_off[a + 1]; ++k) {
+          const int32_t c = T.ch[k];
+          if (onpath[c] || (int64_t)T.size[c] + depth[a] + 1 > t) continue;
+          if (best < 0 || T.size[c] > T.size[best]) best = c;
         }
-        int64_t tl = std::max<int64_t>((m + max_cuts) / (max_cuts + 1), target_floor), th = span;
-        if (tl < th && heavy_cut(m, th - 1, pick)) {
-          while (tl < th) {  // smallest feasible target
-            const int64_t mid = (tl + th) / 2;
-            if (heavy_cut(m, mid, pick)) th = mid;
-            else tl = mid + 1;
+        if (best >= 0) cand.push_back({T.size[best], best});
+      }
+      std::sort(cand.begin(), cand.end(), [](auto x, auto y) { return x.first > y.first || (x.first == y.first && x.second < y.second); });
+      out.clear();
+      int64_t rest = m;
+      for (auto& cs : cand) {
+        if (rest <= t || (int)out.size() >= max_cuts) break;
+        out.push_back(cs.second);
+        rest -= cs.first;
+      }
+      return rest <= t;
+    };
+    for (int64_t c = c0; c < c1; ++c) {
+      const int64_t lo = cell_offsets[c];
+      const int32_t m = (int32_t)size_of(c);
+      cell_tree(parent, lo, m, T);
+      forced.assign(m, -1);
+      need.assign(m, 0);
+      excl.assign(m, 0);
+      bool done = false;
+      if (m > cut_above) {
+        depth.assign(m, 0);
+        for (int32_t i = 1; i < m; ++i) depth[i] = depth[parent[lo + i] - lo] + 1;
+        // one cut: the subtree closest to m / 2 from below (at least a quarter)
+        // candidate cuts, preferred first: (subtree roots, span)
+        std::vector<std::pair<std::vector<int32_t>, int64_t>> cands;
+        int32_t v = -1;
+        for (int32_t i = 1; i < m; ++i)
+          if (2 * T.size[i] <= m && (v < 0 || T.size[i] > T.size[v])) v = i;
+        int64_t span = m;
+        if (v > 0 && 4 * T.size[v] >= m) {
+          cands.push_back({{v}, cut_span(m, {v}, (int32_t)lo)});
+          span = cands.back().second;
+        }
+        if (span > heavy_above) {  // still much longer than the average (or a slot's share): the heavy path
+          path.assign(1, 0);
+          onpath.assign(m, 0);
+          onpath[0] = 1;
+          for (;;) {
+            const int32_t a = path.back();
+            int32_t h = -1;
+            for (int32_t k = T.ch_off[a]; k < T.ch_off[a + 1]; ++k)
+              if (h < 0 || T.size[T.ch[k]] > T.size[h]) h = T.ch[k];
+            if (h < 0) break;
+            path.push_back(h);
+            onpath[h] = 1;
           }
-          heavy_cut(m, th, pick);
-          if (!pick.empty() && cut_span(m, pick, (int32_t)lo) < span)
-            cands.insert(cands.begin(), {pick, cut_span(m, pick, (int32_t)lo)});
+          int64_t tl = std::max<int64_t>((m + max_cuts) / (max_cuts + 1), target_floor), th = span;
+          if (tl < th && heavy_cut(m, th - 1, pick)) {
+            while (tl < th) {  // smallest feasible target
+              const int64_t mid = (tl + th) / 2;
+              if (heavy_cut(m, mid, pick)) th = mid;
+              else tl = mid + 1;
+            }
+            heavy_cut(m, th, pick);
+            if (!pick.empty() && cut_span(m, pick, (int32_t)lo) < span)
+              cands.insert(cands.begin(), {pick, cut_span(m, pick, (int32_t)lo)});
+          }
+        }
+        // the first candidate whose walks fit the stack and keep every receiver in place
+        for (auto& cand : cands) {
+          if (done) break;
+          std::vector<int32_t> vs = cand.first;
+          span = cand.second;
+          // P's forced path: from the root to the deepest receiver; every receiver on it
+          int32_t deep = -1;
+          for (int32_t x : vs) {
+            const int32_t r = parent[lo + x] - (int32_t)lo;
+            if (deep < 0 || depth[r] > depth[deep]) deep = r;
+          }
+          for (int32_t a = deep; a != 0; a = parent[lo + a] - (int32_t)lo) forced[parent[lo + a] - lo] = a;
+          // S_i in the order P's backward walk meets their receivers: deepest first
+          std::sort(vs.begin(), vs.end(), [&](int32_t x, int32_t y) {
+            const int32_t dx = depth[parent[lo + x] - lo], dy = depth[parent[lo + y] - lo];
+            return dx > dy || (dx == dy && x < y);
+          });
+          Group g;
+          g.lanes.resize(1 + vs.size());
+          fl.assign(m, 0);
+          bool ok = true;
+          int32_t nd = 0;
+          for (size_t i = 0; i < vs.size(); ++i) {
+            pre.clear();
+            nd = std::max(nd, walk(T, vs[i], excl, forced, pre, fl, need, seen, st));
+            fl[vs[i]] |= CF_MBOUT;
+            LaneWork& S = g.lanes[1 + i];
+            S.cell = c;
+            S.pad_after = true;
+            to_back(pre, fl, S);
+            excl[vs[i]] = 1;
+          }
+          pre.clear();
+          nd = std::max(nd, walk(T, 0, excl, forced, pre, fl, need, seen, st));
+          for (size_t i = 0; i < vs.size(); ++i) {
+            const int32_t r = parent[lo + vs[i]] - (int32_t)lo;
+            fl[r] |= CF_MBIN;
+            ok = ok && pre.size() > (size_t)depth[r] && pre[depth[r]] == r;
+            ok = ok && (i == 0 || r != parent[lo + vs[i - 1]] - (int32_t)lo);  // one take per receiver
+          }
+          fl[0] |= CF_ROOT;
+          LaneWork& P = g.lanes[0];
+          P.cell = c;
+          to_back(pre, fl, P);
+          if (ok && nd <= kCellStack) {
+            R.max_need = std::max(R.max_need, nd);
+            g.span = span;
+            groups[c] = std::move(g);
+            done = true;
+          }
+          forced.assign(m, -1);
+          excl.assign(m, 0);
         }
       }
-      // the first candidate whose walks fit the stack and keep every receiver in place
-      for (auto& cand : cands) {
-        if (done) break;
-        std::vector<int32_t> vs = cand.first;
-        span = cand.second;
-        // P's forced path: from the root to the deepest receiver; every receiver on it
-        int32_t deep = -1;
-        for (int32_t x : vs) {
-          const int32_t r = parent[lo + x] - (int32_t)lo;
-          if (deep < 0 || depth[r] > depth[deep]) deep = r;
-        }
-        for (int32_t a = deep; a != 0; a = parent[lo + a] - (int32_t)lo) forced[parent[lo + a] - lo] = a;
-        // S_i in the order P's backward walk meets their receivers: deepest first
-        std::sort(vs.begin(), vs.end(), [&](int32_t x, int32_t y) {
-          const int32_t dx = depth[parent[lo + x] - lo], dy = depth[parent[lo + y] - lo];
-          return dx > dy || (dx == dy && x < y);
-        });
+      if (!done) {
         Group g;
-        g.lanes.resize(1 + vs.size());
+        g.lanes.resize(1);
+        LaneWork& W = g.lanes[0];
+        W.cell = c;
         fl.assign(m, 0);
-        bool ok = true;
-        int32_t nd = 0;
-        for (size_t i = 0; i < vs.size(); ++i) {
-          pre.clear();
-          nd = std::max(nd, walk(T, vs[i], excl, forced, pre, fl, need, seen, st));
-          fl[vs[i]] |= CF_MBOUT;
-          LaneWork& S = g.lanes[1 + i];
-          S.cell = c;
-          S.pad_after = true;
-          to_back(pre, fl, S);
-          excl[vs[i]] = 1;
-        }
         pre.clear();
-        nd = std::max(nd, walk(T, 0, excl, forced, pre, fl, need, seen, st));
-        for (size_t i = 0; i < vs.size(); ++i) {
-          const int32_t r = parent[lo + vs[i]] - (int32_t)lo;
-          fl[r] |= CF_MBIN;
-          ok = ok && pre.size() > (size_t)depth[r] && pre[depth[r]] == r;
-          ok = ok && (i == 0 || r != parent[lo + vs[i - 1]] - (int32_t)lo);  // one take per receiver
+        const int32_t nd = walk(T, 0, excl, forced, pre, fl, need, seen, st);
+        if (nd > kCellStack) {
+          R.bad = c;
+          R.err = "cell " + std::to_string(c) + " needs " + std::to_string(nd) +
+                  " contribution stack entries; the cell-lane kernel holds " + std::to_string(kCellStack);
+          return;
         }
         fl[0] |= CF_ROOT;
-        LaneWork& P = g.lanes[0];
-        P.cell = c;
-        to_back(pre, fl, P);
-        if (ok && nd <= kCellStack) {
-          out.max_need = std::max(out.max_need, nd);
-          g.span = span;
-          groups.push_back(std::move(g));
-          done = true;
-        }
-        forced.assign(m, -1);
-        excl.assign(m, 0);
+        R.max_need = std::max(R.max_need, nd);
+        to_back(pre, fl, W);
+        g.span = (int64_t)W.back.size();
+        groups[c] = std::move(g);
       }
     }
-    if (!done) {
-      Group g;
-      g.lanes.resize(1);
-      LaneWork& W = g.lanes[0];
-      W.cell = c;
-      fl.assign(m, 0);
-      pre.clear();
-      const int32_t nd = walk(T, 0, excl, forced, pre, fl, need, seen, st);
-      if (nd > kCellStack) {
-        err = "cell " + std::to_string(c) + " needs " + std::to_string(nd) +
-              " contribution stack entries; the cell-lane kernel holds " + std::to_string(kCellStack);
-        return ERR_TOO_BIG;
+  };
+  {
+    constexpr int64_t kBlock = 256;
+    const int64_t nblocks = (ncells + kBlock - 1) / kBlock;
+    // threads: HINES_SETUP_THREADS if set, else the host's cores, at most 16
+    int64_t want = std::thread::hardware_concurrency();
+    if (const char* env = std::getenv("HINES_SETUP_THREADS")) want = std::atoll(env);
+    const int nth = (int)std::max<int64_t>(1, std::min<int64_t>({want, 16, nblocks}));
+    std::atomic<int64_t> next{0};
+    std::vector<RangeResult> res(nth);
+    auto worker = [&](int t) {
+      for (;;) {
+        const int64_t b = next.fetch_add(1);
+        if (b >= nblocks) break;
+        RangeResult r;
+        run_range(b * kBlock, std::min(ncells, (b + 1) * kBlock), r);
+        res[t].max_need = std::max(res[t].max_need, r.max_need);
+        if (r.bad >= 0 && (res[t].bad < 0 || r.bad < res[t].bad)) {
+          res[t].bad = r.bad;
+          res[t].err = r.err;
+        }
       }
-      fl[0] |= CF_ROOT;
-      out.max_need = std::max(out.max_need, nd);
-      to_back(pre, fl, W);
-      g.span = (int64_t)W.back.size();
-      groups.push_back(std::move(g));
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nth; ++t) pool.emplace_back(worker, t);
+    worker(0);
+    for (auto& th : pool) th.join();
+    const RangeResult* first = nullptr;  // the lowest failing cell, whatever the thread count
+    for (const RangeResult& r : res) {
+      out.max_need = std::max(out.max_need, r.max_need);
+      if (r.bad >= 0 && (!first || r.bad < first->bad)) first = &r;
+    }
+    if (first) {
+      err = first->err;
+      return ERR_TOO_BIG;
     }
   }
   // waves: groups of the same lane count, longest first.  A wave holds 64

@@ -423,3 +423,30 @@ def test_small_networks_are_cut_to_fill_the_lanes():
     lanes = p.table("cell_lanes")
     assert np.count_nonzero(lanes >= 0) >= 2 * f.ncells
     assert p.info["max_makespan"] * chunk_steps(p) < 1000
+
+
+def test_tables_do_not_depend_on_the_setup_threads():
+    """The cell-lane tables are built over blocks of cells by host threads;
+    one thread and several give the same tables bit for bit."""
+    import os
+    import subprocess
+    import sys
+    code = (
+        "import hashlib, sys\n"
+        "from workloads import configs\n"
+        "from paper_1810_12742_amd import Plan\n"
+        "s = configs.c3(600, seed=4)\n"
+        "f = s.forest\n"
+        "p = Plan(f.parent, f.cell_offsets, f.branch_offsets, host_only=1, cell_lanes=1)\n"
+        "h = hashlib.sha256()\n"
+        "for k in ('cell_waves', 'cell_lanes', 'cell_pos', 'cell_flags', 'cell_mbsrc', 'cell_range'):\n"
+        "    h.update(p.table(k).tobytes())\n"
+        "print(h.hexdigest())\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = []
+    for nth in ("1", "5"):
+        env = dict(os.environ, HINES_SETUP_THREADS=nth, PYTHONPATH=root)
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=root)
+        assert r.returncode == 0, r.stderr
+        out.append(r.stdout.strip())
+    assert out[0] == out[1]
