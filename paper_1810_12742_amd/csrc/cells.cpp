@@ -28,7 +28,9 @@
 #include <algorithm>
 #include <atomic>
 #include <cstdlib>
+#include <new>
 #include <numeric>
+#include <system_error>
 #include <thread>
 
 #include "setup.hpp"
@@ -363,23 +365,32 @@ Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_of
     const int nth = (int)std::max<int64_t>(1, std::min<int64_t>({want, 16, nblocks}));
     std::atomic<int64_t> next{0};
     std::vector<RangeResult> res(nth);
+    std::atomic<bool> oom{false};  // a worker ran out of memory: raised again in this thread
     auto worker = [&](int t) {
-      for (;;) {
-        const int64_t b = next.fetch_add(1);
-        if (b >= nblocks) break;
-        RangeResult r;
-        run_range(b * kBlock, std::min(ncells, (b + 1) * kBlock), r);
-        res[t].max_need = std::max(res[t].max_need, r.max_need);
-        if (r.bad >= 0 && (res[t].bad < 0 || r.bad < res[t].bad)) {
-          res[t].bad = r.bad;
-          res[t].err = r.err;
+      try {
+        for (;;) {
+          const int64_t b = next.fetch_add(1);
+          if (b >= nblocks) break;
+          RangeResult r;
+          run_range(b * kBlock, std::min(ncells, (b + 1) * kBlock), r);
+          res[t].max_need = std::max(res[t].max_need, r.max_need);
+          if (r.bad >= 0 && (res[t].bad < 0 || r.bad < res[t].bad)) {
+            res[t].bad = r.bad;
+            res[t].err = r.err;
+          }
         }
+      } catch (const std::bad_alloc&) {
+        oom = true;
       }
     };
     std::vector<std::thread> pool;
-    for (int t = 1; t < nth; ++t) pool.emplace_back(worker, t);
+    try {
+      for (int t = 1; t < nth; ++t) pool.emplace_back(worker, t);
+    } catch (const std::system_error&) {  // no more threads: the ones started and this one finish the work
+    }
     worker(0);
     for (auto& th : pool) th.join();
+    if (oom) throw std::bad_alloc();
     const RangeResult* first = nullptr;  // the lowest failing cell, whatever the thread count
     for (const RangeResult& r : res) {
       out.max_need = std::max(out.max_need, r.max_need);

@@ -721,26 +721,34 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   hines_plan* p = new (std::nothrow) hines_plan();
   if (!p) return set_err(HINES_ERR_OOM, "host allocation failed");
   std::string why;
-  hines::Status s = hines::build_plan(parent, n, branch_offsets, nbranches, cell_offsets, ncells, o, p->host, why);
-  if (s != hines::OK) {
+  // the host tables can take tens of GB for the largest networks: running
+  // out of host memory is a status, not an exception through the C ABI
+  try {
+    hines::Status s = hines::build_plan(parent, n, branch_offsets, nbranches, cell_offsets, ncells, o, p->host, why);
+    if (s != hines::OK) {
+      delete p;
+      return set_err((hines_status)s, "%s", why.c_str());
+    }
+    if (o.cell_lanes) {
+      s = hines::build_cell_lanes(parent, n, cell_offsets, ncells, p->host.cl, why, o.cell_cut_percent,
+                                  o.cell_max_cuts);
+      if (s == hines::OK && !check_cell_tables(p->host, cell_offsets, why)) s = hines::ERR_STATE;
+      if (s != hines::OK) {
+        delete p;
+        return set_err((hines_status)s, "cell lanes: %s", why.c_str());
+      }
+    }
+    if (o.resident) {
+      s = hines::build_resident(parent, n, cell_offsets, ncells, p->host.res, why, o.res_pack, o.rebalance_root);
+      if (s == hines::OK && !hines::check_resident(p->host.res, parent, n, why)) s = hines::ERR_STATE;
+      if (s != hines::OK) {
+        delete p;
+        return set_err((hines_status)s, "resident: %s", why.c_str());
+      }
+    }
+  } catch (const std::bad_alloc&) {
     delete p;
-    return set_err((hines_status)s, "%s", why.c_str());
-  }
-  if (o.cell_lanes) {
-    s = hines::build_cell_lanes(parent, n, cell_offsets, ncells, p->host.cl, why, o.cell_cut_percent, o.cell_max_cuts);
-    if (s == hines::OK && !check_cell_tables(p->host, cell_offsets, why)) s = hines::ERR_STATE;
-    if (s != hines::OK) {
-      delete p;
-      return set_err((hines_status)s, "cell lanes: %s", why.c_str());
-    }
-  }
-  if (o.resident) {
-    s = hines::build_resident(parent, n, cell_offsets, ncells, p->host.res, why, o.res_pack, o.rebalance_root);
-    if (s == hines::OK && !hines::check_resident(p->host.res, parent, n, why)) s = hines::ERR_STATE;
-    if (s != hines::OK) {
-      delete p;
-      return set_err((hines_status)s, "resident: %s", why.c_str());
-    }
+    return set_err(HINES_ERR_OOM, "host memory exhausted while building the plan tables");
   }
   bool capacity = false;
   bool groups_usable = true;

@@ -450,3 +450,36 @@ def test_tables_do_not_depend_on_the_setup_threads():
         assert r.returncode == 0, r.stderr
         out.append(r.stdout.strip())
     assert out[0] == out[1]
+
+
+def test_host_out_of_memory_is_a_status():
+    """Setup that runs out of host memory (forced with a data-size limit in a
+    child process) returns HINES_ERR_OOM through the C ABI instead of
+    aborting, for the group tables and the threaded cell-lane tables; with
+    the limit lifted the same process builds the plan."""
+    import os
+    import subprocess
+    import sys
+    code = (
+        "import resource\n"
+        "from workloads import configs\n"
+        "import paper_1810_12742_amd.hines as H\n"
+        "from paper_1810_12742_amd import Plan, HinesError\n"
+        "f = configs.c2(8192).forest\n"
+        "H.load()\n"
+        "cur = [int(l.split()[1]) * 1024 for l in open('/proc/self/status') if l.startswith('VmData:')][0]\n"
+        "soft, hard = resource.getrlimit(resource.RLIMIT_DATA)\n"
+        "for opts in ({}, {'cell_lanes': 1}):\n"
+        "    resource.setrlimit(resource.RLIMIT_DATA, (cur + (64 << 20), hard))\n"
+        "    try:\n"
+        "        Plan(f.parent, f.cell_offsets, f.branch_offsets, host_only=1, **opts)\n"
+        "        print('built')\n"
+        "    except HinesError as e:\n"
+        "        print(e.code)\n"
+        "    resource.setrlimit(resource.RLIMIT_DATA, (soft, hard))\n"
+        "print(Plan(f.parent, f.cell_offsets, f.branch_offsets, host_only=1, cell_lanes=1).info['kernel'])\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=root,
+                       env=dict(os.environ, PYTHONPATH=root), timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.split() == ["OOM", "OOM", "3"]
