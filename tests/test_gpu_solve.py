@@ -110,12 +110,12 @@ def test_c2_full_bench_configuration(torch_dev):
         assert cell_rel_err(f, x, xo) <= TOL
     # the layout-resident solve the bench line reports beside it, on the same
     # plan: the same elimination, bit for bit
-    import torch
     from paper_1810_12742_amd import Plan
+    torch, dev = torch_dev
     opts = pick or CELL_CANDIDATES[0]
     if opts.get("cell_lanes"):
         p = Plan(f.parent, f.cell_offsets, f.branch_offsets, **opts)
-        d, u, b = (torch.from_numpy(a).to(torch_dev) for a in (s.diag, s.upper, s.rhs))
+        d, u, b = (torch.from_numpy(a).to(dev) for a in (s.diag, s.upper, s.rhs))
         xs = p.solve(d, u, b).cpu().numpy()
         dl, ul, bl = p.to_layout(d), p.to_layout(u), p.to_layout(b)
         xl = p.from_layout(p.solve_layout(dl, ul, bl)).cpu().numpy()
