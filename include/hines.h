@@ -50,7 +50,9 @@ typedef enum hines_status {
      several branches each, so no width is ever refused */
   HINES_ERR_NCELLS = 6,        /* ncells differs from the plan's */
   HINES_ERR_OPTION = 7,        /* an option value is out of range */
-  HINES_ERR_OOM = 8,           /* host or device allocation failed */
+  HINES_ERR_OOM = 8,           /* host or device allocation failed; the environment variable
+                                  HINES_DEVICE_BYTE_CAP (bytes) caps the device memory the
+                                  library holds, so that this path can be forced */
   HINES_ERR_HIP = 9,           /* a HIP runtime call or kernel launch failed */
   HINES_ERR_TOO_BIG = 10,      /* a group does not fit the device's LDS */
   HINES_ERR_NOT_SDD = 11,      /* hines_check_matrix: a row is not strictly diagonally dominant */

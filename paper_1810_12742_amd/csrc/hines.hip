@@ -25,8 +25,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -111,7 +113,8 @@ struct hines_plan {
   int device = -1;
   void* dev_mem = nullptr;
   void* scr_mem = nullptr;  // cell-lane kernel: (f, y) scratch
-  int64_t dev_bytes = 0;
+  int64_t dev_bytes = 0;    // dev_mem and scr_mem together
+  int64_t scr_bytes = 0;
   DevTables t{};
   struct Bucket {
     int32_t lds_bytes, first, count, global;
@@ -143,6 +146,7 @@ struct hines_plan {
   std::vector<int32_t> parent_host;
   std::vector<int64_t> cell_off_host;
   void* adj_mem = nullptr;
+  int64_t adj_bytes = 0;
   const int32_t* d_parent = nullptr;
   const int32_t* d_ch_off = nullptr;
   const int32_t* d_ch = nullptr;
@@ -155,9 +159,40 @@ struct hines_timeloop {
   hipGraphExec_t exec = nullptr;
   int32_t nsteps = 0;
   void* mem = nullptr;  // cell-lane plans: factors and walk-layout arrays of the loop
+  int64_t bytes = 0;
 };
 
 namespace {
+
+// Device bytes the library holds, and a cap on them: HINES_DEVICE_BYTE_CAP
+// (unset: no cap).  A request past the cap fails as if the device were full,
+// so that the out-of-memory paths can be exercised on any GPU.
+std::atomic<int64_t> g_dev_bytes{0};
+
+int64_t device_byte_cap() {
+  static const int64_t cap = [] {
+    const char* e = std::getenv("HINES_DEVICE_BYTE_CAP");
+    return e ? std::atoll(e) : (int64_t)-1;
+  }();
+  return cap;
+}
+
+hipError_t dev_alloc(void** ptr, int64_t bytes) {
+  const int64_t cap = device_byte_cap();
+  if (cap >= 0 && g_dev_bytes.load() + bytes > cap) {
+    *ptr = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  const hipError_t e = hipMalloc(ptr, (size_t)bytes);
+  if (e == hipSuccess) g_dev_bytes += bytes;
+  return e;
+}
+
+hipError_t dev_free(void* ptr, int64_t bytes) {
+  const hipError_t e = hipFree(ptr);
+  if (e == hipSuccess) g_dev_bytes -= bytes;
+  return e;
+}
 
 template <int T, int MODE>
 void launch_level(const DevTables& t, const hines_plan::Bucket& bk, const RhsSpec& rs, const double* d,
@@ -639,7 +674,8 @@ hines_status ensure_adjoint_tables(hines_plan* p) {
   const int64_t sp = al(4 * std::max<int64_t>(n, 1)), so = al(4 * (n + 1)), sc = al(4 * std::max<int64_t>(n, 1)),
                 sf = al(8 * (int64_t)p->cell_off_host.size());
   void* mem = nullptr;
-  hipError_t e = hipMalloc(&mem, sp + so + sc + sf + 256);
+  const int64_t bytes = sp + so + sc + sf + 256;
+  hipError_t e = dev_alloc(&mem, bytes);
   if (e != hipSuccess) return set_err(HINES_ERR_OOM, "element-wise tables: %s", hipGetErrorString(e));
   char* b = (char*)mem;
   if (n > 0) e = hipMemcpy(b, par.data(), 4 * n, hipMemcpyHostToDevice);
@@ -648,10 +684,11 @@ hines_status ensure_adjoint_tables(hines_plan* p) {
   if (e == hipSuccess)
     e = hipMemcpy(b + sp + so + sc, p->cell_off_host.data(), 8 * p->cell_off_host.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
-    hipFree(mem);
+    dev_free(mem, bytes);
     return set_err(HINES_ERR_HIP, "element-wise table upload: %s", hipGetErrorString(e));
   }
   p->adj_mem = mem;
+  p->adj_bytes = bytes;
   p->d_parent = (const int32_t*)b;
   p->d_ch_off = (const int32_t*)(b + sp);
   p->d_ch = (const int32_t*)(b + sp + so);
@@ -898,23 +935,24 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
     delete p;
     return set_err(HINES_ERR_HIP, "device setup: %s", hipGetErrorString(e));
   }
-  e = hipMalloc(&p->dev_mem, total);
+  e = dev_alloc(&p->dev_mem, total);
   if (e != hipSuccess) {
     p->dev_mem = nullptr;
     delete p;
-    return set_err(HINES_ERR_OOM, "hipMalloc(%lld): %s", (long long)total, hipGetErrorString(e));
+    return set_err(HINES_ERR_OOM, "device allocation of %lld bytes: %s", (long long)total, hipGetErrorString(e));
   }
   if (scr_bytes > 0) {
-    e = hipMalloc(&p->scr_mem, scr_bytes);
+    e = dev_alloc(&p->scr_mem, scr_bytes);
     if (e != hipSuccess) {
       p->scr_mem = nullptr;
-      hipFree(p->dev_mem);
+      dev_free(p->dev_mem, total);
       delete p;
-      return set_err(HINES_ERR_OOM, "hipMalloc(%lld) for the cell-lane scratch: %s", (long long)scr_bytes,
+      return set_err(HINES_ERR_OOM, "device allocation of %lld bytes for the cell-lane scratch: %s", (long long)scr_bytes,
                      hipGetErrorString(e));
     }
   }
   p->dev_bytes = total + scr_bytes;
+  p->scr_bytes = scr_bytes;
   char* base = (char*)p->dev_mem;
   auto up = [&](const void* src, int64_t bytes, int64_t slot) -> hipError_t {
     if (bytes == 0) return hipSuccess;
@@ -986,8 +1024,8 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   p->t.cscr = (double*)p->scr_mem;
   p->t.cslots = CL.nchunks * hines::kCellChunk * 64;
   if (e != hipSuccess) {
-    if (p->scr_mem) hipFree(p->scr_mem);
-    hipFree(p->dev_mem);
+    if (p->scr_mem) dev_free(p->scr_mem, scr_bytes);
+    dev_free(p->dev_mem, total);
     delete p;
     return set_err(HINES_ERR_HIP, "table upload: %s", hipGetErrorString(e));
   }
@@ -1152,10 +1190,12 @@ hines_status hines_timeloop_create(const hines_plan* p, const double* diag, cons
     const int64_t S = p->t.cslots;
     // f, 1 / d', c, the current, V; positions for the draws
     const int64_t bytes = 8 * S * (i_inj ? 5 : 4) + (noise ? 2 * S : 0) + 256;
-    if (hipMalloc(&tl->mem, bytes) != hipSuccess) {
+    if (dev_alloc(&tl->mem, bytes) != hipSuccess) {
       (void)hipGetLastError();  // no room for the factors: capture the plain steps instead
       tl->mem = nullptr;
       factored = false;
+    } else {
+      tl->bytes = bytes;
     }
   }
   if (factored) {
@@ -1217,7 +1257,7 @@ hines_status hines_timeloop_create(const hines_plan* p, const double* diag, cons
   if (e != hipSuccess) {
     if (tl->exec) hipGraphExecDestroy(tl->exec);
     if (tl->graph) hipGraphDestroy(tl->graph);
-    if (tl->mem) hipFree(tl->mem);
+    if (tl->mem) dev_free(tl->mem, tl->bytes);
     delete tl;
     return set_err(HINES_ERR_HIP, "time loop capture: %s", hipGetErrorString(e));
   }
@@ -1243,7 +1283,7 @@ hines_status hines_timeloop_destroy(hines_timeloop* tl) {
     if (e == hipSuccess) e = e2;
   }
   if (tl->mem) {
-    hipError_t e2 = hipFree(tl->mem);  // waits for the device
+    hipError_t e2 = dev_free(tl->mem, tl->bytes);  // waits for the device
     if (e == hipSuccess) e = e2;
   }
   delete tl;
@@ -1437,9 +1477,9 @@ hines_status hines_destroy(hines_plan* p) {
     hipGetDevice(&prev);
     if (prev != p->device) hipSetDevice(p->device);
     hipError_t e = hipDeviceSynchronize();
-    if (e == hipSuccess && p->dev_mem) e = hipFree(p->dev_mem);
-    if (e == hipSuccess && p->scr_mem) e = hipFree(p->scr_mem);
-    if (e == hipSuccess && p->adj_mem) e = hipFree(p->adj_mem);
+    if (e == hipSuccess && p->dev_mem) e = dev_free(p->dev_mem, p->dev_bytes - p->scr_bytes);
+    if (e == hipSuccess && p->scr_mem) e = dev_free(p->scr_mem, p->scr_bytes);
+    if (e == hipSuccess && p->adj_mem) e = dev_free(p->adj_mem, p->adj_bytes);
     if (e != hipSuccess) st = set_err(HINES_ERR_HIP, "destroy: %s", hipGetErrorString(e));
     if (prev != p->device && prev >= 0) hipSetDevice(prev);
   }

@@ -294,3 +294,63 @@ def test_autotune_over_whole_cell_kernel_knobs(torch_dev, tmp_path):
         torch.cuda.synchronize()
         assert cell_rel_err(f, x.cpu().numpy(), xo) <= 1e-12, opts
         p.close()
+
+
+def test_device_byte_cap_forces_the_out_of_memory_paths(tmp_path):
+    """HINES_DEVICE_BYTE_CAP makes the library's device allocations fail past
+    a cap, as on a full device: a plan that does not fit returns
+    HINES_ERR_OOM, and a time loop whose kept factors do not fit falls back
+    to captured plain steps, which give the factored loop's result bit for
+    bit (and the oracle's within 1e-12).  Each cap runs in a child process
+    (the library reads it once)."""
+    import os
+    import subprocess
+    import sys
+    import torch
+    from paper_1810_12742_amd import Plan
+    s = configs.c3(300, seed=5)
+    f = s.forest
+    dev = torch.device("cuda")
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets, cell_lanes=1)
+    table_bytes = p.info["device_table_bytes"]
+    d, u, c = (torch.from_numpy(a).to(dev) for a in (s.diag, s.upper, s.c))
+    V = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    loop = p.timeloop(d, u, c, V, 4, noise_sigma=0.1, noise_seed=3)
+    loop.launch()
+    torch.cuda.synchronize()
+    want = V.cpu().numpy()
+    loop.close()
+    p.close()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys, numpy as np, torch\n"
+        "from workloads import configs\n"
+        "from paper_1810_12742_amd import Plan, HinesError\n"
+        "s = configs.c3(300, seed=5)\n"
+        "f = s.forest\n"
+        "dev = torch.device('cuda')\n"
+        "try:\n"
+        "    p = Plan(f.parent, f.cell_offsets, f.branch_offsets, cell_lanes=1)\n"
+        "except HinesError as e:\n"
+        "    print(e.code)\n"
+        "    sys.exit(0)\n"
+        "d, u, c = (torch.from_numpy(a).to(dev) for a in (s.diag, s.upper, s.c))\n"
+        "V = torch.zeros(f.n, dtype=torch.float64, device=dev)\n"
+        "loop = p.timeloop(d, u, c, V, 4, noise_sigma=0.1, noise_seed=3)\n"
+        "loop.launch()\n"
+        "torch.cuda.synchronize()\n"
+        "np.save(sys.argv[1], V.cpu().numpy())\n"
+        "print('looped')\n")
+    out = str(tmp_path / "v.npy")
+    for cap, expect in ((1 << 20, "OOM"), (table_bytes + (1 << 20), "looped")):
+        env = dict(os.environ, HINES_DEVICE_BYTE_CAP=str(cap), PYTHONPATH=root)
+        print(f"cap {cap}: expect {expect}", flush=True)
+        r = subprocess.run([sys.executable, "-c", code, out], capture_output=True, text=True, env=env, cwd=root,
+                           timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        assert r.stdout.split()[-1] == expect
+    got = np.load(out)
+    assert np.array_equal(got, want)
+    Vo = oracle.timeloop(f, s.diag, s.upper, s.c, 4, noise_seed=3, noise_sigma=0.1)
+    err = np.max(np.abs(got - Vo)) / np.max(np.abs(Vo))
+    assert err <= 1e-12
