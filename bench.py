@@ -10,7 +10,8 @@ bytes per compartment).  The same line carries the FP32-storage + FP64
 refinement form on the same cells at dt in {0.001, 0.025, 1.0}, the
 layout-resident solve, the small single-solve case (4,096 cells of 75
 compartments), the oracle timed on the host's cores, and (key ``c3``, unless
-``--no-c3``) the batched time loop below with the autotuner's cached pick.
+``--no-c3``) the batched time loop below with the autotuner's cached pick, 1,000
+steps per captured graph.
 
 Other workloads (``--workload``): ``c3`` the batched implicit-Euler time loop
 (200,000 cells of 50/500/5,000/20,000 compartments, noise current, K steps per
@@ -699,10 +700,11 @@ def main(argv=None):
 
 
 def c3_summary(args, torch, dev):
-    """The batched time loop (200,000 cells, 100 steps per captured graph) beside
-    the C2 line: the autotuner's cached pick, 3 timed graph launches."""
+    """The batched time loop as the configuration states it (200,000 cells,
+    1,000 implicit-Euler steps captured in one graph) beside the C2 line: the
+    autotuner's cached pick, one untimed and 2 timed graph launches."""
     a = argparse.Namespace(**vars(args))
-    a.steps, a.warmup, a.graph_steps, a.options, a.cells = 3, 1, 100, "", 0
+    a.steps, a.warmup, a.graph_steps, a.options, a.cells = 2, 1, 1000, "", 0
     try:
         r = run_c3(a, torch, dev)
     except Exception as e:  # the C2 line stands on its own
