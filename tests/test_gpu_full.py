@@ -79,7 +79,9 @@ def test_c3_full_configuration_sampled_cells():
     and the kept-factor loop captured in one graph, here over 3 noise steps.
     32 cells of every size class, spread over the network, are compared with
     the oracle's time loop on those cells alone (cells are independent), the
-    draws keyed by the cells' user indices in the full network."""
+    draws keyed by the cells' user indices in the full network.  One step with
+    the matrix assembled inside the solve follows, on the same plan, checked
+    the same way."""
     import torch
     import bench
     from paper_1810_12742_amd import Plan
@@ -107,14 +109,30 @@ def test_c3_full_configuration_sampled_cells():
         pick.append(cls[np.linspace(0, cls.size - 1, 32).astype(np.int64)])
     pick = np.unique(np.concatenate(pick))
     idx = np.concatenate([np.arange(f.cell_offsets[q], f.cell_offsets[q + 1]) for q in pick])
-    got = V[torch.from_numpy(idx).to(dev)].cpu().numpy()
+    tidx = torch.from_numpy(idx).to(dev)
+    got = V[tidx].cpu().numpy()
     loop.close()
+    # one step with the matrix assembled inside the solve (diagonal c + g +
+    # incident edge conductances), which the bench times beside the loop,
+    # from the loop's state
+    rng = np.random.default_rng(5)
+    g = rng.uniform(0.0, 1.0, f.n)
+    ge = -65.0 * rng.uniform(0.0, 1.0, f.n)
+    G, GE = torch.from_numpy(g).to(dev), torch.from_numpy(ge).to(dev)
+    plan.timestep_assembled(G, u, c, GE, V, V)
+    torch.cuda.synchronize()
+    got_a = V[tidx].cpu().numpy()
     plan.close()
+    del G, GE, V, d, u, c
     sub = f.subset(pick)
     Vo = oracle.timeloop(sub, s.diag[idx], s.upper[idx], s.c[idx], steps, noise_seed=3, noise_sigma=0.1, index=idx)
     err = cell_rel_err(sub, got, Vo)
     print(f"{pick.size} sampled cells, {idx.size} unknowns: error {err:.2e}", flush=True)
     assert err <= 1e-12
+    Va = oracle.timestep_assembled(sub, s.upper[idx], s.c[idx], g[idx], ge[idx], got)
+    err_a = cell_rel_err(sub, got_a, Va)
+    print(f"assembled step on the sampled cells: error {err_a:.2e}", flush=True)
+    assert err_a <= 1e-12
 
 
 def test_c5_central_differences_full_configuration():
