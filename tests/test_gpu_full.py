@@ -8,6 +8,8 @@
   per class, not the full 200,000.  The full 200,000 cells run once more in
   the bench's plan over 3 steps, and 128 of them are checked against the
   oracle.
+* Config 4 (precision): the full C2 cells at dt = 1.0 on the bench's plan,
+  FP32 sweep 0 and 3 refinement sweeps against the oracle.
 * Config 5 (differentiation): the full 16,384 cells x 1,000 compartments over
   100 steps with checkpoints every 10; central differences (h = 1e-6) on 32
   parameters drawn with seed 5 from the edge conductances, capacitive terms
@@ -133,6 +135,40 @@ def test_c3_full_configuration_sampled_cells():
     err_a = cell_rel_err(sub, got_a, Va)
     print(f"assembled step on the sampled cells: error {err_a:.2e}", flush=True)
     assert err_a <= 1e-12
+
+
+def test_c4_full_configuration_refinement():
+    """Config 4 at full size (the 65,536 C2 cells, dt = 1.0, the least
+    dominant case) on the plan the bench times: FP32 storage and elimination,
+    FP64 residual and accumulation, 3 sweeps.  Sweep 0 against the oracle's
+    FP32 solve of the same system (rounding only: within 4x the oracle's own
+    distance from the FP64 solution), 3 sweeps within 1e-11 of the oracle's
+    FP64 solve of the FP32-stored matrix."""
+    import torch
+    from paper_1810_12742_amd import Plan
+    from paper_1810_12742_amd.autotune import CELL_CANDIDATES, SHIPPED_CACHE, cached_pick
+    dev = torch.device("cuda")
+    s = configs.c4(dts=(1.0,))[1.0]
+    f = s.forest
+    d32 = s.diag.astype(np.float32)
+    u32 = s.upper.astype(np.float32)
+    xs = oracle.solve(f, d32.astype(np.float64), u32.astype(np.float64), s.rhs)
+    its = oracle.refine(f, d32, u32, s.rhs, sweeps=0)
+    e_o32 = cell_rel_err(f, its[0], xs)
+    opts = cached_pick(f.parent, f.cell_offsets, f.branch_offsets, candidates=CELL_CANDIDATES,
+                       cache_path=SHIPPED_CACHE) or {}
+    print(f"c4 full: {f.ncells} cells, {f.n} unknowns, plan {opts}", flush=True)
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets, **opts)
+    D, U, B = (torch.from_numpy(a).to(dev) for a in (d32, u32, s.rhs))
+    x0 = p.solve_mixed(D, U, B, sweeps=0).cpu().numpy()
+    x3 = p.solve_mixed(D, U, B, sweeps=3).cpu().numpy()
+    p.close()
+    e0 = cell_rel_err(f, x0, its[0])
+    e3 = cell_rel_err(f, x3, xs)
+    print(f"sweep 0 against the oracle's FP32 solve {e0:.2e} (oracle FP32 vs FP64 {e_o32:.2e}); "
+          f"3 sweeps {e3:.2e}", flush=True)
+    assert e0 <= 4.0 * e_o32 + 1e-7
+    assert e3 <= 1e-11
 
 
 def test_c5_central_differences_full_configuration():
