@@ -323,8 +323,8 @@ def run_c2(args, torch, dev):
             "workload": "c2: 65,536 random dendritic cells, 16-256 branches, geometric(12) branch "
                         "lengths, dt=0.025, one FP64 solve per step",
             "ncells": f.ncells, "unknowns": n, "groups": info["ngroups"], "launches_per_step": launches,
-            "kernel": {4: "LDS-resident", 3: "cell lanes", 1: "flow", 2: "bitwise"}.get(info["kernel"],
-                                                                                         "level-synchronous"),
+            "kernel": {5: "index-order cell lanes", 4: "LDS-resident", 3: "cell lanes", 1: "flow",
+                       2: "bitwise"}.get(info["kernel"], "level-synchronous"),
             "options": opts, "setup_s": round(setup_s, 3),
             "autotune_ms": [[o, round(t, 4)] for o, t in tried],
         },
@@ -335,17 +335,28 @@ def run_c2(args, torch, dev):
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": _traffic(launches),
-            "kernel": {4: "k_solve_res", 3: "k_solve_cells", 1: "k_solve_flow"}.get(info["kernel"], "k_solve_level"),
+            "kernel": {5: "k_solve_seq", 4: "k_solve_res", 3: "k_solve_cells",
+                       1: "k_solve_flow"}.get(info["kernel"], "k_solve_level"),
             "bytes_per_launch": bytes_per_solve / launches,
             "avg_launch_us": ms * 1e3 / launches,
         },
         "max_rel_err_vs_oracle": err,
     }
-    if not args.no_forms and info["kernel"] == 3:
-        out["layout_resident"] = layout_resident(args, torch, plan, s, d, u, b, x, stream)
     if not args.no_forms:
+        # the solver layout and the FP32-stored matrix are forms of the
+        # depth-first cell-lane plan: when the pick is another kernel, they
+        # run on the fastest depth-first cell-lane candidate the tuner timed
+        fplan = plan
+        if info["kernel"] != 3:
+            dfs = [(o, t) for o, t in tried if o.get("cell_lanes") == 1]
+            fopts = min(dfs, key=lambda r: r[1])[0] if dfs else dict(cell_lanes=1)
+            fplan = Plan(f.parent, f.cell_offsets, f.branch_offsets, **fopts)
+            out["forms_options"] = fopts
+        out["layout_resident"] = layout_resident(args, torch, fplan, s, d, u, b, x, stream)
         del d, u
-        out["fp32_refine"] = fp32_refine(torch, dev, plan, s, ms, max(3, args.steps // 2), not args.no_check)
+        out["fp32_refine"] = fp32_refine(torch, dev, fplan, s, ms, max(3, args.steps // 2), not args.no_check)
+        if fplan is not plan:
+            fplan.close()
     plan.close()
     if not args.no_forms:
         out["c1"] = run_c1(torch, dev)

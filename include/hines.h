@@ -87,7 +87,18 @@ typedef struct hines_options {
                                  device scratch of 16 bytes per step owned by the plan).  Needs
                                  bitwise 0, cells of at most 65535 compartments and a stack need
                                  of at most 12 (HINES_ERR_TOO_BIG otherwise).  hines_solve_mixed
-                                 keeps using the groups.  0 (default): groups (§3-§4)        */
+                                 keeps using the groups.
+                                 2: hines_solve runs index-order cell lanes: the same solver,
+                                 but each lane eliminates its piece of a cell in decreasing
+                                 user index (children first by §2's numbering), so that a
+                                 cell numbered level by level is read in long runs of whole
+                                 memory lines; contributions to a parent that is not the next
+                                 step wait in up to 26 LDS slots per lane (a lane that would
+                                 need more walks depth-first); a cell longer than
+                                 cell_cut_percent of the mean is cut once.  Runs start on
+                                 128-byte lines when the arrays do.  The other forms
+                                 (timestep, time loop, noalloc, layout, FP32) are refused or
+                                 run on the groups.  0 (default): groups (§3-§4)             */
   int32_t resident;           /* 1: hines_solve runs the LDS-resident kernel: consecutive whole
                                  cells form a group of up to 1400 compartments (a larger cell is
                                  a group of its own; see res_pack); one wave stages the group's
@@ -123,7 +134,7 @@ typedef struct hines_plan_info {
   int64_t device_table_bytes; /* device memory held by the plan */
   int64_t max_group_lds_bytes;
   int32_t kernel;             /* 0 level-synchronous, 1 flow (static step schedule), 2 bitwise,
-                                 3 cell lanes, 4 LDS-resident                                 */
+                                 3 cell lanes, 4 LDS-resident, 5 index-order cell lanes       */
   int32_t max_makespan;       /* flow plans: longest schedule, in chunk steps; cell-lane plans:
                                  chunks per sweep of the longest wave; resident plans: steps
                                  per sweep of the longest group                              */
@@ -180,7 +191,7 @@ enum {
   HINES_TABLE_CELL_RANGE = 18,      /* [nwaves*64] per lane: the steps q0 .. q1 - 1 of its walk
                                         (bits 0-31: q0, bits 32-63: q1); every other step of
                                         the lane is padding; 0 for empty lanes                */
-  HINES_TABLE_RES_BLOB = 19          /* [blob bytes / 2] the group blobs as 16-bit words: per lane
+  HINES_TABLE_RES_BLOB = 19,         /* [blob bytes / 2] the group blobs as 16-bit words: per lane
                                         its first record and its first slot-list entry (65 + 65
                                         words, 136 in all), the root slots padded to 8 words,
                                         the re-rooting pairs (slot, slot whose staged u becomes
@@ -191,6 +202,20 @@ enum {
                                         0xffff, 0), then per lane one entry per active chunk:
                                         the byte offsets (slot * 8) of its steps, the path's
                                         bottom first (padding steps point at the zero entry) */
+  /* Index-order cell-lane plans (hines_plan_info.kernel == 5), chunks of K = 8 steps.       */
+  HINES_TABLE_SEQ_WAVES = 20,        /* [nwaves*3] first chunk, chunks, cells                  */
+  HINES_TABLE_SEQ_LANES = 21,        /* [nwaves*64] cell of each lane (-1: empty); a cut cell
+                                        holds lanes c (the rest) and c + 1 (the subtree)      */
+  HINES_TABLE_SEQ_POS = 22,          /* [chunks*K*64] as HINES_TABLE_CELL_POS with K = 8       */
+  HINES_TABLE_SEQ_CODE = 23,         /* [chunks*K*64] per chunk, lane c, element e: bits 0-4 the
+                                        slot the step's contribution goes into (0: the next
+                                        step takes it), bits 5-9 the slot the step reads (its
+                                        other children's contributions; 0: none), 1024 no
+                                        carry from the previous step, 2048 padding, 4096 root
+                                        of the cut-off subtree (mailbox c), 8192 its parent
+                                        (takes the mailbox of the source lane), 16384 first
+                                        contribution into its slot, 32768 the cell root       */
+  HINES_TABLE_SEQ_MBSRC = 24         /* [nwaves*64] as HINES_TABLE_CELL_MBSRC                  */
 };
 
 /* Fill *opt with the defaults: no re-rooting, no splitting, group_width 64,

@@ -30,13 +30,14 @@ DEFAULT_CANDIDATES = [
 ] + [dict(cell_lanes=1)]
 
 # Candidates for large networks of whole-cell kernels: the one-lane-per-cell
-# kernel with its cut threshold (percent of the mean cell) and the number of
-# lanes a long cell may be cut into, and the LDS-resident kernel with its
-# packing target (compartments per group), with or without re-rooting the
-# cells at their centres (paper §6).
+# kernel (depth-first walks, and index-order walks) with its cut threshold
+# (percent of the mean cell) and the number of lanes a long cell may be cut
+# into, and the LDS-resident kernel with its packing target (compartments per
+# group), with or without re-rooting the cells at their centres (paper §6).
 CELL_CANDIDATES = [
     dict(cell_lanes=1, cell_cut_percent=cp, cell_max_cuts=mc) for cp in (60, 80, 110) for mc in (1, 3)
-] + [dict(resident=1, res_pack=rp, rebalance_root=rr) for rp in (1400, 3000) for rr in (0, 1)]
+] + [dict(cell_lanes=2, cell_cut_percent=cp, cell_max_cuts=3) for cp in (80, 100, 130)
+     ] + [dict(resident=1, res_pack=rp, rebalance_root=rr) for rp in (1400, 3000) for rr in (0, 1)]
 
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "hines_mi355x_autotune.json")
 # Picks measured on one MI355X for the benchmark workloads, shipped with the

@@ -292,6 +292,10 @@ hipError_t launch_resident(const hines_plan* p, const double* d, const double* u
 hipError_t launch_solve(const hines_plan* p, const RhsSpec& rs, const double* d, const double* u, double* x,
                         hipStream_t s) {
   if (p->host.res.built && rs.mode == hdev::kRhsGiven) return launch_resident(p, d, u, rs.rhs, x, s);
+  if (p->host.sq.built) {
+    hipLaunchKernelGGL(hdev::k_solve_seq, dim3((unsigned)p->host.sq.nwaves), dim3(64), 0, s, p->t, d, u, rs.rhs, x);
+    return hipGetLastError();
+  }
   if (p->host.cl.built) {
     const dim3 grid((unsigned)p->host.cl.nwaves);
     if (rs.mode == hdev::kRhsGiven)
@@ -652,6 +656,8 @@ hines_status check_call(const hines_plan* p, int32_t ncells) {
 
 hines_status run_solve(const hines_plan* p, const RhsSpec& rs, const double* diag, const double* upper, double* x,
                        void* stream) {
+  if (p->host.sq.built && rs.mode != hdev::kRhsGiven)
+    return set_err(HINES_ERR_STATE, "index-order cell lanes (cell_lanes 2) serve hines_solve only");
   hipError_t e = launch_solve(p, rs, diag, upper, x, (hipStream_t)stream);
   if (e != hipSuccess) return set_err(HINES_ERR_HIP, "launch: %s", hipGetErrorString(e));
   return ok();
@@ -734,6 +740,7 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   if (opt.cell_cut_percent < 0 || opt.cell_max_cuts < 0 || opt.cell_max_cuts > hines::kCellMaxCuts ||
       opt.res_pack < 0 || opt.res_pack > hines::kResMaxSlots)
     return set_err(HINES_ERR_OPTION, "tuning option out of range");
+  if (opt.cell_lanes < 0 || opt.cell_lanes > 2) return set_err(HINES_ERR_OPTION, "cell_lanes must be 0, 1 or 2");
   if (opt.cell_lanes && opt.bitwise)
     return set_err(HINES_ERR_OPTION, "cell_lanes needs the fast arithmetic form (bitwise 0)");
   if (opt.resident && (opt.bitwise || opt.cell_lanes))
@@ -749,12 +756,13 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   o.keep_tables = opt.keep_tables != 0;
   o.bitwise = opt.bitwise != 0;
   o.scheduler = opt.level_sync ? 0 : 1;
-  o.cell_lanes = opt.cell_lanes != 0;
+  o.cell_lanes = opt.cell_lanes == 1;
+  o.cell_seq = opt.cell_lanes == 2;
   o.resident = opt.resident != 0;
   if (opt.cell_cut_percent > 0) o.cell_cut_percent = opt.cell_cut_percent;
   if (opt.cell_max_cuts > 0) o.cell_max_cuts = opt.cell_max_cuts;
   if (opt.res_pack > 0) o.res_pack = opt.res_pack;
-  if (o.cell_lanes) o.scheduler = 0;  // the groups serve hines_solve_mixed only
+  if (o.cell_lanes || o.cell_seq) o.scheduler = 0;  // the groups serve the other forms only
   hines_plan* p = new (std::nothrow) hines_plan();
   if (!p) return set_err(HINES_ERR_OOM, "host allocation failed");
   std::string why;
@@ -775,6 +783,16 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
         return set_err((hines_status)s, "cell lanes: %s", why.c_str());
       }
     }
+    if (o.cell_seq) {
+      s = hines::build_seq_lanes(parent, n, cell_offsets, ncells, p->host.sq, why, o.cell_cut_percent,
+                                 o.cell_max_cuts);
+      if (s == hines::OK && !hines::check_seq_lanes(p->host.sq, parent, n, cell_offsets, ncells, why))
+        s = hines::ERR_STATE;
+      if (s != hines::OK) {
+        delete p;
+        return set_err((hines_status)s, "index-order cell lanes: %s", why.c_str());
+      }
+    }
     if (o.resident) {
       s = hines::build_resident(parent, n, cell_offsets, ncells, p->host.res, why, o.res_pack, o.rebalance_root);
       if (s == hines::OK && !hines::check_resident(p->host.res, parent, n, why)) s = hines::ERR_STATE;
@@ -790,7 +808,7 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   bool capacity = false;
   bool groups_usable = true;
   if (!o.host_only && !check_kernel_tables(p->host, why, capacity)) {
-    if (o.cell_lanes && capacity) {
+    if ((o.cell_lanes || o.cell_seq) && capacity) {
       // the cell-lane kernels never read the group tables; only the groups'
       // FP32+refinement solve needs them, and it is refused on this plan
       groups_usable = false;
@@ -913,13 +931,20 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
   const int64_t sz_cm = al((int64_t)CL.mbsrc.size() * sizeof(uint64_t));
   const int64_t sz_cr = al((int64_t)CL.range.size() * sizeof(uint64_t));
   const int64_t sz_cz = CL.built ? al(64 * 16) : 0;  // the step kernel's zero block
+  const hines::SeqLanes& SQ = P.sq;
+  const int64_t sz_sw = al((int64_t)SQ.waves.size() * sizeof(hines::KCellWave));
+  const int64_t sz_sb = al((int64_t)SQ.base.size() * sizeof(int64_t));
+  const int64_t sz_sp = al((int64_t)SQ.pos.size() * sizeof(uint16_t));
+  const int64_t sz_sc = al((int64_t)SQ.code.size() * sizeof(uint16_t));
+  const int64_t sz_sm = al((int64_t)SQ.mbsrc.size() * sizeof(uint64_t));
   const hines::ResPlan& RP = P.res;
   const int64_t sz_rg = al((int64_t)RP.groups.size() * sizeof(hines::KResGroup));
   const int64_t sz_rl = al((int64_t)p->res_list.size() * sizeof(int32_t));
   const int64_t sz_rb = al((int64_t)RP.blob.size());
   const int64_t total = sz_br + sz_grp + sz_seg + sz_cell + sz_gl + sz_ws + sz_fl + sz_fm + sz_fp + sz_fa + sz_cw +
-                        sz_cb + sz_cp + sz_cf + sz_cm + sz_cr + sz_cz + sz_rg + sz_rl + sz_rb + 256;
-  const int64_t scr_bytes = CL.nchunks * hines::kCellChunk * 64 * 16;
+                        sz_cb + sz_cp + sz_cf + sz_cm + sz_cr + sz_cz + sz_sw + sz_sb + sz_sp + sz_sc + sz_sm +
+                        sz_rg + sz_rl + sz_rb + 256;
+  const int64_t scr_bytes = CL.nchunks * hines::kCellChunk * 64 * 16 + SQ.nchunks * hines::kSeqChunk * 64 * 16;
   hipError_t e = hipGetDevice(&p->device);
   if (e == hipSuccess) e = static_scratch_init(p->device);
   if (e == hipSuccess) e = allow_lds(o.group_width);
@@ -1012,6 +1037,21 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
     e = up(zeros, sizeof(zeros), off);
   }
   off += sz_cz;
+  p->t.swave = (const hines::KCellWave*)(base + off);
+  if (e == hipSuccess) e = up(SQ.waves.data(), (int64_t)SQ.waves.size() * sizeof(hines::KCellWave), off);
+  off += sz_sw;
+  p->t.sbase = (const int64_t*)(base + off);
+  if (e == hipSuccess) e = up(SQ.base.data(), (int64_t)SQ.base.size() * sizeof(int64_t), off);
+  off += sz_sb;
+  p->t.spos = (const uint16_t*)(base + off);
+  if (e == hipSuccess) e = up(SQ.pos.data(), (int64_t)SQ.pos.size() * sizeof(uint16_t), off);
+  off += sz_sp;
+  p->t.scode = (const uint16_t*)(base + off);
+  if (e == hipSuccess) e = up(SQ.code.data(), (int64_t)SQ.code.size() * sizeof(uint16_t), off);
+  off += sz_sc;
+  p->t.smsrc = (const uint64_t*)(base + off);
+  if (e == hipSuccess) e = up(SQ.mbsrc.data(), (int64_t)SQ.mbsrc.size() * sizeof(uint64_t), off);
+  off += sz_sm;
   p->t.rgrp = (const hines::KResGroup*)(base + off);
   if (e == hipSuccess) e = up(RP.groups.data(), (int64_t)RP.groups.size() * sizeof(hines::KResGroup), off);
   off += sz_rg;
@@ -1037,6 +1077,8 @@ hines_status hines_setup(const int32_t* parent, int64_t n, const int64_t* branch
     std::vector<int16_t>().swap(p->host.faux);
     std::vector<uint16_t>().swap(p->host.cl.pos);
     std::vector<uint8_t>().swap(p->host.cl.flags);
+    std::vector<uint16_t>().swap(p->host.sq.pos);
+    std::vector<uint16_t>().swap(p->host.sq.code);
   }
   *out = p;
   return ok();
@@ -1437,8 +1479,11 @@ hines_status hines_plan_info_get(const hines_plan* p, hines_plan_info* info) {
   info->nclasses = nb;
   info->device_table_bytes = p->dev_bytes;
   info->max_group_lds_bytes = p->max_lds;
-  info->kernel = p->host.res.built ? 4 : p->host.cl.built ? 3 : (p->host.flow ? 1 : (p->host.opt.bitwise ? 2 : 0));
-  if (p->host.cl.built) info->nclasses = 1;
+  info->kernel = p->host.sq.built ? 5
+                 : p->host.res.built ? 4
+                 : p->host.cl.built ? 3
+                                    : (p->host.flow ? 1 : (p->host.opt.bitwise ? 2 : 0));
+  if (p->host.cl.built || p->host.sq.built) info->nclasses = 1;
   if (p->host.res.built) info->nclasses = (int32_t)p->res_buckets.size();
   int32_t mk = 0;
   int64_t ng_ws = 0;
@@ -1448,6 +1493,8 @@ hines_status hines_plan_info_get(const hines_plan* p, hines_plan_info* info) {
   }
   if (p->host.cl.built)
     for (const auto& W : p->host.cl.waves) mk = std::max(mk, W.nchunk);
+  if (p->host.sq.built)
+    for (const auto& W : p->host.sq.waves) mk = std::max(mk, W.nchunk);
   if (p->host.res.built) {
     mk = 0;
     for (const auto& G : p->host.res.groups) mk = std::max(mk, G.nchunk * hines::kResK);

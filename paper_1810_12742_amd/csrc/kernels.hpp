@@ -40,8 +40,13 @@ struct DevTables {
   const uint64_t* crange;         // cell-lane kernel: per lane the steps [q0, q1) that are not padding
   double* czero;                  // cell-lane kernel: 1 KiB of zeros (64 lanes x 16 bytes), the stand-in
                                   // for walk-layout pairs of padding steps (only zeros are stored to it)
-  double* cscr;                   // cell-lane kernel: (f, y) per step and lane
+  double* cscr;                   // cell-lane kernels: (f, y) per step and lane
   int64_t cslots;                 // cell-lane kernel: steps x lanes of all waves (walk-layout array length)
+  const hines::KCellWave* swave;  // index-order cell lanes: per wave
+  const int64_t* sbase;           // index-order cell lanes: first user index of each lane's cell
+  const uint16_t* spos;           // index-order cell lanes: positions, staging order
+  const uint16_t* scode;          // index-order cell lanes: step codes, cell-lane order
+  const uint64_t* smsrc;          // index-order cell lanes: mailbox source lists per lane
   const hines::KResGroup* rgrp;   // resident kernel: per group
   const int32_t* rlist;           // resident kernel: group ids of one launch
   const uint8_t* rblob;           // resident kernel: per-group lane offsets, roots and path records
@@ -1225,6 +1230,234 @@ __global__ __launch_bounds__(64) void k_solve_cells(DevTables tb, RhsSpec rs, co
     }
     cell_forward(fb_, PB, fb, pb, xrd, stx, mb, lane, xc, xt, m, x, base, msf);
     if (k < 2) break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Index-order cell lanes: the cell-lane solve with each lane walking its piece
+// of a cell in decreasing user index (children before parents by the
+// numbering of paper §2), kSeqChunk = 8 steps per chunk, so that a cell
+// numbered level by level is gathered in long runs of whole lines.  The gather
+// and the LDS planes are those of the cell-lane kernel at 8 steps (8 lanes read
+// one 64-byte run of a lane's walk).  A contribution whose parent is not the
+// next step is written or added into an LDS slot of the lane named by the
+// step code, and the parent reads the slot; in the forward sweep the parent
+// writes its x into that slot for the same children.  A cut-off subtree's root
+// leaves through its lane's mailbox, as in the cell-lane kernel.
+// ---------------------------------------------------------------------------
+constexpr int SK = hines::kSeqChunk;
+constexpr int SG = hines::kSeqSlotCells;
+constexpr int kSeqRowDU = 64 * 16 + 256 / SK;  // the padding rule of the cell-lane planes
+constexpr int kSeqRowB = 64 * 8 + 256 / SK;
+constexpr int kSeqLdsB = SK * kSeqRowDU;
+constexpr int kSeqLdsSlot = kSeqLdsB + SK * kSeqRowB;
+constexpr int kSeqLdsMail = kSeqLdsSlot + hines::kSeqSlots * 64 * 16;
+constexpr int kSeqLds = kSeqLdsMail + 64 * 16;
+static_assert(SK == 8, "one 16-byte table word per lane and chunk");
+static_assert(4 * kSeqLds <= 160 * 1024, "four waves per compute unit");
+
+// 16-bit field r of a lane's 16-byte table word (positions or codes)
+__device__ __forceinline__ unsigned seq_field(const u32x4& v, int r) { return (v[r >> 1] >> (16 * (r & 1))) & 0xffffu; }
+
+__device__ __forceinline__ void seq_load(double* dv, double* uv, double* bv, const double* __restrict__ d,
+                                         const double* __restrict__ u, const double* __restrict__ b,
+                                         const int64_t* base, const u32x4& P) {
+#pragma unroll
+  for (int r = 0; r < SK; ++r) {
+    const unsigned p = seq_field(P, r);
+    const int64_t i = base[r] + (p == hines::kCellPadPos ? 0u : p);
+    dv[r] = d[i];
+    uv[r] = u[i];
+    bv[r] = b[i];
+  }
+}
+
+// Into the LDS planes (the lane that eliminates an element zeroes its coupling
+// when the step code marks padding or the cell root).
+__device__ __forceinline__ void seq_put(const double* dv, const double* uv, const double* bv, lds_char* lds,
+                                        int lane) {
+  const int e = lane % SK;
+#pragma unroll
+  for (int r = 0; r < SK; ++r) {
+    const int c = SG * r + lane / SK;
+    *(lds_d2*)(lds + e * kSeqRowDU + c * 16) = double2_t{dv[r], uv[r]};
+    *(lds_f64*)(lds + kSeqLdsB + e * kSeqRowB + c * 8) = bv[r];
+  }
+}
+
+// Backward elimination of one chunk; (f, y) per step into fy.  slot: the
+// lane's slot 1 at slot[0], slot s at slot[64 (s - 1)].
+__device__ __forceinline__ void seq_backward(const u32x4& cw, const lds_d2* pdu, const lds_f64* pb, lds_d2* slot,
+                                             lds_d2* mb, int lane, double& cd, double& cb, double2_t* fy,
+                                             unsigned& msrc) {
+#pragma unroll
+  for (int e = 0; e < SK; ++e) {
+    const unsigned q = seq_field(cw, e);
+    const double2_t du = pdu[e * (kSeqRowDU / 16)];
+    double dd = du.x, bb = pb[e * (kSeqRowB / 8)];
+    // padding (d and b of the cell's first compartment) and the cell root have no coupling
+    const double uu = (q & (hines::SQ_PAD | hines::SQ_ROOT)) ? 0.0 : du.y;
+    const double kc = (q & hines::SQ_TIP) ? 0.0 : 1.0;  // the previous step is this one's child
+    dd = __builtin_fma(-kc, cd, dd);
+    bb = __builtin_fma(-kc, cb, bb);
+    if (q & hines::SQ_MBIN) {  // a cut-off subtree's contribution, posted at an earlier step
+      const double2_t mv = mb[msrc & 63u];
+      msrc >>= 6;
+      dd = dd - mv.x;
+      bb = bb - mv.y;
+    }
+    const unsigned rs = (q >> hines::SQ_READ_SHIFT) & hines::SQ_SLOT;
+    if (rs) {  // the other children's contributions
+      const double2_t t = slot[64 * (rs - 1)];
+      dd = dd - t.x;
+      bb = bb - t.y;
+    }
+    const double rr = rcp_nr(dd);
+    const double fv = uu * rr, yv = bb * rr;
+    cd = uu * fv;
+    cb = fv * bb;
+    const unsigned ds = q & hines::SQ_SLOT;
+    if (ds) {
+      lds_d2* sp = slot + 64 * (ds - 1);
+      *sp = (q & hines::SQ_FIRST) ? double2_t{cd, cb} : *sp + double2_t{cd, cb};
+    }
+    if (q & hines::SQ_MBOUT) mb[lane] = double2_t{cd, cb};
+    fy[e] = double2_t{fv, yv};
+  }
+}
+
+// Forward substitution of one chunk (steps in reverse), then the stores in
+// the user order through the gather mapping.
+__device__ __forceinline__ void seq_forward(const u32x4& cw, const u32x4& P, const double2_t* fy, lds_f64* pb,
+                                            const lds_f64* xrd, lds_d2* slot, lds_d2* mb, int lane, double& xc,
+                                            double* x, const int64_t* base, unsigned& msrc) {
+#pragma unroll
+  for (int e = SK - 1; e >= 0; --e) {
+    const unsigned q = seq_field(cw, e);
+    double xp = xc;  // the parent is the step after this one, unless named below
+    const unsigned ds = q & hines::SQ_SLOT;
+    if (ds) xp = ((lds_f64*)(slot + 64 * (ds - 1)))[0];
+    if (q & hines::SQ_MBOUT) xp = mb[lane].x;
+    // a padding step's factors are not used: its value must not reach a later step
+    const double xv = (q & hines::SQ_PAD) ? 0.0 : __builtin_fma(-fy[e].x, xp, fy[e].y);
+    const unsigned rs = (q >> hines::SQ_READ_SHIFT) & hines::SQ_SLOT;
+    if (rs) ((lds_f64*)(slot + 64 * (rs - 1)))[0] = xv;
+    if (q & hines::SQ_MBIN) {
+      mb[msrc & 63u].x = xv;
+      msrc >>= 6;
+    }
+    xc = xv;
+    pb[e * (kSeqRowB / 8)] = xv;
+  }
+  // (a padding element stores nothing: redirecting its 8 bytes elsewhere
+  // costs partial-line writes, measured slower than the branch)
+#pragma unroll
+  for (int r = 0; r < SK; ++r) {
+    const double xv = xrd[SG * r];
+    const unsigned p = seq_field(P, r);
+    if (p != hines::kCellPadPos) x[base[r] + p] = xv;
+  }
+}
+
+// Register set of one forward chunk: its factors, positions and codes.
+struct SeqFwd {
+  double2_t fy[SK];
+  u32x4 P, c;
+};
+
+__global__ __launch_bounds__(64) void k_solve_seq(DevTables tb, const double* __restrict__ d,
+                                                  const double* __restrict__ u, const double* __restrict__ b,
+                                                  double* x) {
+  __shared__ __attribute__((aligned(16))) char sq_raw[kSeqLds];
+  lds_char* lds = (lds_char*)sq_raw;
+  const int lane = threadIdx.x;
+  const hines::KCellWave W = tb.swave[blockIdx.x];
+  const int nk = W.nchunk;
+  int64_t base[SK];
+#pragma unroll
+  for (int r = 0; r < SK; ++r) base[r] = tb.sbase[(int64_t)blockIdx.x * 64 + SG * r + lane / SK];
+  const u32x4* posv = (const u32x4*)(tb.spos + W.chunk_off * hines::kSeqChunkElems) + lane;   // + 64 per chunk
+  const u32x4* codv = (const u32x4*)(tb.scode + W.chunk_off * hines::kSeqChunkElems) + lane;  // + 64 per chunk
+  double2_t* scr = (double2_t*)tb.cscr + W.chunk_off * (SK * 64) + lane;                      // + SK * 64 per chunk
+  lds_d2* slot = (lds_d2*)(lds + kSeqLdsSlot) + lane;
+  lds_d2* mb = (lds_d2*)(lds + kSeqLdsMail);
+  const lds_d2* pdu = (const lds_d2*)lds + lane;
+  lds_f64* pb = (lds_f64*)(lds + kSeqLdsB) + lane;
+  auto chunk = [&](int k) { return 64 * max(0, min(k, nk - 1)); };  // table offset of chunk k, clamped
+
+  // ---- backward sweep.  Memory latency under load is microseconds while a
+  // chunk's elimination takes a few hundred cycles, so the gathers run two
+  // chunks ahead (two register sets, used in turn), the positions four and
+  // the codes two.  Every load is unconditional (clamped to the last chunk):
+  // the loop body stays straight-line and each wait covers only the data it
+  // needs.  Loads land in the registers that use them: no copies. ----
+  // (the prologue issues in the steady state's order: each position load
+  // right after the gathers that used its registers)
+  double dA[SK], uA[SK], bA[SK], dB[SK], uB[SK], bB[SK];
+  u32x4 PA = __builtin_nontemporal_load(posv), PB = __builtin_nontemporal_load(posv + chunk(1));
+  u32x4 cA = __builtin_nontemporal_load(codv), cB = __builtin_nontemporal_load(codv + chunk(1));
+  seq_load(dA, uA, bA, d, u, b, base, PA);
+  PA = __builtin_nontemporal_load(posv + chunk(2));
+  seq_load(dB, uB, bB, d, u, b, base, PB);
+  PB = __builtin_nontemporal_load(posv + chunk(3));
+  double cd = 0.0, cb = 0.0;
+  double2_t fy[SK];
+  const uint64_t ms = tb.smsrc[(int64_t)blockIdx.x * 64 + lane];
+  unsigned msb = (unsigned)ms, msf = (unsigned)(ms >> 32);
+  auto bstep = [&](int k, double* dv, double* uv, double* bv, u32x4& Pn, u32x4& cc) {
+    seq_put(dv, uv, bv, lds, lane);                       // chunk k
+    seq_load(dv, uv, bv, d, u, b, base, Pn);              // chunk k + 2
+    Pn = __builtin_nontemporal_load(posv + chunk(k + 4));
+    seq_backward(cc, pdu, pb, slot, mb, lane, cd, cb, fy, msb);
+    // every step stored, padding too (into its own entry, never used): whole
+    // 1 KiB rows, and no branch splits the bookkeeping of outstanding memory
+    // operations (skipping padding measured slower)
+    double2_t* sk = scr + (int64_t)k * (SK * 64);
+#pragma unroll
+    for (int e = 0; e < SK; ++e) __builtin_nontemporal_store(fy[e], sk + e * 64);
+    cc = __builtin_nontemporal_load(codv + chunk(k + 2));
+  };
+  for (int k = 0;; k += 2) {
+    bstep(k, dA, uA, bA, PA, cA);
+    if (k + 1 >= nk) break;
+    bstep(k + 1, dB, uB, bB, PB, cB);
+    if (k + 2 >= nk) break;
+  }
+  // the forward sweep reads back this wave's own scratch stores
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+
+  // ---- forward sweep: chunks nk - 1 down to 0, three register sets in turn,
+  // so that the loads of the next three chunks are in flight while one is
+  // substituted.  Chunk nk - 1's factors are still in fy. ----
+  const lds_f64* xrd = (const lds_f64*)(lds + kSeqLdsB + (lane % SK) * kSeqRowB) + lane / SK;
+  double xc = 0.0;
+  SeqFwd FA, FB, FC;
+  auto fload = [&](SeqFwd& F, int k) {
+    const int kc = max(k, 0);
+    const double2_t* sk = scr + (int64_t)kc * (SK * 64);
+#pragma unroll
+    for (int e = 0; e < SK; ++e) F.fy[e] = __builtin_nontemporal_load(sk + e * 64);
+    F.P = __builtin_nontemporal_load(posv + chunk(kc));
+    F.c = __builtin_nontemporal_load(codv + chunk(kc));
+  };
+#pragma unroll
+  for (int e = 0; e < SK; ++e) FA.fy[e] = fy[e];
+  FA.P = __builtin_nontemporal_load(posv + chunk(nk - 1));
+  FA.c = __builtin_nontemporal_load(codv + chunk(nk - 1));
+  fload(FB, nk - 2);
+  fload(FC, nk - 3);
+  auto fstep = [&](int k, SeqFwd& F) {
+    seq_forward(F.c, F.P, F.fy, pb, xrd, slot, mb, lane, xc, x, base, msf);
+    fload(F, k - 3);
+  };
+  for (int k = nk - 1;; k -= 3) {
+    fstep(k, FA);
+    if (k < 1) break;
+    fstep(k - 1, FB);
+    if (k < 2) break;
+    fstep(k - 2, FC);
+    if (k < 3) break;
   }
 }
 

@@ -1032,6 +1032,22 @@ int64_t export_table(const HostPlan& p, int32_t id, int64_t* out, int64_t capaci
     case T_CELL_FLAGS: return put(p.cl.flags);
     case T_CELL_MBSRC: return put(p.cl.mbsrc);
     case T_CELL_RANGE: return put(p.cl.range);
+    case T_SEQ_WAVES: {
+      const int64_t cnt = 3 * (int64_t)p.sq.waves.size();
+      if (out) {
+        if (capacity < cnt) return -1;
+        for (int64_t w = 0; w < cnt / 3; ++w) {
+          out[3 * w] = p.sq.waves[w].chunk_off;
+          out[3 * w + 1] = p.sq.waves[w].nchunk;
+          out[3 * w + 2] = p.sq.waves[w].ncell;
+        }
+      }
+      return cnt;
+    }
+    case T_SEQ_LANES: return put(p.sq.lane_cell);
+    case T_SEQ_POS: return put(p.sq.pos);
+    case T_SEQ_CODE: return put(p.sq.code);
+    case T_SEQ_MBSRC: return put(p.sq.mbsrc);
     case T_RES_GROUPS: {
       constexpr int64_t kF = 16;
       const int64_t cnt = kF * (int64_t)p.res.groups.size();

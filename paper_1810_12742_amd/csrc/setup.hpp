@@ -40,6 +40,7 @@ struct Options {
   int32_t scheduler = 1;           // 1: static heavy-path lane schedule when every branch ascends;
                                    // 0: level-synchronous sweeps (paper §3)
   int32_t cell_lanes = 0;          // 1: one lane per cell (streaming kernel) for hines_solve / timestep
+  int32_t cell_seq = 0;            // 1: index-order cell lanes for hines_solve
   int32_t resident = 0;            // 1: LDS-resident path-walk kernel for hines_solve
   int32_t cell_cut_percent = 80;   // cell lanes: cut cells longer than this percentage of the mean
   int32_t cell_max_cuts = 3;       // cell lanes: cut-off subtrees per cell
@@ -103,7 +104,12 @@ enum TableId : int32_t {
                           // npath, nlist, rec_off, list_off, cls, steps per chunk, nflip
   T_CELL_RANGE = 18,      // int64[nwaves*64]: first step of the lane's walk | end step << 32 (padding outside)
   T_RES_BLOB = 19,        // int64[blob bytes / 2]: the blobs as uint16 words
-  T_NUM = 20,
+  T_SEQ_WAVES = 20,       // int64[nwaves*3]: chunk_off, nchunk, ncell (index-order lanes)
+  T_SEQ_LANES = 21,       // int64[nwaves*64]: cell of each lane (-1: empty)
+  T_SEQ_POS = 22,         // int64[nchunks*kSeqChunkElems]: [chunk][staging lane][slot] relative position
+  T_SEQ_CODE = 23,        // int64[nchunks*kSeqChunkElems]: [chunk][cell lane][element] step code
+  T_SEQ_MBSRC = 24,       // int64[nwaves*64]: mailbox source lanes, backward | forward << 32
+  T_NUM = 25,
 };
 
 // Cell-lane kernel (one lane per cell, or per half of a long cell).  Each cell is processed in a depth-
@@ -174,6 +180,70 @@ struct CellLanes {
 Status build_cell_lanes(const int32_t* parent, int64_t n, const int64_t* cell_offsets, int64_t ncells,
                         CellLanes& out, std::string& err, int32_t cut_percent = 80,
                         int32_t max_cuts = kCellMaxCuts);
+
+// Index-order cell lanes (option cell_lanes 2).  Same one-lane-per-cell
+// elimination, but a lane walks its piece of a cell in decreasing user index in
+// the backward sweep.  The parent of every compartment has a lower index (the
+// numbering §2 requires), so that order puts children before parents, and a
+// cell numbered level by level is read in a few long runs of consecutive
+// compartments, whole memory lines, instead of one short branch at a time.  A
+// contribution whose parent is not the next step waits in a per-lane LDS slot
+// from the first child that adds into it to the parent's step (slots assigned
+// by interval colouring); the forward sweep sends the parent's x back to the
+// same children through the same slot.  A lane whose index walk would need
+// more than kSeqSlots slots walks depth-first instead (the slot code serves
+// any children-first order).  Runs of kSeqMinRun or more compartments start
+// so that every chunk pair covers one 128-byte line of the user arrays (when
+// the arrays start on 128-byte boundaries); a cell much longer than the mean is
+// cut into up to kCellMaxCuts + 1 pieces (the longest piece cut again while it
+// stays long) on adjacent lanes of one wave, the contribution of each cut-off
+// subtree's root crossing through its lane's mailbox as in the cell-lane
+// kernel.
+constexpr int32_t kSeqChunk = 8;                       // steps per chunk
+constexpr int32_t kSeqSlotCells = 64 / kSeqChunk;      // cells per gather slot
+constexpr int32_t kSeqChunkElems = 64 * kSeqChunk;     // table entries per chunk
+constexpr int32_t kSeqSlots = 26;                      // LDS contribution slots per lane
+constexpr int32_t kSeqLine = 16;                       // compartments per 128-byte line
+constexpr int32_t kSeqMinRun = 16;                     // runs this long start line-aligned
+constexpr int64_t seq_pos_index(int64_t chunk, int32_t c, int32_t e) {
+  return chunk * kSeqChunkElems + (int64_t)((c % kSeqSlotCells) * kSeqChunk + e) * kSeqChunk + c / kSeqSlotCells;
+}
+constexpr int64_t seq_code_index(int64_t chunk, int32_t c, int32_t e) {
+  return chunk * kSeqChunkElems + (int64_t)c * kSeqChunk + e;
+}
+enum : uint16_t {
+  SQ_SLOT = 31,         // bits 0-4: slot the step's contribution goes into (0: none)
+  SQ_READ_SHIFT = 5,    // bits 5-9: slot holding the contributions of the step's other children
+  SQ_TIP = 1 << 10,     // the previous step's contribution does not enter
+  SQ_PAD = 1 << 11,     // padding: identity row
+  SQ_MBOUT = 1 << 12,   // root of the cut-off subtree: leaves through the lane's mailbox
+  SQ_MBIN = 1 << 13,    // its parent: takes the next mailbox of the lane's source list
+  SQ_FIRST = 1 << 14,   // first contribution into its slot: written, not added
+  SQ_ROOT = 1 << 15,    // the cell root: no coupling to a parent
+};
+struct SeqLanes {
+  bool built = false;
+  int64_t nwaves = 0, nchunks = 0;
+  int32_t max_slots = 0;            // most slots any lane uses
+  int64_t depth_first = 0;          // lanes walked depth-first
+  std::vector<KCellWave> waves;     // [nwaves], longest first
+  std::vector<int32_t> lane_cell;   // [nwaves*64] cell of each lane, -1 for empty lanes
+  std::vector<int64_t> base;        // [nwaves*64] first user index of the lane's cell (0: empty)
+  std::vector<uint16_t> pos;        // [nchunks*kSeqChunkElems] staging order
+  std::vector<uint16_t> code;       // [nchunks*kSeqChunkElems] cell-lane order
+  std::vector<uint64_t> mbsrc;      // [nwaves*64] as CellLanes::mbsrc
+};
+// ERR_TOO_BIG if a cell has more than kCellMaxSize compartments or a lane
+// needs more than kSeqSlots slots in both walk orders.
+Status build_seq_lanes(const int32_t* parent, int64_t n, const int64_t* cell_offsets, int64_t ncells,
+                       SeqLanes& out, std::string& err, int32_t cut_percent = 80,
+                       int32_t max_cuts = kCellMaxCuts);
+// Replay of the index-order tables: every compartment walked once, carries
+// only from a child, every slot taken by a child of its owner, read by the
+// owner and free again at the end, and each mailbox taken strictly after it
+// was posted.
+bool check_seq_lanes(const SeqLanes& Q, const int32_t* parent, int64_t n, const int64_t* cell_offsets,
+                     int64_t ncells, std::string& why);
 
 // LDS-resident solve (one wave per group of whole cells).  A group's d, u, b
 // are staged into LDS once, as three planes in the user numbering (slot s
@@ -366,6 +436,7 @@ struct HostPlan {
   std::vector<int16_t> faux;      // [pushes]: parent position
   int64_t ws_doubles = 0;         // global workspace for groups that exceed LDS
   CellLanes cl;                   // cell-lane kernel tables (opt.cell_lanes)
+  SeqLanes sq;                    // index-order cell-lane tables (opt.cell_seq)
   ResPlan res;                    // LDS-resident kernel tables (opt.resident)
 };
 

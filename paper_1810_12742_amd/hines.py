@@ -20,6 +20,7 @@ TABLES = {
     "flow_groups": 8, "flow_masks": 9, "flow_pos": 10, "flow_aux": 11,
     "cell_waves": 12, "cell_lanes": 13, "cell_pos": 14, "cell_flags": 15, "cell_mbsrc": 16,
     "cell_range": 18, "res_groups": 17, "res_blob": 19,
+    "seq_waves": 20, "seq_lanes": 21, "seq_pos": 22, "seq_code": 23, "seq_mbsrc": 24,
 }
 STATUS = {0: "OK", 1: "NULL", 2: "BAD_OFFSETS", 3: "BAD_PARENT", 4: "BAD_BRANCHES",
           6: "NCELLS", 7: "OPTION", 8: "OOM", 9: "HIP", 10: "TOO_BIG", 11: "NOT_SDD", 12: "STATE"}
@@ -144,7 +145,7 @@ class Plan:
         opt.keep_tables = int(bool(keep_tables))
         opt.bitwise = int(bool(bitwise))
         opt.level_sync = int(bool(level_sync))
-        opt.cell_lanes = int(bool(cell_lanes))
+        opt.cell_lanes = int(cell_lanes)
         opt.resident = int(bool(resident))
         opt.cell_cut_percent = int(cell_cut_percent)
         opt.cell_max_cuts = int(cell_max_cuts)

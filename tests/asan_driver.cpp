@@ -1,7 +1,7 @@
 // Host-side table builders under AddressSanitizer / UndefinedBehaviorSanitizer.
 // Reads a forest (n, ncells, parent[n], cell_offsets[ncells+1]) and option
-// values from a binary file, builds the plan tables, the cell-lane tables and
-// the resident tables, runs their replay checks, and writes every exported
+// values from a binary file, builds the plan tables, the cell-lane tables (depth-
+// first or index order) and the resident tables, runs their replay checks, and writes every exported
 // table (int64, with its count) to the output file.  Built and run by
 // tests/test_sanitizers.py with g++ only (no device code).
 #include <cstdio>
@@ -40,10 +40,17 @@ int main(int argc, char** argv) {
     std::printf("build_plan: %d %s\n", (int)s, err.c_str());
     return 3;
   }
-  if (opts[6]) {
+  if (opts[6] == 1) {
     s = hines::build_cell_lanes(par.data(), n, off.data(), nc, P.cl, err);
     if (s != hines::OK) {
       std::printf("build_cell_lanes: %d %s\n", (int)s, err.c_str());
+      return 3;
+    }
+  } else if (opts[6] == 2) {
+    s = hines::build_seq_lanes(par.data(), n, off.data(), nc, P.sq, err);
+    if (s == hines::OK && !hines::check_seq_lanes(P.sq, par.data(), n, off.data(), nc, err)) s = hines::ERR_STATE;
+    if (s != hines::OK) {
+      std::printf("build_seq_lanes: %d %s\n", (int)s, err.c_str());
       return 3;
     }
   }

@@ -1,6 +1,7 @@
-"""The host-side table builders (setup, cell lanes, resident) compiled with
-AddressSanitizer and UndefinedBehaviorSanitizer (g++, CPU only) on forests and
-option sets of the table-parity suite; the tables they export must equal the
+"""The host-side table builders (setup, cell lanes in both walk orders,
+resident) compiled with AddressSanitizer and UndefinedBehaviorSanitizer (g++,
+CPU only) on forests and option sets of the table-parity suite; the tables
+they export must equal the
 library's (built without sanitizers), so the sanitized run executes the same
 code paths.  A heap overflow, use after free or undefined operation aborts
 the driver with a report."""
@@ -17,7 +18,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1810_12742_amd", "csrc")
 TABLES = ["node_plan", "branches", "u_src", "group_offsets", "group_cells", "group_seg_offsets", "seg_offsets",
           "lanes", "flow_groups", "flow_masks", "flow_pos", "flow_aux", "cell_waves", "cell_lanes", "cell_pos",
-          "cell_flags", "cell_mbsrc", "res_groups", "cell_range", "res_blob"]
+          "cell_flags", "cell_mbsrc", "res_groups", "cell_range", "res_blob", "seq_waves", "seq_lanes", "seq_pos",
+          "seq_code", "seq_mbsrc"]
 
 
 @pytest.fixture(scope="module")
@@ -41,6 +43,8 @@ CASES = [
     ("c3", dict(level_balance=1, max_group_unknowns=0)),
     ("c2", dict(level_balance=1, max_group_unknowns=0, resident=1)),
     ("small", dict(cell_order=1, max_group_unknowns=900, split_branches=2, cell_lanes=1, resident=1)),
+    ("c2", dict(cell_lanes=2)),
+    ("small", dict(cell_lanes=2, resident=1)),
 ]
 
 

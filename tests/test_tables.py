@@ -33,7 +33,7 @@ def lib_tables(f, branch_offsets="user", **opts):
     bo = f.branch_offsets if branch_offsets == "user" else branch_offsets
     p = Plan(f.parent, f.cell_offsets, bo, host_only=True, max_group_unknowns=mg, **opts)
     # the paper's tables; the flow kernel's step schedule is checked by its replay test
-    t = {k: v for k, v in p.tables().items() if not k.startswith(("flow_", "cell_", "res_"))}
+    t = {k: v for k, v in p.tables().items() if not k.startswith(("flow_", "cell_", "res_", "seq_"))}
     p.close()
     return t
 
