@@ -94,9 +94,12 @@ typedef struct hines_options {
                                  cell numbered level by level is read in long runs of whole
                                  memory lines; contributions to a parent that is not the next
                                  step wait in up to 26 LDS slots per lane (a lane that would
-                                 need more walks depth-first); a cell longer than
-                                 cell_cut_percent of the mean is cut once.  Runs start on
-                                 128-byte lines when the arrays do.  The other forms
+                                 need more walks depth-first); while a piece of a cell is
+                                 longer than cell_cut_percent of the mean cell it is cut
+                                 again, into at most cell_max_cuts + 1 pieces on adjacent
+                                 lanes.  Runs start on 128-byte lines when the arrays do.
+                                 Needs bitwise 0 and cells of at most 65535 compartments
+                                 (HINES_ERR_TOO_BIG otherwise).  The other forms
                                  (timestep, time loop, noalloc, layout, FP32) are refused or
                                  run on the groups.  0 (default): groups (§3-§4)             */
   int32_t resident;           /* 1: hines_solve runs the LDS-resident kernel: consecutive whole
