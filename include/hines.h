@@ -99,9 +99,11 @@ typedef struct hines_options {
                                  again, into at most cell_max_cuts + 1 pieces on adjacent
                                  lanes.  Runs start on 128-byte lines when the arrays do.
                                  Needs bitwise 0 and cells of at most 65535 compartments
-                                 (HINES_ERR_TOO_BIG otherwise).  The other forms
-                                 (timestep, time loop, noalloc, layout, FP32) are refused or
-                                 run on the groups.  0 (default): groups (§3-§4)             */
+                                 (HINES_ERR_TOO_BIG otherwise).  hines_timestep and the time
+                                 loop (one solve per step) run on it too; the solver layout,
+                                 hines_solve_stored32, hines_timestep_assembled and
+                                 hines_solve_noalloc need cell_lanes 1 (HINES_ERR_STATE).
+                                 0 (default): groups (§3-§4)                                 */
   int32_t resident;           /* 1: hines_solve runs the LDS-resident kernel: consecutive whole
                                  cells form a group of up to 1400 compartments (a larger cell is
                                  a group of its own; see res_pack); one wave stages the group's

@@ -293,7 +293,15 @@ hipError_t launch_solve(const hines_plan* p, const RhsSpec& rs, const double* d,
                         hipStream_t s) {
   if (p->host.res.built && rs.mode == hdev::kRhsGiven) return launch_resident(p, d, u, rs.rhs, x, s);
   if (p->host.sq.built) {
-    hipLaunchKernelGGL(hdev::k_solve_seq, dim3((unsigned)p->host.sq.nwaves), dim3(64), 0, s, p->t, d, u, rs.rhs, x);
+    const dim3 grid((unsigned)p->host.sq.nwaves);
+    if (rs.mode == hdev::kRhsGiven)
+      hipLaunchKernelGGL(hdev::k_solve_seq<hdev::kFlowGiven>, grid, dim3(64), 0, s, p->t, rs, d, u, x);
+    else if (rs.mode == hdev::kRhsNoise)
+      hipLaunchKernelGGL(hdev::k_solve_seq<hdev::kFlowNoise>, grid, dim3(64), 0, s, p->t, rs, d, u, x);
+    else if (rs.icur)
+      hipLaunchKernelGGL(hdev::k_solve_seq<hdev::kFlowCVI>, grid, dim3(64), 0, s, p->t, rs, d, u, x);
+    else
+      hipLaunchKernelGGL(hdev::k_solve_seq<hdev::kFlowCV>, grid, dim3(64), 0, s, p->t, rs, d, u, x);
     return hipGetLastError();
   }
   if (p->host.cl.built) {
@@ -656,8 +664,6 @@ hines_status check_call(const hines_plan* p, int32_t ncells) {
 
 hines_status run_solve(const hines_plan* p, const RhsSpec& rs, const double* diag, const double* upper, double* x,
                        void* stream) {
-  if (p->host.sq.built && rs.mode != hdev::kRhsGiven)
-    return set_err(HINES_ERR_STATE, "index-order cell lanes (cell_lanes 2) serve hines_solve only");
   hipError_t e = launch_solve(p, rs, diag, upper, x, (hipStream_t)stream);
   if (e != hipSuccess) return set_err(HINES_ERR_HIP, "launch: %s", hipGetErrorString(e));
   return ok();

@@ -1259,29 +1259,56 @@ static_assert(4 * kSeqLds <= 160 * 1024, "four waves per compute unit");
 // 16-bit field r of a lane's 16-byte table word (positions or codes)
 __device__ __forceinline__ unsigned seq_field(const u32x4& v, int r) { return (v[r >> 1] >> (16 * (r & 1))) & 0xffffu; }
 
-__device__ __forceinline__ void seq_load(double* dv, double* uv, double* bv, const double* __restrict__ d,
-                                         const double* __restrict__ u, const double* __restrict__ b,
-                                         const int64_t* base, const u32x4& P) {
+// Register set of one backward chunk: the gathered d, u and right-hand side
+// ingredients (b given; or c and v, with i for c v + i), and, for the noise
+// form, the chunk's positions (the draw is keyed by the user index).
+template <int RHS>
+struct SeqSet {
+  double d[SK], u[SK], b[SK];
+  double c[RHS == kFlowGiven ? 1 : SK];
+  double i[RHS == kFlowCVI ? SK : 1];
+  u32x4 P;
+};
+
+template <int RHS>
+__device__ __forceinline__ void seq_load(SeqSet<RHS>& S, const RhsSpec& rs, const double* __restrict__ d,
+                                         const double* __restrict__ u, const int64_t* base, const u32x4& P) {
 #pragma unroll
   for (int r = 0; r < SK; ++r) {
     const unsigned p = seq_field(P, r);
     const int64_t i = base[r] + (p == hines::kCellPadPos ? 0u : p);
-    dv[r] = d[i];
-    uv[r] = u[i];
-    bv[r] = b[i];
+    S.d[r] = d[i];
+    S.u[r] = u[i];
+    if constexpr (RHS == kFlowGiven) {
+      S.b[r] = rs.rhs[i];
+    } else {
+      S.c[r] = rs.c[i];
+      S.b[r] = rs.v[i];
+      if constexpr (RHS == kFlowCVI) S.i[r] = rs.icur[i];
+    }
   }
+  if constexpr (RHS == kFlowNoise) S.P = P;
 }
 
-// Into the LDS planes (the lane that eliminates an element zeroes its coupling
-// when the step code marks padding or the cell root).
-__device__ __forceinline__ void seq_put(const double* dv, const double* uv, const double* bv, lds_char* lds,
-                                        int lane) {
+// Into the LDS planes, forming the right-hand side (the lane that eliminates
+// an element zeroes its coupling when the step code marks padding or the
+// cell root).
+template <int RHS>
+__device__ __forceinline__ void seq_put(const SeqSet<RHS>& S, const RhsSpec& rs, const int64_t* base,
+                                        lds_char* lds, int lane) {
   const int e = lane % SK;
 #pragma unroll
   for (int r = 0; r < SK; ++r) {
     const int c = SG * r + lane / SK;
-    *(lds_d2*)(lds + e * kSeqRowDU + c * 16) = double2_t{dv[r], uv[r]};
-    *(lds_f64*)(lds + kSeqLdsB + e * kSeqRowB + c * 8) = bv[r];
+    double bb = S.b[r];
+    if constexpr (RHS != kFlowGiven) bb = S.c[r] * S.b[r];
+    if constexpr (RHS == kFlowCVI) bb = bb + S.i[r];
+    if constexpr (RHS == kFlowNoise) {
+      const unsigned p = seq_field(S.P, r);
+      bb = bb + noise_draw(rs.seed, rs.step, (uint64_t)(base[r] + (p == hines::kCellPadPos ? 0u : p)), rs.sigma);
+    }
+    *(lds_d2*)(lds + e * kSeqRowDU + c * 16) = double2_t{S.d[r], S.u[r]};
+    *(lds_f64*)(lds + kSeqLdsB + e * kSeqRowB + c * 8) = bb;
   }
 }
 
@@ -1365,9 +1392,9 @@ struct SeqFwd {
   u32x4 P, c;
 };
 
-__global__ __launch_bounds__(64) void k_solve_seq(DevTables tb, const double* __restrict__ d,
-                                                  const double* __restrict__ u, const double* __restrict__ b,
-                                                  double* x) {
+template <int RHS>
+__global__ __launch_bounds__(64) void k_solve_seq(DevTables tb, RhsSpec rs, const double* __restrict__ d,
+                                                  const double* __restrict__ u, double* x) {
   __shared__ __attribute__((aligned(16))) char sq_raw[kSeqLds];
   lds_char* lds = (lds_char*)sq_raw;
   const int lane = threadIdx.x;
@@ -1393,20 +1420,20 @@ __global__ __launch_bounds__(64) void k_solve_seq(DevTables tb, const double* __
   // needs.  Loads land in the registers that use them: no copies. ----
   // (the prologue issues in the steady state's order: each position load
   // right after the gathers that used its registers)
-  double dA[SK], uA[SK], bA[SK], dB[SK], uB[SK], bB[SK];
+  SeqSet<RHS> SA, SB;
   u32x4 PA = __builtin_nontemporal_load(posv), PB = __builtin_nontemporal_load(posv + chunk(1));
   u32x4 cA = __builtin_nontemporal_load(codv), cB = __builtin_nontemporal_load(codv + chunk(1));
-  seq_load(dA, uA, bA, d, u, b, base, PA);
+  seq_load(SA, rs, d, u, base, PA);
   PA = __builtin_nontemporal_load(posv + chunk(2));
-  seq_load(dB, uB, bB, d, u, b, base, PB);
+  seq_load(SB, rs, d, u, base, PB);
   PB = __builtin_nontemporal_load(posv + chunk(3));
   double cd = 0.0, cb = 0.0;
   double2_t fy[SK];
   const uint64_t ms = tb.smsrc[(int64_t)blockIdx.x * 64 + lane];
   unsigned msb = (unsigned)ms, msf = (unsigned)(ms >> 32);
-  auto bstep = [&](int k, double* dv, double* uv, double* bv, u32x4& Pn, u32x4& cc) {
-    seq_put(dv, uv, bv, lds, lane);                       // chunk k
-    seq_load(dv, uv, bv, d, u, b, base, Pn);              // chunk k + 2
+  auto bstep = [&](int k, SeqSet<RHS>& S, u32x4& Pn, u32x4& cc) {
+    seq_put(S, rs, base, lds, lane);                      // chunk k
+    seq_load(S, rs, d, u, base, Pn);                      // chunk k + 2
     Pn = __builtin_nontemporal_load(posv + chunk(k + 4));
     seq_backward(cc, pdu, pb, slot, mb, lane, cd, cb, fy, msb);
     // every step stored, padding too (into its own entry, never used): whole
@@ -1418,9 +1445,9 @@ __global__ __launch_bounds__(64) void k_solve_seq(DevTables tb, const double* __
     cc = __builtin_nontemporal_load(codv + chunk(k + 2));
   };
   for (int k = 0;; k += 2) {
-    bstep(k, dA, uA, bA, PA, cA);
+    bstep(k, SA, PA, cA);
     if (k + 1 >= nk) break;
-    bstep(k + 1, dB, uB, bB, PB, cB);
+    bstep(k + 1, SB, PB, cB);
     if (k + 2 >= nk) break;
   }
   // the forward sweep reads back this wave's own scratch stores

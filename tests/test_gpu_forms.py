@@ -140,7 +140,8 @@ def test_noise_graph_and_charge_conservation(torch_dev):
     loop.close()
 
 
-def test_adjoint_vs_oracle(torch_dev):
+@pytest.mark.parametrize("opts", [dict(), dict(cell_lanes=2)], ids=["groups", "index_order_lanes"])
+def test_adjoint_vs_oracle(torch_dev, opts):
     torch, dev = torch_dev
     from paper_1810_12742_amd import Plan
     from paper_1810_12742_amd.adjoint import soma_traces
@@ -149,7 +150,7 @@ def test_adjoint_vs_oracle(torch_dev):
     steps, every = 23, 5
     target = s.meta["target"]
     I = s.meta["I"]
-    p = Plan(f.parent, f.cell_offsets, f.branch_offsets)
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets, **opts)
     a_t = torch.from_numpy(s.a).to(dev).requires_grad_(True)
     c_t = torch.from_numpy(s.c).to(dev).requires_grad_(True)
     I_t = torch.from_numpy(I).to(dev).requires_grad_(True)

@@ -3,7 +3,8 @@ k_solve_seq) through the C-ABI against the FP64 oracle, within 1e-12
 relative error per cell (max norm): C2 slices with cut cells, trees with many
 children per compartment, trees too wide for the slots (walked depth-first),
 unbranched and single-compartment cells, the full 65,536-cell workload, the
-right-hand side aliasing x, and the forms such a plan refuses."""
+right-hand side aliasing x, the time-step forms and their captured loop,
+and the forms such a plan refuses."""
 import numpy as np
 import pytest
 
@@ -77,7 +78,51 @@ def test_seq_full_c2(torch_dev):
         assert cell_rel_err(f, x, xo) <= TOL
 
 
-def test_seq_plan_refuses_the_other_forms(torch_dev):
+def test_seq_timestep_forms_and_graph(torch_dev):
+    """c V + I, c V + sigma Z and plain c V right-hand sides formed in the
+    index-order kernel, against the oracle's time loop; a captured graph of
+    the steps equals the eager steps on every replay."""
+    torch, dev = torch_dev
+    from paper_1810_12742_amd import Plan
+    s = configs.c3(300)
+    f = s.forest
+    print("seq: timestep forms", flush=True)
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets, cell_lanes=2)
+    assert p.info["kernel"] == 5
+    d, u, c = (torch.from_numpy(a).to(dev) for a in (s.diag, s.upper, s.c))
+    steps = 3
+    V = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    for k in range(steps):
+        p.timestep(d, u, c, V, V, noise_sigma=0.1, noise_seed=5, step=k)
+    Vo = oracle.timeloop(f, s.diag, s.upper, s.c, steps, noise_seed=5, noise_sigma=0.1)
+    assert cell_rel_err(f, V.cpu().numpy(), Vo) <= TOL
+    I = 0.1 * np.random.default_rng(4).standard_normal(f.n)
+    It = torch.from_numpy(I).to(dev)
+    Va = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    for k in range(steps):
+        Va = p.timestep(d, u, c, Va, i_inj=It, step=k)
+    Vo = oracle.timeloop(f, s.diag, s.upper, s.c, steps, I_const=I)
+    assert cell_rel_err(f, Va.cpu().numpy(), Vo) <= TOL
+    V0 = np.random.default_rng(6).standard_normal(f.n)
+    Vc = p.timestep(d, u, c, torch.from_numpy(V0).to(dev), step=0)
+    Voc = oracle.timeloop(f, s.diag, s.upper, s.c, 1, V0=V0, I_const=np.zeros(f.n))
+    assert cell_rel_err(f, Vc.cpu().numpy(), Voc) <= TOL
+    Vg = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    loop = p.timeloop(d, u, c, Vg, steps, i_inj=It)
+    for rep in range(3):
+        Vg.zero_()
+        loop.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(Vg.cpu().numpy(), Va.cpu().numpy()), rep
+        _ = (d * 2).sum().item()
+    loop.close()
+    p.close()
+
+
+def test_seq_plan_refuses_the_depth_first_forms(torch_dev):
+    """The solver layout, the FP32-stored matrix and the assembled step are
+    forms of the depth-first cell-lane plan: an index-order plan refuses them
+    with a status, and its solve still runs."""
     torch, dev = torch_dev
     from paper_1810_12742_amd import Plan
     from paper_1810_12742_amd.hines import HinesError
@@ -86,11 +131,12 @@ def test_seq_plan_refuses_the_other_forms(torch_dev):
     p = Plan(f.parent, f.cell_offsets, f.branch_offsets, cell_lanes=2)
     assert p.info["kernel"] == 5
     d, u, b = (torch.from_numpy(a).to(dev) for a in (s.diag, s.upper, s.rhs))
-    c = torch.ones_like(d)
-    with pytest.raises(HinesError):
-        p.timestep(d, u, c, b)
     with pytest.raises(HinesError):
         p.layout_size
+    with pytest.raises(HinesError):
+        p.solve_stored32(d.float(), u.float(), b)
+    with pytest.raises(HinesError):
+        p.timestep_assembled(d, u, d, d, b)
     x = p.solve(d, u, b)
     torch.cuda.synchronize()
     assert cell_rel_err(f, x.cpu().numpy(), oracle.solve(f, s.diag, s.upper, s.rhs)) <= TOL
