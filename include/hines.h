@@ -101,8 +101,8 @@ typedef struct hines_options {
                                  Needs bitwise 0 and cells of at most 65535 compartments
                                  (HINES_ERR_TOO_BIG otherwise).  hines_timestep and the time
                                  loop (one solve per step) run on it too; the solver layout,
-                                 hines_solve_stored32, hines_timestep_assembled and
-                                 hines_solve_noalloc need cell_lanes 1 (HINES_ERR_STATE).
+                                 hines_solve_stored32 and hines_timestep_assembled need
+                                 cell_lanes 1 (HINES_ERR_STATE).
                                  0 (default): groups (§3-§4)                                 */
   int32_t resident;           /* 1: hines_solve runs the LDS-resident kernel: consecutive whole
                                  cells form a group of up to 1400 compartments (a larger cell is
@@ -257,17 +257,19 @@ hines_status hines_solve(const hines_plan* plan, const double* diag, const doubl
 
 /* hines_solve for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid allocation): the
- * same cell-lane kernel and results as hines_solve, with its per-step factors
- * (16 bytes per walk slot) kept in a file-scope device array of 256 MiB
- * (kStaticScratchBytes) instead of the plan's own scratch.  The call launches
- * one kernel and allocates or frees nothing.  Each device holds one such array
- * from the first hines_setup on it until the process ends; every call on that
- * device uses it, so calls that overlap on one device (several streams, or
- * host threads) race and must be serialised by the caller.  The kernel writes
- * every scratch slot it reads within the same call, so nothing needs clearing.
- *   Cell-lane plans only (HINES_ERR_STATE otherwise).  HINES_ERR_TOO_BIG if the
- *   plan's factors exceed the array (about 14 million compartments of C2-like
- *   cells).  Arguments as hines_solve; x may alias rhs.  Async on stream. */
+ * same cell-lane kernel (depth-first or index-order lanes) and results as
+ * hines_solve, with its per-step factors (16 bytes per walk slot) kept in a
+ * file-scope device array of 256 MiB (kStaticScratchBytes) instead of the
+ * plan's own scratch.  The call launches one kernel and allocates or frees
+ * nothing.  Each device holds one such array from the first hines_setup on it
+ * until the process ends; every call on that device uses it, so calls that
+ * overlap on one device (several streams, or host threads) race and must be
+ * serialised by the caller.  The kernel writes every scratch slot it reads
+ * within the same call, so nothing needs clearing.
+ *   Cell-lane plans only, cell_lanes 1 or 2 (HINES_ERR_STATE otherwise).
+ *   HINES_ERR_TOO_BIG if the plan's factors exceed the array (about 14 million
+ *   compartments of C2-like cells).  Arguments as hines_solve; x may alias
+ *   rhs.  Async on stream. */
 hines_status hines_solve_noalloc(const hines_plan* plan, const double* diag, const double* upper,
                                  const double* rhs, double* x, int32_t ncells, void* stream);
 

@@ -1108,12 +1108,14 @@ hines_status hines_solve_noalloc(const hines_plan* p, const double* diag, const 
                                  double* x, int32_t ncells, void* stream) {
   hines_status st = check_call(p, ncells);
   if (st != HINES_OK) return st;
-  if (!p->host.cl.built) return set_err(HINES_ERR_STATE, "hines_solve_noalloc needs a cell-lane plan");
+  const bool seq = p->host.sq.built;  // index-order lanes, else depth-first ones
+  if (!p->host.cl.built && !seq)
+    return set_err(HINES_ERR_STATE, "hines_solve_noalloc needs a cell-lane plan (cell_lanes 1 or 2)");
   if (p->host.n == 0) return ok();
   if (!diag || !upper || !rhs || !x) return set_err(HINES_ERR_NULL, "a device array is NULL");
   if ((const void*)x == (const void*)diag || (const void*)x == (const void*)upper)
     return set_err(HINES_ERR_STATE, "x must not alias diag or upper");
-  const int64_t need = p->t.cslots * 16;
+  const int64_t need = seq ? p->host.sq.nchunks * hines::kSeqChunk * 64 * 16 : p->t.cslots * 16;
   if (need > kStaticScratchBytes)
     return set_err(HINES_ERR_TOO_BIG, "the plan's factors need %lld bytes; the static scratch holds %lld",
                    (long long)need, (long long)kStaticScratchBytes);
@@ -1124,8 +1126,12 @@ hines_status hines_solve_noalloc(const hines_plan* p, const double* diag, const 
   RhsSpec rs{};
   rs.rhs = rhs;
   rs.mode = hdev::kRhsGiven;
-  hipLaunchKernelGGL(hdev::k_solve_cells<hdev::kFlowGiven>, dim3((unsigned)p->host.cl.nwaves), dim3(64), 0,
-                     (hipStream_t)stream, t, rs, diag, upper, x);
+  if (seq)
+    hipLaunchKernelGGL(hdev::k_solve_seq<hdev::kFlowGiven>, dim3((unsigned)p->host.sq.nwaves), dim3(64), 0,
+                       (hipStream_t)stream, t, rs, diag, upper, x);
+  else
+    hipLaunchKernelGGL(hdev::k_solve_cells<hdev::kFlowGiven>, dim3((unsigned)p->host.cl.nwaves), dim3(64), 0,
+                       (hipStream_t)stream, t, rs, diag, upper, x);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_err(HINES_ERR_HIP, "launch: %s", hipGetErrorString(e));
   return ok();

@@ -1,5 +1,6 @@
-"""hines_solve_noalloc through the C-ABI: the cell-lane solve with its factors
-in the library's static device scratch instead of the plan's allocation.
+"""hines_solve_noalloc through the C-ABI: the cell-lane solve (depth-first or
+index-order lanes) with its factors in the library's static device scratch
+instead of the plan's allocation.
 
 Its output must equal hines_solve's on the same plan and inputs (same kernel,
 same arithmetic; only the scratch address differs), on two calls in a row,
@@ -45,7 +46,7 @@ def _both(lib, torch, s, **opts):
     from paper_1810_12742_amd import Plan
     f = s.forest
     dev = torch.device("cuda")
-    p = Plan(f.parent, f.cell_offsets, f.branch_offsets, cell_lanes=True, **opts)
+    p = Plan(f.parent, f.cell_offsets, f.branch_offsets, **{"cell_lanes": 1, **opts})
     d, u, b = (torch.from_numpy(a).to(dev) for a in (s.diag, s.upper, s.rhs))
     x_ref = torch.full_like(b, np.nan)
     x_new = torch.full_like(b, np.nan)
@@ -59,13 +60,14 @@ def _both(lib, torch, s, **opts):
     return x_ref.cpu().numpy(), x_new.cpu().numpy()
 
 
-def test_noalloc_equals_solve_on_two_calls():
+@pytest.mark.parametrize("lanes", [1, 2], ids=["depth_first", "index_order"])
+def test_noalloc_equals_solve_on_two_calls(lanes):
     import torch
     lib = _lib()
     for s in (configs.c2(2048), configs.c2(300)):   # the second call is smaller
         f = s.forest
-        print(f"noalloc: {f.ncells} cells, {f.n} unknowns", flush=True)
-        x_ref, x_new = _both(lib, torch, s)
+        print(f"noalloc: cell_lanes {lanes}, {f.ncells} cells, {f.n} unknowns", flush=True)
+        x_ref, x_new = _both(lib, torch, s, cell_lanes=lanes)
         assert np.array_equal(x_new, x_ref)
         xo = oracle.solve(f, s.diag, s.upper, s.rhs)
         assert cell_rel_err(f, x_new, xo) <= TOL
