@@ -330,3 +330,18 @@ def test_seq_option_errors():
         Plan(f.parent, f.cell_offsets, host_only=1, cell_lanes=3)
     with pytest.raises(HinesError):
         Plan(f.parent, f.cell_offsets, host_only=1, cell_lanes=2, bitwise=True)
+
+
+@pytest.mark.parametrize("cut,max_cuts", [(1, 1), (1, 3), (100, 2), (1000, 3)])
+def test_seq_cut_settings(cut, max_cuts):
+    """Cut thresholds of 1%, 100% and 1000% of the mean cell on bushy trees
+    and C2 cells: the replay matches the oracle and no cell has more than
+    max_cuts + 1 lanes.  These networks are small, so every cell longer than
+    a wave slot's share is cut whatever the threshold (as for the depth-first
+    lanes)."""
+    for f, diag, upper in (bushy_system(60, 7, max_children=4, size=(1, 700)),
+                           (lambda s: (s.forest, s.diag, s.upper))(configs.c2(50, seed=3))):
+        p = _check(f, diag, upper, cell_cut_percent=cut, cell_max_cuts=max_cuts)
+        cells = p.table("seq_lanes")
+        cells = cells[cells >= 0]
+        assert np.bincount(cells).max() <= max_cuts + 1
