@@ -345,3 +345,14 @@ def test_seq_cut_settings(cut, max_cuts):
         cells = p.table("seq_lanes")
         cells = cells[cells >= 0]
         assert np.bincount(cells).max() <= max_cuts + 1
+
+
+def test_seq_many_small_cells_take_the_threshold():
+    """40,000 cells (more than half the device's lanes): the cut threshold,
+    not a wave slot's share, decides, and cut cells (up to four pieces)
+    replay to the oracle."""
+    s = random_system(40000, 3)
+    p = _check(s.forest, s.diag, s.upper, cell_cut_percent=100, cell_max_cuts=3)
+    cells = p.table("seq_lanes")
+    per = np.bincount(cells[cells >= 0])
+    assert per.max() == 4 and (per == 1).sum() > 0
