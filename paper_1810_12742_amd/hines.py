@@ -126,7 +126,11 @@ def _dev(t, n, dtype, name):
 
 
 class Plan:
-    """A setup plan (``hines_setup``) and the solves that use it."""
+    """A setup plan (``hines_setup``) and the solves that use it.
+
+    Options are those of ``hines_options`` in include/hines.h; ``cell_lanes``
+    is 0 (groups), 1 (one lane per cell, depth-first walks) or 2 (one lane per
+    cell, walks in decreasing user index)."""
 
     def __init__(self, parent, cell_offsets, branch_offsets=None, *, rebalance_root=False,
                  split_branches=False, group_width=64, cell_order=0, max_group_unknowns=None,
