@@ -528,9 +528,11 @@ SCALING_CELLS = (64, 256, 1024, 4096, 16384, 65536)
 
 def run_scaling(args, torch, dev):
     """Solve time against the number of cells for the cell-lane kernel (one
-    lane per cell, the paper's "old" solver) and the flow kernel (branch-level
-    parallelism, the "fine" solver): the first n cells of the headline
-    workload, each plan timed with HIP events."""
+    lane per cell, the paper's "old" solver, with depth-first walks and with
+    walks in index order) and the flow kernel (branch-level parallelism, the
+    "fine" solver): the first n cells of the headline workload, each plan
+    timed with HIP events.  The speed-up compares the fine solver with the
+    depth-first old one."""
     from workloads import configs
     from paper_1810_12742_amd import Plan
 
@@ -540,7 +542,8 @@ def run_scaling(args, torch, dev):
     u = torch.from_numpy(s.upper).to(dev)
     b = torch.from_numpy(s.rhs).to(dev)
     stream = torch.cuda.current_stream()
-    kernels = {"cell_lanes": dict(cell_lanes=1), "flow": dict(C2_FLOW_OPTIONS)}
+    kernels = {"cell_lanes": dict(cell_lanes=1), "cell_lanes_index_order": dict(cell_lanes=2),
+               "flow": dict(C2_FLOW_OPTIONS)}
     rows = []
     for nc in SCALING_CELLS:
         sub = f.subset(np.arange(nc)) if nc < f.ncells else f
@@ -557,7 +560,7 @@ def run_scaling(args, torch, dev):
         rows.append(row)
         print(json.dumps(row), file=sys.stderr, flush=True)
     last = rows[-1]
-    best = min(last["cell_lanes_ms"], last["flow_ms"])
+    best = min(last[k + "_ms"] for k in kernels)
     return {
         "metric": METRIC, "value": last["unknowns"] / (best * 1e-3), "unit": "unknowns/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": best, "higher_is_better": True,
