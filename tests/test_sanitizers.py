@@ -1,10 +1,9 @@
 """The host-side table builders (setup, cell lanes in both walk orders,
 resident) compiled with AddressSanitizer and UndefinedBehaviorSanitizer (g++,
 CPU only) on forests and option sets of the table-parity suite; the tables
-they export must equal the
-library's (built without sanitizers), so the sanitized run executes the same
-code paths.  A heap overflow, use after free or undefined operation aborts
-the driver with a report."""
+they export must equal the library's (built without sanitizers), so the
+sanitized run executes the same code paths.  A heap overflow, use after free
+or undefined operation aborts the driver with a report."""
 import os
 import shutil
 import subprocess
